@@ -1,0 +1,153 @@
+/*
+ * FP64 CPU oracle for the differentiable Monte Carlo polarization ray trace
+ * through a geometric waveguide (arXiv 2601.04370, Methods).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this code; only the test-suite, the smoke check and the bench's CPU
+ * baseline leg do.  It is deliberately plain and slow: one ray at a time,
+ * double precision, no blocking or fusion, every step in the order the paper
+ * describes it.  It shares no code with the HIP implementation.
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - time dependence exp(-i w t); complex index N = n + i k, k >= 0 absorbs;
+ *     a layer's phase factor is exp(+i delta), so single-layer results are the
+ *     complex conjugates of the Airy formulas (Eq. 4) as printed, which use
+ *     exp(-2 i delta); intensities are identical;
+ *   - Fresnel coefficients exactly as Eq. 3 (s: TE, p: TM with p = k x s for
+ *     each ray), so r_p(0 deg) = -r_s(0 deg);
+ *   - normal-direction wavenumber q = sqrt(N^2 - kappa^2), kappa = n_0 sin(theta_0),
+ *     branch Im q >= 0 (and Re q >= 0 when Im q = 0).
+ *
+ * Units: lengths in mm for geometry, layer thicknesses and wavelengths in nm.
+ */
+#ifndef GWG_ORACLE_H
+#define GWG_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- Philox */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): out = bijection(ctr, key). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* ------------------------------------------------------------- thin film */
+/* One stack in incidence order: layer j has index (nre[j], nim[j]) and
+ * thickness thk_nm[j]; incident medium n_in (real), exit medium (nout_re, nout_im).
+ * kappa = n_in * sin(theta_in).  Output out[8] = r_s, r_p, t_s, t_p as
+ * (re, im) pairs in the Eq. 3 amplitude convention.  Recursive Airy (Rouard)
+ * evaluation of Eq. 4 from the exit medium outwards. */
+void orc_tmm_rt(int n_layers, const double* thk_nm, const double* nre, const double* nim,
+                double n_in, double nout_re, double nout_im,
+                double lambda_nm, double kappa, double out[8]);
+
+/* Holomorphic derivatives d c / d thk_j (per nm) of the four coefficients,
+ * by reverse-mode through the same recursion.  d_out[j*16 + 4*c + 0..3] holds,
+ * for c = r_s, r_p, t_s, t_p: (re, im) of dc/dthk_j, then 2 unused slots. */
+void orc_tmm_dthk(int n_layers, const double* thk_nm, const double* nre, const double* nim,
+                  double n_in, double nout_re, double nout_im,
+                  double lambda_nm, double kappa, double* d_out);
+
+/* ------------------------------------------------------------------ scene */
+typedef struct {
+    /* refractive-index table, [n_lambda][n_mat] */
+    int32_t n_lambda, n_mat;
+    const double* lambda_nm;
+    const double* n_re;
+    const double* n_im;
+    /* slab */
+    double T, Lx, eye_relief;
+    int32_t mat_glass, mat_air;
+    double pupil_x0, pupil_w, pupil_h;
+    double eye_x0, eye_y0, eye_w, eye_h;
+    int32_t bins_x, bins_y;
+    /* mirrors */
+    int32_t n_mirrors;
+    double tilt_deg, pitch, center_x;
+    const double* omega;            /* [M] reflection probability */
+    /* stacks, [D][M][Lmax] */
+    int32_t n_designs, max_layers;
+    const double* thk;
+    const uint8_t* mat;
+    const int32_t* n_layers;        /* [D][M] */
+    /* rays */
+    int32_t n_lsel;
+    const int32_t* lambda_sel;      /* [n_lsel] indices into the table */
+    int32_t fov_mode;               /* 0 grid, 1 uniform random per ray */
+    int32_t n_fov;
+    const double* fov_deg;          /* grid: [F][2]; random: [[xlo,xhi],[ylo,yhi]] */
+    int64_t rays_per_point;
+    int32_t max_events;
+    int32_t fp_shift;
+    uint64_t seed, step;
+} orc_scene;
+
+/* Termination categories. */
+enum { ORC_EYEBOX = 0, ORC_MISS = 1, ORC_LEAK = 2, ORC_END = 3, ORC_TRUNC = 4,
+       ORC_LOST = 5, ORC_FACE_R = 6, ORC_NCAT = 8 };
+
+/* Per-ray record (sampled parity). */
+typedef struct {
+    int64_t ray_id;
+    int32_t bin;          /* flat bin index within the point, -1 if none */
+    int32_t category;
+    int32_t n_events;     /* ray-surface interactions */
+    int32_t n_prma;       /* mirror hits */
+    double w;             /* final |E|^2 (at the eyebox, or where the ray ended) */
+    double exit_dir[3];   /* direction in air after leaving the top face */
+    double exit_pos[3];
+} orc_ray_record;
+
+/* Statistics: counters[0..] = rays, interactions, prma_hits, saturated,
+ * then per category counts [4 + c]; power[c] = summed weight per category. */
+typedef struct {
+    int64_t counters[16];
+    double power[ORC_NCAT];
+} orc_stats;
+
+/* Full forward: every ray of every (design, lambda, fov) point.
+ * q_bins, counts, wsum have shape [D][n_lsel][F][bins_y][bins_x] (any may be NULL). */
+int orc_trace_forward(const orc_scene* sc, uint64_t* q_bins, uint32_t* counts,
+                      double* wsum, orc_stats* stats);
+
+/* Trace the listed rays only (global ray ids), writing one record each. */
+int orc_trace_rays(const orc_scene* sc, int64_t n, const int64_t* ray_ids, orc_ray_record* rec);
+
+/* Event log of one ray for geometry tests: up to cap events of
+ * (type, surface, x, y, z, dx, dy, dz, aoi_deg, branch). Returns count. */
+int orc_ray_events(const orc_scene* sc, int64_t ray_id, int cap, double* ev10);
+
+/* Adjoint: dL/dthk[D][M][Lmax] for dL/dI given per bin (same shape as bins).
+ * Only rays with ray_id % sample_stride == 0 contribute when stride > 1
+ * (the matching forward is then the sampled one). */
+int orc_trace_backward(const orc_scene* sc, const double* dL_dI, int64_t sample_stride,
+                       double* grad);
+
+/* Sampled forward matching orc_trace_backward's sampling: irradiance of the
+ * rays with ray_id % stride == 0, normalised by the full per-point ray count. */
+int orc_trace_forward_sampled(const orc_scene* sc, int64_t sample_stride, double* irr);
+
+/* Brute-force deterministic splitting of the births [first, first + n) of
+ * point (d, l, f): exact expected bin power sum_paths |E_path|^2 (no
+ * sampling), summed per bin. */
+int orc_split_bruteforce(const orc_scene* sc, int32_t d, int32_t lsel, int32_t f,
+                         int64_t first, int64_t n_rays, double* bin_power, int64_t* n_paths);
+
+/* Monte Carlo weight of one birth under a forced decision sequence
+ * (bit k = 1 means "reflect" at the k-th mirror hit).  Returns the bin (-1 if
+ * none) and writes the weight and the path probability. */
+int orc_trace_forced(const orc_scene* sc, int64_t ray_id, uint64_t decisions, int n_decisions,
+                     double* w, double* prob, int* n_used);
+
+/* --------------------------------------------------------------- the loss */
+/* irr: [D][n_l][F][B] irradiance.  kind 0: -mean eta + w_e Var_eyebox + w_f Var_fov;
+ * kind 1: -mean eta + w_f CV_fov + w_e CV_eyebox (Eq. 1).  Returns L, writes dL/dI. */
+double orc_loss(const double* irr, int32_t D, int32_t n_l, int32_t F, int32_t B,
+                int32_t kind, double w_f, double w_e, double* dL_dI);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
