@@ -1,0 +1,246 @@
+/*
+ * gwg.h — C ABI of the MI355X (gfx950) differentiable Monte Carlo
+ * polarization ray trace through a geometric waveguide.
+ *
+ * The operations follow arXiv 2601.04370 (Methods):
+ *   - gwg_tmm_rt: effective Fresnel coefficients of a multilayer coating,
+ *     "Multilayer thin-film solver" (Eq. 3 interface coefficients, Eq. 4 Airy
+ *     sums, transfer-matrix method);
+ *   - gwg_trace_forward: non-sequential Monte Carlo polarization ray trace,
+ *     "Polarization ray tracing" (Eq. 5) and "Differentiable Monte Carlo
+ *     non-sequential ray tracing" (Eq. 6, incoherent eyebox sum of |E|^2);
+ *   - gwg_trace_backward: gradient of a loss on the eyebox irradiance with
+ *     respect to every layer thickness through the sampled paths
+ *     (reparameterized sampling; two-pass intersection and gradient
+ *     checkpointing between the tracer and the thin-film solver);
+ *   - gwg_loss: the eyebox loss of Eq. 1 (and its variance form) and its
+ *     gradient with respect to the irradiance.
+ *
+ * Conventions shared by every entry point
+ *   - time dependence exp(-i w t); complex index N = n + i k with k >= 0
+ *     absorbing.  Lossless results are the complex conjugates of Eq. 4 as
+ *     printed (which uses exp(-2 i delta)); |r|^2, |t|^2 are identical.
+ *   - r_s, r_p, t_s, t_p are field-amplitude ratios in the convention of
+ *     Eq. 3 (p unit vector = k x s for each wave), so r_p(0) = -r_s(0).
+ *   - lengths: geometry in mm, wavelengths and thicknesses in nm.
+ *   - "device" pointers are HIP device memory of the context's GPU, owned by
+ *     the caller; "host" pointers are read during the call only.
+ *   - all work is enqueued on `stream` (a hipStream_t, NULL = default
+ *     stream) and is asynchronous unless a host output is requested.
+ *
+ * Errors: every call returns a gwg_status.  Arguments are validated on the
+ * host before anything is enqueued; on GWG_E_INVAL nothing was launched.
+ * gwg_last_error() gives a message for the last failing call on a context.
+ * A context is used by one host thread at a time.
+ */
+#ifndef GWG_H
+#define GWG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GWG_ABI_VERSION 1
+
+typedef struct gwg_ctx gwg_ctx;   /* opaque; owns scratch memory and scene tables */
+
+typedef enum {
+    GWG_OK = 0,
+    GWG_E_INVAL = 1,        /* invalid argument; nothing was launched */
+    GWG_E_NOMEM = 2,        /* device allocation failed */
+    GWG_E_HIP = 3,          /* HIP runtime error (message in gwg_last_error) */
+    GWG_E_STATE = 4,        /* call out of order (e.g. backward without forward) */
+    GWG_E_OVERFLOW = 5,     /* fixed-point bin saturated (only reported with stats) */
+    GWG_E_NODEVICE = 6      /* no usable gfx950 device for this context */
+} gwg_status;
+
+typedef enum {
+    GWG_FP64 = 0,           /* every step in double precision */
+    GWG_FP32_MIXED = 1,     /* thin-film solve in single precision, re-solved in
+                               double precision for flagged hits (near-critical
+                               angle or large estimated conditioning); geometry,
+                               fields and reductions in double precision */
+    GWG_FP32 = 2            /* thin-film solve in single precision, no re-solve
+                               (diagnostics: measures the single-precision error) */
+} gwg_precision;
+
+/* Refractive-index table (host): n_re/n_im are [n_lambda][n_mat]. */
+typedef struct {
+    int32_t n_lambda, n_mat;
+    const double* lambda_nm;    /* [n_lambda] vacuum wavelengths, nm, > 0 */
+    const double* n_re;         /* [n_lambda][n_mat] real part, > 0 */
+    const double* n_im;         /* [n_lambda][n_mat] extinction, >= 0 */
+} gwg_materials;
+
+/* ------------------------------------------------------------ lifecycle */
+/* Create a context on HIP device `device`.  Returns GWG_E_NODEVICE if the
+ * device does not exist or is not gfx950.  *out is NULL on failure. */
+int gwg_create(gwg_ctx** out, int32_t device);
+/* Release the context and every device buffer it owns (synchronizes). */
+int gwg_destroy(gwg_ctx* ctx);
+/* Message of the last failing call on ctx (never NULL; "" if none).  Valid
+ * until the next call on ctx.  With ctx == NULL, the last gwg_create error. */
+const char* gwg_last_error(const gwg_ctx* ctx);
+/* ABI version (GWG_ABI_VERSION). */
+int32_t gwg_abi_version(void);
+
+/* ------------------------------------------------------------ thin film */
+/* One coating stack in incidence order. */
+typedef struct {
+    int32_t n_layers;           /* 0 <= n_layers <= 4096 */
+    const double* thk_nm;       /* device [n_layers], >= 0 */
+    const uint8_t* mat;         /* host [n_layers], indices into the material table */
+    int32_t mat_in, mat_out;    /* incident (lossless) and exit media */
+} gwg_stack;
+
+/* Effective coefficients of one stack for n_q queries (Methods, thin-film
+ * solver; Eq. 3 amplitude convention).  Query q uses wavelength index
+ * d_lambda_idx[q] (device int32, < n_lambda) and angle of incidence
+ * d_theta[q] (device f64, radians, in [0, pi/2)) in the incident medium.
+ * d_out (device f64 [n_q][8]) receives r_s, r_p, t_s, t_p as (re, im).
+ * precision: GWG_FP64 or GWG_FP32 (GWG_FP32_MIXED applies the tracer's
+ * re-solve rule).  Out-of-range indices in device arrays give NaN outputs. */
+int gwg_tmm_rt(gwg_ctx* ctx, const gwg_stack* stack, const gwg_materials* mats,
+               int64_t n_q, const int32_t* d_lambda_idx, const double* d_theta,
+               int32_t precision, double* d_out, void* stream);
+
+/* ---------------------------------------------------------------- trace */
+/* Slab: glass 0 <= z <= T_mm, 0 <= x <= L_mm, unbounded in y; rays enter
+ * through the top-face window [pupil_x0, pupil_x0 + pupil_w] x
+ * [-pupil_h/2, pupil_h/2]; they are binned on the plane z = T + eye_relief
+ * over the rectangle [eye_x0, eye_x0 + eye_w) x [eye_y0, eye_y0 + eye_h). */
+typedef struct {
+    double T_mm, L_mm, eye_relief_mm;
+    int32_t mat_glass, mat_air;
+    double pupil_x0_mm, pupil_w_mm, pupil_h_mm;
+    double eye_x0_mm, eye_y0_mm, eye_w_mm, eye_h_mm;
+    int32_t bins_x, bins_y;     /* 1..4096 each */
+} gwg_slab;
+
+/* Partially reflective mirror array: n_mirrors (1..16) parallel planes with
+ * normal (-sin tilt, 0, cos tilt) through (center_x + (m - (M-1)/2) pitch, ., T/2),
+ * spanning the slab thickness.  omega[m] in (0, 1) is the probability of
+ * sampling the reflected branch at mirror m (Eq. 6). */
+typedef struct {
+    int32_t n_mirrors;
+    double tilt_deg, pitch_mm, center_x_mm;
+    const double* omega;        /* host [n_mirrors] */
+} gwg_prma;
+
+/* Coating stacks of n_designs candidate designs.  Layer 0 faces the +normal
+ * side of its mirror; a hit from the -normal side sees the reverse order.
+ * Slots j >= n_layers[d][m] are padding and ignored. */
+typedef struct {
+    int32_t n_designs, n_mirrors, max_layers;   /* max_layers 1..1024 */
+    const double* thk_nm;       /* device [D][M][Lmax] f64, >= 0 */
+    const uint8_t* mat;         /* host [D][M][Lmax] material indices */
+    const int32_t* n_layers;    /* host [D][M], 0..max_layers */
+} gwg_stacks;
+
+/* Ray batch: every (design, selected wavelength, FoV point) gets
+ * rays_per_point rays.  fov_mode 0: fov_deg is [n_fov][2] (theta_x, theta_y)
+ * field angles in degrees; fov_mode 1: one point whose rays draw field
+ * angles uniformly in fov_deg = [[x_lo, x_hi], [y_lo, y_hi]] (n_fov = 1).
+ * A field angle (tx, ty) is the direction normalize(tan tx, tan ty, 1) in
+ * air at the eye. */
+typedef struct {
+    int32_t n_lambda_sel;
+    const int32_t* lambda_sel;  /* host [n_lambda_sel] indices into the table */
+    int32_t fov_mode;
+    int32_t n_fov;
+    const double* fov_deg;      /* host */
+    int64_t rays_per_point;     /* 1 .. 2^40 */
+    int32_t max_events;         /* 1..256 ray-surface interactions per ray */
+} gwg_rays;
+
+/* Eyebox outputs, device arrays of shape [D][n_lambda_sel][F][bins_y][bins_x]
+ * (F = n_fov, or 1 in fov_mode 1).  q_bins accumulates round-half-even(w 2^fp_shift)
+ * per ray (per-ray value clamped at 2^40), counts the number of rays
+ * landing in the bin (geometry only).  irradiance (optional, may be NULL)
+ * receives q_bins 2^-fp_shift / rays_per_point.  Every output is
+ * overwritten. */
+typedef struct {
+    uint64_t* q_bins;
+    uint32_t* counts;
+    double* irradiance;
+    int32_t fp_shift;           /* 0..40 */
+} gwg_eyebox;
+
+/* Per-ray record for sampled comparisons: written for ray ids
+ * id = k * record_stride into records[k]. */
+typedef struct {
+    int32_t bin;        /* flat bin within its point, -1 if not binned */
+    int32_t category;   /* GWG_CAT_* */
+    int32_t n_events;   /* ray-surface interactions */
+    int32_t n_prma;     /* mirror hits */
+    double w;           /* final |E|^2 */
+} gwg_ray_record;
+
+enum { GWG_CAT_EYEBOX = 0, GWG_CAT_MISS = 1, GWG_CAT_LEAK = 2, GWG_CAT_END = 3,
+       GWG_CAT_TRUNC = 4, GWG_CAT_LOST = 5, GWG_CAT_FACE_R = 6, GWG_NCAT = 8 };
+
+typedef struct {
+    int64_t rays, interactions, prma_hits, fp64_hits, saturated;
+    int64_t n_cat[GWG_NCAT];
+    double power[GWG_NCAT];     /* summed final |E|^2 per category (fixed-point, 2^-24) */
+} gwg_stats;
+
+/* Forward Monte Carlo trace of the whole batch (Methods; Eq. 5, Eq. 6).
+ * Ray id = ((d * n_lambda_sel + l) * F + f) * rays_per_point + i draws its
+ * random numbers from Philox4x32-10 with key (seed_lo, seed_hi ^ step_lo),
+ * counter (id_lo, id_hi, block, tag): tag 0 block 0 gives the birth words,
+ * tag 1 block h/4 the word of the h-th mirror hit.  step < 2^32.
+ * records: optional device array (NULL to skip) with record_stride >= 1.
+ * stats: optional host struct; when given the call synchronizes the stream
+ * and returns GWG_E_OVERFLOW if any bin contribution saturated.
+ * The context remembers the scene, seed, step, precision and thk pointer
+ * for gwg_trace_backward; thk must not change in between. */
+int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
+                      const gwg_materials* mats, const gwg_stacks* stacks,
+                      const gwg_rays* rays, uint64_t seed, uint64_t step,
+                      int32_t precision, const gwg_eyebox* out,
+                      gwg_ray_record* records, int64_t record_stride,
+                      gwg_stats* stats, void* stream);
+
+/* Gradient of a loss with respect to every layer thickness, given
+ * d_dL_dI (device f64, the eyebox shape of the last forward).  The sampled
+ * paths of the last forward are regenerated (same seed and step), so the
+ * result is the pathwise derivative of the unquantized estimator
+ * I = sum w / rays_per_point.  d_grad: device f64 [D][M][max_layers],
+ * overwritten (padding slots get 0).  sample_stride >= 1: only rays with
+ * id % sample_stride == 0 contribute (1 = all rays).  Deterministic: the
+ * same inputs give bit-identical gradients. */
+int gwg_trace_backward(gwg_ctx* ctx, const double* d_dL_dI, double* d_grad,
+                       int64_t sample_stride, void* stream);
+
+/* Eyebox loss (Eq. 1) and dL/dI for irradiance d_irr (device f64,
+ * [D][n_l][F][B]), summed over designs.  kind 0: -mean(eta) + w_e Var_b(E_b)
+ * + w_f Var_f(phi_f); kind 1: -mean(eta) + w_f CV_f + w_e CV_b, with
+ * eta = sum_b I (per wavelength and FoV point), E_b the mean of I over
+ * wavelengths and FoV points, phi_f the mean of eta over wavelengths,
+ * population moments.  d_loss: device f64 [1]; d_dL_dI: device f64, same
+ * shape as d_irr (may be NULL).  Fixed-order reductions: deterministic. */
+int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
+             int32_t B, int32_t kind, double w_f, double w_e, double* d_loss,
+             double* d_dL_dI, void* stream);
+
+/* ---------------------------------------------------------------- tuning */
+/* Launch parameters of the trace kernels (0 = automatic).  rays_per_block
+ * is the tile of rays of one (design, wavelength, FoV) point handled by a
+ * workgroup; block_threads is 64, 128 or 256. */
+typedef struct {
+    int32_t block_threads;
+    int64_t rays_per_block;
+    int32_t bwd_block_threads;
+    int64_t bwd_rays_per_block;
+} gwg_tuning;
+
+int gwg_set_tuning(gwg_ctx* ctx, const gwg_tuning* tuning);
+int gwg_get_tuning(const gwg_ctx* ctx, gwg_tuning* tuning);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWG_H */

@@ -1,0 +1,53 @@
+"""Build the HIP library libgwg.so (gfx950) in the package directory.
+
+hipcc compiles the kernels and the host C ABI into one shared library.  The
+flags disable packed-FP32 instruction selection and FMA contraction (the
+thin-film kernels opt back into contraction locally), and keep
+IEEE-conforming division and square root.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libgwg.so")
+SOURCES = ["gwg_kernels.hip", "gwg_api.cpp"]
+HEADERS = ["gwg_internal.h", "gwg_device.h", "gwg_adjoint.h", "gwg_trace.h", "gwg_launch.h"]
+ARCH = "gfx950"
+
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=" + ARCH,
+    "-ffp-contract=off",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+
+
+def hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
+        if c and (os.path.exists(c) or c == "hipcc"):
+            return c
+    return "hipcc"
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + srcs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def sources():
+    return ([os.path.join(CSRC, s) for s in SOURCES + HEADERS]
+            + [os.path.join(ROOT, "include", "gwg.h")])
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    print(LIB)

@@ -1,0 +1,211 @@
+// Adjoint of the per-hit thin-film solve (reverse sweep with segment
+// recomputation).  See gwg_device.h for the formulation.  Always double
+// precision: the covector and the recomputed vectors carry the full
+// conditioning of the stack.
+#pragma once
+#include "gwg_device.h"
+
+namespace gwg {
+
+struct V2d { double br, bi, cr, ci; };
+
+__device__ inline void step_real_d(V2d& v, double C, double X, double Y)
+{
+#pragma clang fp contract(fast)
+    double br = C * v.br + X * v.ci;
+    double bi = C * v.bi - X * v.cr;
+    double cr = Y * v.bi + C * v.cr;
+    double ci = C * v.ci - Y * v.br;
+    v.br = br; v.bi = bi; v.cr = cr; v.ci = ci;
+}
+
+__device__ inline void step_cplx_d(V2d& v, cd C, cd X, cd Y)
+{
+    cd B = mk(v.br, v.bi), Cv = mk(v.cr, v.ci);
+    cd mX = mk(X.im, -X.re), mY = mk(Y.im, -Y.re);
+    cd b = cadd(cmul(C, B), cmul(mX, Cv));
+    cd c = cadd(cmul(mY, B), cmul(C, Cv));
+    v.br = b.re; v.bi = b.im; v.cr = c.re; v.ci = c.im;
+}
+
+// Entries of one layer for both polarizations.  Lossless: C real, X/Y real
+// (imaginary parts zero).  Absorbing: complex.
+struct LayerEnt { cd C, Xs, Ys, Xp, Yp; bool real; };
+
+__device__ inline LayerEnt layer_entries(const double* P, int ls, bool cplx, double k0, double t)
+{
+    LayerEnt e;
+    e.real = !cplx;
+    if (!cplx) {
+        double C, S;
+        layer_cs(P[0], t, &C, &S);
+        e.C = mk(C, 0.0);
+        e.Xs = mk(S * P[ls], 0.0); e.Ys = mk(S * P[2 * ls], 0.0);
+        e.Xp = mk(S * P[3 * ls], 0.0); e.Yp = mk(S * P[4 * ls], 0.0);
+    } else {
+        double Pl[4] = { P[0], P[ls], P[2 * ls], P[3 * ls] };
+        CTv<double> C, Xs, Ys, Xp, Yp;
+        layer_cplx(Pl, k0, t, &C, &Xs, &Ys, &Xp, &Yp);
+        e.C = mk(C.re, C.im); e.Xs = mk(Xs.re, Xs.im); e.Ys = mk(Ys.re, Ys.im);
+        e.Xp = mk(Xp.re, Xp.im); e.Yp = mk(Yp.re, Yp.im);
+    }
+    return e;
+}
+
+__device__ inline void apply_layer(V2d& vs, V2d& vp, const LayerEnt& e)
+{
+    if (e.real) {
+        step_real_d(vs, e.C.re, e.Xs.re, e.Ys.re);
+        step_real_d(vp, e.C.re, e.Xp.re, e.Yp.re);
+    } else {
+        step_cplx_d(vs, e.C, e.Xs, e.Ys);
+        step_cplx_d(vp, e.C, e.Xp, e.Yp);
+    }
+}
+
+// u^T <- u^T M for M = [[C, -iX], [-iY, C]]:  u1' = u1 C - i u2 Y,  u2' = -i u1 X + u2 C
+__device__ inline void cov_step(cd& u1, cd& u2, cd C, cd X, cd Y)
+{
+    cd mY = mk(Y.im, -Y.re), mX = mk(X.im, -X.re);
+    cd n1 = cadd(cmul(u1, C), cmul(u2, mY));
+    cd n2 = cadd(cmul(u1, mX), cmul(u2, C));
+    u1 = n1; u2 = n2;
+}
+
+// Adjoint of one mirror hit.  Adds d(2 Re(Gs c_s + Gp c_p))/dt_j for every
+// layer into grad_row (this mirror's row of the calling wave's LDS
+// accumulator, stack order), where c = r (reflect) or t (transmit).
+// nsq[s] = Re(N_s^2) of slot s and nsq_inv[s] = 1 / Re(N_s^2) (lossless), or
+// for absorbing slots (re, im) of N^2 in nsq_c[2 s], nsq_c[2 s + 1].
+// chk: this lane's checkpoint storage, component k of checkpoint c at
+// chk[(c * 8 + k) * cstride].
+__device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t* __restrict__ slot,
+                                   int L, bool front, const double* __restrict__ sp, int ls,
+                                   uint32_t cplx_mask, double k0, double kappa2,
+                                   const double* __restrict__ nsq_c,
+                                   double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
+                                   double* grad_row, double* __restrict__ chk, int64_t cstride)
+{
+    // 1) exit -> incident sweep, checkpoints w_{kSeg}, w_{2 kSeg}, ...
+    V2d vs = { 1.0, 0.0, eta0s, 0.0 };
+    V2d vp = { 1.0, 0.0, eta0p, 0.0 };
+    for (int jj = L - 1; jj >= 0; --jj) {
+        int idx = front ? jj : (L - 1 - jj);
+        double t = thk[idx];
+        if (t != 0.0) {
+            int s = slot[idx];
+            LayerEnt e = layer_entries(sp + s * NPF * ls, ls, (cplx_mask >> s) & 1u, k0, t);
+            apply_layer(vs, vp, e);
+        }
+        if (jj > 0 && (jj % kSeg) == 0) {
+            double* c = chk + (int64_t)(jj / kSeg) * 8 * cstride;
+            c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
+            c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
+        }
+    }
+    // 2) cotangent row of the taken coefficient w.r.t. [B; C]
+    cd u1s, u2s, u1p, u2p;
+    {
+        cd B = mk(vs.br, vs.bi), C = mk(vs.cr, vs.ci);
+        cd den = cadd(cscale(B, eta0s), C);
+        cd inv2 = cdiv(mk(1.0, 0.0), cmul(den, den));
+        cd dB, dC;
+        if (reflect) { dB = cscale(cmul(C, inv2), 2.0 * eta0s); dC = cscale(cmul(B, inv2), -2.0 * eta0s); }
+        else { dB = cscale(inv2, -2.0 * eta0s * eta0s); dC = cscale(inv2, -2.0 * eta0s); }
+        u1s = cmul(Gs, dB); u2s = cmul(Gs, dC);
+    }
+    {
+        cd B = mk(vp.br, vp.bi), C = mk(vp.cr, vp.ci);
+        cd den = cadd(cscale(B, eta0p), C);
+        cd inv2 = cdiv(mk(1.0, 0.0), cmul(den, den));
+        cd dB, dC;
+        if (reflect) {   // r_p = -r_Mac
+            dB = cscale(cmul(C, inv2), -2.0 * eta0p); dC = cscale(cmul(B, inv2), 2.0 * eta0p);
+        } else { dB = cscale(inv2, -2.0 * eta0p * eta0p); dC = cscale(inv2, -2.0 * eta0p); }
+        u1p = cmul(Gp, dB); u2p = cmul(Gp, dC);
+    }
+    // 3) incident -> exit covector sweep, segment by segment
+    const int nseg = (L + kSeg - 1) / kSeg;
+    for (int k = 0; k < nseg; ++k) {
+        const int lo = k * kSeg;
+        const int hi = min(lo + kSeg, L);
+        V2d ws, wp;
+        if (hi == L) {
+            ws = V2d{ 1.0, 0.0, eta0s, 0.0 };
+            wp = V2d{ 1.0, 0.0, eta0p, 0.0 };
+        } else {
+            const double* c = chk + (int64_t)(hi / kSeg) * 8 * cstride;
+            ws = V2d{ c[0], c[cstride], c[2 * cstride], c[3 * cstride] };
+            wp = V2d{ c[4 * cstride], c[5 * cstride], c[6 * cstride], c[7 * cstride] };
+        }
+        V2d segs[kSeg], segp[kSeg];
+        double segC[kSeg], segS[kSeg];
+#pragma unroll
+        for (int i = kSeg - 1; i >= 0; --i) {
+            const int jj = lo + i;
+            segC[i] = 1.0; segS[i] = 0.0;
+            if (jj < hi) {
+                int idx = front ? jj : (L - 1 - jj);
+                double t = thk[idx];
+                int s = slot[idx];
+                if (t != 0.0) {
+                    const double* P = sp + s * NPF * ls;
+                    if (!((cplx_mask >> s) & 1u)) {
+                        double C, S;
+                        layer_cs(P[0], t, &C, &S);
+                        segC[i] = C; segS[i] = S;
+                        step_real_d(ws, C, S * P[ls], S * P[2 * ls]);
+                        step_real_d(wp, C, S * P[3 * ls], S * P[4 * ls]);
+                    } else {
+                        LayerEnt e = layer_entries(P, ls, true, k0, t);
+                        apply_layer(ws, wp, e);
+                    }
+                }
+                segs[i] = ws; segp[i] = wp;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kSeg; ++i) {
+            const int jj = lo + i;
+            if (jj < hi) {
+                int idx = front ? jj : (L - 1 - jj);
+                double t = thk[idx];
+                int s = slot[idx];
+                const double* P = sp + s * NPF * ls;
+                bool cplx = (cplx_mask >> s) & 1u;
+                // contraction u^T D w (D = -i k0 [[0, a], [b, 0]])
+                cd Bs = mk(segs[i].br, segs[i].bi), Cs = mk(segs[i].cr, segs[i].ci);
+                cd Bp = mk(segp[i].br, segp[i].bi), Cp = mk(segp[i].cr, segp[i].ci);
+                cd As, Ap;
+                if (!cplx) {
+                    double n2 = nsq_c[2 * s];
+                    double z = n2 - kappa2;
+                    As = cadd(cmul(u1s, Cs), cscale(cmul(u2s, Bs), z));
+                    Ap = cadd(cscale(cmul(u1p, Cp), z / n2), cscale(cmul(u2p, Bp), n2));
+                } else {
+                    cd N2 = mk(nsq_c[2 * s], nsq_c[2 * s + 1]);
+                    cd z = csub(N2, mk(kappa2, 0.0));
+                    As = cadd(cmul(u1s, Cs), cmul(z, cmul(u2s, Bs)));
+                    Ap = cadd(cmul(cdiv(z, N2), cmul(u1p, Cp)), cmul(N2, cmul(u2p, Bp)));
+                }
+                // Re(-i k0 A) = k0 Im(A); dw/dt = 2 Re(...)
+                double g = 2.0 * k0 * (As.im + Ap.im);
+                atomicAdd(&grad_row[idx], g);
+                // covector through layer jj
+                if (t != 0.0) {
+                    if (!cplx) {
+                        double C = segC[i], S = segS[i];
+                        cov_step(u1s, u2s, mk(C, 0.0), mk(S * P[ls], 0.0), mk(S * P[2 * ls], 0.0));
+                        cov_step(u1p, u2p, mk(C, 0.0), mk(S * P[3 * ls], 0.0), mk(S * P[4 * ls], 0.0));
+                    } else {
+                        LayerEnt e = layer_entries(P, ls, true, k0, t);
+                        cov_step(u1s, u2s, e.C, e.Xs, e.Ys);
+                        cov_step(u1p, u2p, e.C, e.Xp, e.Yp);
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace gwg

@@ -1,0 +1,606 @@
+// Host side of the C ABI declared in include/gwg.h: argument validation,
+// scene tables, device buffers owned by the context, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gwg.h"
+#include "gwg_internal.h"
+#include "gwg_launch.h"
+
+using namespace gwg;
+
+namespace {
+
+// Device buffer owned by the context (grow-only).
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        if (p) { hipError_t e = hipFree(p); if (e != hipSuccess) return e; p = nullptr; bytes = 0; }
+        size_t want = std::max<size_t>(n, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
+};
+
+uint64_t fnv(uint64_t h, const void* data, size_t n)
+{
+    const unsigned char* b = (const unsigned char*)data;
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+template <typename T> uint64_t fnv_v(uint64_t h, const T& v) { return fnv(h, &v, sizeof(T)); }
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+std::string g_create_error;
+
+}  // namespace
+
+struct gwg_ctx {
+    int device = -1;
+    int n_cu = 0;
+    std::string err;
+    // scene tables
+    uint64_t scene_hash = 0;
+    bool scene_valid = false;
+    SceneDev sc{};
+    DevBuf lam_tab, dir_tab, slot, nlay;
+    std::vector<int32_t> h_nlay;
+    // per-call buffers
+    DevBuf stats, partial, scratch, loss_work;
+    // thin-film queries
+    DevBuf tmm_tab, tmm_slot;
+    // last forward
+    bool have_forward = false;
+    SceneDev fwd{};
+    // tuning
+    gwg_tuning tune{};
+};
+
+namespace {
+
+int fail(gwg_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(gwg_ctx* c, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+int hip_fail(gwg_ctx* c, hipError_t e, const char* what)
+{
+    return fail(c, GWG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_CHECK(ctx, call, what)                          \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) { (void)hipGetDevice(&prev); if (prev != dev) (void)hipSetDevice(dev); }
+    ~DeviceGuard() { int cur = -1; (void)hipGetDevice(&cur); if (prev >= 0 && cur != prev) (void)hipSetDevice(prev); }
+};
+
+// ------------------------------------------------------------ validation
+int check_materials(gwg_ctx* c, const gwg_materials* m)
+{
+    if (!m) return fail(c, GWG_E_INVAL, "materials is NULL");
+    if (m->n_lambda < 1 || m->n_lambda > 4096) return fail(c, GWG_E_INVAL, "n_lambda %d out of range", m->n_lambda);
+    if (m->n_mat < 1 || m->n_mat > 255) return fail(c, GWG_E_INVAL, "n_mat %d out of range", m->n_mat);
+    if (!m->lambda_nm || !m->n_re || !m->n_im) return fail(c, GWG_E_INVAL, "material table pointer is NULL");
+    for (int i = 0; i < m->n_lambda; ++i)
+        if (!is_fin(m->lambda_nm[i]) || m->lambda_nm[i] <= 0.0) return fail(c, GWG_E_INVAL, "lambda_nm[%d] invalid", i);
+    for (int i = 0; i < m->n_lambda * m->n_mat; ++i) {
+        if (!is_fin(m->n_re[i]) || m->n_re[i] <= 0.0) return fail(c, GWG_E_INVAL, "n_re[%d] invalid", i);
+        if (!is_fin(m->n_im[i]) || m->n_im[i] < 0.0) return fail(c, GWG_E_INVAL, "n_im[%d] invalid", i);
+    }
+    return GWG_OK;
+}
+
+bool lossless(const gwg_materials* m, int mat)
+{
+    for (int l = 0; l < m->n_lambda; ++l)
+        if (m->n_im[l * m->n_mat + mat] != 0.0) return false;
+    return true;
+}
+
+int check_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_materials* mt,
+                const gwg_stacks* st, const gwg_rays* ry)
+{
+    int rc = check_materials(c, mt);
+    if (rc) return rc;
+    if (!sl || !pr || !st || !ry) return fail(c, GWG_E_INVAL, "NULL scene argument");
+    if (!(is_fin(sl->T_mm) && sl->T_mm > 0 && is_fin(sl->L_mm) && sl->L_mm > 0 && is_fin(sl->eye_relief_mm) &&
+          sl->eye_relief_mm >= 0))
+        return fail(c, GWG_E_INVAL, "slab dimensions invalid");
+    if (sl->mat_glass < 0 || sl->mat_glass >= mt->n_mat || sl->mat_air < 0 || sl->mat_air >= mt->n_mat)
+        return fail(c, GWG_E_INVAL, "slab material index out of range");
+    if (!lossless(mt, sl->mat_glass) || !lossless(mt, sl->mat_air))
+        return fail(c, GWG_E_INVAL, "slab glass and air must be lossless");
+    if (!(is_fin(sl->pupil_x0_mm) && is_fin(sl->pupil_w_mm) && sl->pupil_w_mm >= 0 && is_fin(sl->pupil_h_mm) &&
+          sl->pupil_h_mm >= 0))
+        return fail(c, GWG_E_INVAL, "pupil window invalid");
+    if (!(is_fin(sl->eye_x0_mm) && is_fin(sl->eye_y0_mm) && is_fin(sl->eye_w_mm) && sl->eye_w_mm > 0 &&
+          is_fin(sl->eye_h_mm) && sl->eye_h_mm > 0))
+        return fail(c, GWG_E_INVAL, "eyebox rectangle invalid");
+    if (sl->bins_x < 1 || sl->bins_x > 4096 || sl->bins_y < 1 || sl->bins_y > 4096)
+        return fail(c, GWG_E_INVAL, "bins %d x %d out of range", sl->bins_x, sl->bins_y);
+    if (pr->n_mirrors < 1 || pr->n_mirrors > kMaxMirrors) return fail(c, GWG_E_INVAL, "n_mirrors %d out of range", pr->n_mirrors);
+    if (!pr->omega) return fail(c, GWG_E_INVAL, "omega is NULL");
+    for (int m = 0; m < pr->n_mirrors; ++m)
+        if (!(is_fin(pr->omega[m]) && pr->omega[m] > 0.0 && pr->omega[m] < 1.0))
+            return fail(c, GWG_E_INVAL, "omega[%d] must be in (0, 1)", m);
+    if (!(is_fin(pr->tilt_deg) && pr->tilt_deg > 0.0 && pr->tilt_deg < 90.0)) return fail(c, GWG_E_INVAL, "tilt_deg invalid");
+    if (!(is_fin(pr->pitch_mm) && is_fin(pr->center_x_mm))) return fail(c, GWG_E_INVAL, "mirror placement invalid");
+    if (st->n_designs < 1 || st->n_mirrors != pr->n_mirrors) return fail(c, GWG_E_INVAL, "stacks shape mismatch");
+    if (st->max_layers < 1 || st->max_layers > kMaxLayers) return fail(c, GWG_E_INVAL, "max_layers %d out of range", st->max_layers);
+    if (!st->thk_nm || !st->mat || !st->n_layers) return fail(c, GWG_E_INVAL, "stack pointer is NULL");
+    int64_t DM = (int64_t)st->n_designs * st->n_mirrors;
+    for (int64_t k = 0; k < DM; ++k) {
+        int nl = st->n_layers[k];
+        if (nl < 0 || nl > st->max_layers) return fail(c, GWG_E_INVAL, "n_layers[%lld] = %d out of range", (long long)k, nl);
+        for (int j = 0; j < nl; ++j) {
+            int mm = st->mat[k * st->max_layers + j];
+            if (mm >= mt->n_mat) return fail(c, GWG_E_INVAL, "layer material %d out of range", mm);
+        }
+    }
+    if (ry->n_lambda_sel < 1 || !ry->lambda_sel) return fail(c, GWG_E_INVAL, "no wavelength selected");
+    for (int i = 0; i < ry->n_lambda_sel; ++i)
+        if (ry->lambda_sel[i] < 0 || ry->lambda_sel[i] >= mt->n_lambda) return fail(c, GWG_E_INVAL, "lambda_sel[%d] out of range", i);
+    if (ry->fov_mode != 0 && ry->fov_mode != 1) return fail(c, GWG_E_INVAL, "fov_mode must be 0 or 1");
+    if (!ry->fov_deg) return fail(c, GWG_E_INVAL, "fov_deg is NULL");
+    if (ry->fov_mode == 0) {
+        if (ry->n_fov < 1) return fail(c, GWG_E_INVAL, "n_fov must be >= 1");
+        for (int i = 0; i < 2 * ry->n_fov; ++i)
+            if (!(is_fin(ry->fov_deg[i]) && std::fabs(ry->fov_deg[i]) < 60.0)) return fail(c, GWG_E_INVAL, "fov_deg[%d] invalid", i);
+    } else {
+        if (ry->n_fov != 1) return fail(c, GWG_E_INVAL, "fov_mode 1 requires n_fov == 1");
+        for (int i = 0; i < 4; ++i)
+            if (!(is_fin(ry->fov_deg[i]) && std::fabs(ry->fov_deg[i]) < 60.0)) return fail(c, GWG_E_INVAL, "fov bound %d invalid", i);
+    }
+    if (ry->rays_per_point < 1 || ry->rays_per_point > (int64_t(1) << 40)) return fail(c, GWG_E_INVAL, "rays_per_point out of range");
+    if (ry->max_events < 1 || ry->max_events > kMaxEvents) return fail(c, GWG_E_INVAL, "max_events out of range");
+    return GWG_OK;
+}
+
+// Guided direction of field angles (thx, thy) in degrees (same operation
+// sequence as the device, so the grid table and per-ray directions agree).
+void field_direction_host(double thx, double thy, double ng, double nx, double nz, double* d)
+{
+    double tx = std::tan(thx * (3.14159265358979323846 / 180.0));
+    double ty = std::tan(thy * (3.14159265358979323846 / 180.0));
+    double inv = 1.0 / std::sqrt(tx * tx + ty * ty + 1.0);
+    double ax = tx * inv, ay = ty * inv;
+    double gx = ax / ng, gy = ay / ng, gz = std::sqrt(1.0 - (ax * ax + ay * ay) / (ng * ng));
+    double gn = nx * gx + nz * gz;
+    double t2 = 2.0 * gn;
+    d[0] = gx - t2 * nx;
+    d[1] = gy;
+    d[2] = gz - t2 * nz;
+}
+
+// Near-critical margin of the mixed-precision rule: 2 degrees around the
+// critical angle glass -> slot material, as a kappa interval.
+constexpr double kCritMarginDeg = 2.0;
+
+void crit_interval(double ng, double ns, double nsi, double* lo, double* hi)
+{
+    *lo = 0.0; *hi = 0.0;
+    if (nsi != 0.0 || ns >= ng) return;
+    double th = std::asin(ns / ng);
+    double m = kCritMarginDeg * (3.14159265358979323846 / 180.0);
+    double a = th - m, b = th + m;
+    if (b > 1.5707963267948966) b = 1.5707963267948966;
+    *lo = ng * std::sin(a);
+    *hi = ng * std::sin(b);
+}
+
+int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_materials* mt,
+                const gwg_stacks* st, const gwg_rays* ry, hipStream_t stream)
+{
+    // content hash of everything the tables depend on
+    uint64_t h = 1469598103934665603ull;
+    h = fnv_v(h, *sl);
+    h = fnv_v(h, pr->n_mirrors); h = fnv_v(h, pr->tilt_deg); h = fnv_v(h, pr->pitch_mm); h = fnv_v(h, pr->center_x_mm);
+    h = fnv(h, pr->omega, sizeof(double) * pr->n_mirrors);
+    h = fnv_v(h, mt->n_lambda); h = fnv_v(h, mt->n_mat);
+    h = fnv(h, mt->lambda_nm, sizeof(double) * mt->n_lambda);
+    h = fnv(h, mt->n_re, sizeof(double) * mt->n_lambda * mt->n_mat);
+    h = fnv(h, mt->n_im, sizeof(double) * mt->n_lambda * mt->n_mat);
+    h = fnv_v(h, st->n_designs); h = fnv_v(h, st->n_mirrors); h = fnv_v(h, st->max_layers);
+    int64_t DML = (int64_t)st->n_designs * st->n_mirrors * st->max_layers;
+    h = fnv(h, st->mat, (size_t)DML);
+    h = fnv(h, st->n_layers, sizeof(int32_t) * st->n_designs * st->n_mirrors);
+    h = fnv_v(h, ry->n_lambda_sel);
+    h = fnv(h, ry->lambda_sel, sizeof(int32_t) * ry->n_lambda_sel);
+    h = fnv_v(h, ry->fov_mode); h = fnv_v(h, ry->n_fov);
+    h = fnv(h, ry->fov_deg, sizeof(double) * (ry->fov_mode == 0 ? 2 * ry->n_fov : 4));
+    h = fnv_v(h, ry->rays_per_point); h = fnv_v(h, ry->max_events);
+    if (c->scene_valid && h == c->scene_hash) return GWG_OK;
+    c->scene_valid = false;
+
+    SceneDev& s = c->sc;
+    s = SceneDev{};
+    s.T = sl->T_mm; s.Lx = sl->L_mm; s.ER = sl->eye_relief_mm;
+    s.px0 = sl->pupil_x0_mm; s.pw = sl->pupil_w_mm; s.ph = sl->pupil_h_mm;
+    s.ex0 = sl->eye_x0_mm; s.ey0 = sl->eye_y0_mm; s.ew = sl->eye_w_mm; s.eh = sl->eye_h_mm;
+    s.bins_x = sl->bins_x; s.bins_y = sl->bins_y;
+    s.M = pr->n_mirrors;
+    double beta = pr->tilt_deg * (3.14159265358979323846 / 180.0);
+    s.nx = -std::sin(beta);
+    s.nz = std::cos(beta);
+    for (int m = 0; m < s.M; ++m) {
+        double xm = pr->center_x_mm + ((double)m - (double)(s.M - 1) * 0.5) * pr->pitch_mm;
+        s.h[m] = s.nx * xm + s.nz * (sl->T_mm * 0.5);
+        double t = std::floor(pr->omega[m] * 4294967296.0);
+        t = std::min(std::max(t, 0.0), 4294967295.0);
+        s.thr[m] = (uint32_t)t;
+        double p = (double)s.thr[m] / 4294967296.0;
+        if (!(p > 0.0 && p < 1.0)) return fail(c, GWG_E_INVAL, "omega[%d] rounds to 0 or 1", m);
+        s.sc_r[m] = 1.0 / std::sqrt(p);
+        s.sc_t[m] = 1.0 / std::sqrt(1.0 - p);
+    }
+    // compact material slots of the stacks
+    std::map<int, int> slot_of;
+    std::vector<int> mat_of_slot;
+    std::vector<uint8_t> slots((size_t)DML, 0);
+    int64_t DM = (int64_t)st->n_designs * st->n_mirrors;
+    for (int64_t k = 0; k < DM; ++k)
+        for (int j = 0; j < st->n_layers[k]; ++j) {
+            int mm = st->mat[k * st->max_layers + j];
+            auto it = slot_of.find(mm);
+            if (it == slot_of.end()) {
+                if ((int)mat_of_slot.size() == kMaxSlots)
+                    return fail(c, GWG_E_INVAL, "more than %d distinct layer materials", kMaxSlots);
+                it = slot_of.emplace(mm, (int)mat_of_slot.size()).first;
+                mat_of_slot.push_back(mm);
+            }
+            slots[(size_t)(k * st->max_layers + j)] = (uint8_t)it->second;
+        }
+    if (mat_of_slot.empty()) mat_of_slot.push_back(sl->mat_glass);
+    s.n_slots = (int)mat_of_slot.size();
+    s.slot_complex = 0;
+    for (int q = 0; q < s.n_slots; ++q)
+        if (!lossless(mt, mat_of_slot[q])) s.slot_complex |= 1u << q;
+    s.D = st->n_designs;
+    s.Lmax = st->max_layers;
+    // wavelength table
+    s.n_lsel = ry->n_lambda_sel;
+    std::vector<double> lt((size_t)s.n_lsel * LT_STRIDE, 0.0);
+    for (int i = 0; i < s.n_lsel; ++i) {
+        int l = ry->lambda_sel[i];
+        double* row = &lt[(size_t)i * LT_STRIDE];
+        row[LT_K0] = 2.0 * 3.14159265358979323846 / mt->lambda_nm[l];
+        row[LT_NG] = mt->n_re[l * mt->n_mat + sl->mat_glass];
+        row[LT_NA] = mt->n_re[l * mt->n_mat + sl->mat_air];
+        for (int q = 0; q < s.n_slots; ++q) {
+            double nr = mt->n_re[l * mt->n_mat + mat_of_slot[q]], ni = mt->n_im[l * mt->n_mat + mat_of_slot[q]];
+            row[LT_SLOT + 2 * q] = nr;
+            row[LT_SLOT + 2 * q + 1] = ni;
+            crit_interval(row[LT_NG], nr, ni, &row[LT_CRIT + 2 * q], &row[LT_CRIT + 2 * q + 1]);
+        }
+        row[LT_NSLOT] = s.n_slots;
+    }
+    s.fov_mode = ry->fov_mode;
+    s.F = ry->fov_mode == 0 ? ry->n_fov : 1;
+    std::vector<double> dirs;
+    if (s.fov_mode == 0) {
+        dirs.assign((size_t)s.n_lsel * s.F * 4, 0.0);
+        for (int i = 0; i < s.n_lsel; ++i)
+            for (int f = 0; f < s.F; ++f)
+                field_direction_host(ry->fov_deg[2 * f], ry->fov_deg[2 * f + 1], lt[(size_t)i * LT_STRIDE + LT_NG],
+                                     s.nx, s.nz, &dirs[((size_t)i * s.F + f) * 4]);
+    } else {
+        s.fov_x0 = ry->fov_deg[0]; s.fov_x1 = ry->fov_deg[1];
+        s.fov_y0 = ry->fov_deg[2]; s.fov_y1 = ry->fov_deg[3];
+        dirs.assign(4, 0.0);
+    }
+    s.N = ry->rays_per_point;
+    s.Kmax = ry->max_events;
+    HIP_CHECK(c, c->lam_tab.ensure(lt.size() * sizeof(double)), "alloc lam_tab");
+    HIP_CHECK(c, c->dir_tab.ensure(dirs.size() * sizeof(double)), "alloc dir_tab");
+    HIP_CHECK(c, c->slot.ensure(slots.size()), "alloc slot");
+    HIP_CHECK(c, c->nlay.ensure(sizeof(int32_t) * DM), "alloc nlay");
+    HIP_CHECK(c, hipMemcpyAsync(c->lam_tab.p, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload lam_tab");
+    HIP_CHECK(c, hipMemcpyAsync(c->dir_tab.p, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload dir_tab");
+    HIP_CHECK(c, hipMemcpyAsync(c->slot.p, slots.data(), slots.size(), hipMemcpyHostToDevice, stream), "upload slots");
+    HIP_CHECK(c, hipMemcpyAsync(c->nlay.p, st->n_layers, sizeof(int32_t) * DM, hipMemcpyHostToDevice, stream), "upload n_layers");
+    HIP_CHECK(c, hipStreamSynchronize(stream), "scene upload");
+    s.lam_tab = (const double*)c->lam_tab.p;
+    s.dir_tab = (const double*)c->dir_tab.p;
+    s.slot = (const uint8_t*)c->slot.p;
+    s.nlay = (const int32_t*)c->nlay.p;
+    c->h_nlay.assign(st->n_layers, st->n_layers + DM);
+    c->scene_hash = h;
+    c->scene_valid = true;
+    return GWG_OK;
+}
+
+int pick_fwd_wg(gwg_ctx* c, const SceneDev& s, bool lds_bins)
+{
+    if (c->tune.block_threads) return c->tune.block_threads;
+    for (int wg : { 256, 128, 64 })
+        if (fwd_smem_bytes(s, wg, lds_bins) <= 65536) return wg;
+    return 64;
+}
+
+int pick_bwd_wg(gwg_ctx* c, const SceneDev& s)
+{
+    if (c->tune.bwd_block_threads) return c->tune.bwd_block_threads;
+    for (int wg : { 128, 64 })
+        if (bwd_smem_bytes(s, wg) <= 65536) return wg;
+    return 64;
+}
+
+void set_tiles(SceneDev& s, int64_t rays_per_tile, int wg, int n_cu)
+{
+    int64_t total = (int64_t)s.D * s.n_lsel * s.F * s.N;
+    int64_t rpt = rays_per_tile;
+    if (rpt <= 0) {
+        // aim for at least 8 workgroups per CU while keeping >= 4 rays per lane
+        int64_t target_items = (int64_t)std::max(n_cu, 1) * 8;
+        rpt = (total + target_items - 1) / target_items;
+        rpt = std::max<int64_t>(rpt, (int64_t)wg * 4);
+        rpt = ((rpt + wg - 1) / wg) * wg;
+    }
+    if (rpt > s.N) rpt = s.N;
+    s.rays_per_tile = rpt;
+    s.tiles_per_point = (s.N + rpt - 1) / rpt;
+    s.n_items = (int64_t)s.D * s.n_lsel * s.F * s.tiles_per_point;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+int32_t gwg_abi_version(void) { return GWG_ABI_VERSION; }
+
+int gwg_create(gwg_ctx** out, int32_t device)
+{
+    if (!out) return fail(nullptr, GWG_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(nullptr, GWG_E_NODEVICE, "no HIP device");
+    if (device < 0 || device >= n) return fail(nullptr, GWG_E_NODEVICE, "device %d does not exist", device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(nullptr, GWG_E_NODEVICE, "device query failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, GWG_E_NODEVICE, "device %d is %s, not gfx950", device, prop.gcnArchName);
+    gwg_ctx* c = new gwg_ctx();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return GWG_OK;
+}
+
+int gwg_destroy(gwg_ctx* c)
+{
+    if (!c) return GWG_E_INVAL;
+    {
+        DeviceGuard g(c->device);
+        (void)hipDeviceSynchronize();
+        for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch,
+                           &c->loss_work, &c->tmm_tab, &c->tmm_slot })
+            b->release();
+    }
+    delete c;
+    return GWG_OK;
+}
+
+const char* gwg_last_error(const gwg_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int gwg_set_tuning(gwg_ctx* c, const gwg_tuning* t)
+{
+    if (!c || !t) return GWG_E_INVAL;
+    for (int wg : { t->block_threads, t->bwd_block_threads })
+        if (wg != 0 && wg != 64 && wg != 128 && wg != 256) return fail(c, GWG_E_INVAL, "block size must be 64, 128 or 256");
+    if (t->bwd_block_threads > 128) return fail(c, GWG_E_INVAL, "adjoint block size must be 64 or 128");
+    if (t->rays_per_block < 0 || t->bwd_rays_per_block < 0) return fail(c, GWG_E_INVAL, "negative tile");
+    c->tune = *t;
+    return GWG_OK;
+}
+
+int gwg_get_tuning(const gwg_ctx* c, gwg_tuning* t)
+{
+    if (!c || !t) return GWG_E_INVAL;
+    *t = c->tune;
+    return GWG_OK;
+}
+
+int gwg_tmm_rt(gwg_ctx* c, const gwg_stack* stack, const gwg_materials* mats, int64_t n_q,
+               const int32_t* d_lambda_idx, const double* d_theta, int32_t precision, double* d_out,
+               void* stream)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    int rc = check_materials(c, mats);
+    if (rc) return rc;
+    if (!stack) return fail(c, GWG_E_INVAL, "stack is NULL");
+    if (stack->n_layers < 0 || stack->n_layers > 4096) return fail(c, GWG_E_INVAL, "n_layers out of range");
+    if (stack->n_layers > 0 && (!stack->thk_nm || !stack->mat)) return fail(c, GWG_E_INVAL, "stack pointer is NULL");
+    if (stack->mat_in < 0 || stack->mat_in >= mats->n_mat || stack->mat_out < 0 || stack->mat_out >= mats->n_mat)
+        return fail(c, GWG_E_INVAL, "medium index out of range");
+    if (!lossless(mats, stack->mat_in)) return fail(c, GWG_E_INVAL, "incident medium must be lossless");
+    if (n_q < 0) return fail(c, GWG_E_INVAL, "n_q < 0");
+    if (precision < GWG_FP64 || precision > GWG_FP32) return fail(c, GWG_E_INVAL, "precision out of range");
+    if (n_q > 0 && (!d_lambda_idx || !d_theta || !d_out)) return fail(c, GWG_E_INVAL, "query pointer is NULL");
+    if (n_q == 0) return GWG_OK;
+    std::map<int, int> slot_of;
+    std::vector<int> mats_of;
+    std::vector<uint8_t> sl((size_t)std::max(stack->n_layers, 1), 0);
+    for (int j = 0; j < stack->n_layers; ++j) {
+        int mm = stack->mat[j];
+        if (mm >= mats->n_mat) return fail(c, GWG_E_INVAL, "layer material %d out of range", mm);
+        auto it = slot_of.find(mm);
+        if (it == slot_of.end()) {
+            if ((int)mats_of.size() == kMaxSlots) return fail(c, GWG_E_INVAL, "more than %d distinct layer materials", kMaxSlots);
+            it = slot_of.emplace(mm, (int)mats_of.size()).first;
+            mats_of.push_back(mm);
+        }
+        sl[j] = (uint8_t)it->second;
+    }
+    int n_slots = std::max<int>(1, (int)mats_of.size());
+    if (mats_of.empty()) mats_of.push_back(stack->mat_in);
+    uint32_t cplx = 0;
+    std::vector<double> lt((size_t)mats->n_lambda * LT_STRIDE, 0.0);
+    for (int l = 0; l < mats->n_lambda; ++l) {
+        double* row = &lt[(size_t)l * LT_STRIDE];
+        row[LT_K0] = 2.0 * 3.14159265358979323846 / mats->lambda_nm[l];
+        row[LT_NG] = mats->n_re[l * mats->n_mat + stack->mat_in];
+        row[LT_NA] = mats->n_re[l * mats->n_mat + stack->mat_out];
+        row[LT_NA + 1] = mats->n_im[l * mats->n_mat + stack->mat_out];
+        for (int q = 0; q < n_slots; ++q) {
+            double nr = mats->n_re[l * mats->n_mat + mats_of[q]], ni = mats->n_im[l * mats->n_mat + mats_of[q]];
+            row[LT_SLOT + 2 * q] = nr;
+            row[LT_SLOT + 2 * q + 1] = ni;
+            if (ni != 0.0) cplx |= 1u << q;
+            crit_interval(row[LT_NG], nr, ni, &row[LT_CRIT + 2 * q], &row[LT_CRIT + 2 * q + 1]);
+        }
+    }
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_CHECK(c, c->tmm_tab.ensure(lt.size() * sizeof(double)), "alloc table");
+    HIP_CHECK(c, c->tmm_slot.ensure(sl.size()), "alloc slots");
+    HIP_CHECK(c, hipMemcpyAsync(c->tmm_tab.p, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice, s), "upload table");
+    HIP_CHECK(c, hipMemcpyAsync(c->tmm_slot.p, sl.data(), sl.size(), hipMemcpyHostToDevice, s), "upload slots");
+    HIP_CHECK(c, hipStreamSynchronize(s), "upload");
+    if (tmm_smem_bytes(stack->n_layers, n_slots, 256) > 65536) return fail(c, GWG_E_INVAL, "stack too large for one workgroup");
+    HIP_CHECK(c, launch_tmm_rt(precision, stack->thk_nm, (const uint8_t*)c->tmm_slot.p, stack->n_layers,
+                               (const double*)c->tmm_tab.p, mats->n_lambda, n_slots, cplx, d_lambda_idx, d_theta,
+                               n_q, d_out, s),
+              "tmm kernel");
+    return GWG_OK;
+}
+
+int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const gwg_materials* mats,
+                      const gwg_stacks* stacks, const gwg_rays* rays, uint64_t seed, uint64_t step,
+                      int32_t precision, const gwg_eyebox* out, gwg_ray_record* records, int64_t record_stride,
+                      gwg_stats* stats, void* stream)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    int rc = check_scene(c, slab, prma, mats, stacks, rays);
+    if (rc) return rc;
+    if (precision < GWG_FP64 || precision > GWG_FP32) return fail(c, GWG_E_INVAL, "precision out of range");
+    if (step >= (uint64_t(1) << 32)) return fail(c, GWG_E_INVAL, "step must be < 2^32");
+    if (!out || !out->q_bins || !out->counts) return fail(c, GWG_E_INVAL, "eyebox outputs are NULL");
+    if (out->fp_shift < 0 || out->fp_shift > 40) return fail(c, GWG_E_INVAL, "fp_shift out of range");
+    if (records && record_stride < 1) return fail(c, GWG_E_INVAL, "record_stride must be >= 1");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    rc = build_scene(c, slab, prma, mats, stacks, rays, s);
+    if (rc) return rc;
+    SceneDev sc = c->sc;
+    sc.thk = stacks->thk_nm;
+    sc.fp_shift = out->fp_shift;
+    sc.key0 = (uint32_t)seed;
+    sc.key1 = (uint32_t)(seed >> 32) ^ (uint32_t)step;
+    sc.precision = precision;
+    const int B = sc.bins_x * sc.bins_y;
+    const bool lds_bins = B <= 2048;
+    const int wg = pick_fwd_wg(c, sc, lds_bins);
+    set_tiles(sc, c->tune.rays_per_block, wg, c->n_cu);
+    if (fwd_smem_bytes(sc, wg, lds_bins) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
+    if (sc.n_items > 0x7fffffff) return fail(c, GWG_E_INVAL, "too many work items; raise rays_per_block");
+    const int64_t nbins = (int64_t)sc.D * sc.n_lsel * sc.F * B;
+    HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
+    HIP_CHECK(c, launch_fill_u64(out->q_bins, nbins, 0, s), "zero bins");
+    HIP_CHECK(c, launch_fill_u32(out->counts, nbins, 0, s), "zero counts");
+    HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
+    HIP_CHECK(c, launch_trace_fwd(sc, wg, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
+                                  records, record_stride, s),
+              "forward kernel");
+    if (out->irradiance)
+        HIP_CHECK(c, launch_irradiance(out->q_bins, nbins, std::ldexp(1.0, -out->fp_shift) / (double)sc.N, out->irradiance, s),
+                  "irradiance kernel");
+    c->fwd = sc;
+    c->have_forward = true;
+    if (stats) {
+        uint64_t w[ST_WORDS];
+        HIP_CHECK(c, hipMemcpyAsync(w, c->stats.p, sizeof(w), hipMemcpyDeviceToHost, s), "read stats");
+        HIP_CHECK(c, hipStreamSynchronize(s), "forward");
+        stats->rays = (int64_t)w[ST_RAYS];
+        stats->interactions = (int64_t)w[ST_EVENTS];
+        stats->prma_hits = (int64_t)w[ST_PRMA];
+        stats->fp64_hits = (int64_t)w[ST_FP64];
+        stats->saturated = (int64_t)w[ST_SAT];
+        for (int k = 0; k < GWG_NCAT; ++k) {
+            stats->n_cat[k] = (int64_t)w[ST_CAT + k];
+            stats->power[k] = (double)w[ST_POW + k] / 16777216.0;
+        }
+        if (stats->saturated) return fail(c, GWG_E_OVERFLOW, "%lld bin contributions saturated", (long long)stats->saturated);
+    }
+    return GWG_OK;
+}
+
+int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_t sample_stride, void* stream)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    if (!c->have_forward) return fail(c, GWG_E_STATE, "gwg_trace_backward called before gwg_trace_forward");
+    if (!d_dL_dI || !d_grad) return fail(c, GWG_E_INVAL, "NULL gradient pointer");
+    if (sample_stride < 1) return fail(c, GWG_E_INVAL, "sample_stride must be >= 1");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    SceneDev sc = c->fwd;
+    const int wg = pick_bwd_wg(c, sc);
+    set_tiles(sc, c->tune.bwd_rays_per_block, wg, c->n_cu);
+    if (bwd_smem_bytes(sc, wg) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
+    // persistent grid: two workgroups per CU (the kernel is register-bound)
+    int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * 2);
+    const int ML = sc.M * sc.Lmax;
+    const int64_t n_chk = sc.Lmax / kSeg + 1;
+    const int64_t lane_doubles = (int64_t)sc.Kmax * kTapeStride + n_chk * 8;
+    HIP_CHECK(c, c->scratch.ensure(sizeof(double) * lane_doubles * grid * wg), "alloc adjoint scratch");
+    HIP_CHECK(c, c->partial.ensure(sizeof(double) * (size_t)sc.n_items * ML), "alloc partial gradients");
+    HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (double*)c->partial.p, (double*)c->scratch.p,
+                                  sample_stride, s),
+              "adjoint kernel");
+    HIP_CHECK(c, launch_grad_reduce((const double*)c->partial.p, sc.n_items / sc.D, ML, sc.D, d_grad, sc.nlay, sc.M,
+                                    sc.Lmax, s),
+              "gradient reduction");
+    return GWG_OK;
+}
+
+int gwg_loss(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, int32_t F, int32_t B, int32_t kind,
+             double w_f, double w_e, double* d_loss, double* d_dL_dI, void* stream)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    if (!d_irr || !d_loss) return fail(c, GWG_E_INVAL, "NULL loss pointer");
+    if (D < 1 || n_l < 1 || F < 1 || B < 1) return fail(c, GWG_E_INVAL, "loss shape invalid");
+    if ((int64_t)D * n_l * F > 0x7fffffff) return fail(c, GWG_E_INVAL, "loss shape too large");
+    if (kind != 0 && kind != 1) return fail(c, GWG_E_INVAL, "kind must be 0 or 1");
+    if (!(is_fin(w_f) && is_fin(w_e))) return fail(c, GWG_E_INVAL, "weights must be finite");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    size_t n = (size_t)D * n_l * F + (size_t)D * B + (size_t)D * F + (size_t)D * 8;
+    HIP_CHECK(c, c->loss_work.ensure(n * sizeof(double)), "alloc loss work");
+    HIP_CHECK(c, launch_loss(d_irr, D, n_l, F, B, kind, w_f, w_e, (double*)c->loss_work.p, d_loss, d_dL_dI, s),
+              "loss kernels");
+    return GWG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,347 @@
+// Device building blocks for gfx950: complex arithmetic, Philox4x32-10,
+// sine/cosine, and the per-hit characteristic-matrix thin-film solve with its
+// adjoint.  Included by the kernel translation unit only.
+//
+// Thin-film solve (Methods, "Multilayer thin-film solver"): for a stack of
+// layers j = 0..L-1 in incidence order between an incident medium 0 and an
+// exit medium, with invariant kappa = n_0 sin(theta_0) and
+// z_j = N_j^2 - kappa^2, each layer is the 2x2 characteristic matrix
+//     M_j = [[cos d_j, -i sin d_j / eta_j], [-i eta_j sin d_j, cos d_j]],
+//     d_j = k0 q_j t_j,  q_j = sqrt(z_j) (Im >= 0),
+//     eta_j = q_j (s) or N_j^2 / q_j (p)       [exp(-i w t) convention],
+// and [B; C] = M_0 M_1 ... M_{L-1} [1; eta_exit].  The Eq. 3-convention
+// coefficients are r_s = (eta_0 B - C)/(eta_0 B + C), t_s = 2 eta_0/(eta_0 B + C),
+// r_p = -(same with p admittances), t_p = (2 eta_0/(...)) cos(theta_0)/cos(theta_exit).
+//
+// For a lossless layer the matrix entries are real multiples of 1 and -i
+// whether the layer is propagating (z > 0: circular functions) or evanescent
+// (z < 0: hyperbolic functions), so the chain runs on real coefficients
+// [[C, -i X], [-i Y, C]] with per-polarization real X, Y.  Absorbing layers
+// take a general complex path.
+//
+// Derivative (adjoint): dM_j/dt_j = M_j D_j with the constant generator
+//     D_s = -i k0 [[0, 1], [z_j, 0]],   D_p = -i k0 [[0, z_j/N_j^2], [N_j^2, 0]],
+// so for a coefficient c with cotangent row rho = dc/d[B; C],
+//     dc/dt_j = u_{j-1}^T D_j w_j,  u_{j-1}^T = rho^T M_0..M_{j-1},  w_j = M_j..M_{L-1}[1; eta_exit].
+// The covector u runs from the incident side, the vector w from the exit
+// side; w is recomputed segment by segment from checkpoints stored during a
+// first exit-to-incident sweep, which keeps both recurrences in their
+// numerically stable direction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gwg {
+
+// ---------------------------------------------------------------- complex
+struct cd { double re, im; };
+__device__ __host__ inline cd mk(double r, double i) { cd z; z.re = r; z.im = i; return z; }
+__device__ inline cd cadd(cd a, cd b) { return mk(a.re + b.re, a.im + b.im); }
+__device__ inline cd csub(cd a, cd b) { return mk(a.re - b.re, a.im - b.im); }
+__device__ inline cd cmul(cd a, cd b) { return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+__device__ inline cd cscale(cd a, double s) { return mk(a.re * s, a.im * s); }
+__device__ inline cd cconj(cd a) { return mk(a.re, -a.im); }
+__device__ inline cd cdiv(cd a, cd b)
+{
+    // Smith's algorithm
+    if (fabs(b.re) >= fabs(b.im)) {
+        double r = b.im / b.re, den = b.re + b.im * r;
+        return mk((a.re + a.im * r) / den, (a.im - a.re * r) / den);
+    }
+    double r = b.re / b.im, den = b.im + b.re * r;
+    return mk((a.re * r + a.im) / den, (a.im * r - a.re) / den);
+}
+__device__ inline cd csqrt_up(cd z)
+{
+    // principal root rotated to Im >= 0 (and Re >= 0 on the real axis)
+    double m = sqrt(z.re * z.re + z.im * z.im);
+    double a = sqrt(0.5 * (m + fabs(z.re)));
+    cd r;
+    if (a == 0.0) return mk(0.0, 0.0);
+    if (z.re >= 0.0) r = mk(a, 0.5 * z.im / a);
+    else r = mk(0.5 * fabs(z.im) / a, z.im >= 0.0 ? a : -a);
+    if (r.im < 0.0 || (r.im == 0.0 && r.re < 0.0)) r = mk(-r.re, -r.im);
+    return r;
+}
+
+// ------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, SC'11: ten rounds of the 4x32 Philox S-box,
+// multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments 0x9E3779B9 / 0xBB67AE85.
+struct u32x4 { uint32_t x, y, z, w; };
+__device__ inline u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                 uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    u32x4 r; r.x = c0; r.y = c1; r.z = c2; r.w = c3;
+    return r;
+}
+__device__ inline double u24(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+
+// ------------------------------------------------------------ sin / cos
+// Phases here are finite and moderate (|x| < 1e4).  Reduction by multiples
+// of pi/2 with a two-term Cody-Waite split (each product subtracted with one
+// FMA), then Taylor polynomials of sin and cos on [-pi/4, pi/4]: truncation
+// below 1e-16 (f64, degree 15/16) or 2e-9 (f32, degree 9/8).
+constexpr double inv_fact(int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= (double)i; return 1.0 / f; }
+
+__device__ inline void sincos_cw(double x, double* s, double* c)
+{
+#pragma clang fp contract(fast)
+    const double two_over_pi = 0.63661977236758134308;
+    const double pio2_hi = 1.5707963267948966;          // nearest double to pi/2
+    const double pio2_lo = 6.123233995736766e-17;       // pi/2 - pio2_hi
+    double n = rint(x * two_over_pi);
+    double r = fma(-n, pio2_hi, x);
+    r = fma(-n, pio2_lo, r);
+    double r2 = r * r;
+    double ps = inv_fact(15);
+    ps = fma(ps, -r2, inv_fact(13));
+    ps = fma(ps, -r2, inv_fact(11));
+    ps = fma(ps, -r2, inv_fact(9));
+    ps = fma(ps, -r2, inv_fact(7));
+    ps = fma(ps, -r2, inv_fact(5));
+    ps = fma(ps, -r2, inv_fact(3));
+    double sn = fma(-r * r2, ps, r);                    // r - r^3/3! + ...
+    double pc = inv_fact(16);
+    pc = fma(pc, -r2, inv_fact(14));
+    pc = fma(pc, -r2, inv_fact(12));
+    pc = fma(pc, -r2, inv_fact(10));
+    pc = fma(pc, -r2, inv_fact(8));
+    pc = fma(pc, -r2, inv_fact(6));
+    pc = fma(pc, -r2, inv_fact(4));
+    pc = fma(pc, -r2, inv_fact(2));
+    double cs = fma(-r2, pc, 1.0);                      // 1 - r^2/2! + ...
+    int q = (int)n & 3;
+    double so = (q & 1) ? cs : sn;
+    double co = (q & 1) ? sn : cs;
+    *s = (q & 2) ? -so : so;
+    *c = ((q + 1) & 2) ? -co : co;
+}
+
+__device__ inline void sincos_cw(float x, float* s, float* c)
+{
+#pragma clang fp contract(fast)
+    const float two_over_pi = 0.636619772f;
+    const float pio2_hi = 1.57079637f;                  // nearest float to pi/2
+    const float pio2_lo = -4.37113883e-8f;              // pi/2 - pio2_hi
+    float n = rintf(x * two_over_pi);
+    float r = fmaf(-n, pio2_hi, x);
+    r = fmaf(-n, pio2_lo, r);
+    float r2 = r * r;
+    float ps = (float)inv_fact(9);
+    ps = fmaf(ps, -r2, (float)inv_fact(7));
+    ps = fmaf(ps, -r2, (float)inv_fact(5));
+    ps = fmaf(ps, -r2, (float)inv_fact(3));
+    float sn = fmaf(-r * r2, ps, r);
+    float pc = (float)inv_fact(10);
+    pc = fmaf(pc, -r2, (float)inv_fact(8));
+    pc = fmaf(pc, -r2, (float)inv_fact(6));
+    pc = fmaf(pc, -r2, (float)inv_fact(4));
+    pc = fmaf(pc, -r2, (float)inv_fact(2));
+    float cs = fmaf(-r2, pc, 1.0f);
+    int q = (int)n & 3;
+    float so = (q & 1) ? cs : sn;
+    float co = (q & 1) ? sn : cs;
+    *s = (q & 2) ? -so : so;
+    *c = ((q + 1) & 2) ? -co : co;
+}
+
+// cosh and sinh of x >= 0 from expm1 (no cancellation for small x)
+__device__ inline void coshsinh(double x, double* ch, double* sh)
+{
+    double em = expm1(x);
+    double ep = em + 1.0;
+    *sh = 0.5 * em * (em + 2.0) / ep;
+    *ch = 1.0 + 0.5 * em * em / ep;
+}
+__device__ inline void coshsinh(float x, float* ch, float* sh)
+{
+    float em = expm1f(x);
+    float ep = em + 1.0f;
+    *sh = 0.5f * em * (em + 2.0f) / ep;
+    *ch = 1.0f + 0.5f * em * em / ep;
+}
+
+// ------------------------------------------------------ per-hit slot params
+// Per lane and per material slot, NPF values:
+//   lossless:  P0 kq (signed: >= 0 circular with d = kq t; < 0 hyperbolic with
+//              d = -kq t), P1 xs, P2 ys, P3 xp, P4 yp  (X = S x, Y = S y for s / p)
+//   absorbing: P0, P1 = q (re, im); P2, P3 = N^2 (re, im); P4 unused.
+// The table of a lane stores element (s, p) at sp[(s * NPF + p) * ls].
+constexpr int NPF = 5;
+constexpr double kTinyZ = 1e-24;   // |z| floor: keeps q != 0 exactly at the critical angle
+
+__device__ inline void slot_params(double nre, double nim, double kappa, double k0, double* P)
+{
+    if (nim == 0.0) {
+        double n2 = nre * nre;
+        double z = n2 - kappa * kappa;
+        if (fabs(z) < kTinyZ) z = kTinyZ;
+        if (z > 0.0) {
+            double q = sqrt(z);
+            P[0] = k0 * q; P[1] = 1.0 / q; P[2] = q;
+            P[3] = q / n2; P[4] = n2 / q;
+        } else {
+            double Q = sqrt(-z);
+            P[0] = -k0 * Q; P[1] = 1.0 / Q; P[2] = -Q;
+            P[3] = -Q / n2; P[4] = n2 / Q;
+        }
+    } else {
+        cd N = mk(nre, nim);
+        cd N2 = cmul(N, N);
+        cd z = csub(N2, mk(kappa * kappa, 0.0));
+        cd q = csqrt_up(z);
+        P[0] = q.re; P[1] = q.im; P[2] = N2.re; P[3] = N2.im; P[4] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------ chain steps
+template <typename T> struct V2 { T br, bi, cr, ci; };   // [B; C] of one polarization
+template <typename T> struct CTv { T re, im; };
+
+// [B; C] <- [[C, -i X], [-i Y, C]] [B; C] with real C, X, Y
+template <typename T>
+__device__ inline void step_real(V2<T>& v, T C, T X, T Y)
+{
+#pragma clang fp contract(fast)
+    T br = C * v.br + X * v.ci;
+    T bi = C * v.bi - X * v.cr;
+    T cr = Y * v.bi + C * v.cr;
+    T ci = C * v.ci - Y * v.br;
+    v.br = br; v.bi = bi; v.cr = cr; v.ci = ci;
+}
+
+template <typename T>
+__device__ inline CTv<T> tmul(CTv<T> a, CTv<T> b)
+{
+#pragma clang fp contract(fast)
+    CTv<T> r; r.re = a.re * b.re - a.im * b.im; r.im = a.re * b.im + a.im * b.re; return r;
+}
+template <typename T>
+__device__ inline CTv<T> tdiv(CTv<T> a, CTv<T> b)
+{
+    T den = b.re * b.re + b.im * b.im;
+    CTv<T> r; r.re = (a.re * b.re + a.im * b.im) / den; r.im = (a.im * b.re - a.re * b.im) / den; return r;
+}
+
+// general complex step: [B; C] <- [[C, -iX], [-iY, C]] [B; C]
+template <typename T>
+__device__ inline void step_cplx(V2<T>& v, CTv<T> C, CTv<T> X, CTv<T> Y)
+{
+    CTv<T> B = { v.br, v.bi }, Cv = { v.cr, v.ci };
+    CTv<T> mX = { X.im, -X.re }, mY = { Y.im, -Y.re };   // -i X, -i Y
+    CTv<T> b1 = tmul(C, B), b2 = tmul(mX, Cv), c1 = tmul(mY, B), c2 = tmul(C, Cv);
+    v.br = b1.re + b2.re; v.bi = b1.im + b2.im;
+    v.cr = c1.re + c2.re; v.ci = c1.im + c2.im;
+}
+
+// Trig part of a lossless layer: circular or hyperbolic by the sign of kq.
+template <typename T>
+__device__ inline void layer_cs(T kq, T t, T* C, T* S)
+{
+    if (kq >= (T)0) {
+        sincos_cw(kq * t, S, C);
+    } else {
+        coshsinh(-kq * t, C, S);
+    }
+}
+
+// Entries of an absorbing layer: returns C, X_s, Y_s, X_p, Y_p.
+template <typename T>
+__device__ inline void layer_cplx(const T* P, T k0, T t, CTv<T>* C, CTv<T>* Xs, CTv<T>* Ys,
+                                  CTv<T>* Xp, CTv<T>* Yp)
+{
+    CTv<T> q = { P[0], P[1] }, N2 = { P[2], P[3] };
+    T a = k0 * q.re * t, b = k0 * q.im * t;
+    T sa, ca, ch, sh;
+    sincos_cw(a, &sa, &ca);
+    coshsinh(b, &ch, &sh);
+    CTv<T> cosd = { ca * ch, -sa * sh }, sind = { sa * ch, ca * sh };
+    *C = cosd;
+    *Xs = tdiv(sind, q);
+    *Ys = tmul(q, sind);
+    *Xp = tdiv(tmul(sind, q), N2);
+    *Yp = tdiv(tmul(N2, sind), q);
+}
+
+// Renormalize a single-precision chain vector (exact power-of-two scaling).
+template <typename T>
+__device__ inline void renorm(V2<T>& v, int& e)
+{
+    T m = fmax(fmax(fabs(v.br), fabs(v.bi)), fmax(fabs(v.cr), fabs(v.ci)));
+    if (m > (T)1e18) {
+        int ex;
+        frexp(m, &ex);
+        v.br = ldexp(v.br, -ex); v.bi = ldexp(v.bi, -ex);
+        v.cr = ldexp(v.cr, -ex); v.ci = ldexp(v.ci, -ex);
+        e += ex;
+    }
+}
+
+// Coefficients (Eq. 3 convention) from the chain result.
+struct Coef4 { cd rs, rp, ts, tp; };
+
+template <typename T>
+__device__ inline Coef4 finish_coeffs(const V2<T>& vs, const V2<T>& vp, int es, int ep,
+                                      double eta0s, double eta0p, cd tp_factor)
+{
+    cd Bs = mk((double)vs.br, (double)vs.bi), Cs = mk((double)vs.cr, (double)vs.ci);
+    cd Bp = mk((double)vp.br, (double)vp.bi), Cp = mk((double)vp.cr, (double)vp.ci);
+    cd dens = cadd(cscale(Bs, eta0s), Cs), denp = cadd(cscale(Bp, eta0p), Cp);
+    Coef4 o;
+    o.rs = cdiv(csub(cscale(Bs, eta0s), Cs), dens);
+    cd rpm = cdiv(csub(cscale(Bp, eta0p), Cp), denp);
+    o.rp = mk(-rpm.re, -rpm.im);
+    o.ts = cscale(cdiv(mk(2.0 * eta0s, 0.0), dens), ldexp(1.0, -es));
+    o.tp = cscale(cmul(cdiv(mk(2.0 * eta0p, 0.0), denp), tp_factor), ldexp(1.0, -ep));
+    return o;
+}
+
+// Forward solve of one hit.  thk/slot: this mirror's layers in stack order
+// (LDS); `front` selects incidence order 0..L-1 (else reversed).  sp: this
+// lane's slot table, element (s, p) at sp[(s * NPF + p) * ls].  Exit medium
+// admittances (es, ep) are complex in general.
+// The stack thicknesses and slot parameters are read in double precision
+// and rounded to the chain precision T once per layer.
+template <typename T>
+__device__ inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t* __restrict__ slot, int L,
+                                  bool front, const double* __restrict__ sp, int ls, uint32_t cplx_mask,
+                                  double k0d, double eta0s, double eta0p, cd etaEs, cd etaEp,
+                                  cd tp_factor)
+{
+    const T k0 = (T)k0d;
+    V2<T> vs = { (T)1, (T)0, (T)etaEs.re, (T)etaEs.im };
+    V2<T> vp = { (T)1, (T)0, (T)etaEp.re, (T)etaEp.im };
+    int es = 0, ep = 0;
+    for (int j = 0; j < L; ++j) {
+        int idx = front ? (L - 1 - j) : j;
+        T t = (T)thk[idx];
+        if (t == (T)0) continue;            // identity matrix
+        int s = slot[idx];
+        const double* P = sp + s * NPF * ls;
+        if (!((cplx_mask >> s) & 1u)) {
+            T C, S;
+            layer_cs((T)P[0], t, &C, &S);
+            step_real(vs, C, S * (T)P[ls], S * (T)P[2 * ls]);
+            step_real(vp, C, S * (T)P[3 * ls], S * (T)P[4 * ls]);
+        } else {
+            T Pl[4] = { (T)P[0], (T)P[ls], (T)P[2 * ls], (T)P[3 * ls] };
+            CTv<T> C, Xs, Ys, Xp, Yp;
+            layer_cplx(Pl, k0, t, &C, &Xs, &Ys, &Xp, &Yp);
+            step_cplx(vs, C, Xs, Ys);
+            step_cplx(vp, C, Xp, Yp);
+        }
+        if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
+    }
+    return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
+}
+
+}  // namespace gwg

@@ -1,0 +1,80 @@
+// Internal layout shared by the host API and the HIP kernels.
+//
+// The host turns the caller's scene description into one SceneDev value
+// (passed by value to every trace kernel) plus a few small device tables:
+//   - lam_tab  [n_lsel][LT_STRIDE] f64: per selected wavelength the free-space
+//              wavenumber, glass and air indices, the complex index of every
+//              material slot used by the stacks and the near-critical kappa
+//              intervals of the mixed-precision rule;
+//   - dir_tab  [n_lsel][F][4] f64: guided direction of every grid FoV point;
+//   - slot     [D][M][Lmax] u8: compact material slot of every layer.
+// Thicknesses stay in the caller's device array [D][M][Lmax] f64.
+#pragma once
+#include <stdint.h>
+
+namespace gwg {
+
+constexpr int kMaxMirrors = 16;
+constexpr int kMaxSlots = 8;          // distinct layer materials in one scene
+constexpr int kMaxLayers = 1024;
+constexpr int kMaxEvents = 256;
+constexpr int LT_STRIDE = 64;         // doubles per wavelength in lam_tab
+// lam_tab columns
+constexpr int LT_K0 = 0;              // 2 pi / lambda, per nm
+constexpr int LT_NG = 1;              // glass index (real)
+constexpr int LT_NA = 2;              // air index (real)
+constexpr int LT_SLOT = 4;            // slot s: (re, im) at LT_SLOT + 2 s
+constexpr int LT_CRIT = 24;           // slot s: near-critical kappa interval (lo, hi) at LT_CRIT + 2 s
+constexpr int LT_NSLOT = 40;          // number of slots (as double)
+
+constexpr int kTapeStride = 15;       // doubles per tape entry (backward)
+constexpr int kSeg = 8;               // layers per recomputation segment (backward)
+
+enum EventType { EV_NONE = 0, EV_TIR = 1, EV_EXIT = 2, EV_LEAK = 3, EV_END = 4, EV_MIRROR = 5 };
+enum Category { CAT_EYEBOX = 0, CAT_MISS = 1, CAT_LEAK = 2, CAT_END = 3, CAT_TRUNC = 4,
+                CAT_LOST = 5, CAT_FACE_R = 6, NCAT = 8 };
+enum Surface { SURF_TOP = 1000, SURF_BOTTOM = 1001, SURF_END0 = 1002, SURF_END1 = 1003 };
+
+// stats layout (u64 words, device)
+enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4,
+                ST_CAT = 5,           // 8 words of counts
+                ST_POW = 13,          // 8 words of power (fixed point 2^-24)
+                ST_WORDS = 21 };
+
+struct SceneDev {
+    // slab
+    double T, Lx, ER;
+    double px0, pw, ph;
+    double ex0, ey0, ew, eh;
+    int32_t bins_x, bins_y;
+    // mirrors
+    int32_t M;
+    double nx, nz;                    // mirror normal (nx, 0, nz)
+    double h[kMaxMirrors];            // plane offsets n . c_m
+    uint32_t thr[kMaxMirrors];        // reflect iff word < thr
+    double sc_r[kMaxMirrors];         // 1 / sqrt(p_eff)
+    double sc_t[kMaxMirrors];         // 1 / sqrt(1 - p_eff)
+    // stacks
+    int32_t D, Lmax, n_slots;
+    uint32_t slot_complex;            // bit s set: slot s is absorbing
+    const double* thk;                // [D][M][Lmax]
+    const uint8_t* slot;              // [D][M][Lmax]
+    const int32_t* nlay;              // [D][M]
+    // wavelengths and field
+    int32_t n_lsel;
+    const double* lam_tab;            // [n_lsel][LT_STRIDE]
+    int32_t fov_mode, F;
+    const double* dir_tab;            // [n_lsel][F][4]
+    double fov_x0, fov_x1, fov_y0, fov_y1;  // random mode bounds, degrees
+    int64_t N;                        // rays per point
+    int32_t Kmax;
+    int32_t fp_shift;
+    uint32_t key0, key1;
+    int32_t precision;
+    // work decomposition
+    int64_t tiles_per_point;
+    int64_t rays_per_tile;
+    int64_t n_items;
+};
+
+}  // namespace gwg

@@ -1,0 +1,33 @@
+// Launch wrappers of the HIP kernels (defined in gwg_kernels.hip), called by
+// the host API only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "../../include/gwg.h"
+#include "gwg_internal.h"
+
+namespace gwg {
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+
+size_t fwd_smem_bytes(const SceneDev& sc, int wg, bool lds_bins);
+size_t bwd_smem_bytes(const SceneDev& sc, int wg);
+size_t tmm_smem_bytes(int L, int n_slots, int wg);
+
+hipError_t launch_trace_fwd(const SceneDev& sc, int wg, bool lds_bins, uint64_t* q, uint32_t* c,
+                            unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
+                            hipStream_t s);
+hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI,
+                            double* partial, double* scratch, int64_t sample_stride, hipStream_t s);
+hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D,
+                              double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s);
+hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double* irr, hipStream_t s);
+hipError_t launch_tmm_rt(int precision, const double* thk, const uint8_t* slot, int L,
+                         const double* lam_tab, int n_lambda, int n_slots, uint32_t cplx_mask,
+                         const int32_t* lidx, const double* theta, int64_t nq, double* out,
+                         hipStream_t s);
+hipError_t launch_loss(const double* I, int D, int nl, int F, int B, int kind, double w_f, double w_e,
+                       double* work, double* loss, double* G, hipStream_t s);
+
+}  // namespace gwg

@@ -1,0 +1,234 @@
+// Per-ray geometry and polarization steps of the Monte Carlo trace, shared by
+// the forward and adjoint kernels.
+//
+// Geometry (synthetic waveguide): glass slab 0 <= z <= T, 0 <= x <= Lx,
+// unbounded in y; M parallel mirror planes with normal n = (nx, 0, nz)
+// across the full thickness divide it into M + 1 convex cells; a ray leaves
+// its cell through the nearest of the cell's four bounding planes (top,
+// bottom, left boundary, right boundary), never the plane it stands on.
+// The path-determining operations (distances, position updates, mirror
+// reflection, face tests, exit refraction, binning) are individually
+// rounded double operations in a fixed order with FMA contraction disabled,
+// so a CPU implementation with the same operation sequence reproduces every
+// path decision bit for bit (integer bin counts are compared exactly).
+#pragma once
+#include "gwg_internal.h"
+#include "gwg_device.h"
+
+namespace gwg {
+
+struct Ray {
+    double px, py, pz, dx, dy, dz;
+    cd e[3];
+    int cell, last, nev, nprma;
+    uint32_t w4[4];
+    int64_t id;
+};
+
+// Block-uniform data of one (design, wavelength, FoV) point, in LDS.
+struct PointLds {
+    double k0, ng, na;
+    double dir[3];
+    double slotN[2 * kMaxSlots];     // (re, im) per slot
+    double nsq[2 * kMaxSlots];       // N^2 (re, im) per slot
+    double crit[2 * kMaxSlots];      // near-critical kappa interval per slot
+    double h[kMaxMirrors], sc_r[kMaxMirrors], sc_t[kMaxMirrors];
+    uint32_t thr[kMaxMirrors];
+    int32_t nlay[kMaxMirrors];
+};
+
+__device__ inline void cross3(double ax, double ay, double az, double bx, double by, double bz,
+                              double* o)
+{
+    o[0] = ay * bz - az * by;
+    o[1] = az * bx - ax * bz;
+    o[2] = ax * by - ay * bx;
+}
+
+// s unit vector for direction d on a surface of normal n; when d is nearly
+// parallel to n (s and p equivalent) the y axis projected orthogonal to d.
+__device__ inline void s_basis(double dx, double dy, double dz, double nx, double ny, double nz, double* s)
+{
+    double c[3];
+    cross3(dx, dy, dz, nx, ny, nz, c);
+    double l = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    if (l < 1e-6) {
+        double yd = dy;
+        c[0] = -yd * dx; c[1] = 1.0 - yd * dy; c[2] = -yd * dz;
+        l = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    }
+    double il = 1.0 / l;
+    s[0] = c[0] * il; s[1] = c[1] * il; s[2] = c[2] * il;
+}
+
+// Eq. 5 on the local basis: E <- scale (cs (E.s) s + cp (E.p_in) p_out)
+__device__ inline void apply_sp(cd* e, const double* s, const double* pin, const double* pout,
+                                cd cs, cd cp, double scale)
+{
+    cd es = cadd(cadd(cscale(e[0], s[0]), cscale(e[1], s[1])), cscale(e[2], s[2]));
+    cd ep = cadd(cadd(cscale(e[0], pin[0]), cscale(e[1], pin[1])), cscale(e[2], pin[2]));
+    cd as = cscale(cmul(cs, es), scale), ap = cscale(cmul(cp, ep), scale);
+    for (int k = 0; k < 3; ++k) e[k] = cadd(cscale(as, s[k]), cscale(ap, pout[k]));
+}
+
+__device__ inline double norm2(const cd* e)
+{
+    double ax = e[0].re * e[0].re + e[0].im * e[0].im;
+    double ay = e[1].re * e[1].re + e[1].im * e[1].im;
+    double az = e[2].re * e[2].re + e[2].im * e[2].im;
+    return (ax + ay) + az;
+}
+
+// Guided direction for field angles (thx, thy) in degrees: direction at the
+// eye, refracted into the glass through the top face, mirrored by an
+// in-coupler parallel to the mirrors.
+__device__ inline void field_direction(double thx, double thy, double ng, double nx, double nz, double* d)
+{
+    double tx = tan(thx * (3.14159265358979323846 / 180.0));
+    double ty = tan(thy * (3.14159265358979323846 / 180.0));
+    double inv = 1.0 / sqrt(tx * tx + ty * ty + 1.0);
+    double ax = tx * inv, ay = ty * inv;
+    double gx = ax / ng, gy = ay / ng, gz = sqrt(1.0 - (ax * ax + ay * ay) / (ng * ng));
+    double gn = nx * gx + nz * gz;
+    double t2 = 2.0 * gn;
+    d[0] = gx - t2 * nx;
+    d[1] = gy;
+    d[2] = gz - t2 * nz;
+}
+
+__device__ inline void ray_birth(const SceneDev& sc, const PointLds& pl, int64_t id, Ray& r)
+{
+    u32x4 w = philox10((uint32_t)(uint64_t)id, (uint32_t)((uint64_t)id >> 32), 0u, 0u, sc.key0, sc.key1);
+    r.id = id;
+    r.px = sc.px0 + u24(w.x) * sc.pw;
+    r.py = u24(w.y) * sc.ph - 0.5 * sc.ph;
+    r.pz = sc.T;
+    if (sc.fov_mode == 1) {
+        double thx = sc.fov_x0 + u24(w.z) * (sc.fov_x1 - sc.fov_x0);
+        double thy = sc.fov_y0 + u24(w.w) * (sc.fov_y1 - sc.fov_y0);
+        double d[3];
+        field_direction(thx, thy, pl.ng, sc.nx, sc.nz, d);
+        r.dx = d[0]; r.dy = d[1]; r.dz = d[2];
+    } else {
+        r.dx = pl.dir[0]; r.dy = pl.dir[1]; r.dz = pl.dir[2];
+    }
+    double s0[3], p0[3];
+    s_basis(r.dx, r.dy, r.dz, 0.0, 0.0, 1.0, s0);
+    cross3(r.dx, r.dy, r.dz, s0[0], s0[1], s0[2], p0);
+    const double* e = (w.x & 1u) ? p0 : s0;
+    for (int k = 0; k < 3; ++k) r.e[k] = mk(e[k], 0.0);
+    r.cell = 0;
+    r.last = SURF_TOP;
+    r.nev = 0;
+    r.nprma = 0;
+}
+
+// Nearest bounding plane of the current cell; moves the ray onto it.
+__device__ inline int next_surface(const SceneDev& sc, const PointLds& pl, Ray& r)
+{
+    double best = 0.0;
+    int hit = -1;
+    if (r.dz > 0.0 && r.last != SURF_TOP) {
+        double t = (sc.T - r.pz) / r.dz;
+        if (hit < 0 || t < best) { best = t; hit = SURF_TOP; }
+    }
+    if (r.dz < 0.0 && r.last != SURF_BOTTOM) {
+        double t = (0.0 - r.pz) / r.dz;
+        if (hit < 0 || t < best) { best = t; hit = SURF_BOTTOM; }
+    }
+    double dn = sc.nx * r.dx + sc.nz * r.dz;
+    double pn = sc.nx * r.px + sc.nz * r.pz;
+    if (r.cell == 0) {
+        if (r.dx < 0.0 && r.last != SURF_END0) {
+            double t = (0.0 - r.px) / r.dx;
+            if (hit < 0 || t < best) { best = t; hit = SURF_END0; }
+        }
+    } else {
+        int m = r.cell - 1;
+        if (dn > 0.0 && r.last != m) {
+            double t = (pl.h[m] - pn) / dn;
+            if (hit < 0 || t < best) { best = t; hit = m; }
+        }
+    }
+    if (r.cell == sc.M) {
+        if (r.dx > 0.0 && r.last != SURF_END1) {
+            double t = (sc.Lx - r.px) / r.dx;
+            if (hit < 0 || t < best) { best = t; hit = SURF_END1; }
+        }
+    } else {
+        int m = r.cell;
+        if (dn < 0.0 && r.last != m) {
+            double t = (pl.h[m] - pn) / dn;
+            if (hit < 0 || t < best) { best = t; hit = m; }
+        }
+    }
+    if (hit < 0) return -1;
+    r.px = r.px + best * r.dx;
+    r.py = r.py + best * r.dy;
+    r.pz = r.pz + best * r.dz;
+    if (hit == SURF_TOP) r.pz = sc.T;
+    if (hit == SURF_BOTTOM) r.pz = 0.0;
+    if (hit == SURF_END0) r.px = 0.0;
+    if (hit == SURF_END1) r.px = sc.Lx;
+    return hit;
+}
+
+// Bare glass/air face (Eq. 3).  Returns 1 on total internal reflection.
+struct FaceCoef { cd rs, rp, ts, tp; double flux, st2; int tir; };
+
+__device__ inline FaceCoef face_coeffs(double ng, double na, double dx, double dy, double dz)
+{
+    FaceCoef f;
+    double ng2 = ng * ng, na2 = na * na;
+    f.st2 = ng2 * (dx * dx + dy * dy);
+    double qi = ng * fabs(dz);
+    f.tir = f.st2 > na2;
+    cd qt = f.tir ? mk(0.0, sqrt(f.st2 - na2)) : mk(sqrt(na2 - f.st2), 0.0);
+    cd den_s = cadd(mk(qi, 0.0), qt);
+    f.rs = cdiv(csub(mk(qi, 0.0), qt), den_s);
+    f.ts = cdiv(mk(2.0 * qi, 0.0), den_s);
+    cd a = mk(na2 * qi, 0.0), b = cscale(qt, ng2);
+    cd den_p = cadd(a, b);
+    f.rp = cdiv(csub(a, b), den_p);
+    f.tp = cdiv(mk(2.0 * ng * na * qi, 0.0), den_p);
+    f.flux = f.tir ? 0.0 : sqrt(qt.re / qi);
+    return f;
+}
+
+// Eyebox bin of a ray leaving the top face at (px, py) along air direction a.
+__device__ inline int eyebox_bin(const SceneDev& sc, double px, double py, const double* a)
+{
+    double xe = px + sc.ER * (a[0] / a[2]);
+    double ye = py + sc.ER * (a[1] / a[2]);
+    double fx = ((xe - sc.ex0) / sc.ew) * (double)sc.bins_x;
+    double fy = ((ye - sc.ey0) / sc.eh) * (double)sc.bins_y;
+    if (!(fx >= 0.0 && fx < (double)sc.bins_x && fy >= 0.0 && fy < (double)sc.bins_y)) return -1;
+    int bx = (int)fx, by = (int)fy;
+    return by * sc.bins_x + bx;
+}
+
+__device__ inline void exit_direction(double ng, double na, const Ray& r, double st2, double* a)
+{
+    double rn = ng / na;
+    a[0] = rn * r.dx;
+    a[1] = rn * r.dy;
+    a[2] = sqrt(1.0 - st2 / (na * na));
+}
+
+__device__ inline void mirror_reflect(double nx, double nz, double dx, double dz, double* ox, double* oz)
+{
+    double dn = nx * dx + nz * dz;
+    double t2 = 2.0 * dn;
+    *ox = dx - t2 * nx;
+    *oz = dz - t2 * nz;
+}
+
+// Near-critical flag of the mixed-precision rule: kappa within any slot's interval.
+__device__ inline bool near_critical(const PointLds& pl, int n_slots, double kappa)
+{
+    bool f = false;
+    for (int s = 0; s < n_slots; ++s) f |= (kappa > pl.crit[2 * s] && kappa < pl.crit[2 * s + 1]);
+    return f;
+}
+
+}  // namespace gwg

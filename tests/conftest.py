@@ -18,3 +18,14 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gctx():
+    """Library context on cuda:0.  Skips only when no GPU is visible; any
+    failure to load or initialise the HIP library is an error."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2601_04370_amd as gwg
+    return gwg.Context(0)

@@ -1,0 +1,122 @@
+"""Parity of gwg_trace_backward (adjoint kernel) with the oracle's adjoint, and
+of gwg_loss with the oracle's loss.
+
+The oracle differentiates its own recursive-Airy solve and stores the whole
+path; the GPU runs the characteristic-matrix adjoint with segment
+recomputation.  Both receive the same dL/dI.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import paper_2601_04370_amd as gwg
+
+pytestmark = pytest.mark.gpu
+
+
+def _grad_case(gctx, orc, w, inp, precision=0, stride=1, tile=0, bwd_wg=0):
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    osc = orc.OracleScene(w, inp)
+    oirr = osc.forward_sampled(stride)
+    L, dLdI = orc.loss(oirr, 0)
+    gctx.set_tuning(bwd_rays_per_block=tile, bwd_block_threads=bwd_wg)
+    try:
+        gctx.trace_forward(scene, thk, w.seed, 0, precision)
+        g = gctx.trace_backward(torch.tensor(dLdI), scene, sample_stride=stride).cpu().numpy()
+    finally:
+        gctx.set_tuning()
+    og = osc.backward(dLdI, stride)
+    return g, og
+
+
+GCASES = [
+    ("plain_fp64", dict(rays_per_point=4000), 1, 0),
+    ("diff_1200", dict(rays_per_point=96, fov_n=3), 1, 640),
+    ("precision_ag", dict(rays_per_point=64, fov_n=3, lambdas_nm=(530.0,)), 1, 0),
+    ("batched", dict(n_designs=2, rays_per_point=48, fov_n=3, lambdas_nm=(420.0, 680.0)), 1, 0),
+]
+
+
+@pytest.mark.parametrize("name,kw,stride,tile", GCASES)
+def test_backward_fp64_matches_oracle(gctx, orc, name, kw, stride, tile):
+    w = inputs.small_variant(name, **kw)
+    inp = inputs.make_inputs(w)
+    print(f"backward fp64 {name} {kw}", flush=True)
+    g, og = _grad_case(gctx, orc, w, inp, 0, stride, tile)
+    scale = np.max(np.abs(og))
+    assert scale > 0
+    err = np.abs(g - og)
+    print(f"  max |g| {scale:.3e}  max abs err {err.max():.3e}  rel {err.max() / scale:.2e}", flush=True)
+    # elementwise, relative with a floor at 1e-3 of the largest component
+    assert np.all(err <= 1e-4 * np.maximum(np.abs(og), 1e-3 * scale))
+    # padding slots are exactly zero
+    for d in range(inp["thk"].shape[0]):
+        for m in range(w.n_mirrors):
+            assert np.all(g[d, m, inp["n_layers"][d, m]:] == 0.0)
+
+
+def test_backward_is_deterministic(gctx, orc):
+    w = inputs.small_variant("diff_1200", rays_per_point=128, fov_n=3)
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    rng = np.random.default_rng(0)
+    dLdI = torch.tensor(rng.standard_normal(scene.shape))
+    gctx.trace_forward(scene, thk, w.seed, 0, 0)
+    a = gctx.trace_backward(dLdI, scene).cpu().numpy()
+    b = gctx.trace_backward(dLdI, scene).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_backward_full_size_sampled(gctx, orc):
+    """Full differentiation workload, default launch configuration; only rays
+    with id % 4099 == 0 contribute on both sides."""
+    w = inputs.workload("diff_1200")
+    inp = inputs.make_inputs(w)
+    stride = 4099
+    g, og = _grad_case(gctx, orc, w, inp, 0, stride)
+    scale = np.max(np.abs(og))
+    err = np.abs(g - og)
+    print(f"full size sampled: max |g| {scale:.3e} rel err {err.max() / scale:.2e}", flush=True)
+    assert np.all(err <= 1e-4 * np.maximum(np.abs(og), 1e-3 * scale))
+
+
+def test_autograd_function(gctx, orc):
+    w = inputs.small_variant("plain_fp64", rays_per_point=3000)
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    GWGTrace = gwg.make_trace_function()
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    irr = GWGTrace.apply(thk, gctx, scene, w.seed, 0, gwg.FP64)
+    weights = torch.linspace(0.5, 1.5, irr.numel(), dtype=torch.float64, device="cuda:0").view_as(irr)
+    (irr * weights).sum().backward()
+    osc = orc.OracleScene(w, inp)
+    og = osc.backward(weights.cpu().numpy(), 1)
+    g = thk.grad.cpu().numpy()
+    assert np.max(np.abs(g - og)) <= 1e-6 * np.max(np.abs(og))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_loss_matches_oracle(gctx, orc, kind):
+    rng = np.random.default_rng(kind)
+    I = rng.uniform(0, 1e-3, size=(2, 3, 9, 8, 8))
+    wf, we = (10.0, 3.0) if kind else (1.0, 1.0)
+    L, g = gctx.loss(torch.tensor(I), kind, wf, we)
+    oL, og = orc.loss(I, kind, wf, we)
+    assert abs(L.item() - oL) <= 1e-12 * max(1.0, abs(oL))
+    assert np.max(np.abs(g.cpu().numpy() - og)) <= 1e-12 * np.max(np.abs(og))
+
+
+def test_backward_requires_forward(orc):
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = gwg.Context(0)
+    w = inputs.small_variant("plain_fp64", rays_per_point=10)
+    scene = gwg.SceneSpec.from_workload(w, inputs.make_inputs(w))
+    with pytest.raises(gwg.GwgError) as e:
+        ctx.trace_backward(_t.zeros(scene.shape, dtype=_t.float64), scene)
+    assert e.value.code == 4
+    ctx.close()

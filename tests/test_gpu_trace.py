@@ -1,0 +1,142 @@
+"""Parity of gwg_trace_forward with the oracle, sample by sample.
+
+Both sides draw the same Philox words per ray and perform the same geometric
+operations, so bin counts (pure geometry) must agree bit for bit and the
+per-ray weights to FP64 rounding (FP64 mode).  Fixed-point bins may differ by
+one unit per ray where the two (independent) thin-film formulations round
+differently.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import paper_2601_04370_amd as gwg
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(gctx, w, inp, precision=0, stride=1, step=0, stats=True):
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    q, c, irr, rec, st = gctx.trace_forward(scene, thk, w.seed, step, precision, record_stride=stride,
+                                            stats=stats)
+    torch.cuda.synchronize()
+    return scene, q.cpu().numpy().astype(np.uint64), c.cpu().numpy().astype(np.uint32), \
+        irr.cpu().numpy(), (gwg.records_view(rec) if rec is not None else None), st
+
+
+CASES = [
+    ("plain_fp64", dict(rays_per_point=20000), 0),
+    ("fwd_scale", dict(rays_per_point=700, fov_n=3), 0),
+    ("diff_1200", dict(rays_per_point=300, fov_n=3), 2400),
+    ("precision_ag", dict(rays_per_point=200, fov_n=3, lambdas_nm=(460.0, 620.0)), 0),
+    ("batched", dict(n_designs=2, rays_per_point=120, fov_n=3, lambdas_nm=(400.0, 550.0, 700.0)), 0),
+]
+
+
+@pytest.mark.parametrize("name,kw,tile", CASES)
+def test_forward_fp64_matches_oracle(gctx, orc, name, kw, tile):
+    w = inputs.small_variant(name, **kw)
+    inp = inputs.make_inputs(w)
+    print(f"forward fp64 {name} {kw} tile={tile}", flush=True)
+    gctx.set_tuning(rays_per_block=tile)
+    try:
+        scene, q, c, irr, rec, st = _run(gctx, w, inp, 0, stride=1)
+    finally:
+        gctx.set_tuning()
+    osc = orc.OracleScene(w, inp)
+    oq, oc, ows, ost = osc.forward()
+    assert np.array_equal(c, oc), "bin counts differ"
+    # at most one fixed-point unit per ray of rounding difference
+    dq = np.abs(q.astype(np.int64) - oq.astype(np.int64))
+    assert np.all(dq <= oc.astype(np.int64)), dq.max()
+    oirr = osc.forward_sampled(1)
+    assert np.array_equal(irr, q.astype(np.float64) * (2.0 ** -24 / w.rays_per_point))
+    # per-ray records against the oracle, every ray
+    n = scene.n_rays
+    orec = osc.trace_rays(np.arange(n))
+    ob = np.array([r.bin for r in orec])
+    oc_ = np.array([r.category for r in orec])
+    on = np.array([r.n_events for r in orec])
+    op = np.array([r.n_prma for r in orec])
+    ow = np.array([r.w for r in orec])
+    assert np.array_equal(rec["bin"], ob)
+    assert np.array_equal(rec["category"], oc_)
+    assert np.array_equal(rec["n_events"], on)
+    assert np.array_equal(rec["n_prma"], op)
+    assert np.max(np.abs(rec["w"] - ow)) <= 1e-11 * max(1.0, np.max(np.abs(ow)))
+    # statistics
+    assert st["rays"] == ost.counters[0] and st["interactions"] == ost.counters[1]
+    assert st["prma_hits"] == ost.counters[2]
+    for k in range(6):
+        assert st["n_cat"][gwg.gwg.CAT_NAMES[k]] == ost.counters[4 + k]
+    rel = np.abs(irr - oirr).max() / max(np.abs(oirr).max(), 1e-300)
+    print(f"  counts exact; max |dq| {dq.max()}; irradiance rel err {rel:.2e}; "
+          f"interactions {st['interactions']}", flush=True)
+    assert rel < 1e-6
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_forward_single_precision_thin_film(gctx, orc, precision):
+    """Mixed / FP32 thin-film solve: geometry is unchanged (counts exact), the
+    irradiance error against the FP64 oracle is measured."""
+    w = inputs.small_variant("fwd_scale", rays_per_point=600, fov_n=3)
+    inp = inputs.make_inputs(w)
+    scene, q, c, irr, rec, st = _run(gctx, w, inp, precision, stride=1)
+    osc = orc.OracleScene(w, inp)
+    oq, oc, ows, ost = osc.forward()
+    assert np.array_equal(c, oc)
+    oirr = osc.forward_sampled(1)
+    active = oirr > 1e-3 * oirr.max()
+    rel = np.abs(irr - oirr)[active] / oirr[active]
+    print(f"precision {precision}: irradiance rel err max {rel.max():.2e} median {np.median(rel):.2e}; "
+          f"fp64 hits {st['fp64_hits']} / {st['prma_hits']}", flush=True)
+    assert np.all(np.isfinite(irr))
+    assert np.median(rel) < 1e-3
+
+
+def test_forward_is_deterministic(gctx):
+    w = inputs.small_variant("diff_1200", rays_per_point=512, fov_n=5)
+    inp = inputs.make_inputs(w)
+    a = _run(gctx, w, inp, 0, stride=0, stats=False)
+    b = _run(gctx, w, inp, 0, stride=0, stats=False)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    c = _run(gctx, w, inp, 0, stride=0, stats=False, step=1)
+    assert not np.array_equal(a[2], c[2])
+
+
+def test_forward_tile_shape_does_not_change_results(gctx):
+    w = inputs.small_variant("fwd_scale", rays_per_point=1000, fov_n=3)
+    inp = inputs.make_inputs(w)
+    res = []
+    for wg, tile in ((256, 0), (128, 384), (64, 1000), (256, 256)):
+        gctx.set_tuning(block_threads=wg, rays_per_block=tile)
+        try:
+            res.append(_run(gctx, w, inp, 0, stride=0, stats=False))
+        finally:
+            gctx.set_tuning()
+    for r in res[1:]:
+        assert np.array_equal(r[1], res[0][1]) and np.array_equal(r[2], res[0][2])
+
+
+def test_full_size_sampled_rays(gctx, orc):
+    """Differentiation workload at full size (6 mirrors x 200 layers, 3
+    wavelengths, 21 x 21 FoV, 4096 rays per point) in the default launch
+    configuration: every 4099th ray is compared with the oracle."""
+    w = inputs.workload("diff_1200")
+    inp = inputs.make_inputs(w)
+    stride = 4099
+    scene, q, c, irr, rec, st = _run(gctx, w, inp, 0, stride=stride)
+    ids = np.arange(0, scene.n_rays, stride)
+    osc = orc.OracleScene(w, inp)
+    orec = osc.trace_rays(ids)
+    assert np.array_equal(rec["bin"], [r.bin for r in orec])
+    assert np.array_equal(rec["n_events"], [r.n_events for r in orec])
+    ow = np.array([r.w for r in orec])
+    assert np.max(np.abs(rec["w"] - ow)) <= 1e-11 * max(1.0, ow.max())
+    # properties that hold at any size
+    assert c.sum() == st["n_cat"]["eyebox"]
+    assert st["rays"] == scene.n_rays
+    print(f"full size: {scene.n_rays} rays, {st['interactions']} interactions, "
+          f"{st['prma_hits']} mirror hits, {len(ids)} rays compared", flush=True)
