@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of one optimisation step of the differentiable waveguide trace.
+
+A step is the whole hot path on one batch: forward Monte Carlo trace with
+per-hit thin-film solves and fixed-point eyebox scatter, the eyebox loss and
+its dL/dI, and the adjoint trace down to every layer thickness (plus the
+fixed-order gradient reduction).  Each step draws fresh paths (the Philox
+key includes the step index).  The metric is forward ray-surface
+interactions per second of whole steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed|fp32]
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd ray-surface interactions/s @1200 layers; mixed vs FP64, |dR|<=1e-5"
+UNIT = "interactions/s"
+# MI355X vector peaks (TFLOP/s): FP64 78.6; FP32 157.3 (packed dual-issue)
+PEAK_FP64 = 78.6
+# Algorithmic FLOPs per (mirror hit, layer) of a lossless layer, counting an
+# FMA as two and one sine/cosine pair as zero (reported separately):
+#   forward solve 29 = phase 1 + four X/Y products 4 + two real-coefficient
+#     complex 2x2 matrix-vector products 2 x 12;
+#   adjoint 125 = exit-to-incident sweep 29 + segment recomputation 29 +
+#     contraction u^T D w for s and p 39 + covector step for s and p 28.
+FLOP_FWD_LAYER = 29.0
+FLOP_ADJ_LAYER = 125.0
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2601_04370_amd", "csrc")
+    for n in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, n), "rb") as f:
+            h.update(n.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch measured by rocprofv3 PMC runs (profiles/traffic.json),
+    valid only for the kernel sources they were measured on."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    e = t.get(f"{kernel}/{workload}/{precision}")
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, inp, budget_s: float):
+    """The FP64 oracle (single-threaded C) on a bounded sample of the same
+    workload: every s-th ray, forward + loss + adjoint."""
+    import numpy as np
+    import oracle
+    osc = oracle.OracleScene(w, inp)
+    n_rays = w.n_rays
+    # calibrate on a tiny sample
+    s0 = max(1, n_rays // 60)
+    t = time.perf_counter()
+    irr = osc.forward_sampled(s0)
+    _, g = oracle.loss(irr, 0)
+    osc.backward(g, s0)
+    per_ray = (time.perf_counter() - t) / max(1, n_rays // s0)
+    stride = max(1, int(n_rays / max(1.0, budget_s / max(per_ray, 1e-9))))
+    ids = np.arange(0, n_rays, stride)
+    recs = osc.trace_rays(ids)
+    n_int = int(sum(r.n_events for r in recs))
+    t = time.perf_counter()
+    irr = osc.forward_sampled(stride)
+    _, g = oracle.loss(irr, 0)
+    osc.backward(g, stride)
+    el = time.perf_counter() - t
+    return {"value": n_int / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"every {stride}th ray of the workload ({len(ids)} rays, {n_int} interactions), "
+                      f"forward + loss + adjoint, {el:.1f} s single-threaded FP64 C"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32"])
+    ap.add_argument("--workload", default="diff_1200")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; the per-GPU kernel is the whole "
+                                   "measured path (see DESIGN.md for how it would shard)", "n_gpus": a.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_2601_04370_amd as gwg
+
+    w = inputs.workload(a.workload)
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    prec = gwg.PRECISIONS[a.precision]
+    ctx = gwg.Context(0)
+    dev = torch.device("cuda", 0)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device=dev)
+
+    def step(k, ev=None):
+        if ev:
+            ev[0].record()
+        _, _, irr, _, _ = ctx.trace_forward(scene, thk, w.seed, k, prec)
+        if ev:
+            ev[1].record()
+        _, dLdI = ctx.loss(irr, 0)
+        if ev:
+            ev[2].record()
+        g = ctx.trace_backward(dLdI, scene)
+        if ev:
+            ev[3].record()
+        return g
+
+    for k in range(a.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step(a.warmup + i, events[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    fwd_ms = [e[0].elapsed_time(e[1]) for e in events]
+    loss_ms = [e[1].elapsed_time(e[2]) for e in events]
+    bwd_ms = [e[2].elapsed_time(e[3]) for e in events]
+
+    # counters of the timed steps (recomputed untimed: same seeds, same paths)
+    inter = hits = lay_f = lay_b = lay_a = fp64h = 0
+    for i in range(a.steps):
+        _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True)
+        _, dLdI = ctx.loss(irr, 0)
+        _, bst = ctx.trace_backward(dLdI, scene, stats=True)
+        inter += st["interactions"]
+        hits += st["prma_hits"]
+        lay_f += st["layer_steps"]
+        fp64h += st["fp64_hits"]
+        lay_b += bst["layer_steps"]
+        lay_a += bst["adjoint_layer_steps"]
+    K = a.steps
+    value = inter / wall
+    f_fwd = FLOP_FWD_LAYER * lay_f / K
+    f_bwd = (FLOP_FWD_LAYER * lay_b + FLOP_ADJ_LAYER * lay_a) / K
+    t_fwd = float(np.mean(fwd_ms)) * 1e-3
+    t_bwd = float(np.mean(bwd_ms)) * 1e-3
+    if t_bwd >= t_fwd:
+        kname, flops, tk = "k_trace_bwd", f_bwd, t_bwd
+    else:
+        kname, flops, tk = "k_trace_fwd", f_fwd, t_fwd
+    achieved = flops / tk / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64, "traffic": load_traffic(kname, a.workload, a.precision),
+            "kernel": kname}
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": a.warmup,
+        "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == gwg.FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": a.workload, "designs": w.n_designs, "mirrors": w.n_mirrors,
+                   "layers_per_mirror": w.max_layers, "thickness_params": w.n_params,
+                   "wavelengths": len(w.lambdas_nm), "fov_points": w.n_fov,
+                   "rays_per_point": w.rays_per_point, "rays_per_step": w.n_rays,
+                   "bins": list(w.bins), "max_events": w.max_events, "precision": a.precision},
+        "roofline": roof,
+        "extra": {"interactions_per_step": inter / K, "mirror_hits_per_step": hits / K,
+                  "mirror_hits_per_s": hits / wall, "fp64_hit_fraction": fp64h / max(hits, 1),
+                  "fwd_ms": float(np.mean(fwd_ms)), "loss_ms": float(np.mean(loss_ms)),
+                  "bwd_ms": float(np.mean(bwd_ms)), "fwd_tflops": f_fwd / t_fwd / 1e12,
+                  "bwd_tflops": f_bwd / t_bwd / 1e12},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, inp, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

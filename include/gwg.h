@@ -181,8 +181,14 @@ typedef struct {
 enum { GWG_CAT_EYEBOX = 0, GWG_CAT_MISS = 1, GWG_CAT_LEAK = 2, GWG_CAT_END = 3,
        GWG_CAT_TRUNC = 4, GWG_CAT_LOST = 5, GWG_CAT_FACE_R = 6, GWG_NCAT = 8 };
 
+/* Counters of one call.  Forward: rays traced, ray-surface interactions,
+ * mirror hits, layer steps (sum over hits of the stack's layer count),
+ * hits solved in double precision, saturated bin contributions, terminations
+ * and final power per category.  Backward: the same for the regenerated
+ * paths, plus rays / hits / layer steps that went through the adjoint. */
 typedef struct {
-    int64_t rays, interactions, prma_hits, fp64_hits, saturated;
+    int64_t rays, interactions, prma_hits, layer_steps, fp64_hits, saturated;
+    int64_t adjoint_rays, adjoint_hits, adjoint_layer_steps;
     int64_t n_cat[GWG_NCAT];
     double power[GWG_NCAT];     /* summed final |E|^2 per category (fixed-point, 2^-24) */
 } gwg_stats;
@@ -211,9 +217,10 @@ int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
  * I = sum w / rays_per_point.  d_grad: device f64 [D][M][max_layers],
  * overwritten (padding slots get 0).  sample_stride >= 1: only rays with
  * id % sample_stride == 0 contribute (1 = all rays).  Deterministic: the
- * same inputs give bit-identical gradients. */
+ * same inputs give bit-identical gradients.  stats: optional host struct
+ * (synchronizes the stream). */
 int gwg_trace_backward(gwg_ctx* ctx, const double* d_dL_dI, double* d_grad,
-                       int64_t sample_stride, void* stream);
+                       int64_t sample_stride, gwg_stats* stats, void* stream);
 
 /* Eyebox loss (Eq. 1) and dL/dI for irradiance d_irr (device f64,
  * [D][n_l][F][B]), summed over designs.  kind 0: -mean(eta) + w_e Var_b(E_b)

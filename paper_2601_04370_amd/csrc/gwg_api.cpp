@@ -370,6 +370,28 @@ void set_tiles(SceneDev& s, int64_t rays_per_tile, int wg, int n_cu)
     s.n_items = (int64_t)s.D * s.n_lsel * s.F * s.tiles_per_point;
 }
 
+int read_stats(gwg_ctx* c, hipStream_t s, gwg_stats* stats)
+{
+    uint64_t w[ST_WORDS];
+    HIP_CHECK(c, hipMemcpyAsync(w, c->stats.p, sizeof(w), hipMemcpyDeviceToHost, s), "read stats");
+    HIP_CHECK(c, hipStreamSynchronize(s), "kernel execution");
+    std::memset(stats, 0, sizeof(*stats));
+    stats->rays = (int64_t)w[ST_RAYS];
+    stats->interactions = (int64_t)w[ST_EVENTS];
+    stats->prma_hits = (int64_t)w[ST_PRMA];
+    stats->layer_steps = (int64_t)w[ST_LAYERS];
+    stats->fp64_hits = (int64_t)w[ST_FP64];
+    stats->saturated = (int64_t)w[ST_SAT];
+    stats->adjoint_rays = (int64_t)w[ST_ADJ_RAYS];
+    stats->adjoint_hits = (int64_t)w[ST_ADJ_HITS];
+    stats->adjoint_layer_steps = (int64_t)w[ST_ADJ_LAYERS];
+    for (int k = 0; k < GWG_NCAT; ++k) {
+        stats->n_cat[k] = (int64_t)w[ST_CAT + k];
+        stats->power[k] = (double)w[ST_POW + k] / 16777216.0;
+    }
+    return GWG_OK;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -538,24 +560,15 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     c->fwd = sc;
     c->have_forward = true;
     if (stats) {
-        uint64_t w[ST_WORDS];
-        HIP_CHECK(c, hipMemcpyAsync(w, c->stats.p, sizeof(w), hipMemcpyDeviceToHost, s), "read stats");
-        HIP_CHECK(c, hipStreamSynchronize(s), "forward");
-        stats->rays = (int64_t)w[ST_RAYS];
-        stats->interactions = (int64_t)w[ST_EVENTS];
-        stats->prma_hits = (int64_t)w[ST_PRMA];
-        stats->fp64_hits = (int64_t)w[ST_FP64];
-        stats->saturated = (int64_t)w[ST_SAT];
-        for (int k = 0; k < GWG_NCAT; ++k) {
-            stats->n_cat[k] = (int64_t)w[ST_CAT + k];
-            stats->power[k] = (double)w[ST_POW + k] / 16777216.0;
-        }
+        rc = read_stats(c, s, stats);
+        if (rc) return rc;
         if (stats->saturated) return fail(c, GWG_E_OVERFLOW, "%lld bin contributions saturated", (long long)stats->saturated);
     }
     return GWG_OK;
 }
 
-int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_t sample_stride, void* stream)
+int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_t sample_stride,
+                       gwg_stats* stats, void* stream)
 {
     if (!c) return GWG_E_INVAL;
     c->err.clear();
@@ -575,12 +588,15 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     const int64_t lane_doubles = (int64_t)sc.Kmax * kTapeStride + n_chk * 8;
     HIP_CHECK(c, c->scratch.ensure(sizeof(double) * lane_doubles * grid * wg), "alloc adjoint scratch");
     HIP_CHECK(c, c->partial.ensure(sizeof(double) * (size_t)sc.n_items * ML), "alloc partial gradients");
-    HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (double*)c->partial.p, (double*)c->scratch.p,
-                                  sample_stride, s),
+    HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
+    HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
+    HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
+                                  (double*)c->scratch.p, sample_stride, s),
               "adjoint kernel");
     HIP_CHECK(c, launch_grad_reduce((const double*)c->partial.p, sc.n_items / sc.D, ML, sc.D, d_grad, sc.nlay, sc.M,
                                     sc.Lmax, s),
               "gradient reduction");
+    if (stats) return read_stats(c, s, stats);
     return GWG_OK;
 }
 

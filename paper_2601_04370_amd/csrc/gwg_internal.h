@@ -37,9 +37,10 @@ enum Surface { SURF_TOP = 1000, SURF_BOTTOM = 1001, SURF_END0 = 1002, SURF_END1 
 
 // stats layout (u64 words, device)
 enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4,
-                ST_CAT = 5,           // 8 words of counts
-                ST_POW = 13,          // 8 words of power (fixed point 2^-24)
-                ST_WORDS = 21 };
+                ST_LAYERS = 5, ST_ADJ_RAYS = 6, ST_ADJ_HITS = 7, ST_ADJ_LAYERS = 8,
+                ST_CAT = 9,           // 8 words of counts
+                ST_POW = 17,          // 8 words of power (fixed point 2^-24)
+                ST_WORDS = 25 };
 
 struct SceneDev {
     // slab

@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
     bool have = i < i1;
     Ray r;
     if (have) ray_birth(sc, *pl, base + i, r);
-    unsigned long long n_fp64 = 0;
+    unsigned long long n_fp64 = 0, n_lay = 0;
     for (;;) {
         int m = -1;
         while (have) {
@@ -324,9 +324,11 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
             bool u64 = false;
             mirror_event<MODE, false>(sc, *pl, s_thk, s_slot, sp, WG, r, m, none, &nt, &u64);
             n_fp64 += u64 ? 1ull : 0ull;
+            n_lay += (unsigned long long)pl->nlay[m];
         }
     }
     if (n_fp64) atomicAdd(&s_st[ST_FP64], n_fp64);
+    if (n_lay) atomicAdd(&s_st[ST_LAYERS], n_lay);
     __syncthreads();
     if (lds_bins) {
         for (int k = tid; k < B; k += WG) {
@@ -353,7 +355,8 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
 template <int MODE>
 __global__ void __launch_bounds__(128) k_trace_bwd(SceneDev sc, const double* __restrict__ dLdI,
                                                    double* __restrict__ partial,
-                                                   double* __restrict__ scratch, int64_t sample_stride)
+                                                   double* __restrict__ scratch, int64_t sample_stride,
+                                                   unsigned long long* __restrict__ stats)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int WG = blockDim.x;
@@ -374,6 +377,10 @@ __global__ void __launch_bounds__(128) k_trace_bwd(SceneDev sc, const double* __
     const int64_t gtid = (int64_t)blockIdx.x * WG + tid;
     TapeRef tape = { scratch + gtid, nthreads };
     double* chk = scratch + (int64_t)sc.Kmax * kTapeStride * nthreads + gtid;
+    unsigned long long* s_st = (unsigned long long*)(smem + lay.off_st);
+    for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
+    unsigned long long c_rays = 0, c_ev = 0, c_hits = 0, c_lay = 0, c_fp64 = 0;
+    unsigned long long c_arays = 0, c_ahits = 0, c_alay = 0;
 
     for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
         int64_t point, i0, i1;
@@ -397,10 +404,16 @@ __global__ void __launch_bounds__(128) k_trace_bwd(SceneDev sc, const double* __
                 if (m < 0) break;
                 bool u64;
                 mirror_event<MODE, true>(sc, *pl, s_thk, s_slot, sp, WG, r, m, tape, &nt, &u64);
+                c_lay += (unsigned long long)pl->nlay[m];
+                c_fp64 += u64 ? 1ull : 0ull;
             }
+            c_rays += 1;
+            c_ev += (unsigned long long)r.nev;
+            c_hits += (unsigned long long)r.nprma;
             if (o.cat != CAT_EYEBOX) continue;
             const double gscale = g_bins[o.bin] / (double)sc.N;
             if (gscale == 0.0) continue;
+            c_arays += 1;
             cd lam[3] = { r.e[0], r.e[1], r.e[2] };
             for (int k = nt - 1; k >= 0; --k) {
                 const double* b = tape.base + (int64_t)k * kTapeStride * tape.ts;
@@ -441,6 +454,8 @@ __global__ void __launch_bounds__(128) k_trace_bwd(SceneDev sc, const double* __
                     tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl->nlay[m], front, sp, WG,
                                 sc.slot_complex, pl->k0, kappa * kappa, pl->nsq, q0, pl->ng * pl->ng / q0,
                                 refl, Gs, Gp, gw + m * sc.Lmax, chk, nthreads);
+                    c_ahits += 1;
+                    c_alay += (unsigned long long)pl->nlay[m];
                 } else {
                     s_basis(dx, dy, dz, 0.0, 0.0, 1.0, sv);
                     cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
@@ -469,6 +484,12 @@ __global__ void __launch_bounds__(128) k_trace_bwd(SceneDev sc, const double* __
             out[k] = acc;
         }
     }
+    const unsigned long long cnt[9] = { c_rays, c_ev, c_hits, c_fp64, 0ull, c_lay, c_arays, c_ahits, c_alay };
+    for (int k = 0; k < 9; ++k)
+        if (cnt[k]) atomicAdd(&s_st[k], cnt[k]);
+    __syncthreads();
+    for (int k = tid; k < 9; k += WG)
+        if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
 }
 
 // Sum per-item partial gradients in item order: grad[d][k] = sum_items(d) partial[item][k].
@@ -701,20 +722,20 @@ hipError_t launch_trace_fwd(const SceneDev& sc, int wg, bool lds_bins, uint64_t*
     return hipGetLastError();
 }
 
-hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI,
+hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI, unsigned long long* stats,
                             double* partial, double* scratch, int64_t sample_stride, hipStream_t s)
 {
     size_t sm = bwd_smem_bytes(sc, wg);
     dim3 grid((unsigned)grid_blocks), block(wg);
     switch (sc.precision) {
     case GWG_FP64:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP64>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride);
+        hipLaunchKernelGGL(k_trace_bwd<GWG_FP64>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, stats);
         break;
     case GWG_FP32_MIXED:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride);
+        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, stats);
         break;
     default:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride);
+        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, stats);
         break;
     }
     return hipGetLastError();

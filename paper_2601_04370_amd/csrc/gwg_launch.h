@@ -18,7 +18,7 @@ size_t tmm_smem_bytes(int L, int n_slots, int wg);
 hipError_t launch_trace_fwd(const SceneDev& sc, int wg, bool lds_bins, uint64_t* q, uint32_t* c,
                             unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
                             hipStream_t s);
-hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI,
+hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI, unsigned long long* stats,
                             double* partial, double* scratch, int64_t sample_stride, hipStream_t s);
 hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D,
                               double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s);

@@ -78,14 +78,16 @@ class RayRecord(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("rays", C.c_int64), ("interactions", C.c_int64), ("prma_hits", C.c_int64),
-                ("fp64_hits", C.c_int64), ("saturated", C.c_int64), ("n_cat", C.c_int64 * 8),
+                ("layer_steps", C.c_int64), ("fp64_hits", C.c_int64), ("saturated", C.c_int64),
+                ("adjoint_rays", C.c_int64), ("adjoint_hits", C.c_int64),
+                ("adjoint_layer_steps", C.c_int64), ("n_cat", C.c_int64 * 8),
                 ("power", C.c_double * 8)]
 
     def as_dict(self):
-        return dict(rays=self.rays, interactions=self.interactions, prma_hits=self.prma_hits,
-                    fp64_hits=self.fp64_hits, saturated=self.saturated,
-                    n_cat={CAT_NAMES[k]: self.n_cat[k] for k in range(7)},
-                    power={CAT_NAMES[k]: self.power[k] for k in range(7)})
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("n_cat", "power")}
+        d["n_cat"] = {CAT_NAMES[k]: self.n_cat[k] for k in range(7)}
+        d["power"] = {CAT_NAMES[k]: self.power[k] for k in range(7)}
+        return d
 
 
 class Tuning(C.Structure):
@@ -118,7 +120,8 @@ def load_library(path: str = LIB_PATH):
     L.gwg_trace_forward.argtypes = [C.c_void_p, C.POINTER(Slab), C.POINTER(Prma), C.POINTER(Materials),
                                     C.POINTER(Stacks), C.POINTER(Rays), C.c_uint64, C.c_uint64, C.c_int32,
                                     C.POINTER(Eyebox), C.c_void_p, C.c_int64, C.POINTER(Stats), C.c_void_p]
-    L.gwg_trace_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    L.gwg_trace_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Stats),
+                                     C.c_void_p]
     L.gwg_loss.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                            C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
     L.gwg_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
@@ -310,15 +313,19 @@ class Context:
             self._check(rc)
         return q, c, irr, rec, (sts.as_dict() if sts is not None else None)
 
-    def trace_backward(self, dLdI, scene: SceneSpec, sample_stride: int = 1):
+    def trace_backward(self, dLdI, scene: SceneSpec, sample_stride: int = 1, stats: bool = False):
+        """dL/dthk [D][M][Lmax] for dL/dI of the last forward (and a stats dict if asked)."""
         torch = self.torch
         dev = torch.device("cuda", self.device)
         dLdI = dLdI.to(dev, torch.float64).contiguous()
         if dLdI.numel() != int(np.prod(scene.shape)):
             raise GwgError(GWG_E_INVAL, f"dL/dI has {dLdI.numel()} elements, the eyebox has {int(np.prod(scene.shape))}")
         grad = torch.empty(scene.thk_shape, dtype=torch.float64, device=dev)
+        sts = Stats() if stats else None
         self._check(self.lib.gwg_trace_backward(self.h, dLdI.data_ptr(), grad.data_ptr(), int(sample_stride),
-                                                _stream(torch, dev)))
+                                                C.byref(sts) if sts is not None else None, _stream(torch, dev)))
+        if stats:
+            return grad, sts.as_dict()
         return grad
 
     def loss(self, irr, kind: int = 0, w_f: float = 1.0, w_e: float = 1.0, want_grad: bool = True):
