@@ -209,9 +209,10 @@ WORKLOADS = {
     "fwd_scale": _cfg(
         2, name="fwd_scale", n_mirrors=6, n_layers=40, thk_range=(0.0, 250.0),
         rays_per_point=500_000, bins=(32, 32)),
+    # 8192 rays per (wavelength, FoV) point: about 1e8 ray-surface interactions per step
     "diff_1200": _cfg(
         3, name="diff_1200", n_mirrors=6, n_layers=200, thk_range=(0.0, 300.0),
-        rays_per_point=4096, bins=(32, 32)),
+        rays_per_point=8192, bins=(32, 32)),
     "precision_ag": _cfg(
         4, name="precision_ag", n_mirrors=6, n_layers=200, thk_range=(0.0, 300.0),
         ag_layer_at=100, rays_per_point=4096, bins=(32, 32)),

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gwg.h"
+#include "gwg.h"
 #include "gwg_internal.h"
 #include "gwg_launch.h"
 
@@ -584,9 +584,7 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     // persistent grid: two workgroups per CU (the kernel is register-bound)
     int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * 2);
     const int ML = sc.M * sc.Lmax;
-    const int64_t n_chk = sc.Lmax / kSeg + 1;
-    const int64_t lane_doubles = (int64_t)sc.Kmax * kTapeStride + n_chk * 8;
-    HIP_CHECK(c, c->scratch.ensure(sizeof(double) * lane_doubles * grid * wg), "alloc adjoint scratch");
+    HIP_CHECK(c, c->scratch.ensure(sizeof(double) * (size_t)bwd_scratch_doubles(sc, grid, wg)), "alloc adjoint scratch");
     HIP_CHECK(c, c->partial.ensure(sizeof(double) * (size_t)sc.n_items * ML), "alloc partial gradients");
     HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");

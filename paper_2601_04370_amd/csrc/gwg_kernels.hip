@@ -342,155 +342,7 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
         if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
 }
 
-// ======================================================== adjoint kernel
-// Persistent workgroups walk the work items with a fixed stride (static
-// assignment, so the floating-point summation order never depends on
-// scheduling).  Per ray: pass A regenerates the sampled path (same Philox
-// words, same geometry) and records a tape of its events; if the ray lands
-// in a bin with nonzero dL/dI, pass B walks the tape backwards carrying the
-// adjoint field, and at every mirror hit runs the adjoint thin-film solve,
-// adding d w / d t_j into the wave's private LDS row for that mirror.  At the
-// end of a work item the waves' rows are summed in wave order into the
-// item's partial gradient.
-template <int MODE>
-__global__ void __launch_bounds__(128) k_trace_bwd(SceneDev sc, const double* __restrict__ dLdI,
-                                                   double* __restrict__ partial,
-                                                   double* __restrict__ scratch, int64_t sample_stride,
-                                                   unsigned long long* __restrict__ stats)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int WG = blockDim.x;
-    const int n_waves = (WG + 63) / 64;
-    const int B = sc.bins_x * sc.bins_y;
-    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, false, n_waves);
-    PointLds* pl = (PointLds*)(smem + lay.off_pl);
-    double* s_thk = (double*)(smem + lay.off_thk);
-    uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
-    double* s_sp = (double*)(smem + lay.off_sp);
-    double* s_grad = (double*)(smem + lay.off_grad);
-    const int tid = threadIdx.x;
-    const int wave = tid / 64;
-    const int ML = sc.M * sc.Lmax;
-    double* gw = s_grad + (int64_t)wave * ML;
-    double* sp = s_sp + tid;
-    const int64_t nthreads = (int64_t)gridDim.x * WG;
-    const int64_t gtid = (int64_t)blockIdx.x * WG + tid;
-    TapeRef tape = { scratch + gtid, nthreads };
-    double* chk = scratch + (int64_t)sc.Kmax * kTapeStride * nthreads + gtid;
-    unsigned long long* s_st = (unsigned long long*)(smem + lay.off_st);
-    for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
-    unsigned long long c_rays = 0, c_ev = 0, c_hits = 0, c_lay = 0, c_fp64 = 0;
-    unsigned long long c_arays = 0, c_ahits = 0, c_alay = 0;
-
-    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
-        int64_t point, i0, i1;
-        int d, l, f;
-        decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
-        __syncthreads();
-        stage_point(sc, d, l, f, pl, s_thk, s_slot);
-        for (int k = tid; k < n_waves * ML; k += WG) s_grad[k] = 0.0;
-        __syncthreads();
-        const int64_t base = point * sc.N;
-        const double* g_bins = dLdI + point * B;
-        for (int64_t i = i0 + tid; i < i1; i += WG) {
-            const int64_t id = base + i;
-            if (sample_stride > 1 && (id % sample_stride) != 0) continue;
-            Ray r;
-            ray_birth(sc, *pl, id, r);
-            int nt = 0;
-            Outcome o;
-            for (;;) {
-                int m = advance<true>(sc, *pl, r, o, tape, &nt);
-                if (m < 0) break;
-                bool u64;
-                mirror_event<MODE, true>(sc, *pl, s_thk, s_slot, sp, WG, r, m, tape, &nt, &u64);
-                c_lay += (unsigned long long)pl->nlay[m];
-                c_fp64 += u64 ? 1ull : 0ull;
-            }
-            c_rays += 1;
-            c_ev += (unsigned long long)r.nev;
-            c_hits += (unsigned long long)r.nprma;
-            if (o.cat != CAT_EYEBOX) continue;
-            const double gscale = g_bins[o.bin] / (double)sc.N;
-            if (gscale == 0.0) continue;
-            c_arays += 1;
-            cd lam[3] = { r.e[0], r.e[1], r.e[2] };
-            for (int k = nt - 1; k >= 0; --k) {
-                const double* b = tape.base + (int64_t)k * kTapeStride * tape.ts;
-                const int64_t ts = tape.ts;
-                double dx = b[0], dy = b[ts], dz = b[2 * ts];
-                cd E[3];
-                for (int c = 0; c < 3; ++c) E[c] = mk(b[(3 + 2 * c) * ts], b[(4 + 2 * c) * ts]);
-                cd cs = mk(b[9 * ts], b[10 * ts]), cp = mk(b[11 * ts], b[12 * ts]);
-                double scale = b[13 * ts];
-                int meta = (int)b[14 * ts];
-                int type = meta & 15, m = (meta >> 4) & 255;
-                bool front = (meta >> 12) & 1, refl = (meta >> 13) & 1;
-                double sv[3], pin[3], pout[3];
-                if (type == EV_MIRROR) {
-                    s_basis(dx, dy, dz, sc.nx, 0.0, sc.nz, sv);
-                    cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
-                    double ndx = dx, ndz = dz;
-                    if (refl) mirror_reflect(sc.nx, sc.nz, dx, dz, &ndx, &ndz);
-                    cross3(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
-                    // holomorphic sensitivities of w = |E_K|^2 to this event's coefficients
-                    cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
-                    cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
-                    cd es = cadd(cadd(cscale(E[0], sv[0]), cscale(E[1], sv[1])), cscale(E[2], sv[2]));
-                    cd ep = cadd(cadd(cscale(E[0], pin[0]), cscale(E[1], pin[1])), cscale(E[2], pin[2]));
-                    cd Gs = cscale(cmul(cconj(ls), es), scale * gscale);
-                    cd Gp = cscale(cmul(cconj(lp), ep), scale * gscale);
-                    double c[3];
-                    cross3(dx, dy, dz, sc.nx, 0.0, sc.nz, c);
-                    double kappa = pl->ng * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-                    for (int s = 0; s < sc.n_slots; ++s) {
-                        double P[NPF];
-                        slot_params(pl->slotN[2 * s], pl->slotN[2 * s + 1], kappa, pl->k0, P);
-#pragma unroll
-                        for (int p = 0; p < NPF; ++p) sp[(s * NPF + p) * WG] = P[p];
-                    }
-                    double z0 = pl->ng * pl->ng - kappa * kappa;
-                    double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
-                    tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl->nlay[m], front, sp, WG,
-                                sc.slot_complex, pl->k0, kappa * kappa, pl->nsq, q0, pl->ng * pl->ng / q0,
-                                refl, Gs, Gp, gw + m * sc.Lmax, chk, nthreads);
-                    c_ahits += 1;
-                    c_alay += (unsigned long long)pl->nlay[m];
-                } else {
-                    s_basis(dx, dy, dz, 0.0, 0.0, 1.0, sv);
-                    cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
-                    if (type == EV_TIR) {
-                        cross3(dx, dy, -dz, sv[0], sv[1], sv[2], pout);
-                    } else {
-                        Ray tmp; tmp.dx = dx; tmp.dy = dy; tmp.dz = dz;
-                        double st2 = (pl->ng * pl->ng) * (dx * dx + dy * dy);
-                        double a[3];
-                        exit_direction(pl->ng, pl->na, tmp, st2, a);
-                        cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
-                    }
-                }
-                // lambda <- A^H lambda,  A = scale (cs s s^T + cp p_out p_in^T)
-                cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
-                cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
-                cd as = cscale(cmul(cconj(cs), ls), scale), ap = cscale(cmul(cconj(cp), lp), scale);
-                for (int c = 0; c < 3; ++c) lam[c] = cadd(cscale(as, sv[c]), cscale(ap, pin[c]));
-            }
-        }
-        __syncthreads();
-        double* out = partial + item * (int64_t)ML;
-        for (int k = tid; k < ML; k += WG) {
-            double acc = 0.0;
-            for (int w = 0; w < n_waves; ++w) acc += s_grad[(int64_t)w * ML + k];
-            out[k] = acc;
-        }
-    }
-    const unsigned long long cnt[9] = { c_rays, c_ev, c_hits, c_fp64, 0ull, c_lay, c_arays, c_ahits, c_alay };
-    for (int k = 0; k < 9; ++k)
-        if (cnt[k]) atomicAdd(&s_st[k], cnt[k]);
-    __syncthreads();
-    for (int k = tid; k < 9; k += WG)
-        if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
-}
+#include "gwg_bwd_kernel.h"
 
 // Sum per-item partial gradients in item order: grad[d][k] = sum_items(d) partial[item][k].
 __global__ void k_grad_reduce(const double* __restrict__ partial, int64_t items_per_design, int ML,

@@ -2,7 +2,7 @@
 // the host API only.
 #pragma once
 #include <hip/hip_runtime.h>
-#include "../../include/gwg.h"
+#include "gwg.h"
 #include "gwg_internal.h"
 
 namespace gwg {
@@ -14,6 +14,7 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 size_t fwd_smem_bytes(const SceneDev& sc, int wg, bool lds_bins);
 size_t bwd_smem_bytes(const SceneDev& sc, int wg);
 size_t tmm_smem_bytes(int L, int n_slots, int wg);
+int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
 hipError_t launch_trace_fwd(const SceneDev& sc, int wg, bool lds_bins, uint64_t* q, uint32_t* c,
                             unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
