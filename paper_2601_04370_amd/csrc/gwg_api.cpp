@@ -60,7 +60,7 @@ struct gwg_ctx {
     DevBuf lam_tab, dir_tab, slot, nlay;
     std::vector<int32_t> h_nlay;
     // per-call buffers
-    DevBuf stats, partial, scratch, loss_work;
+    DevBuf stats, partial, scratch, fwd_scratch, loss_work;
     // thin-film queries
     DevBuf tmm_tab, tmm_slot;
     // last forward
@@ -423,7 +423,7 @@ int gwg_destroy(gwg_ctx* c)
     {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch,
+        for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot })
             b->release();
     }
@@ -547,12 +547,16 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     if (fwd_smem_bytes(sc, wg, lds_bins) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
     if (sc.n_items > 0x7fffffff) return fail(c, GWG_E_INVAL, "too many work items; raise rays_per_block");
     const int64_t nbins = (int64_t)sc.D * sc.n_lsel * sc.F * B;
+    // persistent grid: as many workgroups as fit on the device at once
+    const int per_cu = trace_blocks_per_cu(false, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
+    const int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * per_cu);
+    HIP_CHECK(c, c->fwd_scratch.ensure(sizeof(double) * (size_t)fwd_scratch_doubles(sc, grid, wg)), "alloc hit queues");
     HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
     HIP_CHECK(c, launch_fill_u64(out->q_bins, nbins, 0, s), "zero bins");
     HIP_CHECK(c, launch_fill_u32(out->counts, nbins, 0, s), "zero counts");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
-    HIP_CHECK(c, launch_trace_fwd(sc, wg, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
-                                  records, record_stride, s),
+    HIP_CHECK(c, launch_trace_fwd(sc, wg, (int)grid, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
+                                  records, record_stride, (double*)c->fwd_scratch.p, s),
               "forward kernel");
     if (out->irradiance)
         HIP_CHECK(c, launch_irradiance(out->q_bins, nbins, std::ldexp(1.0, -out->fp_shift) / (double)sc.N, out->irradiance, s),
@@ -581,8 +585,9 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     const int wg = pick_bwd_wg(c, sc);
     set_tiles(sc, c->tune.bwd_rays_per_block, wg, c->n_cu);
     if (bwd_smem_bytes(sc, wg) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
-    // persistent grid: two workgroups per CU (the kernel is register-bound)
-    int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * 2);
+    // persistent grid: as many workgroups as fit on the device at once
+    const int per_cu = trace_blocks_per_cu(true, sc.precision, wg, bwd_smem_bytes(sc, wg));
+    const int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * per_cu);
     const int ML = sc.M * sc.Lmax;
     HIP_CHECK(c, c->scratch.ensure(sizeof(double) * (size_t)bwd_scratch_doubles(sc, grid, wg)), "alloc adjoint scratch");
     HIP_CHECK(c, c->partial.ensure(sizeof(double) * (size_t)sc.n_items * ML), "alloc partial gradients");

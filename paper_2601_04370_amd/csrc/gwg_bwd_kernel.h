@@ -28,22 +28,6 @@
 
 constexpr int kQFields = 6;      // kappa, Gs.re, Gs.im, Gp.re, Gp.im, meta
 
-__device__ inline int wave_lane() { return (int)(threadIdx.x & 63); }
-
-// Exclusive prefix sum over the 64 lanes of a wave; *total gets the sum.
-__device__ inline int wave_excl_scan(int x, int* total)
-{
-    const int lane = wave_lane();
-    int v = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(v, o, 64);
-        if (lane >= o) v += y;
-    }
-    *total = __shfl(v, 63, 64);
-    return v - x;
-}
-
 struct Queue {
     double* base;      // this wave's queue, field f of slot p at base[f * cap + p]
     int cap;
@@ -116,8 +100,11 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     const int64_t n_chk = sc.Lmax / kSeg + 1;
     double* chk = scratch + (int64_t)sc.Kmax * kTapeStride * nthreads + gtid;
     const int qcap = 64 * (sc.Kmax + 1);
-    Queue q = { scratch + ((int64_t)sc.Kmax * kTapeStride + n_chk * 8) * nthreads + gwave * (int64_t)kQFields * qcap,
-                qcap };
+    const int64_t n_waves_total = (int64_t)gridDim.x * n_waves;
+    double* qbase = scratch + ((int64_t)sc.Kmax * kTapeStride + n_chk * 8) * nthreads;
+    Queue q = { qbase + gwave * (int64_t)kQFields * qcap, qcap };
+    const int hcap = 64 * sc.Kmax;
+    const HitQueue hq = { qbase + n_waves_total * (int64_t)kQFields * qcap + gwave * (int64_t)kHitFields * hcap, hcap };
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long c_rays = 0, c_ev = 0, c_hits = 0, c_lay = 0, c_fp64 = 0;
     unsigned long long c_arays = 0, c_ahits = 0, c_alay = 0;
@@ -144,16 +131,25 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             o.cat = CAT_LOST;
             o.bin = -1;
             int nt = 0;
+            TapeRef none = { nullptr, 0 };
+            int nh = 0;
             if (active) {
                 ray_birth(sc, *pl, id, r);
-                for (;;) {
-                    int m = advance<true>(sc, *pl, r, o, tape, &nt);
-                    if (m < 0) break;
-                    bool u64;
-                    mirror_event<MODE, true>(sc, *pl, s_thk, s_slot, sp, WG, r, m, tape, &nt, &u64);
-                    c_lay += (unsigned long long)pl->nlay[m];
-                    c_fp64 += u64 ? 1ull : 0ull;
-                }
+                walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
+                nh = r.nprma;
+            }
+            int htotal;
+            const int hoff = wave_excl_scan(nh, &htotal);
+            if (active) {
+                ray_birth(sc, *pl, id, r);
+                walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, hoff }, NoCoef{}, none, nullptr);
+            }
+            __threadfence_block();
+            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sp, WG, hq, htotal, &c_fp64, &c_lay);
+            __threadfence_block();
+            if (active) {
+                ray_birth(sc, *pl, id, r);
+                walk_ray<true, true>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, hoff }, tape, &nt);
                 c_rays += 1;
                 c_ev += (unsigned long long)r.nev;
                 c_hits += (unsigned long long)r.nprma;
@@ -217,6 +213,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
                 }
             }
             qcount += total;
+            __threadfence_block();
             // phase 2: drain full batches
             while (qcount >= 64) {
                 adjoint_entry(sc, *pl, s_thk, s_slot, sp, WG, gw, q, qhead + lane, chk, nthreads);
@@ -257,5 +254,6 @@ int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg)
     const int64_t nthreads = grid_blocks * wg;
     const int64_t n_chk = sc.Lmax / kSeg + 1;
     const int64_t n_waves = grid_blocks * ((wg + 63) / 64);
-    return ((int64_t)sc.Kmax * kTapeStride + n_chk * 8) * nthreads + n_waves * (int64_t)kQFields * 64 * (sc.Kmax + 1);
+    return ((int64_t)sc.Kmax * kTapeStride + n_chk * 8) * nthreads
+           + n_waves * ((int64_t)kQFields * 64 * (sc.Kmax + 1) + (int64_t)kHitFields * 64 * sc.Kmax);
 }

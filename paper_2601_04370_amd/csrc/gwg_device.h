@@ -154,6 +154,113 @@ __device__ inline void sincos_cw(float x, float* s, float* c)
     *c = ((q + 1) & 2) ? -co : co;
 }
 
+// Circular or hyperbolic cosine and sine of a >= 0 with one shared
+// polynomial.  With u = -r^2 (circular) or +r^2 (hyperbolic),
+//     sin r or sinh r = r (1 + u/3! + u^2/5! + ...),
+//     cos r or cosh r = 1 + u/2! + u^2/4! + ...,
+// so the dominant Horner evaluation is common to lanes of either kind and a
+// wave that mixes propagating and evanescent layers executes it once.
+// Circular: r = a - n pi/2 (two-term Cody-Waite), then a quadrant rotation.
+// Hyperbolic: r = a / 2^k <= pi/4, then k doublings
+// (sinh 2r = 2 sinh r cosh r, cosh 2r = cosh^2 r + sinh^2 r).
+// Truncation as for sincos_cw (degree 15/16 in f64, 9/10 in f32).
+__device__ inline void gtrig(double a, bool hyper, double* C, double* S)
+{
+#pragma clang fp contract(fast)
+    const double two_over_pi = 0.63661977236758134308;
+    const double pio2_hi = 1.5707963267948966;
+    const double pio2_lo = 6.123233995736766e-17;
+    double n = rint(a * two_over_pi);
+    double r = fma(-n, pio2_hi, a);
+    r = fma(-n, pio2_lo, r);
+    int k = 0;
+    if (hyper) {
+        // smallest k with a / 2^k <= pi/4 (a is finite and moderate)
+        int e;
+        frexp(a * 1.2732395447351628, &e);      // a / (pi/4) = m 2^e, m in [0.5, 1)
+        k = e > 0 ? e : 0;
+        r = ldexp(a, -k);
+    }
+    double u = hyper ? r * r : -(r * r);
+    double ps = inv_fact(15);
+    ps = fma(ps, u, inv_fact(13));
+    ps = fma(ps, u, inv_fact(11));
+    ps = fma(ps, u, inv_fact(9));
+    ps = fma(ps, u, inv_fact(7));
+    ps = fma(ps, u, inv_fact(5));
+    ps = fma(ps, u, inv_fact(3));
+    double sn = fma(r * u, ps, r);
+    double pc = inv_fact(16);
+    pc = fma(pc, u, inv_fact(14));
+    pc = fma(pc, u, inv_fact(12));
+    pc = fma(pc, u, inv_fact(10));
+    pc = fma(pc, u, inv_fact(8));
+    pc = fma(pc, u, inv_fact(6));
+    pc = fma(pc, u, inv_fact(4));
+    pc = fma(pc, u, inv_fact(2));
+    double cs = fma(u, pc, 1.0);
+    if (!hyper) {
+        int q = (int)n & 3;
+        double so = (q & 1) ? cs : sn;
+        double co = (q & 1) ? sn : cs;
+        *S = (q & 2) ? -so : so;
+        *C = ((q + 1) & 2) ? -co : co;
+    } else {
+        for (int i = 0; i < k; ++i) {
+            double s2 = 2.0 * sn * cs;
+            cs = fma(cs, cs, sn * sn);
+            sn = s2;
+        }
+        *S = sn;
+        *C = cs;
+    }
+}
+
+__device__ inline void gtrig(float a, bool hyper, float* C, float* S)
+{
+#pragma clang fp contract(fast)
+    const float two_over_pi = 0.636619772f;
+    const float pio2_hi = 1.57079637f;
+    const float pio2_lo = -4.37113883e-8f;
+    float n = rintf(a * two_over_pi);
+    float r = fmaf(-n, pio2_hi, a);
+    r = fmaf(-n, pio2_lo, r);
+    int k = 0;
+    if (hyper) {
+        int e;
+        frexpf(a * 1.27323954f, &e);
+        k = e > 0 ? e : 0;
+        r = ldexpf(a, -k);
+    }
+    float u = hyper ? r * r : -(r * r);
+    float ps = (float)inv_fact(9);
+    ps = fmaf(ps, u, (float)inv_fact(7));
+    ps = fmaf(ps, u, (float)inv_fact(5));
+    ps = fmaf(ps, u, (float)inv_fact(3));
+    float sn = fmaf(r * u, ps, r);
+    float pc = (float)inv_fact(10);
+    pc = fmaf(pc, u, (float)inv_fact(8));
+    pc = fmaf(pc, u, (float)inv_fact(6));
+    pc = fmaf(pc, u, (float)inv_fact(4));
+    pc = fmaf(pc, u, (float)inv_fact(2));
+    float cs = fmaf(u, pc, 1.0f);
+    if (!hyper) {
+        int q = (int)n & 3;
+        float so = (q & 1) ? cs : sn;
+        float co = (q & 1) ? sn : cs;
+        *S = (q & 2) ? -so : so;
+        *C = ((q + 1) & 2) ? -co : co;
+    } else {
+        for (int i = 0; i < k; ++i) {
+            float s2 = 2.0f * sn * cs;
+            cs = fmaf(cs, cs, sn * sn);
+            sn = s2;
+        }
+        *S = sn;
+        *C = cs;
+    }
+}
+
 // cosh and sinh of x >= 0 from expm1 (no cancellation for small x)
 __device__ inline void coshsinh(double x, double* ch, double* sh)
 {
@@ -247,11 +354,8 @@ __device__ inline void step_cplx(V2<T>& v, CTv<T> C, CTv<T> X, CTv<T> Y)
 template <typename T>
 __device__ inline void layer_cs(T kq, T t, T* C, T* S)
 {
-    if (kq >= (T)0) {
-        sincos_cw(kq * t, S, C);
-    } else {
-        coshsinh(-kq * t, C, S);
-    }
+    const bool hyper = kq < (T)0;
+    gtrig(hyper ? -kq * t : kq * t, hyper, C, S);
 }
 
 // Entries of an absorbing layer: returns C, X_s, Y_s, X_p, Y_p.
@@ -323,8 +427,7 @@ __device__ inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t*
     int es = 0, ep = 0;
     for (int j = 0; j < L; ++j) {
         int idx = front ? (L - 1 - j) : j;
-        T t = (T)thk[idx];
-        if (t == (T)0) continue;            // identity matrix
+        T t = (T)thk[idx];                  // t = 0 gives the identity exactly
         int s = slot[idx];
         const double* P = sp + s * NPF * ls;
         if (!((cplx_mask >> s) & 1u)) {

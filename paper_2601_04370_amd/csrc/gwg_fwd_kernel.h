@@ -1,0 +1,200 @@
+// Forward trace kernel.  Included by gwg_kernels.hip inside namespace gwg.
+//
+// Two-pass intersection (Methods, memory-saving strategies): the path of a
+// ray (surfaces, branch decisions) does not depend on the coatings, so each
+// wave processes its rays in rounds of one ray per lane:
+//   1. a geometry-only walk counts each ray's mirror hits; a wave prefix sum
+//      gives each ray a contiguous range of the wave's hit queue;
+//   2. a second geometry-only walk writes each hit's kappa, mirror and side;
+//   3. the hits are solved in batches of 64, one per lane, so every lane of
+//      the wave runs the same layer loop whatever the path lengths;
+//   4. a third walk replays the path with the polarization field, taking the
+//      coefficients from the queue, and scatters into the eyebox bins.
+// Walks are cheap next to the thin-film solves (a few hundred operations per
+// event against tens of thousands per hit).
+
+// Thin-film coefficients of one hit for this lane (fills the lane's slot table).
+template <int MODE>
+__device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
+                                  const uint8_t* s_slot, double* sp, int ls, int m, bool front, double kappa,
+                                  bool* used_fp64)
+{
+    for (int s = 0; s < sc.n_slots; ++s) {
+        double P[NPF];
+        slot_params(pl.slotN[2 * s], pl.slotN[2 * s + 1], kappa, pl.k0, P);
+#pragma unroll
+        for (int p = 0; p < NPF; ++p) sp[(s * NPF + p) * ls] = P[p];
+    }
+    const double z0 = pl.ng * pl.ng - kappa * kappa;
+    const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
+    const double eta0s = q0, eta0p = pl.ng * pl.ng / q0;
+    const int L = pl.nlay[m];
+    const double* thk = s_thk + m * sc.Lmax;
+    const uint8_t* slot = s_slot + m * sc.Lmax;
+    const bool fp64 = (MODE == GWG_FP64) || (MODE == GWG_FP32_MIXED && near_critical(pl, sc.n_slots, kappa));
+    *used_fp64 = fp64;
+    if (fp64)
+        return tmm_solve<double>(thk, slot, L, front, sp, ls, sc.slot_complex, pl.k0, eta0s, eta0p,
+                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
+    return tmm_solve<float>(thk, slot, L, front, sp, ls, sc.slot_complex, pl.k0, eta0s, eta0p,
+                            mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
+}
+
+// Solve queue entries [0, total) in batches of 64 (one per lane).
+template <int MODE>
+__device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
+                                  const uint8_t* s_slot, double* sp, int ls, const HitQueue& hq, int total,
+                                  unsigned long long* n_fp64, unsigned long long* n_lay)
+{
+    const int lane = wave_lane();
+    for (int b = 0; b < total; b += 64) {
+        const int p = b + lane;
+        if (p < total) {
+            const double kappa = hq.kappa(p);
+            const int meta = hq.meta(p);
+            const int m = meta & 255;
+            bool u64 = false;
+            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sp, ls, m, (meta >> 8) & 1, kappa, &u64);
+            hq.put_coef(p, c);
+            *n_fp64 += u64 ? 1ull : 0ull;
+            *n_lay += (unsigned long long)pl.nlay[m];
+        }
+    }
+}
+
+struct NoHit {
+    __device__ void operator()(int, double, int) const {}
+};
+struct NoCoef {
+    __device__ Coef4 operator()(int) const { Coef4 c; c.rs = c.rp = c.ts = c.tp = mk(0.0, 0.0); return c; }
+};
+struct PutHit {
+    HitQueue q;
+    int off;
+    __device__ void operator()(int h, double kappa, int meta) const { q.put(off + h, kappa, meta); }
+};
+struct GetCoef {
+    HitQueue q;
+    int off;
+    __device__ Coef4 operator()(int h) const { return q.coef(off + h); }
+};
+
+// Persistent workgroups walk the work items with a fixed stride; each wave
+// handles a strided share of the item's rays.  Eyebox bins of the current
+// point accumulate in LDS (integer atomics) and are flushed per item with
+// integer global atomics: the result does not depend on scheduling.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __restrict__ q_out,
+                                                   uint32_t* __restrict__ c_out,
+                                                   unsigned long long* __restrict__ stats,
+                                                   gwg_ray_record* __restrict__ rec, int64_t rec_stride,
+                                                   int lds_bins, double* __restrict__ scratch)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int B = sc.bins_x * sc.bins_y;
+    const int WG = blockDim.x;
+    const int n_waves = WG / 64;
+    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, lds_bins != 0, 0);
+    PointLds* pl = (PointLds*)(smem + lay.off_pl);
+    double* s_thk = (double*)(smem + lay.off_thk);
+    uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
+    double* s_sp = (double*)(smem + lay.off_sp);
+    unsigned long long* s_q = (unsigned long long*)(smem + lay.off_q);
+    uint32_t* s_c = (uint32_t*)(smem + lay.off_c);
+    unsigned long long* s_st = (unsigned long long*)(smem + lay.off_st);
+    const int tid = threadIdx.x, wave = tid / 64, lane = wave_lane();
+    const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
+    const int cap = 64 * sc.Kmax;
+    const HitQueue hq = { scratch + gwave * (int64_t)kHitFields * cap, cap };
+    double* sp = s_sp + tid;
+    const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
+    for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
+    unsigned long long n_fp64 = 0, n_lay = 0;
+
+    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+        int64_t point, i0, i1;
+        int d, l, f;
+        decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
+        __syncthreads();
+        stage_point(sc, d, l, f, pl, s_thk, s_slot);
+        if (lds_bins)
+            for (int k = tid; k < B; k += WG) { s_q[k] = 0ull; s_c[k] = 0u; }
+        __syncthreads();
+        const int64_t base = point * sc.N;
+        uint64_t* gq = q_out + point * B;
+        uint32_t* gc = c_out + point * B;
+        for (int64_t round = 0;; ++round) {
+            const int64_t wave_first = i0 + (int64_t)wave * 64 + round * WG;
+            if (wave_first >= i1) break;                  // uniform across the wave
+            const int64_t i = wave_first + lane;
+            const bool active = i < i1;
+            const int64_t id = base + i;
+            Ray r;
+            Outcome o;
+            TapeRef none = { nullptr, 0 };
+            int nh = 0;
+            if (active) {
+                ray_birth(sc, *pl, id, r);
+                walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
+                nh = r.nprma;
+            }
+            int total;
+            const int off = wave_excl_scan(nh, &total);
+            if (active) {
+                ray_birth(sc, *pl, id, r);
+                walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, off }, NoCoef{}, none, nullptr);
+            }
+            __threadfence_block();
+            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sp, WG, hq, total, &n_fp64, &n_lay);
+            __threadfence_block();
+            if (active) {
+                ray_birth(sc, *pl, id, r);
+                walk_ray<true, false>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off }, none, nullptr);
+                atomicAdd(&s_st[ST_RAYS], 1ull);
+                atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
+                atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);
+                atomicAdd(&s_st[ST_CAT + o.cat], 1ull);
+                const double pw = o.w * pscale;
+                atomicAdd(&s_st[ST_POW + o.cat], (unsigned long long)rint(pw < wcap ? pw : wcap));
+                if (o.cat == CAT_EYEBOX || o.cat == CAT_MISS) {
+                    const double pr = (o.w_in - o.w) * pscale;
+                    if (pr > 0.0) atomicAdd(&s_st[ST_POW + CAT_FACE_R], (unsigned long long)rint(pr < wcap ? pr : wcap));
+                }
+                if (o.cat == CAT_EYEBOX) {
+                    double u = o.w * wscale;
+                    if (!(u <= wcap)) { u = (u > wcap) ? wcap : 0.0; atomicAdd(&s_st[ST_SAT], 1ull); }
+                    const unsigned long long qv = (unsigned long long)rint(u);
+                    if (lds_bins) { atomicAdd(&s_q[o.bin], qv); atomicAdd(&s_c[o.bin], 1u); }
+                    else { atomicAdd((unsigned long long*)&gq[o.bin], qv); atomicAdd(&gc[o.bin], 1u); }
+                }
+                if (rec && (id % rec_stride) == 0) {
+                    gwg_ray_record* q = rec + id / rec_stride;
+                    q->bin = o.cat == CAT_EYEBOX ? o.bin : -1;
+                    q->category = o.cat;
+                    q->n_events = r.nev;
+                    q->n_prma = r.nprma;
+                    q->w = o.w;
+                }
+            }
+        }
+        __syncthreads();
+        if (lds_bins) {
+            for (int k = tid; k < B; k += WG) {
+                if (s_c[k]) {
+                    atomicAdd((unsigned long long*)&gq[k], s_q[k]);
+                    atomicAdd(&gc[k], s_c[k]);
+                }
+            }
+        }
+    }
+    if (n_fp64) atomicAdd(&s_st[ST_FP64], n_fp64);
+    if (n_lay) atomicAdd(&s_st[ST_LAYERS], n_lay);
+    __syncthreads();
+    for (int k = tid; k < ST_WORDS; k += WG)
+        if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
+}
+
+int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg)
+{
+    return grid_blocks * (wg / 64) * (int64_t)kHitFields * 64 * sc.Kmax;
+}

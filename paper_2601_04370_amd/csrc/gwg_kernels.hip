@@ -98,250 +98,7 @@ __device__ inline void decode_item(const SceneDev& sc, int64_t item, int64_t* po
     *i1 = e < sc.N ? e : sc.N;
 }
 
-// Per-hit thin-film coefficients for this lane (fills the lane's slot table).
-template <int MODE>
-__device__ inline Coef4 hit_coeffs(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                   const uint8_t* s_slot, double* sp, int ls, int m, bool front,
-                                   double kappa, bool* used_fp64)
-{
-    for (int s = 0; s < sc.n_slots; ++s) {
-        double P[NPF];
-        slot_params(pl.slotN[2 * s], pl.slotN[2 * s + 1], kappa, pl.k0, P);
-#pragma unroll
-        for (int p = 0; p < NPF; ++p) sp[(s * NPF + p) * ls] = P[p];
-    }
-    double z0 = pl.ng * pl.ng - kappa * kappa;
-    double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
-    double eta0s = q0, eta0p = pl.ng * pl.ng / q0;
-    const int L = pl.nlay[m];
-    const double* thk = s_thk + m * sc.Lmax;
-    const uint8_t* slot = s_slot + m * sc.Lmax;
-    bool fp64 = (MODE == GWG_FP64) || (MODE == GWG_FP32_MIXED && near_critical(pl, sc.n_slots, kappa));
-    *used_fp64 = fp64;
-    if (MODE == GWG_FP64)
-        return tmm_solve<double>(thk, slot, L, front, sp, ls, sc.slot_complex, pl.k0, eta0s, eta0p,
-                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
-    if (fp64)
-        return tmm_solve<double>(thk, slot, L, front, sp, ls, sc.slot_complex, pl.k0, eta0s, eta0p,
-                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
-    return tmm_solve<float>(thk, slot, L, front, sp, ls, sc.slot_complex, pl.k0, eta0s, eta0p,
-                            mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
-}
-
-// Tape of one event for the adjoint (double slots of this lane, stride ts).
-struct TapeRef { double* base; int64_t ts; };
-
-__device__ inline void tape_put(TapeRef t, int k, const Ray& r_before, cd cs, cd cp, double scale,
-                                int type, int m, int front, int refl)
-{
-    double* b = t.base + (int64_t)k * kTapeStride * t.ts;
-    b[0] = r_before.dx; b[t.ts] = r_before.dy; b[2 * t.ts] = r_before.dz;
-    for (int c = 0; c < 3; ++c) { b[(3 + 2 * c) * t.ts] = r_before.e[c].re; b[(4 + 2 * c) * t.ts] = r_before.e[c].im; }
-    b[9 * t.ts] = cs.re; b[10 * t.ts] = cs.im; b[11 * t.ts] = cp.re; b[12 * t.ts] = cp.im;
-    b[13 * t.ts] = scale;
-    b[14 * t.ts] = (double)(type | (m << 4) | (front << 12) | (refl << 13));
-}
-
-// Outcome of a terminated ray.
-struct Outcome { int cat; int bin; double w; double w_in; };
-
-// Advance one ray through face events until it hits a mirror (returns the
-// mirror index, event already counted) or terminates (returns -1, fills o).
-template <bool TAPE>
-__device__ inline int advance(const SceneDev& sc, const PointLds& pl, Ray& r, Outcome& o,
-                              TapeRef tape, int* ntape)
-{
-    for (;;) {
-        if (r.nev >= sc.Kmax) { o.cat = CAT_TRUNC; o.bin = -1; o.w = norm2(r.e); o.w_in = o.w; return -1; }
-        int s = next_surface(sc, pl, r);
-        if (s < 0) { o.cat = CAT_LOST; o.bin = -1; o.w = norm2(r.e); o.w_in = o.w; return -1; }
-        r.nev++;
-        if (s == SURF_TOP || s == SURF_BOTTOM) {
-            FaceCoef fc = face_coeffs(pl.ng, pl.na, r.dx, r.dy, r.dz);
-            double sv[3], pin[3], pout[3];
-            s_basis(r.dx, r.dy, r.dz, 0.0, 0.0, 1.0, sv);
-            cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
-            if (fc.tir) {
-                cross3(r.dx, r.dy, -r.dz, sv[0], sv[1], sv[2], pout);
-                if (TAPE) tape_put(tape, (*ntape)++, r, fc.rs, fc.rp, 1.0, EV_TIR, 0, 0, 0);
-                apply_sp(r.e, sv, pin, pout, fc.rs, fc.rp, 1.0);
-                r.dz = -r.dz;
-                r.last = s;
-                continue;
-            }
-            if (s == SURF_TOP) {
-                double a[3];
-                exit_direction(pl.ng, pl.na, r, fc.st2, a);
-                cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
-                o.w_in = norm2(r.e);
-                if (TAPE) tape_put(tape, (*ntape)++, r, fc.ts, fc.tp, fc.flux, EV_EXIT, 0, 0, 0);
-                apply_sp(r.e, sv, pin, pout, fc.ts, fc.tp, fc.flux);
-                r.dx = a[0]; r.dy = a[1]; r.dz = a[2];
-                o.w = norm2(r.e);
-                o.bin = eyebox_bin(sc, r.px, r.py, a);
-                o.cat = o.bin >= 0 ? CAT_EYEBOX : CAT_MISS;
-                return -1;
-            }
-            o.cat = CAT_LEAK; o.bin = -1; o.w = norm2(r.e); o.w_in = o.w;
-            return -1;
-        }
-        if (s == SURF_END0 || s == SURF_END1) {
-            o.cat = CAT_END; o.bin = -1; o.w = norm2(r.e); o.w_in = o.w;
-            return -1;
-        }
-        return s;
-    }
-}
-
-// Mirror event: branch (Eq. 6), Eq. 5 field update, cell bookkeeping.
-template <int MODE, bool TAPE>
-__device__ inline void mirror_event(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                    const uint8_t* s_slot, double* sp, int ls, Ray& r, int m,
-                                    TapeRef tape, int* ntape, bool* used_fp64)
-{
-    const double nx = sc.nx, nz = sc.nz;
-    double dn = nx * r.dx + nz * r.dz;
-    bool front = dn < 0.0;
-    double c[3];
-    cross3(r.dx, r.dy, r.dz, nx, 0.0, nz, c);
-    double kappa = pl.ng * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-    Coef4 co = hit_coeffs<MODE>(sc, pl, s_thk, s_slot, sp, ls, m, front, kappa, used_fp64);
-    int h = r.nprma;
-    if ((h & 3) == 0) {
-        u32x4 w = philox10((uint32_t)(uint64_t)r.id, (uint32_t)((uint64_t)r.id >> 32), (uint32_t)(h >> 2), 1u,
-                           sc.key0, sc.key1);
-        r.w4[0] = w.x; r.w4[1] = w.y; r.w4[2] = w.z; r.w4[3] = w.w;
-    }
-    const int hw = h & 3;
-    uint32_t word = hw == 0 ? r.w4[0] : hw == 1 ? r.w4[1] : hw == 2 ? r.w4[2] : r.w4[3];
-    bool refl = word < pl.thr[m];
-    double ndx = r.dx, ndz = r.dz;
-    if (refl) mirror_reflect(nx, nz, r.dx, r.dz, &ndx, &ndz);
-    double sv[3], pin[3], pout[3];
-    s_basis(r.dx, r.dy, r.dz, nx, 0.0, nz, sv);
-    cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
-    cross3(ndx, r.dy, ndz, sv[0], sv[1], sv[2], pout);
-    cd cs = refl ? co.rs : co.ts;
-    cd cp = refl ? co.rp : co.tp;
-    double scale = refl ? pl.sc_r[m] : pl.sc_t[m];
-    if (TAPE) tape_put(tape, (*ntape)++, r, cs, cp, scale, EV_MIRROR, m, front ? 1 : 0, refl ? 1 : 0);
-    apply_sp(r.e, sv, pin, pout, cs, cp, scale);
-    r.dx = ndx; r.dz = ndz;
-    if (!refl) r.cell += (m == r.cell) ? 1 : -1;
-    r.last = m;
-    r.nprma++;
-}
-
-// ======================================================== forward kernel
-// One workgroup per work item (design, wavelength, FoV point, ray tile).  Each
-// lane traces rays tile_start + lane, + blockDim, ...; a lane whose ray
-// terminates starts its next ray within the same step so that every mirror
-// solve of the wave runs with as many lanes as possible.  Eyebox bins of the
-// point accumulate in LDS (integer atomics) and are flushed with integer
-// global atomics, so results do not depend on scheduling.
-template <int MODE>
-__global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __restrict__ q_out,
-                                                   uint32_t* __restrict__ c_out,
-                                                   unsigned long long* __restrict__ stats,
-                                                   gwg_ray_record* __restrict__ rec, int64_t rec_stride,
-                                                   int lds_bins)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int B = sc.bins_x * sc.bins_y;
-    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, blockDim.x, B, lds_bins != 0, 0);
-    PointLds* pl = (PointLds*)(smem + lay.off_pl);
-    double* s_thk = (double*)(smem + lay.off_thk);
-    uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
-    double* s_sp = (double*)(smem + lay.off_sp);
-    unsigned long long* s_q = (unsigned long long*)(smem + lay.off_q);
-    uint32_t* s_c = (uint32_t*)(smem + lay.off_c);
-    unsigned long long* s_st = (unsigned long long*)(smem + lay.off_st);
-
-    int64_t point, i0, i1;
-    int d, l, f;
-    decode_item(sc, blockIdx.x, &point, &d, &l, &f, &i0, &i1);
-    stage_point(sc, d, l, f, pl, s_thk, s_slot);
-    const int tid = threadIdx.x, WG = blockDim.x;
-    if (lds_bins)
-        for (int i = tid; i < B; i += WG) { s_q[i] = 0ull; s_c[i] = 0u; }
-    for (int i = tid; i < ST_WORDS; i += WG) s_st[i] = 0ull;
-    __syncthreads();
-
-    double* sp = s_sp + tid;
-    const int64_t base = point * sc.N;
-    uint64_t* gq = q_out + point * B;
-    uint32_t* gc = c_out + point * B;
-    const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
-
-    int64_t i = i0 + tid;
-    bool have = i < i1;
-    Ray r;
-    if (have) ray_birth(sc, *pl, base + i, r);
-    unsigned long long n_fp64 = 0, n_lay = 0;
-    for (;;) {
-        int m = -1;
-        while (have) {
-            Outcome o;
-            TapeRef none = { nullptr, 0 };
-            int nt = 0;
-            m = advance<false>(sc, *pl, r, o, none, &nt);
-            if (m >= 0) break;
-            // terminated: scatter and bookkeeping
-            atomicAdd(&s_st[ST_RAYS], 1ull);
-            atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
-            atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);
-            atomicAdd(&s_st[ST_CAT + o.cat], 1ull);
-            double pw = o.w * pscale;
-            atomicAdd(&s_st[ST_POW + o.cat], (unsigned long long)rint(pw < wcap ? pw : wcap));
-            if (o.cat == CAT_EYEBOX || o.cat == CAT_MISS) {
-                double pr = (o.w_in - o.w) * pscale;
-                if (pr > 0.0) atomicAdd(&s_st[ST_POW + CAT_FACE_R], (unsigned long long)rint(pr < wcap ? pr : wcap));
-            }
-            if (o.cat == CAT_EYEBOX) {
-                double u = o.w * wscale;
-                if (u > wcap) { u = wcap; atomicAdd(&s_st[ST_SAT], 1ull); }
-                unsigned long long qv = (unsigned long long)rint(u);
-                if (lds_bins) { atomicAdd(&s_q[o.bin], qv); atomicAdd(&s_c[o.bin], 1u); }
-                else { atomicAdd((unsigned long long*)&gq[o.bin], qv); atomicAdd(&gc[o.bin], 1u); }
-            }
-            if (rec && (r.id % rec_stride) == 0) {
-                gwg_ray_record* q = rec + r.id / rec_stride;
-                q->bin = o.cat == CAT_EYEBOX ? o.bin : -1;
-                q->category = o.cat;
-                q->n_events = r.nev;
-                q->n_prma = r.nprma;
-                q->w = o.w;
-            }
-            i += WG;
-            have = i < i1;
-            if (have) ray_birth(sc, *pl, base + i, r);
-            m = -1;
-        }
-        if (!__any(m >= 0)) break;
-        if (m >= 0) {
-            TapeRef none = { nullptr, 0 };
-            int nt = 0;
-            bool u64 = false;
-            mirror_event<MODE, false>(sc, *pl, s_thk, s_slot, sp, WG, r, m, none, &nt, &u64);
-            n_fp64 += u64 ? 1ull : 0ull;
-            n_lay += (unsigned long long)pl->nlay[m];
-        }
-    }
-    if (n_fp64) atomicAdd(&s_st[ST_FP64], n_fp64);
-    if (n_lay) atomicAdd(&s_st[ST_LAYERS], n_lay);
-    __syncthreads();
-    if (lds_bins) {
-        for (int k = tid; k < B; k += WG) {
-            if (s_c[k]) {
-                atomicAdd((unsigned long long*)&gq[k], s_q[k]);
-                atomicAdd(&gc[k], s_c[k]);
-            }
-        }
-    }
-    for (int k = tid; k < ST_WORDS; k += WG)
-        if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
-}
-
+#include "gwg_fwd_kernel.h"
 #include "gwg_bwd_kernel.h"
 
 // Sum per-item partial gradients in item order: grad[d][k] = sum_items(d) partial[item][k].
@@ -554,21 +311,41 @@ size_t bwd_smem_bytes(const SceneDev& sc, int wg)
     return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, false, (wg + 63) / 64).total;
 }
 
-hipError_t launch_trace_fwd(const SceneDev& sc, int wg, bool lds_bins, uint64_t* q, uint32_t* c,
-                            unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
+template <class K>
+static int blocks_per_cu(K kernel, int wg, size_t smem)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, wg, smem) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+int trace_blocks_per_cu(bool backward, int precision, int wg, size_t smem)
+{
+    if (!backward) {
+        if (precision == GWG_FP64) return blocks_per_cu(k_trace_fwd<GWG_FP64>, wg, smem);
+        if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_fwd<GWG_FP32_MIXED>, wg, smem);
+        return blocks_per_cu(k_trace_fwd<GWG_FP32>, wg, smem);
+    }
+    if (precision == GWG_FP64) return blocks_per_cu(k_trace_bwd<GWG_FP64>, wg, smem);
+    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_bwd<GWG_FP32_MIXED>, wg, smem);
+    return blocks_per_cu(k_trace_bwd<GWG_FP32>, wg, smem);
+}
+
+hipError_t launch_trace_fwd(const SceneDev& sc, int wg, int grid_blocks, bool lds_bins, uint64_t* q, uint32_t* c,
+                            unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride, double* scratch,
                             hipStream_t s)
 {
     size_t sm = fwd_smem_bytes(sc, wg, lds_bins);
-    dim3 grid((unsigned)sc.n_items), block(wg);
+    dim3 grid((unsigned)grid_blocks), block(wg);
     switch (sc.precision) {
     case GWG_FP64:
-        hipLaunchKernelGGL(k_trace_fwd<GWG_FP64>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins);
+        hipLaunchKernelGGL(k_trace_fwd<GWG_FP64>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins, scratch);
         break;
     case GWG_FP32_MIXED:
-        hipLaunchKernelGGL(k_trace_fwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins);
+        hipLaunchKernelGGL(k_trace_fwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins, scratch);
         break;
     default:
-        hipLaunchKernelGGL(k_trace_fwd<GWG_FP32>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins);
+        hipLaunchKernelGGL(k_trace_fwd<GWG_FP32>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins, scratch);
         break;
     }
     return hipGetLastError();

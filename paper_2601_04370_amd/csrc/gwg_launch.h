@@ -16,8 +16,10 @@ size_t bwd_smem_bytes(const SceneDev& sc, int wg);
 size_t tmm_smem_bytes(int L, int n_slots, int wg);
 int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
-hipError_t launch_trace_fwd(const SceneDev& sc, int wg, bool lds_bins, uint64_t* q, uint32_t* c,
-                            unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
+int trace_blocks_per_cu(bool backward, int precision, int wg, size_t smem);
+int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
+hipError_t launch_trace_fwd(const SceneDev& sc, int wg, int grid_blocks, bool lds_bins, uint64_t* q, uint32_t* c,
+                            unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride, double* scratch,
                             hipStream_t s);
 hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI, unsigned long long* stats,
                             double* partial, double* scratch, int64_t sample_stride, hipStream_t s);

@@ -231,4 +231,176 @@ __device__ inline bool near_critical(const PointLds& pl, int n_slots, double kap
     return f;
 }
 
+// ------------------------------------------------------- wave utilities
+__device__ inline int wave_lane() { return (int)(threadIdx.x & 63); }
+
+// Exclusive prefix sum over the 64 lanes of a wave; *total gets the sum.
+__device__ inline int wave_excl_scan(int x, int* total)
+{
+    const int lane = wave_lane();
+    int v = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    *total = __shfl(v, 63, 64);
+    return v - x;
+}
+
+// ------------------------------------------------------------ hit queue
+// Mirror hits of one wave's current round of rays, in ray order: entry p
+// holds the hit's kappa and meta (mirror | front << 8) and, after the solve,
+// its four coefficients.  Field f of entry p at base[f * cap + p].
+struct HitQueue {
+    double* base;
+    int cap;
+    __device__ double kappa(int p) const { return base[p]; }
+    __device__ int meta(int p) const { return (int)base[cap + p]; }
+    __device__ void put(int p, double kappa, int meta) const
+    {
+        base[p] = kappa;
+        base[cap + p] = (double)meta;
+    }
+    __device__ void put_coef(int p, const Coef4& c) const
+    {
+        double* b = base + 2 * cap + p;
+        b[0] = c.rs.re; b[cap] = c.rs.im; b[2 * cap] = c.rp.re; b[3 * cap] = c.rp.im;
+        b[4 * cap] = c.ts.re; b[5 * cap] = c.ts.im; b[6 * cap] = c.tp.re; b[7 * cap] = c.tp.im;
+    }
+    __device__ Coef4 coef(int p) const
+    {
+        const double* b = base + 2 * cap + p;
+        Coef4 c;
+        c.rs = mk(b[0], b[cap]); c.rp = mk(b[2 * cap], b[3 * cap]);
+        c.ts = mk(b[4 * cap], b[5 * cap]); c.tp = mk(b[6 * cap], b[7 * cap]);
+        return c;
+    }
+};
+constexpr int kHitFields = 10;
+
+// ------------------------------------------------------------ tape
+// Field-changing events of one ray for the adjoint (this lane's doubles, stride ts).
+struct TapeRef { double* base; int64_t ts; };
+
+__device__ inline void tape_put(TapeRef t, int k, const Ray& r_before, cd cs, cd cp, double scale,
+                                int type, int m, int front, int refl)
+{
+    double* b = t.base + (int64_t)k * kTapeStride * t.ts;
+    b[0] = r_before.dx; b[t.ts] = r_before.dy; b[2 * t.ts] = r_before.dz;
+    for (int c = 0; c < 3; ++c) { b[(3 + 2 * c) * t.ts] = r_before.e[c].re; b[(4 + 2 * c) * t.ts] = r_before.e[c].im; }
+    b[9 * t.ts] = cs.re; b[10 * t.ts] = cs.im; b[11 * t.ts] = cp.re; b[12 * t.ts] = cp.im;
+    b[13 * t.ts] = scale;
+    b[14 * t.ts] = (double)(type | (m << 4) | (front << 12) | (refl << 13));
+}
+
+// Outcome of a terminated ray.
+struct Outcome { int cat; int bin; double w; double w_in; };
+
+// Walk one ray (already born) from its current state to termination.
+// FIELD = false: geometry and branch decisions only; every mirror hit h calls
+//   on_hit(h, kappa, meta).
+// FIELD = true: also the polarization field (Eq. 5 at every event, Eq. 6 at
+//   mirrors); mirror hit h takes its coefficients from get_coef(h); with
+//   TAPE, field-changing events are recorded for the adjoint.
+// Both modes perform the same geometric operations, so they visit the same
+// surfaces and take the same branches.
+template <bool FIELD, bool TAPE, class OnHit, class GetCoef>
+__device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, Outcome& o,
+                                OnHit on_hit, GetCoef get_coef, TapeRef tape, int* ntape)
+{
+    const double nx = sc.nx, nz = sc.nz;
+    for (;;) {
+        if (r.nev >= sc.Kmax) {
+            o.cat = CAT_TRUNC; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
+            return;
+        }
+        int s = next_surface(sc, pl, r);
+        if (s < 0) {
+            o.cat = CAT_LOST; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
+            return;
+        }
+        r.nev++;
+        if (s == SURF_TOP || s == SURF_BOTTOM) {
+            FaceCoef fc = face_coeffs(pl.ng, pl.na, r.dx, r.dy, r.dz);
+            double sv[3], pin[3], pout[3];
+            if (FIELD) {
+                s_basis(r.dx, r.dy, r.dz, 0.0, 0.0, 1.0, sv);
+                cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
+            }
+            if (fc.tir) {
+                if (FIELD) {
+                    cross3(r.dx, r.dy, -r.dz, sv[0], sv[1], sv[2], pout);
+                    if (TAPE) tape_put(tape, (*ntape)++, r, fc.rs, fc.rp, 1.0, EV_TIR, 0, 0, 0);
+                    apply_sp(r.e, sv, pin, pout, fc.rs, fc.rp, 1.0);
+                }
+                r.dz = -r.dz;
+                r.last = s;
+                continue;
+            }
+            if (s == SURF_TOP) {
+                double a[3];
+                exit_direction(pl.ng, pl.na, r, fc.st2, a);
+                o.w_in = 0.0;
+                o.w = 0.0;
+                if (FIELD) {
+                    cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
+                    o.w_in = norm2(r.e);
+                    if (TAPE) tape_put(tape, (*ntape)++, r, fc.ts, fc.tp, fc.flux, EV_EXIT, 0, 0, 0);
+                    apply_sp(r.e, sv, pin, pout, fc.ts, fc.tp, fc.flux);
+                    o.w = norm2(r.e);
+                }
+                r.dx = a[0]; r.dy = a[1]; r.dz = a[2];
+                o.bin = eyebox_bin(sc, r.px, r.py, a);
+                o.cat = o.bin >= 0 ? CAT_EYEBOX : CAT_MISS;
+                return;
+            }
+            o.cat = CAT_LEAK; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
+            return;
+        }
+        if (s == SURF_END0 || s == SURF_END1) {
+            o.cat = CAT_END; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
+            return;
+        }
+        // mirror hit
+        const int m = s;
+        const double dn = nx * r.dx + nz * r.dz;
+        const bool front = dn < 0.0;
+        const int h = r.nprma;
+        if (!FIELD) {
+            double c[3];
+            cross3(r.dx, r.dy, r.dz, nx, 0.0, nz, c);
+            double kappa = pl.ng * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            on_hit(h, kappa, m | ((front ? 1 : 0) << 8));
+        }
+        if ((h & 3) == 0) {
+            u32x4 w = philox10((uint32_t)(uint64_t)r.id, (uint32_t)((uint64_t)r.id >> 32), (uint32_t)(h >> 2), 1u,
+                               sc.key0, sc.key1);
+            r.w4[0] = w.x; r.w4[1] = w.y; r.w4[2] = w.z; r.w4[3] = w.w;
+        }
+        const int hw = h & 3;
+        const uint32_t word = hw == 0 ? r.w4[0] : hw == 1 ? r.w4[1] : hw == 2 ? r.w4[2] : r.w4[3];
+        const bool refl = word < pl.thr[m];
+        double ndx = r.dx, ndz = r.dz;
+        if (refl) mirror_reflect(nx, nz, r.dx, r.dz, &ndx, &ndz);
+        if (FIELD) {
+            const Coef4 co = get_coef(h);
+            double sv[3], pin[3], pout[3];
+            s_basis(r.dx, r.dy, r.dz, nx, 0.0, nz, sv);
+            cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
+            cross3(ndx, r.dy, ndz, sv[0], sv[1], sv[2], pout);
+            const cd cs = refl ? co.rs : co.ts;
+            const cd cp = refl ? co.rp : co.tp;
+            const double scale = refl ? pl.sc_r[m] : pl.sc_t[m];
+            if (TAPE) tape_put(tape, (*ntape)++, r, cs, cp, scale, EV_MIRROR, m, front ? 1 : 0, refl ? 1 : 0);
+            apply_sp(r.e, sv, pin, pout, cs, cp, scale);
+        }
+        r.dx = ndx;
+        r.dz = ndz;
+        if (!refl) r.cell += (m == r.cell) ? 1 : -1;
+        r.last = m;
+        r.nprma++;
+    }
+}
+
 }  // namespace gwg
