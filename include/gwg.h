@@ -247,6 +247,20 @@ typedef struct {
 int gwg_set_tuning(gwg_ctx* ctx, const gwg_tuning* tuning);
 int gwg_get_tuning(const gwg_ctx* ctx, gwg_tuning* tuning);
 
+/* ---------------------------------------------------------------- timing */
+/* Kernel timing for measurement.  While enabled, the library records a HIP
+ * event on the caller's stream right before and right after each launch of
+ * the forward trace kernel and of the adjoint trace kernel, in a ring of
+ * GWG_TIMING_RING launches per kernel.  Enabling (again) clears the rings.
+ * gwg_kernel_times writes the durations in milliseconds of the last n
+ * launches of `kernel` (GWG_KERNEL_FORWARD or GWG_KERNEL_ADJOINT), oldest
+ * first; it waits for those events.  Errors: GWG_E_INVAL for a bad kernel id,
+ * n < 1, n > GWG_TIMING_RING, or n larger than the launches recorded since
+ * timing was enabled; GWG_E_STATE when timing is off. */
+enum { GWG_KERNEL_FORWARD = 0, GWG_KERNEL_ADJOINT = 1, GWG_TIMING_RING = 64 };
+int gwg_set_timing(gwg_ctx* ctx, int32_t enable);
+int gwg_kernel_times(gwg_ctx* ctx, int32_t kernel, int32_t n, double* ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,28 @@ bool is_fin(double x) { return std::isfinite(x); }
 
 std::string g_create_error;
 
+// Ring of begin/end event pairs around one kernel's launches.
+struct KernelTimer {
+    hipEvent_t ev[GWG_TIMING_RING][2] = {};
+    int64_t recorded = 0;
+    hipError_t create()
+    {
+        for (auto& p : ev)
+            for (hipEvent_t& e : p)
+                if (!e) { hipError_t r = hipEventCreate(&e); if (r != hipSuccess) return r; }
+        return hipSuccess;
+    }
+    void destroy()
+    {
+        for (auto& p : ev)
+            for (hipEvent_t& e : p)
+                if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        recorded = 0;
+    }
+    hipEvent_t begin() const { return ev[recorded % GWG_TIMING_RING][0]; }
+    hipEvent_t end() const { return ev[recorded % GWG_TIMING_RING][1]; }
+};
+
 }  // namespace
 
 struct gwg_ctx {
@@ -68,6 +90,9 @@ struct gwg_ctx {
     SceneDev fwd{};
     // tuning
     gwg_tuning tune{};
+    // kernel timing
+    bool timing = false;
+    KernelTimer timer[2];
 };
 
 namespace {
@@ -426,6 +451,7 @@ int gwg_destroy(gwg_ctx* c)
         for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot })
             b->release();
+        for (KernelTimer& t : c->timer) t.destroy();
     }
     delete c;
     return GWG_OK;
@@ -448,6 +474,41 @@ int gwg_get_tuning(const gwg_ctx* c, gwg_tuning* t)
 {
     if (!c || !t) return GWG_E_INVAL;
     *t = c->tune;
+    return GWG_OK;
+}
+
+int gwg_set_timing(gwg_ctx* c, int32_t enable)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (enable) {
+        for (KernelTimer& t : c->timer) {
+            HIP_CHECK(c, t.create(), "create timing events");
+            t.recorded = 0;
+        }
+    }
+    c->timing = enable != 0;
+    return GWG_OK;
+}
+
+int gwg_kernel_times(gwg_ctx* c, int32_t kernel, int32_t n, double* ms)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    if (!c->timing) return fail(c, GWG_E_STATE, "kernel timing is not enabled");
+    if (kernel != GWG_KERNEL_FORWARD && kernel != GWG_KERNEL_ADJOINT) return fail(c, GWG_E_INVAL, "unknown kernel id %d", kernel);
+    const KernelTimer& t = c->timer[kernel];
+    if (!ms || n < 1 || n > GWG_TIMING_RING || n > t.recorded)
+        return fail(c, GWG_E_INVAL, "n=%d: between 1 and min(%d, %lld recorded)", n, GWG_TIMING_RING, (long long)t.recorded);
+    DeviceGuard g(c->device);
+    for (int k = 0; k < n; ++k) {
+        const int64_t slot = (t.recorded - n + k) % GWG_TIMING_RING;
+        HIP_CHECK(c, hipEventSynchronize(t.ev[slot][1]), "wait for timing event");
+        float v = 0.f;
+        HIP_CHECK(c, hipEventElapsedTime(&v, t.ev[slot][0], t.ev[slot][1]), "elapsed time");
+        ms[k] = v;
+    }
     return GWG_OK;
 }
 
@@ -555,9 +616,14 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     HIP_CHECK(c, launch_fill_u64(out->q_bins, nbins, 0, s), "zero bins");
     HIP_CHECK(c, launch_fill_u32(out->counts, nbins, 0, s), "zero counts");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
+    if (c->timing) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].begin(), s), "timing event");
     HIP_CHECK(c, launch_trace_fwd(sc, wg, (int)grid, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
                                   records, record_stride, (double*)c->fwd_scratch.p, s),
               "forward kernel");
+    if (c->timing) {
+        HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].end(), s), "timing event");
+        ++c->timer[GWG_KERNEL_FORWARD].recorded;
+    }
     if (out->irradiance)
         HIP_CHECK(c, launch_irradiance(out->q_bins, nbins, std::ldexp(1.0, -out->fp_shift) / (double)sc.N, out->irradiance, s),
                   "irradiance kernel");
@@ -593,9 +659,14 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     HIP_CHECK(c, c->partial.ensure(sizeof(double) * (size_t)sc.n_items * ML), "alloc partial gradients");
     HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
+    if (c->timing) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].begin(), s), "timing event");
     HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
                                   (double*)c->scratch.p, sample_stride, s),
               "adjoint kernel");
+    if (c->timing) {
+        HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].end(), s), "timing event");
+        ++c->timer[GWG_KERNEL_ADJOINT].recorded;
+    }
     HIP_CHECK(c, launch_grad_reduce((const double*)c->partial.p, sc.n_items / sc.D, ML, sc.D, d_grad, sc.nlay, sc.M,
                                     sc.Lmax, s),
               "gradient reduction");

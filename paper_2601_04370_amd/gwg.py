@@ -97,7 +97,10 @@ class Tuning(C.Structure):
 
 #: every function declared in include/gwg.h
 EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gwg_tmm_rt",
-           "gwg_trace_forward", "gwg_trace_backward", "gwg_loss", "gwg_set_tuning", "gwg_get_tuning"]
+           "gwg_trace_forward", "gwg_trace_backward", "gwg_loss", "gwg_set_tuning", "gwg_get_tuning",
+           "gwg_set_timing", "gwg_kernel_times"]
+
+KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 
 _lib = None
 
@@ -126,6 +129,8 @@ def load_library(path: str = LIB_PATH):
                            C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
     L.gwg_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.gwg_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    L.gwg_set_timing.argtypes = [C.c_void_p, C.c_int32]
+    L.gwg_kernel_times.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     _lib = L
     return L
 
@@ -260,6 +265,16 @@ class Context:
     def set_tuning(self, block_threads=0, rays_per_block=0, bwd_block_threads=0, bwd_rays_per_block=0):
         t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
+
+    def set_timing(self, enable: bool = True):
+        """Record HIP events around each forward / adjoint trace kernel launch."""
+        self._check(self.lib.gwg_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_times(self, kernel: int, n: int):
+        """Durations (ms) of the last n launches of KERNEL_FORWARD or KERNEL_ADJOINT."""
+        out = (C.c_double * max(n, 1))()
+        self._check(self.lib.gwg_kernel_times(self.h, kernel, n, out))
+        return [out[i] for i in range(n)]
 
     # ------------------------------------------------------------ thin film
     def tmm_rt(self, thk, mat: np.ndarray, mat_in: int, mat_out: int, lambda_nm, n_re, n_im,

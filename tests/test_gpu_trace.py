@@ -140,3 +140,26 @@ def test_full_size_sampled_rays(gctx, orc):
     assert st["rays"] == scene.n_rays
     print(f"full size: {scene.n_rays} rays, {st['interactions']} interactions, "
           f"{st['prma_hits']} mirror hits, {len(ids)} rays compared", flush=True)
+
+
+def test_kernel_timing_rings(gctx):
+    """gwg_set_timing / gwg_kernel_times return one positive duration per launch."""
+    w = inputs.small_variant("diff_1200", rays_per_point=64, fov_n=3)
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    with pytest.raises(gwg.GwgError):
+        gctx.kernel_times(gwg.KERNEL_FORWARD, 1)      # timing off
+    gctx.set_timing(True)
+    try:
+        for k in range(3):
+            _, _, irr, _, _ = gctx.trace_forward(scene, thk, w.seed, k, 0)
+        _, dLdI = gctx.loss(irr, 0)
+        gctx.trace_backward(dLdI, scene)
+        tf = gctx.kernel_times(gwg.KERNEL_FORWARD, 3)
+        tb = gctx.kernel_times(gwg.KERNEL_ADJOINT, 1)
+        assert len(tf) == 3 and all(t > 0 for t in tf) and tb[0] > 0
+        with pytest.raises(gwg.GwgError):
+            gctx.kernel_times(gwg.KERNEL_ADJOINT, 2)  # only one recorded
+    finally:
+        gctx.set_timing(False)
