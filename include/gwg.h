@@ -185,7 +185,9 @@ enum { GWG_CAT_EYEBOX = 0, GWG_CAT_MISS = 1, GWG_CAT_LEAK = 2, GWG_CAT_END = 3,
  * mirror hits, layer steps (sum over hits of the stack's layer count),
  * hits solved in double precision, saturated bin contributions, terminations
  * and final power per category.  Backward: the same for the regenerated
- * paths, plus rays / hits / layer steps that went through the adjoint. */
+ * paths (only rays that end in a bin with nonzero dL/dI are regenerated past
+ * their geometry), plus rays / hits / layer steps that went through the
+ * adjoint. */
 typedef struct {
     int64_t rays, interactions, prma_hits, layer_steps, fp64_hits, saturated;
     int64_t adjoint_rays, adjoint_hits, adjoint_layer_steps;

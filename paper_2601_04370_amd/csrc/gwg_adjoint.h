@@ -208,4 +208,119 @@ __device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t
     }
 }
 
+// u^T <- u^T M for a lossless layer, M = [[C, -iX], [-iY, C]] with real C, X, Y.
+__device__ inline void cov_step_real(cd& u1, cd& u2, double C, double X, double Y)
+{
+#pragma clang fp contract(fast)
+    const double a = u1.re * C + Y * u2.im, b = u1.im * C - Y * u2.re;
+    const double c = u2.re * C + X * u1.im, d = u2.im * C - X * u1.re;
+    u1 = mk(a, b);
+    u2 = mk(c, d);
+}
+
+// Cotangent row of the taken coefficient with respect to [B; C] at the
+// incident side (Eq. 3 convention; r_p = -r_p of the characteristic matrix).
+__device__ inline void coef_cotangent(const V2d& v, double eta0, bool reflect, bool p_pol, cd G, cd* u1, cd* u2)
+{
+    cd B = mk(v.br, v.bi), C = mk(v.cr, v.ci);
+    cd den = cadd(cscale(B, eta0), C);
+    cd inv2 = cdiv(mk(1.0, 0.0), cmul(den, den));
+    cd dB, dC;
+    if (reflect) {
+        const double sg = p_pol ? -2.0 * eta0 : 2.0 * eta0;
+        dB = cscale(cmul(C, inv2), sg);
+        dC = cscale(cmul(B, inv2), -sg);
+    } else {
+        dB = cscale(inv2, -2.0 * eta0 * eta0);
+        dC = cscale(inv2, -2.0 * eta0);
+    }
+    *u1 = cmul(G, dB);
+    *u2 = cmul(G, dC);
+}
+
+// Adjoint of one mirror hit whose stack has no absorbing layer (every layer
+// matrix has real C, X, Y).  Same contract as tmm_adjoint.  The contraction
+// uses the slot parameters (x_s, y_s, x_p, y_p) = (1/q, q, q/N^2, N^2/q) for a
+// propagating layer or (1/Q, -Q, -Q/N^2, N^2/Q) for an evanescent one
+// (q = iQ), with sg = +1 or -1 respectively:
+//     z = sg y_s^2,  z / N^2 = sg y_s x_p,  N^2 = sg y_s y_p.
+__device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, const uint8_t* __restrict__ slot,
+                                            int L, bool front, const double* __restrict__ sp, int ls, double k0,
+                                            double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
+                                            double* grad_row, double* __restrict__ chk, int64_t cstride)
+{
+    // 1) exit -> incident sweep, checkpoints w_{kSeg}, w_{2 kSeg}, ...
+    V2d vs = { 1.0, 0.0, eta0s, 0.0 };
+    V2d vp = { 1.0, 0.0, eta0p, 0.0 };
+    for (int jj = L - 1; jj >= 0; --jj) {
+        const int idx = front ? jj : (L - 1 - jj);
+        const double* P = sp + slot[idx] * NPF * ls;
+        double C, S;
+        layer_cs(P[0], thk[idx], &C, &S);       // t = 0 gives the identity exactly
+        step_real_d(vs, C, S * P[ls], S * P[2 * ls]);
+        step_real_d(vp, C, S * P[3 * ls], S * P[4 * ls]);
+        if (jj > 0 && (jj % kSeg) == 0) {
+            double* c = chk + (int64_t)(jj / kSeg) * 8 * cstride;
+            c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
+            c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
+        }
+    }
+    // 2) cotangent rows of the taken coefficients
+    cd u1s, u2s, u1p, u2p;
+    coef_cotangent(vs, eta0s, reflect, false, Gs, &u1s, &u2s);
+    coef_cotangent(vp, eta0p, reflect, true, Gp, &u1p, &u2p);
+    // 3) incident -> exit covector sweep, segment by segment
+    const double k2 = 2.0 * k0;
+    const int nseg = (L + kSeg - 1) / kSeg;
+    for (int k = 0; k < nseg; ++k) {
+        const int lo = k * kSeg;
+        const int hi = min(lo + kSeg, L);
+        V2d ws, wp;
+        if (hi == L) {
+            ws = V2d{ 1.0, 0.0, eta0s, 0.0 };
+            wp = V2d{ 1.0, 0.0, eta0p, 0.0 };
+        } else {
+            const double* c = chk + (int64_t)(hi / kSeg) * 8 * cstride;
+            ws = V2d{ c[0], c[cstride], c[2 * cstride], c[3 * cstride] };
+            wp = V2d{ c[4 * cstride], c[5 * cstride], c[6 * cstride], c[7 * cstride] };
+        }
+        V2d segs[kSeg], segp[kSeg];
+        double segC[kSeg], segS[kSeg];
+#pragma unroll
+        for (int i = kSeg - 1; i >= 0; --i) {
+            const int jj = lo + i;
+            if (jj < hi) {
+                const int idx = front ? jj : (L - 1 - jj);
+                const double* P = sp + slot[idx] * NPF * ls;
+                double C, S;
+                layer_cs(P[0], thk[idx], &C, &S);
+                segC[i] = C; segS[i] = S;
+                step_real_d(ws, C, S * P[ls], S * P[2 * ls]);
+                step_real_d(wp, C, S * P[3 * ls], S * P[4 * ls]);
+                segs[i] = ws; segp[i] = wp;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kSeg; ++i) {
+            const int jj = lo + i;
+            if (jj < hi) {
+                const int idx = front ? jj : (L - 1 - jj);
+                const double* P = sp + slot[idx] * NPF * ls;
+                const double kq = P[0], xs = P[ls], ys = P[2 * ls], xp = P[3 * ls], yp = P[4 * ls];
+                const double sg = kq < 0.0 ? -1.0 : 1.0;
+                // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
+                const double i_s1 = u1s.re * segs[i].ci + u1s.im * segs[i].cr;   // Im(u1s C_s)
+                const double i_s2 = u2s.re * segs[i].bi + u2s.im * segs[i].br;   // Im(u2s B_s)
+                const double i_p1 = u1p.re * segp[i].ci + u1p.im * segp[i].cr;   // Im(u1p C_p)
+                const double i_p2 = u2p.re * segp[i].bi + u2p.im * segp[i].br;   // Im(u2p B_p)
+                const double g = k2 * (i_s1 + sg * ys * (ys * i_s2 + xp * i_p1 + yp * i_p2));
+                atomicAdd(&grad_row[idx], g);
+                const double C = segC[i], S = segS[i];
+                cov_step_real(u1s, u2s, C, S * xs, S * ys);
+                cov_step_real(u1p, u2p, C, S * xp, S * yp);
+            }
+        }
+    }
+}
+
 }  // namespace gwg

@@ -425,8 +425,38 @@ __device__ inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t*
     V2<T> vs = { (T)1, (T)0, (T)etaEs.re, (T)etaEs.im };
     V2<T> vp = { (T)1, (T)0, (T)etaEp.re, (T)etaEp.im };
     int es = 0, ep = 0;
-    for (int j = 0; j < L; ++j) {
-        int idx = front ? (L - 1 - j) : j;
+    if (L <= 0) return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
+    const int dir = front ? -1 : 1;
+    const int last = front ? 0 : L - 1;
+    int idx = front ? L - 1 : 0;
+    if (cplx_mask == 0u) {
+        // Lossless stack: one loop body for every layer.  The LDS reads run
+        // ahead of the arithmetic: thickness and slot two layers ahead, the
+        // slot's parameters one layer ahead.
+        double t0 = thk[idx];
+        const double* P = sp + slot[idx] * NPF * ls;
+        double kq = P[0], xs = P[ls], ys = P[2 * ls], xp = P[3 * ls], yp = P[4 * ls];
+        int idx1 = idx == last ? idx : idx + dir;
+        double t1 = thk[idx1];
+        int s1 = slot[idx1];
+#pragma unroll 2
+        for (int j = 0; j < L; ++j) {
+            const int idx2 = idx1 == last ? idx1 : idx1 + dir;
+            const double t2 = thk[idx2];
+            const int s2 = slot[idx2];
+            const double* Q = sp + s1 * NPF * ls;
+            const double kq1 = Q[0], xs1 = Q[ls], ys1 = Q[2 * ls], xp1 = Q[3 * ls], yp1 = Q[4 * ls];
+            T C, S;
+            layer_cs((T)kq, (T)t0, &C, &S);    // t = 0 gives the identity exactly
+            step_real(vs, C, S * (T)xs, S * (T)ys);
+            step_real(vp, C, S * (T)xp, S * (T)yp);
+            if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
+            t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+            t1 = t2; s1 = s2; idx1 = idx2;
+        }
+        return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
+    }
+    for (int j = 0; j < L; ++j, idx += dir) {
         T t = (T)thk[idx];                  // t = 0 gives the identity exactly
         int s = slot[idx];
         const double* P = sp + s * NPF * ls;
