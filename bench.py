@@ -145,7 +145,7 @@ def main():
     def step(k, ev=None):
         if ev:
             ev[0].record()
-        _, _, irr, _, _ = ctx.trace_forward(scene, thk, w.seed, k, prec)
+        _, _, irr, _, _ = ctx.trace_forward(scene, thk, w.seed, k, prec, grad=True)
         if ev:
             ev[1].record()
         _, dLdI = ctx.loss(irr, 0)
@@ -181,7 +181,7 @@ def main():
     # counters of the timed steps (recomputed untimed: same seeds, same paths)
     inter = hits = lay_f = lay_b = lay_a = fp64h = 0
     for i in range(a.steps):
-        _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True)
+        _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True, grad=True)
         _, dLdI = ctx.loss(irr, 0)
         _, bst = ctx.trace_backward(dLdI, scene, stats=True)
         inter += st["interactions"]

@@ -200,15 +200,22 @@ typedef struct {
  * random numbers from Philox4x32-10 with key (seed_lo, seed_hi ^ step_lo),
  * counter (id_lo, id_hi, block, tag): tag 0 block 0 gives the birth words,
  * tag 1 block h/4 the word of the h-th mirror hit.  step < 2^32.
+ * flags: 0 or GWG_FWD_GRAD.  With GWG_FWD_GRAD (a gwg_trace_backward will
+ * follow) the trace also runs the path part of the adjoint for every ray
+ * that reaches the eyebox and keeps one entry per mirror hit in the context
+ * (about 48 bytes per hit, within a fixed memory budget); the backward then
+ * only runs the thin-film adjoints.  Without it (or beyond the budget) the
+ * backward regenerates the paths.  Results are identical either way.
  * records: optional device array (NULL to skip) with record_stride >= 1.
  * stats: optional host struct; when given the call synchronizes the stream
  * and returns GWG_E_OVERFLOW if any bin contribution saturated.
  * The context remembers the scene, seed, step, precision and thk pointer
  * for gwg_trace_backward; thk must not change in between. */
+#define GWG_FWD_GRAD 1u
 int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
                       const gwg_materials* mats, const gwg_stacks* stacks,
                       const gwg_rays* rays, uint64_t seed, uint64_t step,
-                      int32_t precision, const gwg_eyebox* out,
+                      int32_t precision, uint32_t flags, const gwg_eyebox* out,
                       gwg_ray_record* records, int64_t record_stride,
                       gwg_stats* stats, void* stream);
 
@@ -238,12 +245,16 @@ int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t 
 /* ---------------------------------------------------------------- tuning */
 /* Launch parameters of the trace kernels (0 = automatic).  rays_per_block
  * is the tile of rays of one (design, wavelength, FoV) point handled by a
- * workgroup; block_threads is 64, 128 or 256. */
+ * workgroup; block_threads is 64, 128 or 256 (adjoint: 64 or 128).
+ * adj_entries_per_ray (0..64, 0 = 6) sizes the adjoint entry regions of
+ * GWG_FWD_GRAD: a region holding more entries than this times its rays is
+ * regenerated by the backward instead. */
 typedef struct {
     int32_t block_threads;
     int64_t rays_per_block;
     int32_t bwd_block_threads;
     int64_t bwd_rays_per_block;
+    int32_t adj_entries_per_ray;
 } gwg_tuning;
 
 int gwg_set_tuning(gwg_ctx* ctx, const gwg_tuning* tuning);

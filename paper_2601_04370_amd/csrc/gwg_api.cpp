@@ -71,6 +71,11 @@ struct KernelTimer {
 
 }  // namespace
 
+// Adjoint entry capacity: entries per ray of a (work item, wave) region, and
+// the most device memory the entries may take.
+constexpr int64_t kAdjEntriesPerRay = 6;
+constexpr double kAdjBudgetBytes = 32.0 * 1024 * 1024 * 1024;
+
 struct gwg_ctx {
     int device = -1;
     int n_cu = 0;
@@ -88,6 +93,10 @@ struct gwg_ctx {
     // last forward
     bool have_forward = false;
     SceneDev fwd{};
+    // adjoint entries recorded by the last forward (GWG_FWD_GRAD)
+    DevBuf adj_ent, adj_cnt, adj_ovf, fwd_tape;
+    bool adj_valid = false;
+    AdjStore adj{};
     // tuning
     gwg_tuning tune{};
     // kernel timing
@@ -449,7 +458,7 @@ int gwg_destroy(gwg_ctx* c)
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
         for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
-                           &c->loss_work, &c->tmm_tab, &c->tmm_slot })
+                           &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape })
             b->release();
         for (KernelTimer& t : c->timer) t.destroy();
     }
@@ -466,6 +475,7 @@ int gwg_set_tuning(gwg_ctx* c, const gwg_tuning* t)
         if (wg != 0 && wg != 64 && wg != 128 && wg != 256) return fail(c, GWG_E_INVAL, "block size must be 64, 128 or 256");
     if (t->bwd_block_threads > 128) return fail(c, GWG_E_INVAL, "adjoint block size must be 64 or 128");
     if (t->rays_per_block < 0 || t->bwd_rays_per_block < 0) return fail(c, GWG_E_INVAL, "negative tile");
+    if (t->adj_entries_per_ray < 0 || t->adj_entries_per_ray > 64) return fail(c, GWG_E_INVAL, "adj_entries_per_ray out of range");
     c->tune = *t;
     return GWG_OK;
 }
@@ -579,7 +589,7 @@ int gwg_tmm_rt(gwg_ctx* c, const gwg_stack* stack, const gwg_materials* mats, in
 
 int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const gwg_materials* mats,
                       const gwg_stacks* stacks, const gwg_rays* rays, uint64_t seed, uint64_t step,
-                      int32_t precision, const gwg_eyebox* out, gwg_ray_record* records, int64_t record_stride,
+                      int32_t precision, uint32_t flags, const gwg_eyebox* out, gwg_ray_record* records, int64_t record_stride,
                       gwg_stats* stats, void* stream)
 {
     if (!c) return GWG_E_INVAL;
@@ -591,8 +601,11 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     if (!out || !out->q_bins || !out->counts) return fail(c, GWG_E_INVAL, "eyebox outputs are NULL");
     if (out->fp_shift < 0 || out->fp_shift > 40) return fail(c, GWG_E_INVAL, "fp_shift out of range");
     if (records && record_stride < 1) return fail(c, GWG_E_INVAL, "record_stride must be >= 1");
+    if (flags & ~(uint32_t)GWG_FWD_GRAD) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
+    c->adj_valid = false;
+    c->have_forward = false;
     rc = build_scene(c, slab, prma, mats, stacks, rays, s);
     if (rc) return rc;
     SceneDev sc = c->sc;
@@ -608,17 +621,40 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     if (fwd_smem_bytes(sc, wg, lds_bins) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
     if (sc.n_items > 0x7fffffff) return fail(c, GWG_E_INVAL, "too many work items; raise rays_per_block");
     const int64_t nbins = (int64_t)sc.D * sc.n_lsel * sc.F * B;
+    // adjoint entries: per (item, wave) region of cap_w entries, if they fit the budget
+    bool adj = false;
+    if (flags & GWG_FWD_GRAD) {
+        const int waves = wg / 64;
+        const int64_t per_ray = c->tune.adj_entries_per_ray > 0 ? c->tune.adj_entries_per_ray : kAdjEntriesPerRay;
+        const int64_t cap_w = ((sc.rays_per_tile + wg - 1) / wg) * 64 * per_ray;
+        const int64_t total = sc.n_items * waves * cap_w;
+        const double bytes = (double)total * kEntFields * sizeof(double) + (double)sc.n_items * (waves + 1) * 4.0;
+        size_t free_b = 0, total_b = 0;
+        (void)hipMemGetInfo(&free_b, &total_b);
+        if (bytes <= std::min<double>(kAdjBudgetBytes, 0.5 * (double)free_b + (double)c->adj_ent.bytes)) {
+            HIP_CHECK(c, c->adj_ent.ensure(sizeof(double) * (size_t)(total * kEntFields)), "alloc adjoint entries");
+            HIP_CHECK(c, c->adj_cnt.ensure(sizeof(int32_t) * (size_t)(sc.n_items * waves)), "alloc entry counts");
+            HIP_CHECK(c, c->adj_ovf.ensure(sizeof(int32_t) * (size_t)sc.n_items), "alloc overflow flags");
+            HIP_CHECK(c, launch_fill_u32((uint32_t*)c->adj_ovf.p, sc.n_items, 0u, s), "zero overflow flags");
+            c->adj = AdjStore{ (double*)c->adj_ent.p, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, cap_w, total, waves };
+            adj = true;
+        }
+    }
     // persistent grid: as many workgroups as fit on the device at once
-    const int per_cu = trace_blocks_per_cu(false, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
+    const int per_cu = trace_blocks_per_cu(adj ? KIND_FWD_ADJ : KIND_FWD, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
     const int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * per_cu);
     HIP_CHECK(c, c->fwd_scratch.ensure(sizeof(double) * (size_t)fwd_scratch_doubles(sc, grid, wg)), "alloc hit queues");
+    if (adj)
+        HIP_CHECK(c, c->fwd_tape.ensure(sizeof(double) * (size_t)(grid * wg * (int64_t)sc.Kmax * kTapeStride)),
+                  "alloc forward tape");
     HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
     HIP_CHECK(c, launch_fill_u64(out->q_bins, nbins, 0, s), "zero bins");
     HIP_CHECK(c, launch_fill_u32(out->counts, nbins, 0, s), "zero counts");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
     if (c->timing) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].begin(), s), "timing event");
     HIP_CHECK(c, launch_trace_fwd(sc, wg, (int)grid, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
-                                  records, record_stride, (double*)c->fwd_scratch.p, s),
+                                  records, record_stride, (double*)c->fwd_scratch.p, adj ? &c->adj : nullptr,
+                                  (double*)c->fwd_tape.p, s),
               "forward kernel");
     if (c->timing) {
         HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].end(), s), "timing event");
@@ -629,6 +665,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
                   "irradiance kernel");
     c->fwd = sc;
     c->have_forward = true;
+    c->adj_valid = adj;
     if (stats) {
         rc = read_stats(c, s, stats);
         if (rc) return rc;
@@ -649,19 +686,30 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     hipStream_t s = (hipStream_t)stream;
     SceneDev sc = c->fwd;
     const int wg = pick_bwd_wg(c, sc);
-    set_tiles(sc, c->tune.bwd_rays_per_block, wg, c->n_cu);
+    // With entries from the forward, the backward keeps the forward's work
+    // items: the entry kernel covers items whose regions fit, the
+    // regenerating kernel the rest.  Otherwise every item is regenerated.
+    const bool entries = c->adj_valid && sample_stride == 1;
+    if (!entries) set_tiles(sc, c->tune.bwd_rays_per_block, wg, c->n_cu);
     if (bwd_smem_bytes(sc, wg) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
-    // persistent grid: as many workgroups as fit on the device at once
-    const int per_cu = trace_blocks_per_cu(true, sc.precision, wg, bwd_smem_bytes(sc, wg));
-    const int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * per_cu);
+    // persistent grids: as many workgroups as fit on the device at once
+    const size_t smem = bwd_smem_bytes(sc, wg);
+    const int64_t n_cu = std::max(c->n_cu, 1);
+    const int64_t grid = std::min<int64_t>(sc.n_items, n_cu * trace_blocks_per_cu(KIND_BWD_REGEN, sc.precision, wg, smem));
+    const int64_t grid_e = std::min<int64_t>(sc.n_items, n_cu * trace_blocks_per_cu(KIND_ADJ_ENTRIES, sc.precision, wg, smem));
     const int ML = sc.M * sc.Lmax;
-    HIP_CHECK(c, c->scratch.ensure(sizeof(double) * (size_t)bwd_scratch_doubles(sc, grid, wg)), "alloc adjoint scratch");
+    const int64_t scratch_d = std::max(bwd_scratch_doubles(sc, grid, wg), entries ? adj_scratch_doubles(sc, grid_e, wg) : 0);
+    HIP_CHECK(c, c->scratch.ensure(sizeof(double) * (size_t)scratch_d), "alloc adjoint scratch");
     HIP_CHECK(c, c->partial.ensure(sizeof(double) * (size_t)sc.n_items * ML), "alloc partial gradients");
     HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
     if (c->timing) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].begin(), s), "timing event");
+    if (entries)
+        HIP_CHECK(c, launch_adj_entries(sc, wg, (int)grid_e, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
+                                        c->adj, (double*)c->scratch.p, s),
+                  "adjoint entry kernel");
     HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
-                                  (double*)c->scratch.p, sample_stride, s),
+                                  (double*)c->scratch.p, sample_stride, entries ? c->adj.ovf : nullptr, s),
               "adjoint kernel");
     if (c->timing) {
         HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].end(), s), "timing event");

@@ -1,30 +1,27 @@
-// Adjoint trace kernel.  Included by gwg_kernels.hip inside namespace gwg.
+// Adjoint trace kernels.  Included by gwg_kernels.hip inside namespace gwg.
 //
 // Gradient checkpointing between the tracer and the thin-film solver
 // (Methods, memory-saving strategies): the path part and the thin-film part
-// of the adjoint run in two phases within each wave.
+// of the adjoint run separately.
 //
-// Phase 1, per ray (one ray per lane per round): a geometry-only walk finds
-// the ray's bin; rays ending in a bin with nonzero dL/dI are regenerated by
-// pass A (same Philox words, same geometry, same coefficients), which writes
-// a tape of the field-changing events, and pass B walks the tape backwards carrying the adjoint field
-// lambda (lambda_K = E_K, lambda_{k-1} = A_k^H lambda_k) and, at every mirror
-// hit, pushes the hit's kappa, mirror, side, branch and the holomorphic
-// cotangents of its two coefficients
-//     G_s = scale conj(lambda_k . s) (s . E_{k-1}),
-//     G_p = scale conj(lambda_k . p_out) (p_in . E_{k-1})
-// (times dL/dI / N) onto the wave's ring queue.  Positions come from a wave
-// prefix sum over lanes, so the queue order is a fixed function of the ray
-// order.
+// Path part.  For every ray ending in an eyebox bin, the reverse field sweep
+// (reverse_sweep) gives each of its mirror hits the holomorphic cotangents
+// G_s, G_p of the two coefficients the ray took.  When the forward trace was
+// asked to prepare a gradient it ran this sweep itself and stored one entry
+// per hit (AdjStore); otherwise, or for work items whose entry regions
+// overflowed, k_trace_bwd regenerates the paths: a geometry-only walk finds
+// each ray's bin, rays in a bin with nonzero dL/dI are walked again with
+// their thin-film solves and a tape of their field-changing events, and the
+// sweep runs on the tape.
 //
-// Phase 2, whenever 64 entries are queued (and once more at the end of a work
-// item): every lane takes one entry and runs the adjoint thin-film solve,
-// adding dw/dt_j into the wave's private LDS row of that mirror.  All lanes
-// run the same layer loop, independent of how long their rays were.
+// Thin-film part.  Entries are drained 64 at a time, one per lane, so every
+// lane runs the same layer loop whatever the length of its ray: the adjoint
+// thin-film solve of the hit adds (dL/dI[bin] / N) d(2 Re(G_s c_s + G_p c_p))/dt_j
+// into the wave's private LDS row of that mirror.
 //
-// Work items are assigned to persistent workgroups with a fixed stride, each
-// wave owns its LDS accumulator, and the per-item partials are summed in item
-// order afterwards, so the gradient is bit-identical from run to run.
+// Work items go to persistent workgroups with a fixed stride, each wave owns
+// its LDS accumulator, and the per-item partials are summed in item order
+// afterwards, so the gradient is bit-identical from run to run.
 
 constexpr int kQFields = 6;      // kappa, Gs.re, Gs.im, Gp.re, Gp.im, meta
 
@@ -44,26 +41,22 @@ __device__ inline void q_put(const Queue& q, int pos, double kappa, cd Gs, cd Gp
     q.base[5 * q.cap + p] = (double)meta;
 }
 
-// Adjoint thin-film solve of queue entry `pos` (one per lane).
-__device__ inline void adjoint_entry(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                     const uint8_t* s_slot, double* sp, int ls, double* gw, const Queue& q,
-                                     int pos, double* chk, int64_t cstride)
+// Adjoint thin-film solve of one mirror hit (one per lane): kappa, the
+// scaled cotangents and meta = mirror | front << 8 | reflected << 9.
+__device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const double* s_thk,
+                                   const uint8_t* s_slot, double* sp, int ls, double* gw, double kappa, cd Gs,
+                                   cd Gp, int meta, double* chk, int64_t cstride)
 {
-    int p = pos % q.cap;
-    double kappa = q.base[p];
-    cd Gs = mk(q.base[1 * q.cap + p], q.base[2 * q.cap + p]);
-    cd Gp = mk(q.base[3 * q.cap + p], q.base[4 * q.cap + p]);
-    int meta = (int)q.base[5 * q.cap + p];
-    int m = meta & 255;
-    bool front = (meta >> 8) & 1, refl = (meta >> 9) & 1;
+    const int m = meta & 255;
+    const bool front = (meta >> 8) & 1, refl = (meta >> 9) & 1;
     for (int s = 0; s < sc.n_slots; ++s) {
         double P[NPF];
         slot_params(pl.slotN[2 * s], pl.slotN[2 * s + 1], kappa, pl.k0, P);
 #pragma unroll
         for (int k = 0; k < NPF; ++k) sp[(s * NPF + k) * ls] = P[k];
     }
-    double z0 = pl.ng * pl.ng - kappa * kappa;
-    double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
+    const double z0 = pl.ng * pl.ng - kappa * kappa;
+    const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
     if (sc.slot_complex == 0u)
         tmm_adjoint_lossless(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sp, ls, pl.k0, q0,
                              pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride);
@@ -73,10 +66,32 @@ __device__ inline void adjoint_entry(const SceneDev& sc, const PointLds& pl, con
                     cstride);
 }
 
+// Adjoint thin-film solve of ring-queue entry `pos`.
+__device__ inline void adjoint_entry(const SceneDev& sc, const PointLds& pl, const double* s_thk,
+                                     const uint8_t* s_slot, double* sp, int ls, double* gw, const Queue& q,
+                                     int pos, double* chk, int64_t cstride)
+{
+    const int p = pos % q.cap;
+    adjoint_hit(sc, pl, s_thk, s_slot, sp, ls, gw, q.base[p], mk(q.base[1 * q.cap + p], q.base[2 * q.cap + p]),
+                mk(q.base[3 * q.cap + p], q.base[4 * q.cap + p]), (int)q.base[5 * q.cap + p], chk, cstride);
+}
+
+// Pushes the entries of one ray onto the ring queue with the dL/dI factor applied.
+struct QueueEmit {
+    Queue q;
+    int* pos;
+    double gscale;
+    __device__ void operator()(double kappa, cd Gs, cd Gp, int meta) const
+    {
+        q_put(q, (*pos)++, kappa, cscale(Gs, gscale), cscale(Gp, gscale), meta);
+    }
+};
+
 template <int MODE>
 __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double* __restrict__ dLdI,
                                                    double* __restrict__ partial,
                                                    double* __restrict__ scratch, int64_t sample_stride,
+                                                   const int32_t* __restrict__ regen,
                                                    unsigned long long* __restrict__ stats)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -114,6 +129,8 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     unsigned long long c_arays = 0, c_ahits = 0, c_alay = 0;
 
     for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+        // regen (optional): only items whose stored entries overflowed
+        if (regen && regen[item] == 0) continue;
         int64_t point, i0, i1;
         int d, l, f;
         decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
@@ -170,55 +187,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             if (contrib) {
                 c_arays += 1;
                 int slotpos = qhead + qcount + off;
-                cd lam[3] = { r.e[0], r.e[1], r.e[2] };
-                for (int k = nt - 1; k >= 0; --k) {
-                    const double* b = tape.base + (int64_t)k * kTapeStride * tape.ts;
-                    const int64_t ts = tape.ts;
-                    double dx = b[0], dy = b[ts], dz = b[2 * ts];
-                    cd cs = mk(b[9 * ts], b[10 * ts]), cp = mk(b[11 * ts], b[12 * ts]);
-                    double scale = b[13 * ts];
-                    int meta = (int)b[14 * ts];
-                    int type = meta & 15, m = (meta >> 4) & 255;
-                    int front = (meta >> 12) & 1, refl = (meta >> 13) & 1;
-                    double sv[3], pin[3], pout[3];
-                    if (type == EV_MIRROR) {
-                        s_basis(dx, dy, dz, sc.nx, 0.0, sc.nz, sv);
-                        cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
-                        double ndx = dx, ndz = dz;
-                        if (refl) mirror_reflect(sc.nx, sc.nz, dx, dz, &ndx, &ndz);
-                        cross3(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
-                        cd E[3];
-                        for (int c = 0; c < 3; ++c) E[c] = mk(b[(3 + 2 * c) * ts], b[(4 + 2 * c) * ts]);
-                        cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
-                        cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
-                        cd es = cadd(cadd(cscale(E[0], sv[0]), cscale(E[1], sv[1])), cscale(E[2], sv[2]));
-                        cd ep = cadd(cadd(cscale(E[0], pin[0]), cscale(E[1], pin[1])), cscale(E[2], pin[2]));
-                        cd Gs = cscale(cmul(cconj(ls), es), scale * gscale);
-                        cd Gp = cscale(cmul(cconj(lp), ep), scale * gscale);
-                        double c3[3];
-                        cross3(dx, dy, dz, sc.nx, 0.0, sc.nz, c3);
-                        double kappa = pl->ng * sqrt(c3[0] * c3[0] + c3[1] * c3[1] + c3[2] * c3[2]);
-                        q_put(q, slotpos++, kappa, Gs, Gp, m | (front << 8) | (refl << 9));
-                    } else {
-                        s_basis(dx, dy, dz, 0.0, 0.0, 1.0, sv);
-                        cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
-                        if (type == EV_TIR) {
-                            cross3(dx, dy, -dz, sv[0], sv[1], sv[2], pout);
-                        } else {
-                            Ray tmp;
-                            tmp.dx = dx; tmp.dy = dy; tmp.dz = dz;
-                            double st2 = (pl->ng * pl->ng) * (dx * dx + dy * dy);
-                            double a[3];
-                            exit_direction(pl->ng, pl->na, tmp, st2, a);
-                            cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
-                        }
-                    }
-                    // lambda <- A^H lambda,  A = scale (cs s s^T + cp p_out p_in^T)
-                    cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
-                    cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
-                    cd as = cscale(cmul(cconj(cs), ls), scale), ap = cscale(cmul(cconj(cp), lp), scale);
-                    for (int c = 0; c < 3; ++c) lam[c] = cadd(cscale(as, sv[c]), cscale(ap, pin[c]));
-                }
+                reverse_sweep(sc, *pl, r.e, tape, nt, QueueEmit{ q, &slotpos, gscale });
             }
             qcount += total;
             __threadfence_block();
@@ -255,6 +224,89 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     __syncthreads();
     for (int k = tid; k < 9; k += WG)
         if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
+}
+
+// Thin-film part of the adjoint over the entries stored by the forward trace.
+// Items whose regions overflowed are left to k_trace_bwd.
+template <int MODE>
+__global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const double* __restrict__ dLdI,
+                                                     double* __restrict__ partial, AdjStore st,
+                                                     double* __restrict__ scratch,
+                                                     unsigned long long* __restrict__ stats)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int WG = blockDim.x;
+    const int n_waves = (WG + 63) / 64;
+    const int B = sc.bins_x * sc.bins_y;
+    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, false, n_waves);
+    PointLds* pl = (PointLds*)(smem + lay.off_pl);
+    double* s_thk = (double*)(smem + lay.off_thk);
+    uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
+    double* s_sp = (double*)(smem + lay.off_sp);
+    double* s_grad = (double*)(smem + lay.off_grad);
+    unsigned long long* s_st = (unsigned long long*)(smem + lay.off_st);
+    const int tid = threadIdx.x;
+    const int wave = tid / 64;
+    const int lane = wave_lane();
+    const int ML = sc.M * sc.Lmax;
+    double* gw = s_grad + (int64_t)wave * ML;
+    double* sp = s_sp + tid;
+    const int64_t nthreads = (int64_t)gridDim.x * WG;
+    double* chk = scratch + (int64_t)blockIdx.x * WG + tid;
+    for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
+    unsigned long long c_ahits = 0, c_alay = 0;
+
+    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+        if (st.ovf[item] != 0) continue;
+        int64_t point, i0, i1;
+        int d, l, f;
+        decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
+        __syncthreads();
+        stage_point(sc, d, l, f, pl, s_thk, s_slot);
+        for (int k = tid; k < n_waves * ML; k += WG) s_grad[k] = 0.0;
+        __syncthreads();
+        const double* g_bins = dLdI + point * B;
+        const int32_t* cnt = st.cnt + item * st.waves;
+        int total = 0;
+        for (int w = 0; w < st.waves; ++w) total += cnt[w];
+        for (int b = wave; b * 64 < total; b += n_waves) {
+            const int v = b * 64 + lane;
+            if (v < total) {
+                int rr = 0, k = v;
+                while (k >= cnt[rr]) { k -= cnt[rr]; ++rr; }
+                const int64_t e = (item * st.waves + rr) * st.cap_w + k;
+                const double kappa = st.ent[e];
+                const int64_t meta = (int64_t)st.ent[5 * st.total + e];
+                const int bin = (int)(meta >> 10);
+                const double gscale = g_bins[bin] / (double)sc.N;
+                if (gscale != 0.0) {
+                    const cd Gs = cscale(mk(st.ent[1 * st.total + e], st.ent[2 * st.total + e]), gscale);
+                    const cd Gp = cscale(mk(st.ent[3 * st.total + e], st.ent[4 * st.total + e]), gscale);
+                    const int mm = (int)(meta & 1023);
+                    adjoint_hit(sc, *pl, s_thk, s_slot, sp, WG, gw, kappa, Gs, Gp, mm, chk, nthreads);
+                    c_ahits += 1;
+                    c_alay += (unsigned long long)pl->nlay[mm & 255];
+                }
+            }
+        }
+        __syncthreads();
+        double* out = partial + item * (int64_t)ML;
+        for (int k = tid; k < ML; k += WG) {
+            double acc = 0.0;
+            for (int w = 0; w < n_waves; ++w) acc += s_grad[(int64_t)w * ML + k];
+            out[k] = acc;
+        }
+    }
+    if (c_ahits) atomicAdd(&s_st[ST_ADJ_HITS], c_ahits);
+    if (c_alay) atomicAdd(&s_st[ST_ADJ_LAYERS], c_alay);
+    __syncthreads();
+    for (int k = tid; k < ST_WORDS; k += WG)
+        if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
+}
+
+int64_t adj_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg)
+{
+    return (sc.Lmax / kSeg + 1) * 8 * grid_blocks * wg;
 }
 
 int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg)

@@ -9,7 +9,11 @@
 //   3. the hits are solved in batches of 64, one per lane, so every lane of
 //      the wave runs the same layer loop whatever the path lengths;
 //   4. a third walk replays the path with the polarization field, taking the
-//      coefficients from the queue, and scatters into the eyebox bins.
+//      coefficients from the queue, and scatters into the eyebox bins;
+//   5. with ADJ (a gradient will follow), the third walk also writes a tape
+//      of the field-changing events and every ray that reached the eyebox
+//      runs the reverse field sweep, storing one adjoint entry per mirror hit
+//      (AdjStore) for the backward.
 // Walks are cheap next to the thin-film solves (a few hundred operations per
 // event against tens of thousands per hit).
 
@@ -83,12 +87,13 @@ struct GetCoef {
 // handles a strided share of the item's rays.  Eyebox bins of the current
 // point accumulate in LDS (integer atomics) and are flushed per item with
 // integer global atomics: the result does not depend on scheduling.
-template <int MODE>
+template <int MODE, bool ADJ>
 __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __restrict__ q_out,
                                                    uint32_t* __restrict__ c_out,
                                                    unsigned long long* __restrict__ stats,
                                                    gwg_ray_record* __restrict__ rec, int64_t rec_stride,
-                                                   int lds_bins, double* __restrict__ scratch)
+                                                   int lds_bins, double* __restrict__ scratch, AdjStore st,
+                                                   double* __restrict__ tape_scratch)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int B = sc.bins_x * sc.bins_y;
@@ -110,6 +115,7 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
     const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;
+    const TapeRef tape = { tape_scratch + (int64_t)blockIdx.x * WG + tid, (int64_t)gridDim.x * WG };
 
     for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
         int64_t point, i0, i1;
@@ -123,6 +129,8 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
         const int64_t base = point * sc.N;
         uint64_t* gq = q_out + point * B;
         uint32_t* gc = c_out + point * B;
+        int64_t n_ent = 0;                                // this wave's entries in this item (uniform)
+        const int64_t ent0 = (item * st.waves + wave) * st.cap_w;
         for (int64_t round = 0;; ++round) {
             const int64_t wave_first = i0 + (int64_t)wave * 64 + round * WG;
             if (wave_first >= i1) break;                  // uniform across the wave
@@ -147,9 +155,10 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
             __threadfence_block();
             solve_hits<MODE>(sc, *pl, s_thk, s_slot, sp, WG, hq, total, &n_fp64, &n_lay);
             __threadfence_block();
+            int nt = 0;
             if (active) {
                 ray_birth(sc, *pl, id, r);
-                walk_ray<true, false>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off }, none, nullptr);
+                walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off }, tape, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
                 atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);
@@ -176,6 +185,33 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
                     q->w = o.w;
                 }
             }
+            if (ADJ) {
+                const bool eb = active && o.cat == CAT_EYEBOX;
+                int etotal;
+                const int eoff = wave_excl_scan(eb ? r.nprma : 0, &etotal);
+                if (eb) {
+                    int64_t k = n_ent + eoff;
+                    const int64_t cap = st.cap_w;
+                    const int64_t meta_bin = (int64_t)o.bin << 10;
+                    reverse_sweep(sc, *pl, r.e, tape, nt, [&](double kappa, cd Gs, cd Gp, int meta) {
+                        if (k < cap) {
+                            const int64_t e = ent0 + k;
+                            st.ent[e] = kappa;
+                            st.ent[1 * st.total + e] = Gs.re;
+                            st.ent[2 * st.total + e] = Gs.im;
+                            st.ent[3 * st.total + e] = Gp.re;
+                            st.ent[4 * st.total + e] = Gp.im;
+                            st.ent[5 * st.total + e] = (double)(meta_bin | (int64_t)meta);
+                        }
+                        ++k;
+                    });
+                }
+                n_ent += etotal;
+            }
+        }
+        if (ADJ && lane == 0) {
+            st.cnt[item * st.waves + wave] = (int32_t)(n_ent < st.cap_w ? n_ent : st.cap_w);
+            if (n_ent > st.cap_w) st.ovf[item] = 1;
         }
         __syncthreads();
         if (lds_bins) {

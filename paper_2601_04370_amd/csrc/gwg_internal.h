@@ -42,6 +42,23 @@ enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4
                 ST_POW = 17,          // 8 words of power (fixed point 2^-24)
                 ST_WORDS = 25 };
 
+// Adjoint entries recorded by the forward trace for the backward: per
+// (work item, forward wave) a region of cap_w entries, field f of entry e at
+// ent[f * total + e], e = (item * waves + wave) * cap_w + k.  Fields: kappa,
+// G_s (re, im), G_p (re, im) without the dL/dI factor, meta = mirror |
+// front << 8 | reflected << 9 | bin << 10 (an exact integer in a double).
+// cnt[item * waves + wave] = entries of that region; ovf[item] != 0 when a
+// region of the item overflowed (the backward then regenerates that item).
+constexpr int kEntFields = 6;
+struct AdjStore {
+    double* ent;
+    int32_t* cnt;
+    int32_t* ovf;
+    int64_t cap_w;
+    int64_t total;
+    int32_t waves;
+};
+
 struct SceneDev {
     // slab
     double T, Lx, ER;

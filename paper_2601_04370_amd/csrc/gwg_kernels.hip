@@ -319,54 +319,88 @@ static int blocks_per_cu(K kernel, int wg, size_t smem)
     return n;
 }
 
-int trace_blocks_per_cu(bool backward, int precision, int wg, size_t smem)
+template <bool ADJ>
+static int fwd_blocks_per_cu(int precision, int wg, size_t smem)
 {
-    if (!backward) {
-        if (precision == GWG_FP64) return blocks_per_cu(k_trace_fwd<GWG_FP64>, wg, smem);
-        if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_fwd<GWG_FP32_MIXED>, wg, smem);
-        return blocks_per_cu(k_trace_fwd<GWG_FP32>, wg, smem);
+    if (precision == GWG_FP64) return blocks_per_cu(k_trace_fwd<GWG_FP64, ADJ>, wg, smem);
+    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_fwd<GWG_FP32_MIXED, ADJ>, wg, smem);
+    return blocks_per_cu(k_trace_fwd<GWG_FP32, ADJ>, wg, smem);
+}
+
+int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem)
+{
+    switch (kind) {
+    case KIND_FWD: return fwd_blocks_per_cu<false>(precision, wg, smem);
+    case KIND_FWD_ADJ: return fwd_blocks_per_cu<true>(precision, wg, smem);
+    case KIND_BWD_REGEN:
+        if (precision == GWG_FP64) return blocks_per_cu(k_trace_bwd<GWG_FP64>, wg, smem);
+        if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_bwd<GWG_FP32_MIXED>, wg, smem);
+        return blocks_per_cu(k_trace_bwd<GWG_FP32>, wg, smem);
+    default:
+        return blocks_per_cu(k_adj_entries<GWG_FP64>, wg, smem);
     }
-    if (precision == GWG_FP64) return blocks_per_cu(k_trace_bwd<GWG_FP64>, wg, smem);
-    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_bwd<GWG_FP32_MIXED>, wg, smem);
-    return blocks_per_cu(k_trace_bwd<GWG_FP32>, wg, smem);
+}
+
+template <int MODE>
+static void launch_fwd_mode(const SceneDev& sc, dim3 grid, dim3 block, size_t sm, bool lds_bins, uint64_t* q,
+                            uint32_t* c, unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
+                            double* scratch, const AdjStore* adj, double* tape, hipStream_t s)
+{
+    if (adj)
+        hipLaunchKernelGGL((k_trace_fwd<MODE, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+                           (int)lds_bins, scratch, *adj, tape);
+    else
+        hipLaunchKernelGGL((k_trace_fwd<MODE, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+                           (int)lds_bins, scratch, AdjStore{}, (double*)nullptr);
 }
 
 hipError_t launch_trace_fwd(const SceneDev& sc, int wg, int grid_blocks, bool lds_bins, uint64_t* q, uint32_t* c,
                             unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride, double* scratch,
-                            hipStream_t s)
+                            const AdjStore* adj, double* tape, hipStream_t s)
 {
     size_t sm = fwd_smem_bytes(sc, wg, lds_bins);
     dim3 grid((unsigned)grid_blocks), block(wg);
     switch (sc.precision) {
     case GWG_FP64:
-        hipLaunchKernelGGL(k_trace_fwd<GWG_FP64>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins, scratch);
+        launch_fwd_mode<GWG_FP64>(sc, grid, block, sm, lds_bins, q, c, stats, rec, rec_stride, scratch, adj, tape, s);
         break;
     case GWG_FP32_MIXED:
-        hipLaunchKernelGGL(k_trace_fwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins, scratch);
+        launch_fwd_mode<GWG_FP32_MIXED>(sc, grid, block, sm, lds_bins, q, c, stats, rec, rec_stride, scratch, adj, tape, s);
         break;
     default:
-        hipLaunchKernelGGL(k_trace_fwd<GWG_FP32>, grid, block, sm, s, sc, q, c, stats, rec, rec_stride, (int)lds_bins, scratch);
+        launch_fwd_mode<GWG_FP32>(sc, grid, block, sm, lds_bins, q, c, stats, rec, rec_stride, scratch, adj, tape, s);
         break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI, unsigned long long* stats,
-                            double* partial, double* scratch, int64_t sample_stride, hipStream_t s)
+                            double* partial, double* scratch, int64_t sample_stride, const int32_t* regen,
+                            hipStream_t s)
 {
     size_t sm = bwd_smem_bytes(sc, wg);
     dim3 grid((unsigned)grid_blocks), block(wg);
     switch (sc.precision) {
     case GWG_FP64:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP64>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, stats);
+        hipLaunchKernelGGL(k_trace_bwd<GWG_FP64>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, regen, stats);
         break;
     case GWG_FP32_MIXED:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, stats);
+        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, regen, stats);
         break;
     default:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, stats);
+        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, regen, stats);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_entries(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI,
+                              unsigned long long* stats, double* partial, const AdjStore& st, double* scratch,
+                              hipStream_t s)
+{
+    size_t sm = bwd_smem_bytes(sc, wg);
+    hipLaunchKernelGGL(k_adj_entries<GWG_FP64>, dim3((unsigned)grid_blocks), dim3(wg), sm, s, sc, dLdI, partial, st,
+                       scratch, stats);
     return hipGetLastError();
 }
 

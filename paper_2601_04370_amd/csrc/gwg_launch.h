@@ -16,13 +16,19 @@ size_t bwd_smem_bytes(const SceneDev& sc, int wg);
 size_t tmm_smem_bytes(int L, int n_slots, int wg);
 int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
-int trace_blocks_per_cu(bool backward, int precision, int wg, size_t smem);
+enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3 };
+int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem);
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
+int64_t adj_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 hipError_t launch_trace_fwd(const SceneDev& sc, int wg, int grid_blocks, bool lds_bins, uint64_t* q, uint32_t* c,
                             unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride, double* scratch,
-                            hipStream_t s);
+                            const AdjStore* adj, double* tape, hipStream_t s);
 hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI, unsigned long long* stats,
-                            double* partial, double* scratch, int64_t sample_stride, hipStream_t s);
+                            double* partial, double* scratch, int64_t sample_stride, const int32_t* regen,
+                            hipStream_t s);
+hipError_t launch_adj_entries(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI,
+                              unsigned long long* stats, double* partial, const AdjStore& st, double* scratch,
+                              hipStream_t s);
 hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D,
                               double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s);
 hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double* irr, hipStream_t s);

@@ -403,4 +403,66 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
     }
 }
 
+// Reverse field sweep along one ray's fixed path (the adjoint of Eq. 5 and
+// Eq. 6 for w = |E_K|^2): lambda_K = E_K, lambda_{k-1} = A_k^H lambda_k with
+// A = scale (c_s s s^T + c_p p_out p_in^T).  For every mirror hit, last to
+// first, calls emit(kappa, G_s, G_p, meta) with the holomorphic cotangents of
+// the taken coefficients,
+//     G_s = scale conj(lambda_k . s) (s . E_{k-1}),
+//     G_p = scale conj(lambda_k . p_out) (p_in . E_{k-1}),
+// and meta = mirror | front << 8 | reflected << 9.
+template <class Emit>
+__device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, const cd* e_final, TapeRef tape,
+                                     int nt, Emit emit)
+{
+    cd lam[3] = { e_final[0], e_final[1], e_final[2] };
+    const int64_t ts = tape.ts;
+    for (int k = nt - 1; k >= 0; --k) {
+        const double* b = tape.base + (int64_t)k * kTapeStride * ts;
+        const double dx = b[0], dy = b[ts], dz = b[2 * ts];
+        const cd cs = mk(b[9 * ts], b[10 * ts]), cp = mk(b[11 * ts], b[12 * ts]);
+        const double scale = b[13 * ts];
+        const int meta = (int)b[14 * ts];
+        const int type = meta & 15, m = (meta >> 4) & 255;
+        const int front = (meta >> 12) & 1, refl = (meta >> 13) & 1;
+        double sv[3], pin[3], pout[3];
+        if (type == EV_MIRROR) {
+            s_basis(dx, dy, dz, sc.nx, 0.0, sc.nz, sv);
+            cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
+            double ndx = dx, ndz = dz;
+            if (refl) mirror_reflect(sc.nx, sc.nz, dx, dz, &ndx, &ndz);
+            cross3(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
+            cd E[3];
+            for (int c = 0; c < 3; ++c) E[c] = mk(b[(3 + 2 * c) * ts], b[(4 + 2 * c) * ts]);
+            const cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
+            const cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
+            const cd es = cadd(cadd(cscale(E[0], sv[0]), cscale(E[1], sv[1])), cscale(E[2], sv[2]));
+            const cd ep = cadd(cadd(cscale(E[0], pin[0]), cscale(E[1], pin[1])), cscale(E[2], pin[2]));
+            const cd Gs = cscale(cmul(cconj(ls), es), scale);
+            const cd Gp = cscale(cmul(cconj(lp), ep), scale);
+            double c3[3];
+            cross3(dx, dy, dz, sc.nx, 0.0, sc.nz, c3);
+            const double kappa = pl.ng * sqrt(c3[0] * c3[0] + c3[1] * c3[1] + c3[2] * c3[2]);
+            emit(kappa, Gs, Gp, m | (front << 8) | (refl << 9));
+        } else {
+            s_basis(dx, dy, dz, 0.0, 0.0, 1.0, sv);
+            cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
+            if (type == EV_TIR) {
+                cross3(dx, dy, -dz, sv[0], sv[1], sv[2], pout);
+            } else {
+                Ray tmp;
+                tmp.dx = dx; tmp.dy = dy; tmp.dz = dz;
+                const double st2 = (pl.ng * pl.ng) * (dx * dx + dy * dy);
+                double a[3];
+                exit_direction(pl.ng, pl.na, tmp, st2, a);
+                cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
+            }
+        }
+        const cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
+        const cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
+        const cd as = cscale(cmul(cconj(cs), ls), scale), ap = cscale(cmul(cconj(cp), lp), scale);
+        for (int c = 0; c < 3; ++c) lam[c] = cadd(cscale(as, sv[c]), cscale(ap, pin[c]));
+    }
+}
+
 }  // namespace gwg

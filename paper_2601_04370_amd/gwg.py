@@ -92,7 +92,8 @@ class Stats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("rays_per_block", C.c_int64),
-                ("bwd_block_threads", C.c_int32), ("bwd_rays_per_block", C.c_int64)]
+                ("bwd_block_threads", C.c_int32), ("bwd_rays_per_block", C.c_int64),
+                ("adj_entries_per_ray", C.c_int32)]
 
 
 #: every function declared in include/gwg.h
@@ -101,6 +102,7 @@ EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gw
            "gwg_set_timing", "gwg_kernel_times"]
 
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
+GWG_FWD_GRAD = 1
 
 _lib = None
 
@@ -122,7 +124,7 @@ def load_library(path: str = LIB_PATH):
                              C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     L.gwg_trace_forward.argtypes = [C.c_void_p, C.POINTER(Slab), C.POINTER(Prma), C.POINTER(Materials),
                                     C.POINTER(Stacks), C.POINTER(Rays), C.c_uint64, C.c_uint64, C.c_int32,
-                                    C.POINTER(Eyebox), C.c_void_p, C.c_int64, C.POINTER(Stats), C.c_void_p]
+                                    C.c_uint32, C.POINTER(Eyebox), C.c_void_p, C.c_int64, C.POINTER(Stats), C.c_void_p]
     L.gwg_trace_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Stats),
                                      C.c_void_p]
     L.gwg_loss.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -241,6 +243,7 @@ class Context:
         if not torch.cuda.is_available():
             raise GwgError(GWG_E_NODEVICE, "no GPU visible to torch")
         self.device = device
+        self.forward_id = 0
         h = C.c_void_p()
         rc = self.lib.gwg_create(C.byref(h), device)
         if rc != GWG_OK:
@@ -262,8 +265,9 @@ class Context:
         if rc != GWG_OK:
             raise GwgError(rc, self.lib.gwg_last_error(self.h).decode())
 
-    def set_tuning(self, block_threads=0, rays_per_block=0, bwd_block_threads=0, bwd_rays_per_block=0):
-        t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block)
+    def set_tuning(self, block_threads=0, rays_per_block=0, bwd_block_threads=0, bwd_rays_per_block=0,
+                   adj_entries_per_ray=0):
+        t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block, adj_entries_per_ray)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
 
     def set_timing(self, enable: bool = True):
@@ -299,9 +303,11 @@ class Context:
 
     # ---------------------------------------------------------------- trace
     def trace_forward(self, scene: SceneSpec, thk, seed: int, step: int = 0, precision: int = FP64,
-                      record_stride: int = 0, stats: bool = False, want_irradiance: bool = True):
+                      record_stride: int = 0, stats: bool = False, want_irradiance: bool = True,
+                      grad: bool = False):
         """Returns (q_bins u64-as-int64, counts int32, irradiance f64 or None,
-        records or None, stats dict or None); tensors on the context's GPU."""
+        records or None, stats dict or None); tensors on the context's GPU.
+        grad=True prepares the adjoint entries for a following trace_backward."""
         torch = self.torch
         dev = torch.device("cuda", self.device)
         assert tuple(thk.shape) == scene.thk_shape and thk.dtype == torch.float64 and thk.is_contiguous()
@@ -318,8 +324,10 @@ class Context:
             n_rec = (scene.n_rays + record_stride - 1) // record_stride
             rec = torch.zeros((n_rec, 3), dtype=torch.float64, device=dev)  # 24-byte records
         sts = Stats() if stats else None
+        self.forward_id += 1
         rc = self.lib.gwg_trace_forward(self.h, C.byref(s), C.byref(p), C.byref(m), C.byref(st), C.byref(r),
-                                        seed & 0xFFFFFFFFFFFFFFFF, step, precision, C.byref(eb),
+                                        seed & 0xFFFFFFFFFFFFFFFF, step, precision,
+                                        GWG_FWD_GRAD if grad else 0, C.byref(eb),
                                         rec.data_ptr() if rec is not None else None, int(record_stride or 1),
                                         C.byref(sts) if sts is not None else None, _stream(torch, dev))
         if rc == GWG_E_OVERFLOW:
@@ -371,15 +379,19 @@ def make_trace_function():
     class GWGTrace(torch.autograd.Function):
         @staticmethod
         def forward(fctx, thk, context: Context, scene: SceneSpec, seed: int, step: int, precision: int):
-            q, c, irr, _, _ = context.trace_forward(scene, thk.detach().contiguous(), seed, step, precision)
+            q, c, irr, _, _ = context.trace_forward(scene, thk.detach().contiguous(), seed, step, precision,
+                                                    grad=thk.requires_grad)
             fctx.context = context
             fctx.scene = scene
+            fctx.forward_id = context.forward_id
             fctx.save_for_backward(thk)
             return irr
 
         @staticmethod
         def backward(fctx, grad_irr):
             (thk,) = fctx.saved_tensors
+            if fctx.context.forward_id != fctx.forward_id:
+                raise GwgError(GWG_E_STATE, "another forward ran on this context before this backward")
             g = fctx.context.trace_backward(grad_irr, fctx.scene)
             return g, None, None, None, None, None
 

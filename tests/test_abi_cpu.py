@@ -46,7 +46,7 @@ def test_abi_version(lib):
 
 def test_null_context_is_rejected(lib):
     from paper_2601_04370_amd import gwg
-    assert lib.gwg_trace_forward(None, None, None, None, None, None, 0, 0, 0, None, None, 1, None, None) == gwg.GWG_E_INVAL
+    assert lib.gwg_trace_forward(None, None, None, None, None, None, 0, 0, 0, 0, None, None, 1, None, None) == gwg.GWG_E_INVAL
     assert lib.gwg_trace_backward(None, None, None, 1, None, None) == gwg.GWG_E_INVAL
     assert lib.gwg_loss(None, None, 1, 1, 1, 1, 0, 1.0, 1.0, None, None, None) == gwg.GWG_E_INVAL
     assert lib.gwg_tmm_rt(None, None, None, 0, None, None, 0, None, None) == gwg.GWG_E_INVAL

@@ -15,16 +15,24 @@ import paper_2601_04370_amd as gwg
 pytestmark = pytest.mark.gpu
 
 
-def _grad_case(gctx, orc, w, inp, precision=0, stride=1, tile=0, bwd_wg=0):
+# backward modes: adjoint entries recorded by the forward; paths regenerated
+# by the backward; entry regions too small for some items (both kernels run)
+MODES = {"entries": (True, 0), "regen": (False, 0), "mixed": (True, 2)}
+
+
+def _grad_case(gctx, orc, w, inp, precision=0, stride=1, tile=0, bwd_wg=0, mode="entries"):
     scene = gwg.SceneSpec.from_workload(w, inp)
     thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
     osc = orc.OracleScene(w, inp)
     oirr = osc.forward_sampled(stride)
     L, dLdI = orc.loss(oirr, 0)
-    gctx.set_tuning(bwd_rays_per_block=tile, bwd_block_threads=bwd_wg)
+    grad, per_ray = MODES[mode]
+    gctx.set_tuning(bwd_rays_per_block=tile, bwd_block_threads=bwd_wg, adj_entries_per_ray=per_ray)
     try:
-        gctx.trace_forward(scene, thk, w.seed, 0, precision)
-        g = gctx.trace_backward(torch.tensor(dLdI), scene, sample_stride=stride).cpu().numpy()
+        gctx.trace_forward(scene, thk, w.seed, 0, precision, grad=grad)
+        g, st = gctx.trace_backward(torch.tensor(dLdI), scene, sample_stride=stride, stats=True)
+        g = g.cpu().numpy()
+        print(f"  mode {mode}: regenerated rays {st['rays']}, adjoint hits {st['adjoint_hits']}", flush=True)
     finally:
         gctx.set_tuning()
     og = osc.backward(dLdI, stride)
@@ -39,12 +47,13 @@ GCASES = [
 ]
 
 
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("name,kw,stride,tile", GCASES)
-def test_backward_fp64_matches_oracle(gctx, orc, name, kw, stride, tile):
+def test_backward_fp64_matches_oracle(gctx, orc, name, kw, stride, tile, mode):
     w = inputs.small_variant(name, **kw)
     inp = inputs.make_inputs(w)
-    print(f"backward fp64 {name} {kw}", flush=True)
-    g, og = _grad_case(gctx, orc, w, inp, 0, stride, tile)
+    print(f"backward fp64 {name} {kw} {mode}", flush=True)
+    g, og = _grad_case(gctx, orc, w, inp, 0, stride, tile, mode=mode)
     scale = np.max(np.abs(og))
     assert scale > 0
     err = np.abs(g - og)
@@ -57,17 +66,21 @@ def test_backward_fp64_matches_oracle(gctx, orc, name, kw, stride, tile):
             assert np.all(g[d, m, inp["n_layers"][d, m]:] == 0.0)
 
 
-def test_backward_is_deterministic(gctx, orc):
+@pytest.mark.parametrize("grad", [True, False])
+def test_backward_is_deterministic(gctx, orc, grad):
     w = inputs.small_variant("diff_1200", rays_per_point=128, fov_n=3)
     inp = inputs.make_inputs(w)
     scene = gwg.SceneSpec.from_workload(w, inp)
     thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
     rng = np.random.default_rng(0)
     dLdI = torch.tensor(rng.standard_normal(scene.shape))
-    gctx.trace_forward(scene, thk, w.seed, 0, 0)
+    gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=grad)
     a = gctx.trace_backward(dLdI, scene).cpu().numpy()
     b = gctx.trace_backward(dLdI, scene).cpu().numpy()
     assert np.array_equal(a, b)
+    gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=grad)
+    c = gctx.trace_backward(dLdI, scene).cpu().numpy()
+    assert np.array_equal(a, c)
 
 
 def test_backward_full_size_sampled(gctx, orc):
@@ -81,6 +94,29 @@ def test_backward_full_size_sampled(gctx, orc):
     err = np.abs(g - og)
     print(f"full size sampled: max |g| {scale:.3e} rel err {err.max() / scale:.2e}", flush=True)
     assert np.all(err <= 1e-4 * np.maximum(np.abs(og), 1e-3 * scale))
+
+
+def test_backward_full_size_entries_match_regeneration(gctx):
+    """Full differentiation workload in the launch configuration the bench
+    times (adjoint entries from the forward, every ray contributing): the
+    gradient equals that of the regenerating backward (checked against the
+    oracle above on every ray of small cases and on sampled rays at full
+    size) up to summation order."""
+    w = inputs.workload("diff_1200")
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    _, _, irr, _, _ = gctx.trace_forward(scene, thk, w.seed, 3, 0, grad=True)
+    _, dLdI = gctx.loss(irr, 0)
+    ge, st = gctx.trace_backward(dLdI, scene, stats=True)
+    gctx.trace_forward(scene, thk, w.seed, 3, 0, grad=False)
+    gr = gctx.trace_backward(dLdI, scene)
+    ge, gr = ge.cpu().numpy(), gr.cpu().numpy()
+    scale = np.max(np.abs(gr))
+    print(f"full size entries vs regeneration: max |g| {scale:.3e} max diff {np.max(np.abs(ge - gr)):.2e} "
+          f"regenerated rays {st['rays']} adjoint hits {st['adjoint_hits']}", flush=True)
+    assert st["rays"] == 0
+    assert np.all(np.abs(ge - gr) <= 1e-10 * np.maximum(np.abs(gr), 1e-3 * scale))
 
 
 def test_autograd_function(gctx, orc):
