@@ -32,18 +32,20 @@ __device__ inline void step_cplx_d(V2d& v, cd C, cd X, cd Y)
 // (imaginary parts zero).  Absorbing: complex.
 struct LayerEnt { cd C, Xs, Ys, Xp, Yp; bool real; };
 
-__device__ inline LayerEnt layer_entries(const double* P, int ls, bool cplx, double k0, double t)
+__device__ inline LayerEnt layer_entries(const LaneSlots3& sl, int s, bool cplx, double k0, double t)
 {
     LayerEnt e;
     e.real = !cplx;
     if (!cplx) {
-        double C, S;
-        layer_cs(P[0], t, &C, &S);
+        double kq, xs, ys, xp, yp, C, S;
+        sl.lossless(s, kq, xs, ys, xp, yp);
+        layer_cs(kq, t, &C, &S);
         e.C = mk(C, 0.0);
-        e.Xs = mk(S * P[ls], 0.0); e.Ys = mk(S * P[2 * ls], 0.0);
-        e.Xp = mk(S * P[3 * ls], 0.0); e.Yp = mk(S * P[4 * ls], 0.0);
+        e.Xs = mk(S * xs, 0.0); e.Ys = mk(S * ys, 0.0);
+        e.Xp = mk(S * xp, 0.0); e.Yp = mk(S * yp, 0.0);
     } else {
-        double Pl[4] = { P[0], P[ls], P[2 * ls], P[3 * ls] };
+        double Pl[4];
+        sl.absorbing(s, Pl);
         CTv<double> C, Xs, Ys, Xp, Yp;
         layer_cplx(Pl, k0, t, &C, &Xs, &Ys, &Xp, &Yp);
         e.C = mk(C.re, C.im); e.Xs = mk(Xs.re, Xs.im); e.Ys = mk(Ys.re, Ys.im);
@@ -72,20 +74,28 @@ __device__ inline void cov_step(cd& u1, cd& u2, cd C, cd X, cd Y)
     u1 = n1; u2 = n2;
 }
 
+// u^T <- u^T M for a lossless layer, M = [[C, -iX], [-iY, C]] with real C, X, Y.
+__device__ inline void cov_step_real(cd& u1, cd& u2, double C, double X, double Y)
+{
+#pragma clang fp contract(fast)
+    const double a = u1.re * C + Y * u2.im, b = u1.im * C - Y * u2.re;
+    const double c = u2.re * C + X * u1.im, d = u2.im * C - X * u1.re;
+    u1 = mk(a, b);
+    u2 = mk(c, d);
+}
+
 // Adjoint of one mirror hit.  Adds d(2 Re(Gs c_s + Gp c_p))/dt_j for every
 // layer into grad_row (this mirror's row of the calling wave's LDS
 // accumulator, stack order), where c = r (reflect) or t (transmit).
-// nsq[s] = Re(N_s^2) of slot s and nsq_inv[s] = 1 / Re(N_s^2) (lossless), or
-// for absorbing slots (re, im) of N^2 in nsq_c[2 s], nsq_c[2 s + 1].
+// sl: this lane's slot table (N^2 of slot s: sl.nsq[2 s], sl.nsq[2 s + 1]).
 // chk: this lane's checkpoint storage, component k of checkpoint c at
 // chk[(c * 8 + k) * cstride].
 __device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t* __restrict__ slot,
-                                   int L, bool front, const double* __restrict__ sp, int ls,
-                                   uint32_t cplx_mask, double k0, double kappa2,
-                                   const double* __restrict__ nsq_c,
-                                   double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
+                                   int L, bool front, const LaneSlots3& sl, uint32_t cplx_mask, double k0,
+                                   double kappa2, double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
                                    double* grad_row, double* __restrict__ chk, int64_t cstride)
 {
+    const double* nsq_c = sl.nsq;
     // 1) exit -> incident sweep, checkpoints w_{kSeg}, w_{2 kSeg}, ...
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
     V2d vp = { 1.0, 0.0, eta0p, 0.0 };
@@ -94,7 +104,7 @@ __device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t
         double t = thk[idx];
         if (t != 0.0) {
             int s = slot[idx];
-            LayerEnt e = layer_entries(sp + s * NPF * ls, ls, (cplx_mask >> s) & 1u, k0, t);
+            LayerEnt e = layer_entries(sl, s, (cplx_mask >> s) & 1u, k0, t);
             apply_layer(vs, vp, e);
         }
         if (jj > 0 && (jj % kSeg) == 0) {
@@ -149,15 +159,15 @@ __device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t
                 double t = thk[idx];
                 int s = slot[idx];
                 if (t != 0.0) {
-                    const double* P = sp + s * NPF * ls;
                     if (!((cplx_mask >> s) & 1u)) {
-                        double C, S;
-                        layer_cs(P[0], t, &C, &S);
+                        double kq, xs, ys, xp, yp, C, S;
+                        sl.lossless(s, kq, xs, ys, xp, yp);
+                        layer_cs(kq, t, &C, &S);
                         segC[i] = C; segS[i] = S;
-                        step_real_d(ws, C, S * P[ls], S * P[2 * ls]);
-                        step_real_d(wp, C, S * P[3 * ls], S * P[4 * ls]);
+                        step_real_d(ws, C, S * xs, S * ys);
+                        step_real_d(wp, C, S * xp, S * yp);
                     } else {
-                        LayerEnt e = layer_entries(P, ls, true, k0, t);
+                        LayerEnt e = layer_entries(sl, s, true, k0, t);
                         apply_layer(ws, wp, e);
                     }
                 }
@@ -171,7 +181,6 @@ __device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t
                 int idx = front ? jj : (L - 1 - jj);
                 double t = thk[idx];
                 int s = slot[idx];
-                const double* P = sp + s * NPF * ls;
                 bool cplx = (cplx_mask >> s) & 1u;
                 // contraction u^T D w (D = -i k0 [[0, a], [b, 0]])
                 cd Bs = mk(segs[i].br, segs[i].bi), Cs = mk(segs[i].cr, segs[i].ci);
@@ -194,11 +203,13 @@ __device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t
                 // covector through layer jj
                 if (t != 0.0) {
                     if (!cplx) {
-                        double C = segC[i], S = segS[i];
-                        cov_step(u1s, u2s, mk(C, 0.0), mk(S * P[ls], 0.0), mk(S * P[2 * ls], 0.0));
-                        cov_step(u1p, u2p, mk(C, 0.0), mk(S * P[3 * ls], 0.0), mk(S * P[4 * ls], 0.0));
+                        double kq, xs, ys, xp, yp;
+                        sl.lossless(s, kq, xs, ys, xp, yp);
+                        const double C = segC[i], S = segS[i];
+                        cov_step_real(u1s, u2s, C, S * xs, S * ys);
+                        cov_step_real(u1p, u2p, C, S * xp, S * yp);
                     } else {
-                        LayerEnt e = layer_entries(P, ls, true, k0, t);
+                        LayerEnt e = layer_entries(sl, s, true, k0, t);
                         cov_step(u1s, u2s, e.C, e.Xs, e.Ys);
                         cov_step(u1p, u2p, e.C, e.Xp, e.Yp);
                     }
@@ -206,16 +217,6 @@ __device__ inline void tmm_adjoint(const double* __restrict__ thk, const uint8_t
             }
         }
     }
-}
-
-// u^T <- u^T M for a lossless layer, M = [[C, -iX], [-iY, C]] with real C, X, Y.
-__device__ inline void cov_step_real(cd& u1, cd& u2, double C, double X, double Y)
-{
-#pragma clang fp contract(fast)
-    const double a = u1.re * C + Y * u2.im, b = u1.im * C - Y * u2.re;
-    const double c = u2.re * C + X * u1.im, d = u2.im * C - X * u1.re;
-    u1 = mk(a, b);
-    u2 = mk(c, d);
 }
 
 // Cotangent row of the taken coefficient with respect to [B; C] at the
@@ -245,7 +246,7 @@ __device__ inline void coef_cotangent(const V2d& v, double eta0, bool reflect, b
 // (q = iQ), with sg = +1 or -1 respectively:
 //     z = sg y_s^2,  z / N^2 = sg y_s x_p,  N^2 = sg y_s y_p.
 __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, const uint8_t* __restrict__ slot,
-                                            int L, bool front, const double* __restrict__ sp, int ls, double k0,
+                                            int L, bool front, const LaneSlots3& sl, double k0,
                                             double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
                                             double* grad_row, double* __restrict__ chk, int64_t cstride)
 {
@@ -254,11 +255,11 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     V2d vp = { 1.0, 0.0, eta0p, 0.0 };
     for (int jj = L - 1; jj >= 0; --jj) {
         const int idx = front ? jj : (L - 1 - jj);
-        const double* P = sp + slot[idx] * NPF * ls;
-        double C, S;
-        layer_cs(P[0], thk[idx], &C, &S);       // t = 0 gives the identity exactly
-        step_real_d(vs, C, S * P[ls], S * P[2 * ls]);
-        step_real_d(vp, C, S * P[3 * ls], S * P[4 * ls]);
+        double kq, xs, ys, xp, yp, C, S;
+        sl.lossless(slot[idx], kq, xs, ys, xp, yp);
+        layer_cs(kq, thk[idx], &C, &S);         // t = 0 gives the identity exactly
+        step_real_d(vs, C, S * xs, S * ys);
+        step_real_d(vp, C, S * xp, S * yp);
         if (jj > 0 && (jj % kSeg) == 0) {
             double* c = chk + (int64_t)(jj / kSeg) * 8 * cstride;
             c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
@@ -291,12 +292,12 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             const int jj = lo + i;
             if (jj < hi) {
                 const int idx = front ? jj : (L - 1 - jj);
-                const double* P = sp + slot[idx] * NPF * ls;
-                double C, S;
-                layer_cs(P[0], thk[idx], &C, &S);
+                double kq, xs, ys, xp, yp, C, S;
+                sl.lossless(slot[idx], kq, xs, ys, xp, yp);
+                layer_cs(kq, thk[idx], &C, &S);
                 segC[i] = C; segS[i] = S;
-                step_real_d(ws, C, S * P[ls], S * P[2 * ls]);
-                step_real_d(wp, C, S * P[3 * ls], S * P[4 * ls]);
+                step_real_d(ws, C, S * xs, S * ys);
+                step_real_d(wp, C, S * xp, S * yp);
                 segs[i] = ws; segp[i] = wp;
             }
         }
@@ -305,8 +306,8 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             const int jj = lo + i;
             if (jj < hi) {
                 const int idx = front ? jj : (L - 1 - jj);
-                const double* P = sp + slot[idx] * NPF * ls;
-                const double kq = P[0], xs = P[ls], ys = P[2 * ls], xp = P[3 * ls], yp = P[4 * ls];
+                double kq, xs, ys, xp, yp;
+                sl.lossless(slot[idx], kq, xs, ys, xp, yp);
                 const double sg = kq < 0.0 ? -1.0 : 1.0;
                 // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
                 const double i_s1 = u1s.re * segs[i].ci + u1s.im * segs[i].cr;   // Im(u1s C_s)

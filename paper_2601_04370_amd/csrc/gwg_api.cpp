@@ -696,7 +696,8 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     const size_t smem = bwd_smem_bytes(sc, wg);
     const int64_t n_cu = std::max(c->n_cu, 1);
     const int64_t grid = std::min<int64_t>(sc.n_items, n_cu * trace_blocks_per_cu(KIND_BWD_REGEN, sc.precision, wg, smem));
-    const int64_t grid_e = std::min<int64_t>(sc.n_items, n_cu * trace_blocks_per_cu(KIND_ADJ_ENTRIES, sc.precision, wg, smem));
+    const int kind_e = sc.slot_complex == 0u ? KIND_ADJ_LOSSLESS : KIND_ADJ_ENTRIES;
+    const int64_t grid_e = std::min<int64_t>(sc.n_items, n_cu * trace_blocks_per_cu(kind_e, sc.precision, wg, smem));
     const int ML = sc.M * sc.Lmax;
     const int64_t scratch_d = std::max(bwd_scratch_doubles(sc, grid, wg), entries ? adj_scratch_doubles(sc, grid_e, wg) : 0);
     HIP_CHECK(c, c->scratch.ensure(sizeof(double) * (size_t)scratch_d), "alloc adjoint scratch");

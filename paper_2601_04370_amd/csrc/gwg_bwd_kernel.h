@@ -43,8 +43,10 @@ __device__ inline void q_put(const Queue& q, int pos, double kappa, cd Gs, cd Gp
 
 // Adjoint thin-film solve of one mirror hit (one per lane): kappa, the
 // scaled cotangents and meta = mirror | front << 8 | reflected << 9.
+// LOSSLESS: the scene has no absorbing slot (compiled without the general path).
+template <bool LOSSLESS = false>
 __device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                   const uint8_t* s_slot, double* sp, int ls, double* gw, double kappa, cd Gs,
+                                   const uint8_t* s_slot, const LaneSlots3& sl, double* gw, double kappa, cd Gs,
                                    cd Gp, int meta, double* chk, int64_t cstride)
 {
     const int m = meta & 255;
@@ -52,27 +54,26 @@ __device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const
     for (int s = 0; s < sc.n_slots; ++s) {
         double P[NPF];
         slot_params(pl.slotN[2 * s], pl.slotN[2 * s + 1], kappa, pl.k0, P);
-#pragma unroll
-        for (int k = 0; k < NPF; ++k) sp[(s * NPF + k) * ls] = P[k];
+        sl.put(s, P);
     }
     const double z0 = pl.ng * pl.ng - kappa * kappa;
     const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
-    if (sc.slot_complex == 0u)
-        tmm_adjoint_lossless(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sp, ls, pl.k0, q0,
+    if (LOSSLESS || sc.slot_complex == 0u)
+        tmm_adjoint_lossless(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
                              pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride);
-    else
-        tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sp, ls, sc.slot_complex,
-                    pl.k0, kappa * kappa, pl.nsq, q0, pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk,
+    else if (!LOSSLESS)
+        tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, sc.slot_complex,
+                    pl.k0, kappa * kappa, q0, pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk,
                     cstride);
 }
 
 // Adjoint thin-film solve of ring-queue entry `pos`.
 __device__ inline void adjoint_entry(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                     const uint8_t* s_slot, double* sp, int ls, double* gw, const Queue& q,
+                                     const uint8_t* s_slot, const LaneSlots3& sl, double* gw, const Queue& q,
                                      int pos, double* chk, int64_t cstride)
 {
     const int p = pos % q.cap;
-    adjoint_hit(sc, pl, s_thk, s_slot, sp, ls, gw, q.base[p], mk(q.base[1 * q.cap + p], q.base[2 * q.cap + p]),
+    adjoint_hit(sc, pl, s_thk, s_slot, sl, gw, q.base[p], mk(q.base[1 * q.cap + p], q.base[2 * q.cap + p]),
                 mk(q.base[3 * q.cap + p], q.base[4 * q.cap + p]), (int)q.base[5 * q.cap + p], chk, cstride);
 }
 
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     const int lane = wave_lane();
     const int ML = sc.M * sc.Lmax;
     double* gw = s_grad + (int64_t)wave * ML;
-    double* sp = s_sp + tid;
+    const LaneSlots3 sl = { s_sp + tid, WG, pl->nsq, pl->in2 };
     const int64_t nthreads = (int64_t)gridDim.x * WG;
     const int64_t gtid = (int64_t)blockIdx.x * WG + tid;
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
@@ -172,7 +173,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
                 walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, hoff }, NoCoef{}, none, nullptr);
             }
             __threadfence_block();
-            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sp, WG, hq, htotal, &c_fp64, &c_lay);
+            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, htotal, &c_fp64, &c_lay);
             __threadfence_block();
             if (active) {
                 ray_birth(sc, *pl, id, r);
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             __threadfence_block();
             // phase 2: drain full batches
             while (qcount >= 64) {
-                adjoint_entry(sc, *pl, s_thk, s_slot, sp, WG, gw, q, qhead + lane, chk, nthreads);
+                adjoint_entry(sc, *pl, s_thk, s_slot, sl, gw, q, qhead + lane, chk, nthreads);
                 const int m = ((int)q.base[5 * q.cap + (qhead + lane) % q.cap]) & 255;
                 c_ahits += 1;
                 c_alay += (unsigned long long)pl->nlay[m];
@@ -203,7 +204,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
         }
         if (qcount > 0) {
             if (lane < qcount) {
-                adjoint_entry(sc, *pl, s_thk, s_slot, sp, WG, gw, q, qhead + lane, chk, nthreads);
+                adjoint_entry(sc, *pl, s_thk, s_slot, sl, gw, q, qhead + lane, chk, nthreads);
                 const int m = ((int)q.base[5 * q.cap + (qhead + lane) % q.cap]) & 255;
                 c_ahits += 1;
                 c_alay += (unsigned long long)pl->nlay[m];
@@ -227,8 +228,9 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
 }
 
 // Thin-film part of the adjoint over the entries stored by the forward trace.
-// Items whose regions overflowed are left to k_trace_bwd.
-template <int MODE>
+// Items whose regions overflowed are left to k_trace_bwd.  LOSSLESS: the
+// scene has no absorbing slot.
+template <bool LOSSLESS>
 __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const double* __restrict__ dLdI,
                                                      double* __restrict__ partial, AdjStore st,
                                                      double* __restrict__ scratch,
@@ -250,7 +252,7 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
     const int lane = wave_lane();
     const int ML = sc.M * sc.Lmax;
     double* gw = s_grad + (int64_t)wave * ML;
-    double* sp = s_sp + tid;
+    const LaneSlots3 sl = { s_sp + tid, WG, pl->nsq, pl->in2 };
     const int64_t nthreads = (int64_t)gridDim.x * WG;
     double* chk = scratch + (int64_t)blockIdx.x * WG + tid;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
                     const cd Gs = cscale(mk(st.ent[1 * st.total + e], st.ent[2 * st.total + e]), gscale);
                     const cd Gp = cscale(mk(st.ent[3 * st.total + e], st.ent[4 * st.total + e]), gscale);
                     const int mm = (int)(meta & 1023);
-                    adjoint_hit(sc, *pl, s_thk, s_slot, sp, WG, gw, kappa, Gs, Gp, mm, chk, nthreads);
+                    adjoint_hit<LOSSLESS>(sc, *pl, s_thk, s_slot, sl, gw, kappa, Gs, Gp, mm, chk, nthreads);
                     c_ahits += 1;
                     c_alay += (unsigned long long)pl->nlay[mm & 255];
                 }

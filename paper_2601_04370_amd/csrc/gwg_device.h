@@ -310,6 +310,57 @@ __device__ inline void slot_params(double nre, double nim, double kappa, double 
     }
 }
 
+// Per-lane slot tables.  slot_params gives P[5] for one slot; a table keeps
+// what the layer loops read and returns, for slot s,
+//   lossless(s, kq, xs, ys, xp, yp)   P0..P4 of a lossless slot,
+//   absorbing(s, Pl)                  Pl = q (re, im), N^2 (re, im).
+// LaneSlots5 keeps all five values per lane (lanes may differ in
+// wavelength).  LaneSlots3 keeps kq, x_s, y_s per lane and takes N^2 of the
+// slot from arrays shared by the workgroup (one wavelength per workgroup):
+// x_p = y_s / N^2 and y_p = N^2 x_s for both lossless kinds.
+struct LaneSlots5 {
+    static constexpr int kPer = 5;
+    double* sp;
+    int ls;
+    __device__ void put(int s, const double* P) const
+    {
+#pragma unroll
+        for (int p = 0; p < 5; ++p) sp[(s * 5 + p) * ls] = P[p];
+    }
+    __device__ void lossless(int s, double& kq, double& xs, double& ys, double& xp, double& yp) const
+    {
+        const double* P = sp + s * 5 * ls;
+        kq = P[0]; xs = P[ls]; ys = P[2 * ls]; xp = P[3 * ls]; yp = P[4 * ls];
+    }
+    __device__ void absorbing(int s, double* Pl) const
+    {
+        const double* P = sp + s * 5 * ls;
+        Pl[0] = P[0]; Pl[1] = P[ls]; Pl[2] = P[2 * ls]; Pl[3] = P[3 * ls];
+    }
+};
+struct LaneSlots3 {
+    static constexpr int kPer = 3;
+    double* sp;
+    int ls;
+    const double* nsq;          // N^2 (re, im) per slot
+    const double* in2;          // 1 / Re N^2 per lossless slot
+    __device__ void put(int s, const double* P) const
+    {
+        sp[(s * 3) * ls] = P[0]; sp[(s * 3 + 1) * ls] = P[1]; sp[(s * 3 + 2) * ls] = P[2];
+    }
+    __device__ void lossless(int s, double& kq, double& xs, double& ys, double& xp, double& yp) const
+    {
+        const double* P = sp + s * 3 * ls;
+        kq = P[0]; xs = P[ls]; ys = P[2 * ls];
+        xp = ys * in2[s]; yp = xs * nsq[2 * s];
+    }
+    __device__ void absorbing(int s, double* Pl) const
+    {
+        const double* P = sp + s * 3 * ls;
+        Pl[0] = P[0]; Pl[1] = P[ls]; Pl[2] = nsq[2 * s]; Pl[3] = nsq[2 * s + 1];
+    }
+};
+
 // ------------------------------------------------------------ chain steps
 template <typename T> struct V2 { T br, bi, cr, ci; };   // [B; C] of one polarization
 template <typename T> struct CTv { T re, im; };
@@ -410,16 +461,14 @@ __device__ inline Coef4 finish_coeffs(const V2<T>& vs, const V2<T>& vp, int es, 
 }
 
 // Forward solve of one hit.  thk/slot: this mirror's layers in stack order
-// (LDS); `front` selects incidence order 0..L-1 (else reversed).  sp: this
-// lane's slot table, element (s, p) at sp[(s * NPF + p) * ls].  Exit medium
-// admittances (es, ep) are complex in general.
+// (LDS); `front` selects incidence order 0..L-1 (else reversed).  sl: this
+// lane's slot table.  Exit medium admittances (es, ep) are complex in general.
 // The stack thicknesses and slot parameters are read in double precision
 // and rounded to the chain precision T once per layer.
-template <typename T>
-__device__ inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t* __restrict__ slot, int L,
-                                  bool front, const double* __restrict__ sp, int ls, uint32_t cplx_mask,
-                                  double k0d, double eta0s, double eta0p, cd etaEs, cd etaEp,
-                                  cd tp_factor)
+template <typename T, class SL>
+__device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t* __restrict__ slot, int L,
+                                  bool front, const SL& sl, uint32_t cplx_mask, double k0d, double eta0s,
+                                  double eta0p, cd etaEs, cd etaEp, cd tp_factor)
 {
     const T k0 = (T)k0d;
     V2<T> vs = { (T)1, (T)0, (T)etaEs.re, (T)etaEs.im };
@@ -434,8 +483,8 @@ __device__ inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t*
         // ahead of the arithmetic: thickness and slot two layers ahead, the
         // slot's parameters one layer ahead.
         double t0 = thk[idx];
-        const double* P = sp + slot[idx] * NPF * ls;
-        double kq = P[0], xs = P[ls], ys = P[2 * ls], xp = P[3 * ls], yp = P[4 * ls];
+        double kq, xs, ys, xp, yp;
+        sl.lossless(slot[idx], kq, xs, ys, xp, yp);
         int idx1 = idx == last ? idx : idx + dir;
         double t1 = thk[idx1];
         int s1 = slot[idx1];
@@ -444,8 +493,8 @@ __device__ inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t*
             const int idx2 = idx1 == last ? idx1 : idx1 + dir;
             const double t2 = thk[idx2];
             const int s2 = slot[idx2];
-            const double* Q = sp + s1 * NPF * ls;
-            const double kq1 = Q[0], xs1 = Q[ls], ys1 = Q[2 * ls], xp1 = Q[3 * ls], yp1 = Q[4 * ls];
+            double kq1, xs1, ys1, xp1, yp1;
+            sl.lossless(s1, kq1, xs1, ys1, xp1, yp1);
             T C, S;
             layer_cs((T)kq, (T)t0, &C, &S);    // t = 0 gives the identity exactly
             step_real(vs, C, S * (T)xs, S * (T)ys);
@@ -459,14 +508,17 @@ __device__ inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t*
     for (int j = 0; j < L; ++j, idx += dir) {
         T t = (T)thk[idx];                  // t = 0 gives the identity exactly
         int s = slot[idx];
-        const double* P = sp + s * NPF * ls;
         if (!((cplx_mask >> s) & 1u)) {
+            double kq, xs, ys, xp, yp;
+            sl.lossless(s, kq, xs, ys, xp, yp);
             T C, S;
-            layer_cs((T)P[0], t, &C, &S);
-            step_real(vs, C, S * (T)P[ls], S * (T)P[2 * ls]);
-            step_real(vp, C, S * (T)P[3 * ls], S * (T)P[4 * ls]);
+            layer_cs((T)kq, t, &C, &S);
+            step_real(vs, C, S * (T)xs, S * (T)ys);
+            step_real(vp, C, S * (T)xp, S * (T)yp);
         } else {
-            T Pl[4] = { (T)P[0], (T)P[ls], (T)P[2 * ls], (T)P[3 * ls] };
+            double Pd[4];
+            sl.absorbing(s, Pd);
+            T Pl[4] = { (T)Pd[0], (T)Pd[1], (T)Pd[2], (T)Pd[3] };
             CTv<T> C, Xs, Ys, Xp, Yp;
             layer_cplx(Pl, k0, t, &C, &Xs, &Ys, &Xp, &Yp);
             step_cplx(vs, C, Xs, Ys);

@@ -20,14 +20,13 @@
 // Thin-film coefficients of one hit for this lane (fills the lane's slot table).
 template <int MODE>
 __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                  const uint8_t* s_slot, double* sp, int ls, int m, bool front, double kappa,
+                                  const uint8_t* s_slot, const LaneSlots3& sl, int m, bool front, double kappa,
                                   bool* used_fp64)
 {
     for (int s = 0; s < sc.n_slots; ++s) {
         double P[NPF];
         slot_params(pl.slotN[2 * s], pl.slotN[2 * s + 1], kappa, pl.k0, P);
-#pragma unroll
-        for (int p = 0; p < NPF; ++p) sp[(s * NPF + p) * ls] = P[p];
+        sl.put(s, P);
     }
     const double z0 = pl.ng * pl.ng - kappa * kappa;
     const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
@@ -38,16 +37,16 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
     const bool fp64 = (MODE == GWG_FP64) || (MODE == GWG_FP32_MIXED && near_critical(pl, sc.n_slots, kappa));
     *used_fp64 = fp64;
     if (fp64)
-        return tmm_solve<double>(thk, slot, L, front, sp, ls, sc.slot_complex, pl.k0, eta0s, eta0p,
+        return tmm_solve<double>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                                  mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
-    return tmm_solve<float>(thk, slot, L, front, sp, ls, sc.slot_complex, pl.k0, eta0s, eta0p,
+    return tmm_solve<float>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                             mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
 }
 
 // Solve queue entries [0, total) in batches of 64 (one per lane).
 template <int MODE>
 __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                  const uint8_t* s_slot, double* sp, int ls, const HitQueue& hq, int total,
+                                  const uint8_t* s_slot, const LaneSlots3& sl, const HitQueue& hq, int total,
                                   unsigned long long* n_fp64, unsigned long long* n_lay)
 {
     const int lane = wave_lane();
@@ -58,7 +57,7 @@ __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const 
             const int meta = hq.meta(p);
             const int m = meta & 255;
             bool u64 = false;
-            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sp, ls, m, (meta >> 8) & 1, kappa, &u64);
+            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64);
             hq.put_coef(p, c);
             *n_fp64 += u64 ? 1ull : 0ull;
             *n_lay += (unsigned long long)pl.nlay[m];
@@ -88,7 +87,7 @@ struct GetCoef {
 // point accumulate in LDS (integer atomics) and are flushed per item with
 // integer global atomics: the result does not depend on scheduling.
 template <int MODE, bool ADJ>
-__global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __restrict__ q_out,
+__global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __restrict__ q_out,
                                                    uint32_t* __restrict__ c_out,
                                                    unsigned long long* __restrict__ stats,
                                                    gwg_ray_record* __restrict__ rec, int64_t rec_stride,
@@ -111,7 +110,7 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
     const int cap = 64 * sc.Kmax;
     const HitQueue hq = { scratch + gwave * (int64_t)kHitFields * cap, cap };
-    double* sp = s_sp + tid;
+    const LaneSlots3 sl = { s_sp + tid, WG, pl->nsq, pl->in2 };
     const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;
@@ -141,10 +140,12 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
             Outcome o;
             TapeRef none = { nullptr, 0 };
             int nh = 0;
+            bool to_eyebox = false;                        // fixed by geometry alone
             if (active) {
                 ray_birth(sc, *pl, id, r);
                 walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
                 nh = r.nprma;
+                to_eyebox = o.cat == CAT_EYEBOX;
             }
             int total;
             const int off = wave_excl_scan(nh, &total);
@@ -153,12 +154,13 @@ __global__ void __launch_bounds__(256) k_trace_fwd(SceneDev sc, uint64_t* __rest
                 walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, off }, NoCoef{}, none, nullptr);
             }
             __threadfence_block();
-            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sp, WG, hq, total, &n_fp64, &n_lay);
+            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, &n_fp64, &n_lay);
             __threadfence_block();
             int nt = 0;
             if (active) {
                 ray_birth(sc, *pl, id, r);
-                walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off }, tape, &nt);
+                const TapeRef rt = { to_eyebox ? tape.base : nullptr, tape.ts };
+                walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off }, rt, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
                 atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);

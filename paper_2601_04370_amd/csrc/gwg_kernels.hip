@@ -42,7 +42,7 @@ __host__ __device__ inline SmemLayout smem_layout(int M, int Lmax, int n_slots, 
     s.off_pl = o; o = align16(o + (int)sizeof(PointLds));
     s.off_thk = o; o = align16(o + 8 * M * Lmax);
     s.off_slot = o; o = align16(o + M * Lmax);
-    s.off_sp = o; o = align16(o + 8 * n_slots * NPF * wg);
+    s.off_sp = o; o = align16(o + 8 * n_slots * LaneSlots3::kPer * wg);
     s.off_q = o; o = align16(o + (lds_bins ? 8 * B : 0));
     s.off_c = o; o = align16(o + (lds_bins ? 4 * B : 0));
     s.off_st = o; o = align16(o + 8 * ST_WORDS);
@@ -69,6 +69,7 @@ __device__ inline void stage_point(const SceneDev& sc, int d, int l, int f, Poin
             double nr = lt[LT_SLOT + 2 * s], ni = lt[LT_SLOT + 2 * s + 1];
             pl->slotN[2 * s] = nr; pl->slotN[2 * s + 1] = ni;
             pl->nsq[2 * s] = nr * nr - ni * ni; pl->nsq[2 * s + 1] = 2.0 * nr * ni;
+            pl->in2[s] = (ni == 0.0 && nr != 0.0) ? 1.0 / (nr * nr) : 0.0;
             pl->crit[2 * s] = lt[LT_CRIT + 2 * s]; pl->crit[2 * s + 1] = lt[LT_CRIT + 2 * s + 1];
         }
         for (int m = 0; m < sc.M; ++m) {
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(256) k_tmm_rt(const double* __restrict__ thk, 
     double* s_sp = (double*)(smem + align16(8 * L) + align16(L > 0 ? L : 1));
     for (int i = threadIdx.x; i < L; i += blockDim.x) { s_thk[i] = thk[i]; s_slot[i] = slot[i]; }
     __syncthreads();
-    double* sp = s_sp + threadIdx.x;
+    const LaneSlots5 sl = { s_sp + threadIdx.x, (int)blockDim.x };
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
         int li = lidx[q];
         double th = theta[q];
@@ -160,8 +161,7 @@ __global__ void __launch_bounds__(256) k_tmm_rt(const double* __restrict__ thk, 
         for (int s = 0; s < n_slots; ++s) {
             double P[NPF];
             slot_params(lt[LT_SLOT + 2 * s], lt[LT_SLOT + 2 * s + 1], kappa, k0, P);
-#pragma unroll
-            for (int p = 0; p < NPF; ++p) sp[(s * NPF + p) * blockDim.x] = P[p];
+            sl.put(s, P);
         }
         double z0 = n0 * n0 - kappa * kappa;
         double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
@@ -177,8 +177,8 @@ __global__ void __launch_bounds__(256) k_tmm_rt(const double* __restrict__ thk, 
             for (int s = 0; s < n_slots; ++s)
                 fp64 |= (kappa > lt[LT_CRIT + 2 * s] && kappa < lt[LT_CRIT + 2 * s + 1]);
         }
-        Coef4 c = fp64 ? tmm_solve<double>(s_thk, s_slot, L, true, sp, blockDim.x, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf)
-                       : tmm_solve<float>(s_thk, s_slot, L, true, sp, blockDim.x, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf);
+        Coef4 c = fp64 ? tmm_solve<double>(s_thk, s_slot, L, true, sl, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf)
+                       : tmm_solve<float>(s_thk, s_slot, L, true, sl, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf);
         o[0] = c.rs.re; o[1] = c.rs.im; o[2] = c.rp.re; o[3] = c.rp.im;
         o[4] = c.ts.re; o[5] = c.ts.im; o[6] = c.tp.re; o[7] = c.tp.im;
     }
@@ -336,8 +336,10 @@ int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem)
         if (precision == GWG_FP64) return blocks_per_cu(k_trace_bwd<GWG_FP64>, wg, smem);
         if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_bwd<GWG_FP32_MIXED>, wg, smem);
         return blocks_per_cu(k_trace_bwd<GWG_FP32>, wg, smem);
+    case KIND_ADJ_LOSSLESS:
+        return blocks_per_cu(k_adj_entries<true>, wg, smem);
     default:
-        return blocks_per_cu(k_adj_entries<GWG_FP64>, wg, smem);
+        return blocks_per_cu(k_adj_entries<false>, wg, smem);
     }
 }
 
@@ -399,8 +401,12 @@ hipError_t launch_adj_entries(const SceneDev& sc, int wg, int grid_blocks, const
                               hipStream_t s)
 {
     size_t sm = bwd_smem_bytes(sc, wg);
-    hipLaunchKernelGGL(k_adj_entries<GWG_FP64>, dim3((unsigned)grid_blocks), dim3(wg), sm, s, sc, dLdI, partial, st,
-                       scratch, stats);
+    if (sc.slot_complex == 0u)
+        hipLaunchKernelGGL(k_adj_entries<true>, dim3((unsigned)grid_blocks), dim3(wg), sm, s, sc, dLdI, partial, st,
+                           scratch, stats);
+    else
+        hipLaunchKernelGGL(k_adj_entries<false>, dim3((unsigned)grid_blocks), dim3(wg), sm, s, sc, dLdI, partial, st,
+                           scratch, stats);
     return hipGetLastError();
 }
 
@@ -421,7 +427,7 @@ hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double*
 
 size_t tmm_smem_bytes(int L, int n_slots, int wg)
 {
-    return (size_t)(align16(8 * L) + align16(L > 0 ? L : 1) + 8 * n_slots * NPF * wg);
+    return (size_t)(align16(8 * L) + align16(L > 0 ? L : 1) + 8 * n_slots * LaneSlots5::kPer * wg);
 }
 
 hipError_t launch_tmm_rt(int precision, const double* thk, const uint8_t* slot, int L,

@@ -16,7 +16,7 @@ size_t bwd_smem_bytes(const SceneDev& sc, int wg);
 size_t tmm_smem_bytes(int L, int n_slots, int wg);
 int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
-enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3 };
+enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3, KIND_ADJ_LOSSLESS = 4 };
 int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem);
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 int64_t adj_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);

@@ -31,6 +31,7 @@ struct PointLds {
     double dir[3];
     double slotN[2 * kMaxSlots];     // (re, im) per slot
     double nsq[2 * kMaxSlots];       // N^2 (re, im) per slot
+    double in2[kMaxSlots];           // 1 / N^2 per lossless slot
     double crit[2 * kMaxSlots];      // near-critical kappa interval per slot
     double h[kMaxMirrors], sc_r[kMaxMirrors], sc_t[kMaxMirrors];
     uint32_t thr[kMaxMirrors];
@@ -288,7 +289,8 @@ __device__ inline void tape_put(TapeRef t, int k, const Ray& r_before, cd cs, cd
 {
     double* b = t.base + (int64_t)k * kTapeStride * t.ts;
     b[0] = r_before.dx; b[t.ts] = r_before.dy; b[2 * t.ts] = r_before.dz;
-    for (int c = 0; c < 3; ++c) { b[(3 + 2 * c) * t.ts] = r_before.e[c].re; b[(4 + 2 * c) * t.ts] = r_before.e[c].im; }
+    if (type == EV_MIRROR)      // the incoming field is only read back at mirror hits
+        for (int c = 0; c < 3; ++c) { b[(3 + 2 * c) * t.ts] = r_before.e[c].re; b[(4 + 2 * c) * t.ts] = r_before.e[c].im; }
     b[9 * t.ts] = cs.re; b[10 * t.ts] = cs.im; b[11 * t.ts] = cp.re; b[12 * t.ts] = cp.im;
     b[13 * t.ts] = scale;
     b[14 * t.ts] = (double)(type | (m << 4) | (front << 12) | (refl << 13));
@@ -302,7 +304,8 @@ struct Outcome { int cat; int bin; double w; double w_in; };
 //   on_hit(h, kappa, meta).
 // FIELD = true: also the polarization field (Eq. 5 at every event, Eq. 6 at
 //   mirrors); mirror hit h takes its coefficients from get_coef(h); with
-//   TAPE, field-changing events are recorded for the adjoint.
+//   TAPE and a non-null tape, field-changing events are recorded for the
+//   adjoint.
 // Both modes perform the same geometric operations, so they visit the same
 // surfaces and take the same branches.
 template <bool FIELD, bool TAPE, class OnHit, class GetCoef>
@@ -331,7 +334,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
             if (fc.tir) {
                 if (FIELD) {
                     cross3(r.dx, r.dy, -r.dz, sv[0], sv[1], sv[2], pout);
-                    if (TAPE) tape_put(tape, (*ntape)++, r, fc.rs, fc.rp, 1.0, EV_TIR, 0, 0, 0);
+                    if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, fc.rs, fc.rp, 1.0, EV_TIR, 0, 0, 0);
                     apply_sp(r.e, sv, pin, pout, fc.rs, fc.rp, 1.0);
                 }
                 r.dz = -r.dz;
@@ -346,7 +349,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
                 if (FIELD) {
                     cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
                     o.w_in = norm2(r.e);
-                    if (TAPE) tape_put(tape, (*ntape)++, r, fc.ts, fc.tp, fc.flux, EV_EXIT, 0, 0, 0);
+                    if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, fc.ts, fc.tp, fc.flux, EV_EXIT, 0, 0, 0);
                     apply_sp(r.e, sv, pin, pout, fc.ts, fc.tp, fc.flux);
                     o.w = norm2(r.e);
                 }
@@ -392,7 +395,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
             const cd cs = refl ? co.rs : co.ts;
             const cd cp = refl ? co.rp : co.tp;
             const double scale = refl ? pl.sc_r[m] : pl.sc_t[m];
-            if (TAPE) tape_put(tape, (*ntape)++, r, cs, cp, scale, EV_MIRROR, m, front ? 1 : 0, refl ? 1 : 0);
+            if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, cs, cp, scale, EV_MIRROR, m, front ? 1 : 0, refl ? 1 : 0);
             apply_sp(r.e, sv, pin, pout, cs, cp, scale);
         }
         r.dx = ndx;
