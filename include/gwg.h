@@ -260,6 +260,34 @@ typedef struct {
 int gwg_set_tuning(gwg_ctx* ctx, const gwg_tuning* tuning);
 int gwg_get_tuning(const gwg_ctx* ctx, gwg_tuning* tuning);
 
+/* Device step counter for captured graphs.  With d_step != NULL (device
+ * uint32, owned by the caller) the trace kernels draw their Philox key from
+ * (seed_lo, seed_hi ^ (step + *d_step)), reading *d_step when they start, so
+ * a graph that captured forward, loss and backward with a fixed `step` draws
+ * fresh paths on every replay if it also advances *d_step after the
+ * backward.  Forward and backward of one step must see the same value.
+ * NULL restores the plain step argument.  During stream capture the trace,
+ * loss and backward calls allocate nothing and synchronize nothing: every
+ * buffer must have been sized by the same call made once before capturing
+ * (else GWG_E_STATE), and stats cannot be requested. */
+int gwg_set_step_source(gwg_ctx* ctx, const uint32_t* d_step);
+
+/* Autotuner.  Times the forward trace of this scene (same arguments as
+ * gwg_trace_forward, step 0) for workgroup sizes 256/128 and ray tiles of
+ * 1, 2 and 4 times the automatic tile, checks that the eyebox bins are
+ * bit-identical across them (scenes of up to 2^24 bins), then times the
+ * adjoint (dL/dI = 1) for adjoint workgroup sizes 128/64, and keeps the
+ * fastest as the context's tuning (*out).  Results are cached in the
+ * context by scene signature (scene tables, precision, flags, device) and,
+ * with cache_path != NULL, read from and appended to that text file.  Runs
+ * several full traces and synchronizes the stream.  Leaves no forward for
+ * gwg_trace_backward. */
+int gwg_autotune(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
+                 const gwg_materials* mats, const gwg_stacks* stacks,
+                 const gwg_rays* rays, uint64_t seed, int32_t precision,
+                 uint32_t flags, const char* cache_path, gwg_tuning* out,
+                 void* stream);
+
 /* ---------------------------------------------------------------- timing */
 /* Kernel timing for measurement.  While enabled, the library records a HIP
  * event on the caller's stream right before and right after each launch of

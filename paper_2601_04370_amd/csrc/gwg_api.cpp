@@ -102,6 +102,13 @@ struct gwg_ctx {
     // kernel timing
     bool timing = false;
     KernelTimer timer[2];
+    // optional device step counter read by the trace kernels
+    const uint32_t* step_dev = nullptr;
+    // occupancy queries, keyed by (kind, precision, block, LDS bytes)
+    std::map<std::tuple<int, int, int, size_t>, int> occ;
+    // autotuned launch parameters by scene signature, and scratch outputs
+    std::map<uint64_t, gwg_tuning> tuned;
+    DevBuf tune_q, tune_c, tune_g, tune_grad;
 };
 
 namespace {
@@ -129,6 +136,32 @@ int hip_fail(gwg_ctx* c, hipError_t e, const char* what)
         hipError_t e_ = (call);                             \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
     } while (0)
+
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
+
+// Grow a context buffer; during stream capture nothing may be allocated.
+int ensure_buf(gwg_ctx* c, DevBuf& b, size_t n, bool capturing, const char* what)
+{
+    if (b.p && n <= b.bytes) return GWG_OK;
+    if (capturing)
+        return fail(c, GWG_E_STATE, "%s would allocate during stream capture; make the same call once before capturing", what);
+    HIP_CHECK(c, b.ensure(n), what);
+    return GWG_OK;
+}
+
+int occupancy(gwg_ctx* c, int kind, int precision, int wg, size_t smem)
+{
+    const auto key = std::make_tuple(kind, precision, wg, smem);
+    auto it = c->occ.find(key);
+    if (it != c->occ.end()) return it->second;
+    const int n = trace_blocks_per_cu(kind, precision, wg, smem);
+    c->occ[key] = n;
+    return n;
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -272,6 +305,8 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     h = fnv(h, ry->fov_deg, sizeof(double) * (ry->fov_mode == 0 ? 2 * ry->n_fov : 4));
     h = fnv_v(h, ry->rays_per_point); h = fnv_v(h, ry->max_events);
     if (c->scene_valid && h == c->scene_hash) return GWG_OK;
+    if (stream_capturing(stream))
+        return fail(c, GWG_E_STATE, "the scene changed during stream capture; make the same call once before capturing");
     c->scene_valid = false;
 
     SceneDev& s = c->sc;
@@ -604,6 +639,8 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     if (flags & ~(uint32_t)GWG_FWD_GRAD) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
+    const bool cap = stream_capturing(s);
+    if (cap && stats) return fail(c, GWG_E_STATE, "stats need a synchronization: not available during stream capture");
     c->adj_valid = false;
     c->have_forward = false;
     rc = build_scene(c, slab, prma, mats, stacks, rays, s);
@@ -613,6 +650,9 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     sc.fp_shift = out->fp_shift;
     sc.key0 = (uint32_t)seed;
     sc.key1 = (uint32_t)(seed >> 32) ^ (uint32_t)step;
+    sc.seed_hi = (uint32_t)(seed >> 32);
+    sc.step_host = (uint32_t)step;
+    sc.step_dev = c->step_dev;
     sc.precision = precision;
     const int B = sc.bins_x * sc.bins_y;
     const bool lds_bins = B <= 2048;
@@ -630,33 +670,41 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
         const int64_t total = sc.n_items * waves * cap_w;
         const double bytes = (double)total * kEntFields * sizeof(double) + (double)sc.n_items * (waves + 1) * 4.0;
         size_t free_b = 0, total_b = 0;
-        (void)hipMemGetInfo(&free_b, &total_b);
-        if (bytes <= std::min<double>(kAdjBudgetBytes, 0.5 * (double)free_b + (double)c->adj_ent.bytes)) {
-            HIP_CHECK(c, c->adj_ent.ensure(sizeof(double) * (size_t)(total * kEntFields)), "alloc adjoint entries");
-            HIP_CHECK(c, c->adj_cnt.ensure(sizeof(int32_t) * (size_t)(sc.n_items * waves)), "alloc entry counts");
-            HIP_CHECK(c, c->adj_ovf.ensure(sizeof(int32_t) * (size_t)sc.n_items), "alloc overflow flags");
+        if (!cap) (void)hipMemGetInfo(&free_b, &total_b);
+        const double room = cap ? (double)c->adj_ent.bytes : 0.5 * (double)free_b + (double)c->adj_ent.bytes;
+        if (bytes <= std::min<double>(kAdjBudgetBytes, room)) {
+            rc = ensure_buf(c, c->adj_ent, sizeof(double) * (size_t)(total * kEntFields), cap, "alloc adjoint entries");
+            if (rc) return rc;
+            rc = ensure_buf(c, c->adj_cnt, sizeof(int32_t) * (size_t)(sc.n_items * waves), cap, "alloc entry counts");
+            if (rc) return rc;
+            rc = ensure_buf(c, c->adj_ovf, sizeof(int32_t) * (size_t)sc.n_items, cap, "alloc overflow flags");
+            if (rc) return rc;
             HIP_CHECK(c, launch_fill_u32((uint32_t*)c->adj_ovf.p, sc.n_items, 0u, s), "zero overflow flags");
             c->adj = AdjStore{ (double*)c->adj_ent.p, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, cap_w, total, waves };
             adj = true;
         }
     }
     // persistent grid: as many workgroups as fit on the device at once
-    const int per_cu = trace_blocks_per_cu(adj ? KIND_FWD_ADJ : KIND_FWD, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
+    const int per_cu = occupancy(c, adj ? KIND_FWD_ADJ : KIND_FWD, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
     const int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * per_cu);
-    HIP_CHECK(c, c->fwd_scratch.ensure(sizeof(double) * (size_t)fwd_scratch_doubles(sc, grid, wg)), "alloc hit queues");
-    if (adj)
-        HIP_CHECK(c, c->fwd_tape.ensure(sizeof(double) * (size_t)(grid * wg * (int64_t)sc.Kmax * kTapeStride)),
-                  "alloc forward tape");
-    HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
+    rc = ensure_buf(c, c->fwd_scratch, sizeof(double) * (size_t)fwd_scratch_doubles(sc, grid, wg), cap, "alloc hit queues");
+    if (rc) return rc;
+    if (adj) {
+        rc = ensure_buf(c, c->fwd_tape, sizeof(double) * (size_t)(grid * wg * (int64_t)sc.Kmax * kTapeStride), cap,
+                        "alloc forward tape");
+        if (rc) return rc;
+    }
+    rc = ensure_buf(c, c->stats, sizeof(uint64_t) * ST_WORDS, cap, "alloc stats");
+    if (rc) return rc;
     HIP_CHECK(c, launch_fill_u64(out->q_bins, nbins, 0, s), "zero bins");
     HIP_CHECK(c, launch_fill_u32(out->counts, nbins, 0, s), "zero counts");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
-    if (c->timing) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].begin(), s), "timing event");
+    if (c->timing && !cap) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].begin(), s), "timing event");
     HIP_CHECK(c, launch_trace_fwd(sc, wg, (int)grid, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
                                   records, record_stride, (double*)c->fwd_scratch.p, adj ? &c->adj : nullptr,
                                   (double*)c->fwd_tape.p, s),
               "forward kernel");
-    if (c->timing) {
+    if (c->timing && !cap) {
         HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].end(), s), "timing event");
         ++c->timer[GWG_KERNEL_FORWARD].recorded;
     }
@@ -684,6 +732,9 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     if (sample_stride < 1) return fail(c, GWG_E_INVAL, "sample_stride must be >= 1");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
+    const bool cap = stream_capturing(s);
+    if (cap && stats) return fail(c, GWG_E_STATE, "stats need a synchronization: not available during stream capture");
+    int rc = GWG_OK;
     SceneDev sc = c->fwd;
     const int wg = pick_bwd_wg(c, sc);
     // With entries from the forward, the backward keeps the forward's work
@@ -695,16 +746,19 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     // persistent grids: as many workgroups as fit on the device at once
     const size_t smem = bwd_smem_bytes(sc, wg);
     const int64_t n_cu = std::max(c->n_cu, 1);
-    const int64_t grid = std::min<int64_t>(sc.n_items, n_cu * trace_blocks_per_cu(KIND_BWD_REGEN, sc.precision, wg, smem));
+    const int64_t grid = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, KIND_BWD_REGEN, sc.precision, wg, smem));
     const int kind_e = sc.slot_complex == 0u ? KIND_ADJ_LOSSLESS : KIND_ADJ_ENTRIES;
-    const int64_t grid_e = std::min<int64_t>(sc.n_items, n_cu * trace_blocks_per_cu(kind_e, sc.precision, wg, smem));
+    const int64_t grid_e = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, kind_e, sc.precision, wg, smem));
     const int ML = sc.M * sc.Lmax;
     const int64_t scratch_d = std::max(bwd_scratch_doubles(sc, grid, wg), entries ? adj_scratch_doubles(sc, grid_e, wg) : 0);
-    HIP_CHECK(c, c->scratch.ensure(sizeof(double) * (size_t)scratch_d), "alloc adjoint scratch");
-    HIP_CHECK(c, c->partial.ensure(sizeof(double) * (size_t)sc.n_items * ML), "alloc partial gradients");
-    HIP_CHECK(c, c->stats.ensure(sizeof(uint64_t) * ST_WORDS), "alloc stats");
+    rc = ensure_buf(c, c->scratch, sizeof(double) * (size_t)scratch_d, cap, "alloc adjoint scratch");
+    if (rc) return rc;
+    rc = ensure_buf(c, c->partial, sizeof(double) * (size_t)sc.n_items * ML, cap, "alloc partial gradients");
+    if (rc) return rc;
+    rc = ensure_buf(c, c->stats, sizeof(uint64_t) * ST_WORDS, cap, "alloc stats");
+    if (rc) return rc;
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
-    if (c->timing) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].begin(), s), "timing event");
+    if (c->timing && !cap) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].begin(), s), "timing event");
     if (entries)
         HIP_CHECK(c, launch_adj_entries(sc, wg, (int)grid_e, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
                                         c->adj, (double*)c->scratch.p, s),
@@ -712,7 +766,7 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
                                   (double*)c->scratch.p, sample_stride, entries ? c->adj.ovf : nullptr, s),
               "adjoint kernel");
-    if (c->timing) {
+    if (c->timing && !cap) {
         HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].end(), s), "timing event");
         ++c->timer[GWG_KERNEL_ADJOINT].recorded;
     }
@@ -735,10 +789,178 @@ int gwg_loss(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
     if (!(is_fin(w_f) && is_fin(w_e))) return fail(c, GWG_E_INVAL, "weights must be finite");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
+    const bool cap = stream_capturing(s);
+    int rc = GWG_OK;
     size_t n = (size_t)D * n_l * F + (size_t)D * B + (size_t)D * F + (size_t)D * 8;
-    HIP_CHECK(c, c->loss_work.ensure(n * sizeof(double)), "alloc loss work");
+    rc = ensure_buf(c, c->loss_work, n * sizeof(double), cap, "alloc loss work");
+    if (rc) return rc;
     HIP_CHECK(c, launch_loss(d_irr, D, n_l, F, B, kind, w_f, w_e, (double*)c->loss_work.p, d_loss, d_dL_dI, s),
               "loss kernels");
+    return GWG_OK;
+}
+
+int gwg_set_step_source(gwg_ctx* c, const uint32_t* d_step)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    c->step_dev = d_step;
+    return GWG_OK;
+}
+
+int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const gwg_materials* mats,
+                 const gwg_stacks* stacks, const gwg_rays* rays, uint64_t seed, int32_t precision, uint32_t flags,
+                 const char* cache_path, gwg_tuning* out, void* stream)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    if (!out) return fail(c, GWG_E_INVAL, "out is NULL");
+    int rc = check_scene(c, slab, prma, mats, stacks, rays);
+    if (rc) return rc;
+    if (precision < GWG_FP64 || precision > GWG_FP32) return fail(c, GWG_E_INVAL, "precision out of range");
+    if (flags & ~(uint32_t)GWG_FWD_GRAD) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (stream_capturing(s)) return fail(c, GWG_E_STATE, "gwg_autotune cannot run during stream capture");
+    rc = build_scene(c, slab, prma, mats, stacks, rays, s);
+    if (rc) return rc;
+    uint64_t key = fnv_v(c->scene_hash, precision);
+    key = fnv_v(key, flags);
+    key = fnv_v(key, c->n_cu);
+    auto hit = c->tuned.find(key);
+    if (hit != c->tuned.end()) {
+        *out = c->tune = hit->second;
+        return GWG_OK;
+    }
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            unsigned long long k = 0;
+            long long rpb = 0, brpb = 0;
+            int wg = 0, bwg = 0, adj = 0;
+            bool found = false;
+            while (std::fscanf(f, "%llx %d %lld %d %lld %d", &k, &wg, &rpb, &bwg, &brpb, &adj) == 6)
+                if (k == key) {
+                    found = true;
+                    break;
+                }
+            std::fclose(f);
+            if (found) {
+                gwg_tuning t{ wg, rpb, bwg, brpb, adj };
+                if (gwg_set_tuning(c, &t) == GWG_OK) {
+                    c->tuned[key] = t;
+                    *out = t;
+                    return GWG_OK;
+                }
+            }
+        }
+    }
+    const SceneDev sc0 = c->sc;
+    const int B = sc0.bins_x * sc0.bins_y;
+    const bool lds_bins = B <= 2048;
+    const int64_t nbins = (int64_t)sc0.D * sc0.n_lsel * sc0.F * B;
+    const int64_t ngrad = (int64_t)sc0.D * sc0.M * sc0.Lmax;
+    HIP_CHECK(c, c->tune_q.ensure(sizeof(uint64_t) * (size_t)nbins), "alloc autotune bins");
+    HIP_CHECK(c, c->tune_c.ensure(sizeof(uint32_t) * (size_t)nbins), "alloc autotune counts");
+    HIP_CHECK(c, c->tune_g.ensure(sizeof(double) * (size_t)nbins), "alloc autotune dL/dI");
+    HIP_CHECK(c, c->tune_grad.ensure(sizeof(double) * (size_t)ngrad), "alloc autotune gradient");
+    HIP_CHECK(c, launch_fill_f64((double*)c->tune_g.p, nbins, 1.0, s), "fill dL/dI");
+    gwg_eyebox eb{};
+    eb.q_bins = (uint64_t*)c->tune_q.p;
+    eb.counts = (uint32_t*)c->tune_c.p;
+    eb.irradiance = nullptr;
+    eb.fp_shift = 24;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_CHECK(c, hipEventCreate(&e0), "event");
+    HIP_CHECK(c, hipEventCreate(&e1), "event");
+    const gwg_tuning saved = c->tune;
+    // times one call (after one warm-up call); -1 on error
+    auto timed = [&](auto&& call) -> double {
+        if (call() != GWG_OK) return -1.0;
+        if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+        if (call() != GWG_OK) return -1.0;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+        return ms;
+    };
+    auto forward = [&]() {
+        return gwg_trace_forward(c, slab, prma, mats, stacks, rays, seed, 0, precision, flags, &eb, nullptr, 1,
+                                 nullptr, stream);
+    };
+    // forward candidates: block size x ray tile; bins must not depend on them
+    std::vector<gwg_tuning> cands;
+    for (int wg : { 256, 128 }) {
+        if (fwd_smem_bytes(sc0, wg, lds_bins) > 65536) continue;
+        SceneDev t = sc0;
+        set_tiles(t, 0, wg, c->n_cu);
+        int64_t last = -1;
+        for (int mult : { 1, 2, 4 }) {
+            int64_t rpt = std::min<int64_t>(t.rays_per_tile * mult, sc0.N);
+            rpt = ((rpt + wg - 1) / wg) * wg;
+            if (rpt == last) continue;
+            last = rpt;
+            gwg_tuning cand = saved;
+            cand.block_threads = wg;
+            cand.rays_per_block = rpt;
+            cands.push_back(cand);
+        }
+    }
+    const bool verify = nbins <= (int64_t)1 << 24;
+    std::vector<uint64_t> ref, cur;
+    double best_ms = -1.0;
+    gwg_tuning best = saved;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        c->tune = cands[i];
+        const double ms = timed(forward);
+        if (ms < 0.0) continue;
+        if (verify) {
+            cur.resize((size_t)nbins);
+            if (hipMemcpy(cur.data(), c->tune_q.p, sizeof(uint64_t) * (size_t)nbins, hipMemcpyDeviceToHost) != hipSuccess)
+                continue;
+            if (ref.empty()) ref = cur;
+            else if (cur != ref) {
+                (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+                c->tune = saved;
+                c->have_forward = false;
+                return fail(c, GWG_E_STATE, "eyebox bins differ between launch configurations");
+            }
+        }
+        if (best_ms < 0.0 || ms < best_ms) { best_ms = ms; best = cands[i]; }
+    }
+    // adjoint block size, with the chosen forward
+    {
+        double bbest = -1.0;
+        gwg_tuning bsel = best;
+        for (int bwg : { 128, 64 }) {
+            gwg_tuning cand = best;
+            cand.bwd_block_threads = bwg;
+            c->tune = cand;
+            if (forward() != GWG_OK) continue;
+            const double ms = timed([&]() {
+                return gwg_trace_backward(c, (const double*)c->tune_g.p, (double*)c->tune_grad.p, 1, nullptr, stream);
+            });
+            if (ms < 0.0) continue;
+            if (bbest < 0.0 || ms < bbest) { bbest = ms; bsel = cand; }
+        }
+        best = bsel;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->have_forward = false;      // the tuning runs leave nothing for a backward
+    if (best_ms < 0.0) {
+        c->tune = saved;
+        return fail(c, GWG_E_STATE, "no launch configuration ran: %s", c->err.c_str());
+    }
+    c->tune = best;
+    c->tuned[key] = best;
+    *out = best;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%llx %d %lld %d %lld %d\n", (unsigned long long)key, best.block_threads,
+                         (long long)best.rays_per_block, best.bwd_block_threads, (long long)best.bwd_rays_per_block,
+                         best.adj_entries_per_ray);
+            std::fclose(f);
+        }
+    }
     return GWG_OK;
 }
 

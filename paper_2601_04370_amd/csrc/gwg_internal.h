@@ -87,7 +87,9 @@ struct SceneDev {
     int64_t N;                        // rays per point
     int32_t Kmax;
     int32_t fp_shift;
-    uint32_t key0, key1;
+    uint32_t key0, key1;              // Philox key (seed_lo, seed_hi ^ step)
+    uint32_t seed_hi, step_host;      // with step_dev: key1 = seed_hi ^ (step_host + *step_dev)
+    const uint32_t* step_dev;         // optional device step counter (graph replays)
     int32_t precision;
     // work decomposition
     int64_t tiles_per_point;

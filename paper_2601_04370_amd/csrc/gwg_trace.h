@@ -23,6 +23,7 @@ struct Ray {
     int cell, last, nev, nprma;
     uint32_t w4[4];
     int64_t id;
+    uint32_t key1;                    // Philox key word 1 of this launch
 };
 
 // Block-uniform data of one (design, wavelength, FoV) point, in LDS.
@@ -97,9 +98,15 @@ __device__ inline void field_direction(double thx, double thy, double ng, double
     d[2] = gz - t2 * nz;
 }
 
+__device__ inline uint32_t philox_key1(const SceneDev& sc)
+{
+    return sc.step_dev ? (sc.seed_hi ^ (sc.step_host + *sc.step_dev)) : sc.key1;
+}
+
 __device__ inline void ray_birth(const SceneDev& sc, const PointLds& pl, int64_t id, Ray& r)
 {
-    u32x4 w = philox10((uint32_t)(uint64_t)id, (uint32_t)((uint64_t)id >> 32), 0u, 0u, sc.key0, sc.key1);
+    r.key1 = philox_key1(sc);
+    u32x4 w = philox10((uint32_t)(uint64_t)id, (uint32_t)((uint64_t)id >> 32), 0u, 0u, sc.key0, r.key1);
     r.id = id;
     r.px = sc.px0 + u24(w.x) * sc.pw;
     r.py = u24(w.y) * sc.ph - 0.5 * sc.ph;
@@ -378,7 +385,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
         }
         if ((h & 3) == 0) {
             u32x4 w = philox10((uint32_t)(uint64_t)r.id, (uint32_t)((uint64_t)r.id >> 32), (uint32_t)(h >> 2), 1u,
-                               sc.key0, sc.key1);
+                               sc.key0, r.key1);
             r.w4[0] = w.x; r.w4[1] = w.y; r.w4[2] = w.z; r.w4[3] = w.w;
         }
         const int hw = h & 3;

@@ -99,7 +99,7 @@ class Tuning(C.Structure):
 #: every function declared in include/gwg.h
 EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gwg_tmm_rt",
            "gwg_trace_forward", "gwg_trace_backward", "gwg_loss", "gwg_set_tuning", "gwg_get_tuning",
-           "gwg_set_timing", "gwg_kernel_times"]
+           "gwg_set_timing", "gwg_kernel_times", "gwg_set_step_source", "gwg_autotune"]
 
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 GWG_FWD_GRAD = 1
@@ -132,6 +132,10 @@ def load_library(path: str = LIB_PATH):
     L.gwg_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.gwg_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.gwg_set_timing.argtypes = [C.c_void_p, C.c_int32]
+    L.gwg_set_step_source.argtypes = [C.c_void_p, C.c_void_p]
+    L.gwg_autotune.argtypes = [C.c_void_p, C.POINTER(Slab), C.POINTER(Prma), C.POINTER(Materials),
+                               C.POINTER(Stacks), C.POINTER(Rays), C.c_uint64, C.c_int32, C.c_uint32,
+                               C.c_char_p, C.POINTER(Tuning), C.c_void_p]
     L.gwg_kernel_times.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     _lib = L
     return L
@@ -269,6 +273,29 @@ class Context:
                    adj_entries_per_ray=0):
         t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block, adj_entries_per_ray)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
+
+    def set_step_source(self, d_step=None):
+        """Device int32/uint32 tensor [1] whose value is added to `step` by the
+        trace kernels (for captured graphs), or None."""
+        if d_step is not None:
+            assert d_step.is_cuda and d_step.numel() >= 1 and d_step.element_size() == 4
+        self._step_src = d_step
+        self._check(self.lib.gwg_set_step_source(self.h, d_step.data_ptr() if d_step is not None else None))
+
+    def autotune(self, scene: "SceneSpec", thk, seed: int, precision: int = FP64, grad: bool = False,
+                 cache_path: Optional[str] = None) -> dict:
+        """Time launch configurations for this scene; the fastest becomes the tuning."""
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        assert tuple(thk.shape) == scene.thk_shape and thk.dtype == torch.float64 and thk.is_contiguous()
+        m, s, p, st, r = scene.structs()
+        st.thk_nm = thk.data_ptr()
+        t = Tuning()
+        self._check(self.lib.gwg_autotune(self.h, C.byref(s), C.byref(p), C.byref(m), C.byref(st), C.byref(r),
+                                          seed & 0xFFFFFFFFFFFFFFFF, precision, GWG_FWD_GRAD if grad else 0,
+                                          cache_path.encode() if cache_path else None, C.byref(t),
+                                          _stream(torch, dev)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     def set_timing(self, enable: bool = True):
         """Record HIP events around each forward / adjoint trace kernel launch."""

@@ -54,6 +54,8 @@ def test_null_context_is_rejected(lib):
     assert lib.gwg_set_tuning(None, None) == gwg.GWG_E_INVAL
     assert lib.gwg_set_timing(None, 1) == gwg.GWG_E_INVAL
     assert lib.gwg_kernel_times(None, 0, 1, None) == gwg.GWG_E_INVAL
+    assert lib.gwg_set_step_source(None, None) == gwg.GWG_E_INVAL
+    assert lib.gwg_autotune(None, None, None, None, None, None, 0, 0, 0, None, None, None) == gwg.GWG_E_INVAL
 
 
 def test_create_reports_missing_device(lib):
