@@ -62,37 +62,41 @@ def load_traffic(kernel: str, workload: str, precision: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(w, inp, budget_s: float):
+def cpu_baseline(w, inp, budget_s: float, forward_only: bool = False):
     """The FP64 oracle (single-threaded C) on a bounded sample of the same
-    workload: every s-th ray, forward + loss + adjoint."""
+    workload: every s-th ray, forward + loss + adjoint (or forward only)."""
     import numpy as np
     import oracle
     osc = oracle.OracleScene(w, inp)
     n_rays = w.n_rays
+
+    def run(stride):
+        irr = osc.forward_sampled(stride)
+        if not forward_only:
+            _, g = oracle.loss(irr, 0)
+            osc.backward(g, stride)
+
     # calibrate on a tiny sample
     s0 = max(1, n_rays // 60)
     t = time.perf_counter()
-    irr = osc.forward_sampled(s0)
-    _, g = oracle.loss(irr, 0)
-    osc.backward(g, s0)
+    run(s0)
     per_ray = (time.perf_counter() - t) / max(1, n_rays // s0)
     # two passes: the first corrects the calibration (cold caches, tiny sample)
     for _ in range(2):
         stride = max(1, int(n_rays / max(1.0, budget_s / max(per_ray, 1e-9))))
         ids = np.arange(0, n_rays, stride)
         t = time.perf_counter()
-        irr = osc.forward_sampled(stride)
-        _, g = oracle.loss(irr, 0)
-        osc.backward(g, stride)
+        run(stride)
         el = time.perf_counter() - t
         per_ray = el / len(ids)
         if el >= 0.5 * budget_s:
             break
     recs = osc.trace_rays(ids)
     n_int = int(sum(r.n_events for r in recs))
+    what = "forward" if forward_only else "forward + loss + adjoint"
     return {"value": n_int / el, "unit": UNIT, "cores": 1, "kind": "oracle",
             "sample": f"every {stride}th ray of the workload ({len(ids)} rays, {n_int} interactions), "
-                      f"forward + loss + adjoint, {el:.1f} s single-threaded FP64 C"}
+                      f"{what}, {el:.1f} s single-threaded FP64 C"}
 
 
 def copy_probe(torch, mib: int = 1024, reps: int = 5):
@@ -108,6 +112,14 @@ def copy_probe(torch, mib: int = 1024, reps: int = 5):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": reps}))
 
 
+def design_slice(inp, d):
+    """Inputs of design d alone (for per-design launches)."""
+    out = dict(inp)
+    for k in ("thk", "mat", "n_layers"):
+        out[k] = inp[k][d:d + 1].copy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +127,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32"])
     ap.add_argument("--workload", default="diff_1200")
+    ap.add_argument("--rays-per-point", type=int, default=0, help="override the workload's rays per point")
+    ap.add_argument("--forward-only", action="store_true", help="time the forward trace alone")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one step in a graph (device step counter) and time its replays")
+    ap.add_argument("--autotune", action="store_true", help="autotune launch parameters first")
+    ap.add_argument("--per-design", action="store_true",
+                    help="also time one launch per design (the batched workload) for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -122,9 +141,11 @@ def main():
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only; the per-GPU kernel is the whole "
-                                   "measured path (see DESIGN.md for how it would shard)", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "only one GPU is measured: the per-GPU kernel at its real shape is the whole "
+                                   "measured path; sharding over GPUs is not built", "n_gpus": a.gpus}))
         sys.exit(2)
+
+    import dataclasses
 
     import numpy as np
     import torch
@@ -137,23 +158,36 @@ def main():
     import paper_2601_04370_amd as gwg
 
     w = inputs.workload(a.workload)
+    if a.rays_per_point:
+        w = dataclasses.replace(w, rays_per_point=a.rays_per_point)
     inp = inputs.make_inputs(w)
     scene = gwg.SceneSpec.from_workload(w, inp)
     prec = gwg.PRECISIONS[a.precision]
     ctx = gwg.Context(0)
     dev = torch.device("cuda", 0)
     thk = torch.tensor(inp["thk"], dtype=torch.float64, device=dev)
+    fo = a.forward_only
+    extra = {}
+    if a.autotune:
+        t = time.perf_counter()
+        extra["tuning"] = ctx.autotune(scene, thk, w.seed, prec, grad=not fo)
+        extra["autotune_s"] = time.perf_counter() - t
 
-    def step(k, ev=None):
+    def step(k, ev=None, sc=scene, th=thk):
         if ev:
             ev[0].record()
-        _, _, irr, _, _ = ctx.trace_forward(scene, thk, w.seed, k, prec, grad=True)
+        _, _, irr, _, _ = ctx.trace_forward(sc, th, w.seed, k, prec, grad=not fo)
         if ev:
             ev[1].record()
+        if fo:
+            if ev:
+                ev[2].record()
+                ev[3].record()
+            return irr
         _, dLdI = ctx.loss(irr, 0)
         if ev:
             ev[2].record()
-        g = ctx.trace_backward(dLdI, scene)
+        g = ctx.trace_backward(dLdI, sc)
         if ev:
             ev[3].record()
         return g
@@ -177,30 +211,79 @@ def main():
     # the launch stream), for the roofline
     n_t = min(a.steps, gwg.TIMING_RING)
     kfwd_ms = ctx.kernel_times(gwg.KERNEL_FORWARD, n_t)
-    kbwd_ms = ctx.kernel_times(gwg.KERNEL_ADJOINT, n_t)
+    kbwd_ms = ctx.kernel_times(gwg.KERNEL_ADJOINT, n_t) if not fo else [0.0]
     ctx.set_timing(False)
+
+    if a.graph:
+        # one captured step (device step counter advanced inside), replayed
+        d_step = torch.zeros(1, dtype=torch.int32, device=dev)
+        ctx.set_step_source(d_step)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step(a.warmup + a.steps)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step(a.warmup + a.steps)
+            d_step.add_(1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(a.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        g_wall = time.perf_counter() - tg
+        ctx.set_step_source(None)
+        extra["graph_ms_per_step"] = g_wall / a.steps * 1e3
+        extra["eager_ms_per_step"] = wall / a.steps * 1e3
 
     # counters of the timed steps (recomputed untimed: same seeds, same paths)
     inter = hits = lay_f = lay_b = lay_a = fp64h = 0
     for i in range(a.steps):
-        _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True, grad=True)
-        _, dLdI = ctx.loss(irr, 0)
-        _, bst = ctx.trace_backward(dLdI, scene, stats=True)
+        _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True, grad=not fo)
         inter += st["interactions"]
         hits += st["prma_hits"]
         lay_f += st["layer_steps"]
         fp64h += st["fp64_hits"]
-        lay_b += bst["layer_steps"]
-        lay_a += bst["adjoint_layer_steps"]
+        if not fo:
+            _, dLdI = ctx.loss(irr, 0)
+            _, bst = ctx.trace_backward(dLdI, scene, stats=True)
+            lay_b += bst["layer_steps"]
+            lay_a += bst["adjoint_layer_steps"]
     K = a.steps
+    if a.graph:
+        wall = extra["graph_ms_per_step"] * 1e-3 * K
     value = inter / wall
+
+    if a.per_design:
+        # the same batch as one launch per design (64 forward + 64 adjoint launches)
+        scenes = []
+        for d in range(w.n_designs):
+            inp_d = design_slice(inp, d)
+            scenes.append((gwg.SceneSpec.from_workload(w, inp_d),
+                           torch.tensor(inp_d["thk"], dtype=torch.float64, device=dev)))
+        for sc_d, th_d in scenes:
+            step(0, sc=sc_d, th=th_d)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for i in range(K):
+            for sc_d, th_d in scenes:
+                step(a.warmup + i, sc=sc_d, th=th_d)
+        torch.cuda.synchronize()
+        pd_wall = time.perf_counter() - tp
+        extra["per_design_ms_per_step"] = pd_wall / K * 1e3
+        extra["batched_speedup_vs_per_design"] = pd_wall / wall
+
     f_fwd = FLOP_FWD_LAYER * lay_f / K
     f_bwd = (FLOP_FWD_LAYER * lay_b + FLOP_ADJ_LAYER * lay_a) / K
     t_fwd = float(np.mean(kfwd_ms)) * 1e-3
     t_bwd = float(np.mean(kbwd_ms)) * 1e-3
     # the adjoint launch is the entry kernel (plus the regenerating kernel,
     # which only runs for items whose entry regions overflowed)
-    if t_bwd >= t_fwd:
+    if not fo and t_bwd >= t_fwd:
         kname, flops, tk = "k_adj_entries", f_bwd, t_bwd
     else:
         kname, flops, tk = "k_trace_fwd", f_fwd, t_fwd
@@ -208,25 +291,30 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64, "traffic": load_traffic(kname, a.workload, a.precision),
             "kernel": kname, "kernel_ms": tk * 1e3}
+    extra.update({"interactions_per_step": inter / K, "mirror_hits_per_step": hits / K,
+                  "mirror_hits_per_s": hits / wall, "fp64_hit_fraction": fp64h / max(hits, 1),
+                  "fwd_ms": float(np.mean(fwd_ms)), "loss_ms": float(np.mean(loss_ms)),
+                  "bwd_ms": float(np.mean(bwd_ms)), "fwd_kernel_ms": t_fwd * 1e3,
+                  "fwd_tflops": f_fwd / t_fwd / 1e12})
+    if not fo:
+        extra.update({"bwd_kernel_ms": t_bwd * 1e3, "bwd_tflops": f_bwd / t_bwd / 1e12})
     out = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": a.warmup,
+        "metric": METRIC if not fo else "fwd ray-surface interactions/s",
+        "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == gwg.FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": a.workload, "designs": w.n_designs, "mirrors": w.n_mirrors,
                    "layers_per_mirror": w.max_layers, "thickness_params": w.n_params,
                    "wavelengths": len(w.lambdas_nm), "fov_points": w.n_fov,
                    "rays_per_point": w.rays_per_point, "rays_per_step": w.n_rays,
-                   "bins": list(w.bins), "max_events": w.max_events, "precision": a.precision},
+                   "bins": list(w.bins), "max_events": w.max_events, "precision": a.precision,
+                   "step": "forward" if fo else "forward+loss+adjoint",
+                   "launch": "graph" if a.graph else "eager"},
         "roofline": roof,
-        "extra": {"interactions_per_step": inter / K, "mirror_hits_per_step": hits / K,
-                  "mirror_hits_per_s": hits / wall, "fp64_hit_fraction": fp64h / max(hits, 1),
-                  "fwd_ms": float(np.mean(fwd_ms)), "loss_ms": float(np.mean(loss_ms)),
-                  "bwd_ms": float(np.mean(bwd_ms)), "fwd_kernel_ms": t_fwd * 1e3, "bwd_kernel_ms": t_bwd * 1e3,
-                  "fwd_tflops": f_fwd / t_fwd / 1e12,
-                  "bwd_tflops": f_bwd / t_bwd / 1e12},
+        "extra": extra,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, inp, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, inp, a.cpu_seconds, forward_only=fo)
     print(json.dumps(out), flush=True)
 
 

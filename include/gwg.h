@@ -219,6 +219,11 @@ int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
                       gwg_ray_record* records, int64_t record_stride,
                       gwg_stats* stats, void* stream);
 
+/* *kept = 1 if the last gwg_trace_forward (or the one recorded by a stream
+ * capture) stored adjoint entries, so that gwg_trace_backward runs the
+ * thin-film adjoints only; 0 if the backward will regenerate the paths. */
+int gwg_forward_kept_entries(const gwg_ctx* ctx, int32_t* kept);
+
 /* Gradient of a loss with respect to every layer thickness, given
  * d_dL_dI (device f64, the eyebox shape of the last forward).  The sampled
  * paths of the last forward are regenerated (same seed and step), so the
@@ -274,7 +279,7 @@ int gwg_set_step_source(gwg_ctx* ctx, const uint32_t* d_step);
 
 /* Autotuner.  Times the forward trace of this scene (same arguments as
  * gwg_trace_forward, step 0) for workgroup sizes 256/128 and ray tiles of
- * 1, 2 and 4 times the automatic tile, checks that the eyebox bins are
+ * 1/4 to 4 times the automatic tile, checks that the eyebox bins are
  * bit-identical across them (scenes of up to 2^24 bins), then times the
  * adjoint (dL/dI = 1) for adjoint workgroup sizes 128/64, and keeps the
  * fastest as the context's tuning (*out).  Results are cached in the

@@ -424,19 +424,22 @@ int pick_bwd_wg(gwg_ctx* c, const SceneDev& s)
 
 void set_tiles(SceneDev& s, int64_t rays_per_tile, int wg, int n_cu)
 {
-    int64_t total = (int64_t)s.D * s.n_lsel * s.F * s.N;
+    const int64_t points = (int64_t)s.D * s.n_lsel * s.F;
     int64_t rpt = rays_per_tile;
     if (rpt <= 0) {
-        // aim for at least 8 workgroups per CU while keeping >= 4 rays per lane
-        int64_t target_items = (int64_t)std::max(n_cu, 1) * 8;
-        rpt = (total + target_items - 1) / target_items;
+        // Whole points while there are at least ~2 per resident workgroup
+        // (two per CU); otherwise split every point into equal tiles of at
+        // least 4 rays per lane.
+        const int64_t target = (int64_t)std::max(n_cu, 1) * 4;
+        const int64_t tiles = points >= target ? 1 : (target + points - 1) / points;
+        rpt = (s.N + tiles - 1) / tiles;
         rpt = std::max<int64_t>(rpt, (int64_t)wg * 4);
         rpt = ((rpt + wg - 1) / wg) * wg;
     }
     if (rpt > s.N) rpt = s.N;
     s.rays_per_tile = rpt;
     s.tiles_per_point = (s.N + rpt - 1) / rpt;
-    s.n_items = (int64_t)s.D * s.n_lsel * s.F * s.tiles_per_point;
+    s.n_items = points * s.tiles_per_point;
 }
 
 int read_stats(gwg_ctx* c, hipStream_t s, gwg_stats* stats)
@@ -668,16 +671,25 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
         const int64_t per_ray = c->tune.adj_entries_per_ray > 0 ? c->tune.adj_entries_per_ray : kAdjEntriesPerRay;
         const int64_t cap_w = ((sc.rays_per_tile + wg - 1) / wg) * 64 * per_ray;
         const int64_t total = sc.n_items * waves * cap_w;
-        const double bytes = (double)total * kEntFields * sizeof(double) + (double)sc.n_items * (waves + 1) * 4.0;
-        size_t free_b = 0, total_b = 0;
-        if (!cap) (void)hipMemGetInfo(&free_b, &total_b);
-        const double room = cap ? (double)c->adj_ent.bytes : 0.5 * (double)free_b + (double)c->adj_ent.bytes;
-        if (bytes <= std::min<double>(kAdjBudgetBytes, room)) {
-            rc = ensure_buf(c, c->adj_ent, sizeof(double) * (size_t)(total * kEntFields), cap, "alloc adjoint entries");
+        const size_t ent_b = sizeof(double) * (size_t)(total * kEntFields);
+        const size_t cnt_b = sizeof(int32_t) * (size_t)(sc.n_items * waves);
+        const size_t ovf_b = sizeof(int32_t) * (size_t)sc.n_items;
+        bool fits;
+        if (cap) {
+            // nothing may be allocated: use the entries if the buffers already hold them
+            fits = c->adj_ent.p && c->adj_ent.bytes >= ent_b && c->adj_cnt.bytes >= cnt_b && c->adj_ovf.bytes >= ovf_b;
+        } else {
+            size_t free_b = 0, total_b = 0;
+            (void)hipMemGetInfo(&free_b, &total_b);
+            const double bytes = (double)ent_b + (double)cnt_b + (double)ovf_b;
+            fits = bytes <= std::min<double>(kAdjBudgetBytes, 0.5 * (double)free_b + (double)c->adj_ent.bytes);
+        }
+        if (fits) {
+            rc = ensure_buf(c, c->adj_ent, ent_b, cap, "alloc adjoint entries");
             if (rc) return rc;
-            rc = ensure_buf(c, c->adj_cnt, sizeof(int32_t) * (size_t)(sc.n_items * waves), cap, "alloc entry counts");
+            rc = ensure_buf(c, c->adj_cnt, cnt_b, cap, "alloc entry counts");
             if (rc) return rc;
-            rc = ensure_buf(c, c->adj_ovf, sizeof(int32_t) * (size_t)sc.n_items, cap, "alloc overflow flags");
+            rc = ensure_buf(c, c->adj_ovf, ovf_b, cap, "alloc overflow flags");
             if (rc) return rc;
             HIP_CHECK(c, launch_fill_u32((uint32_t*)c->adj_ovf.p, sc.n_items, 0u, s), "zero overflow flags");
             c->adj = AdjStore{ (double*)c->adj_ent.p, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, cap_w, total, waves };
@@ -799,6 +811,13 @@ int gwg_loss(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
     return GWG_OK;
 }
 
+int gwg_forward_kept_entries(const gwg_ctx* c, int32_t* kept)
+{
+    if (!c || !kept) return GWG_E_INVAL;
+    *kept = (c->have_forward && c->adj_valid) ? 1 : 0;
+    return GWG_OK;
+}
+
 int gwg_set_step_source(gwg_ctx* c, const uint32_t* d_step)
 {
     if (!c) return GWG_E_INVAL;
@@ -892,12 +911,13 @@ int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const g
         if (fwd_smem_bytes(sc0, wg, lds_bins) > 65536) continue;
         SceneDev t = sc0;
         set_tiles(t, 0, wg, c->n_cu);
-        int64_t last = -1;
-        for (int mult : { 1, 2, 4 }) {
-            int64_t rpt = std::min<int64_t>(t.rays_per_tile * mult, sc0.N);
-            rpt = ((rpt + wg - 1) / wg) * wg;
-            if (rpt == last) continue;
-            last = rpt;
+        std::vector<int64_t> seen;
+        for (int shift : { 0, -1, 1, -2, 2 }) {
+            int64_t rpt = shift >= 0 ? t.rays_per_tile << shift : t.rays_per_tile >> -shift;
+            rpt = std::max<int64_t>(rpt, (int64_t)wg * 4);
+            rpt = std::min<int64_t>(((rpt + wg - 1) / wg) * wg, sc0.N);
+            if (std::find(seen.begin(), seen.end(), rpt) != seen.end()) continue;
+            seen.push_back(rpt);
             gwg_tuning cand = saved;
             cand.block_threads = wg;
             cand.rays_per_block = rpt;

@@ -99,7 +99,7 @@ class Tuning(C.Structure):
 #: every function declared in include/gwg.h
 EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gwg_tmm_rt",
            "gwg_trace_forward", "gwg_trace_backward", "gwg_loss", "gwg_set_tuning", "gwg_get_tuning",
-           "gwg_set_timing", "gwg_kernel_times", "gwg_set_step_source", "gwg_autotune"]
+           "gwg_set_timing", "gwg_kernel_times", "gwg_set_step_source", "gwg_autotune", "gwg_forward_kept_entries"]
 
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 GWG_FWD_GRAD = 1
@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH):
     L.gwg_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.gwg_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.gwg_set_step_source.argtypes = [C.c_void_p, C.c_void_p]
+    L.gwg_forward_kept_entries.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
     L.gwg_autotune.argtypes = [C.c_void_p, C.POINTER(Slab), C.POINTER(Prma), C.POINTER(Materials),
                                C.POINTER(Stacks), C.POINTER(Rays), C.c_uint64, C.c_int32, C.c_uint32,
                                C.c_char_p, C.POINTER(Tuning), C.c_void_p]
@@ -273,6 +274,12 @@ class Context:
                    adj_entries_per_ray=0):
         t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block, adj_entries_per_ray)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
+
+    def forward_kept_entries(self) -> bool:
+        """True if the last forward stored adjoint entries for the backward."""
+        v = C.c_int32(0)
+        self._check(self.lib.gwg_forward_kept_entries(self.h, C.byref(v)))
+        return bool(v.value)
 
     def set_step_source(self, d_step=None):
         """Device int32/uint32 tensor [1] whose value is added to `step` by the

@@ -30,6 +30,7 @@ def _grad_case(gctx, orc, w, inp, precision=0, stride=1, tile=0, bwd_wg=0, mode=
     gctx.set_tuning(bwd_rays_per_block=tile, bwd_block_threads=bwd_wg, adj_entries_per_ray=per_ray)
     try:
         gctx.trace_forward(scene, thk, w.seed, 0, precision, grad=grad)
+        assert gctx.forward_kept_entries() == grad
         g, st = gctx.trace_backward(torch.tensor(dLdI), scene, sample_stride=stride, stats=True)
         g = g.cpu().numpy()
         print(f"  mode {mode}: regenerated rays {st['rays']}, adjoint hits {st['adjoint_hits']}", flush=True)

@@ -48,6 +48,8 @@ def test_graph_replays_match_eager_steps(gctx):
             irr_g, g_g = _step(gctx, scene, thk, w.seed, 5)
             d_step.add_(1)
         torch.cuda.synchronize()
+        # the captured forward kept the adjoint entries (nothing allocated during capture)
+        assert gctx.forward_kept_entries()
         d_step.zero_()
         torch.cuda.synchronize()
         for k in range(3):
