@@ -251,75 +251,96 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
                                             double* grad_row, double* __restrict__ chk, int64_t cstride)
 {
     // 1) exit -> incident sweep, checkpoints w_{kSeg}, w_{2 kSeg}, ...
+    //    (LDS reads run ahead: thickness and slot two layers, parameters one)
+    if (L <= 0) return;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
     V2d vp = { 1.0, 0.0, eta0p, 0.0 };
-    for (int jj = L - 1; jj >= 0; --jj) {
-        const int idx = front ? jj : (L - 1 - jj);
-        double kq, xs, ys, xp, yp, C, S;
+    {
+        const int dir = front ? -1 : 1;          // stack index step toward the incident side
+        int idx = front ? L - 1 : 0;
+        const int last = front ? 0 : L - 1;
+        double t0 = thk[idx];
+        double kq, xs, ys, xp, yp;
         sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-        layer_cs(kq, thk[idx], &C, &S);         // t = 0 gives the identity exactly
-        step_real_d(vs, C, S * xs, S * ys);
-        step_real_d(vp, C, S * xp, S * yp);
-        if (jj > 0 && (jj % kSeg) == 0) {
-            double* c = chk + (int64_t)(jj / kSeg) * 8 * cstride;
-            c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
-            c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
+        int idx1 = idx == last ? idx : idx + dir;
+        double t1 = thk[idx1];
+        int s1 = slot[idx1];
+        for (int jj = L - 1; jj >= 0; --jj) {
+            const int idx2 = idx1 == last ? idx1 : idx1 + dir;
+            const double t2 = thk[idx2];
+            const int s2 = slot[idx2];
+            double kq1, xs1, ys1, xp1, yp1, C, S;
+            sl.lossless(s1, kq1, xs1, ys1, xp1, yp1);
+            layer_cs(kq, t0, &C, &S);               // t = 0 gives the identity exactly
+            step_real_d(vs, C, S * xs, S * ys);
+            step_real_d(vp, C, S * xp, S * yp);
+            if (jj > 0 && (jj % kSeg) == 0) {
+                double* c = chk + (int64_t)(jj / kSeg) * 8 * cstride;
+                c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
+                c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
+            }
+            t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+            t1 = t2; s1 = s2; idx1 = idx2;
         }
     }
     // 2) cotangent rows of the taken coefficients
     cd u1s, u2s, u1p, u2p;
     coef_cotangent(vs, eta0s, reflect, false, Gs, &u1s, &u2s);
     coef_cotangent(vp, eta0p, reflect, true, Gp, &u1p, &u2p);
-    // 3) incident -> exit covector sweep, segment by segment
+    // 3) incident -> exit covector sweep, segment by segment.  Every segment
+    //    has kSeg layers: layers past the end of the stack get t = 0 (the
+    //    identity, C = 1, S = 0 exactly) and add no gradient, so all loads of
+    //    a segment are independent of the arithmetic and issued first.
     const double k2 = 2.0 * k0;
     const int nseg = (L + kSeg - 1) / kSeg;
     for (int k = 0; k < nseg; ++k) {
         const int lo = k * kSeg;
-        const int hi = min(lo + kSeg, L);
         V2d ws, wp;
-        if (hi == L) {
+        if (lo + kSeg >= L) {
             ws = V2d{ 1.0, 0.0, eta0s, 0.0 };
             wp = V2d{ 1.0, 0.0, eta0p, 0.0 };
         } else {
-            const double* c = chk + (int64_t)(hi / kSeg) * 8 * cstride;
+            const double* c = chk + (int64_t)((lo + kSeg) / kSeg) * 8 * cstride;
             ws = V2d{ c[0], c[cstride], c[2 * cstride], c[3 * cstride] };
             wp = V2d{ c[4 * cstride], c[5 * cstride], c[6 * cstride], c[7 * cstride] };
+        }
+        int sidx[kSeg], sslot[kSeg];
+        double st[kSeg];
+#pragma unroll
+        for (int i = 0; i < kSeg; ++i) {
+            const int jj = lo + i;
+            const int jc = jj < L ? jj : L - 1;
+            sidx[i] = front ? jc : (L - 1 - jc);
+            sslot[i] = slot[sidx[i]];
+            st[i] = jj < L ? thk[sidx[i]] : 0.0;
         }
         V2d segs[kSeg], segp[kSeg];
         double segC[kSeg], segS[kSeg];
 #pragma unroll
         for (int i = kSeg - 1; i >= 0; --i) {
-            const int jj = lo + i;
-            if (jj < hi) {
-                const int idx = front ? jj : (L - 1 - jj);
-                double kq, xs, ys, xp, yp, C, S;
-                sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-                layer_cs(kq, thk[idx], &C, &S);
-                segC[i] = C; segS[i] = S;
-                step_real_d(ws, C, S * xs, S * ys);
-                step_real_d(wp, C, S * xp, S * yp);
-                segs[i] = ws; segp[i] = wp;
-            }
+            double kq, xs, ys, xp, yp, C, S;
+            sl.lossless(sslot[i], kq, xs, ys, xp, yp);
+            layer_cs(kq, st[i], &C, &S);
+            segC[i] = C; segS[i] = S;
+            step_real_d(ws, C, S * xs, S * ys);
+            step_real_d(wp, C, S * xp, S * yp);
+            segs[i] = ws; segp[i] = wp;
         }
 #pragma unroll
         for (int i = 0; i < kSeg; ++i) {
-            const int jj = lo + i;
-            if (jj < hi) {
-                const int idx = front ? jj : (L - 1 - jj);
-                double kq, xs, ys, xp, yp;
-                sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-                const double sg = kq < 0.0 ? -1.0 : 1.0;
-                // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
-                const double i_s1 = u1s.re * segs[i].ci + u1s.im * segs[i].cr;   // Im(u1s C_s)
-                const double i_s2 = u2s.re * segs[i].bi + u2s.im * segs[i].br;   // Im(u2s B_s)
-                const double i_p1 = u1p.re * segp[i].ci + u1p.im * segp[i].cr;   // Im(u1p C_p)
-                const double i_p2 = u2p.re * segp[i].bi + u2p.im * segp[i].br;   // Im(u2p B_p)
-                const double g = k2 * (i_s1 + sg * ys * (ys * i_s2 + xp * i_p1 + yp * i_p2));
-                atomicAdd(&grad_row[idx], g);
-                const double C = segC[i], S = segS[i];
-                cov_step_real(u1s, u2s, C, S * xs, S * ys);
-                cov_step_real(u1p, u2p, C, S * xp, S * yp);
-            }
+            double kq, xs, ys, xp, yp;
+            sl.lossless(sslot[i], kq, xs, ys, xp, yp);
+            const double sg = kq < 0.0 ? -1.0 : 1.0;
+            // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
+            const double i_s1 = u1s.re * segs[i].ci + u1s.im * segs[i].cr;   // Im(u1s C_s)
+            const double i_s2 = u2s.re * segs[i].bi + u2s.im * segs[i].br;   // Im(u2s B_s)
+            const double i_p1 = u1p.re * segp[i].ci + u1p.im * segp[i].cr;   // Im(u1p C_p)
+            const double i_p2 = u2p.re * segp[i].bi + u2p.im * segp[i].br;   // Im(u2p B_p)
+            const double g = k2 * (i_s1 + sg * ys * (ys * i_s2 + xp * i_p1 + yp * i_p2));
+            if (lo + i < L) atomicAdd(&grad_row[sidx[i]], g);
+            const double C = segC[i], S = segS[i];
+            cov_step_real(u1s, u2s, C, S * xs, S * ys);
+            cov_step_real(u1p, u2p, C, S * xp, S * yp);
         }
     }
 }

@@ -164,6 +164,17 @@ __device__ inline void sincos_cw(float x, float* s, float* c)
 // Hyperbolic: r = a / 2^k <= pi/4, then k doublings
 // (sinh 2r = 2 sinh r cosh r, cosh 2r = cosh^2 r + sinh^2 r).
 // Truncation as for sincos_cw (degree 15/16 in f64, 9/10 in f32).
+// Taylor coefficients 1/n!, n = 0..16, in constant memory: uniform operands
+// that the FMAs of the polynomials below take directly from scalar registers.
+__constant__ double kInvFact[17] = {
+    inv_fact(0), inv_fact(1), inv_fact(2), inv_fact(3), inv_fact(4), inv_fact(5), inv_fact(6), inv_fact(7),
+    inv_fact(8), inv_fact(9), inv_fact(10), inv_fact(11), inv_fact(12), inv_fact(13), inv_fact(14),
+    inv_fact(15), inv_fact(16) };
+__constant__ float kInvFactF[11] = {
+    (float)inv_fact(0), (float)inv_fact(1), (float)inv_fact(2), (float)inv_fact(3), (float)inv_fact(4),
+    (float)inv_fact(5), (float)inv_fact(6), (float)inv_fact(7), (float)inv_fact(8), (float)inv_fact(9),
+    (float)inv_fact(10) };
+
 __device__ inline void gtrig(double a, bool hyper, double* C, double* S)
 {
 #pragma clang fp contract(fast)
@@ -182,22 +193,22 @@ __device__ inline void gtrig(double a, bool hyper, double* C, double* S)
         r = ldexp(a, -k);
     }
     double u = hyper ? r * r : -(r * r);
-    double ps = inv_fact(15);
-    ps = fma(ps, u, inv_fact(13));
-    ps = fma(ps, u, inv_fact(11));
-    ps = fma(ps, u, inv_fact(9));
-    ps = fma(ps, u, inv_fact(7));
-    ps = fma(ps, u, inv_fact(5));
-    ps = fma(ps, u, inv_fact(3));
+    double ps = kInvFact[15];
+    ps = fma(ps, u, kInvFact[13]);
+    ps = fma(ps, u, kInvFact[11]);
+    ps = fma(ps, u, kInvFact[9]);
+    ps = fma(ps, u, kInvFact[7]);
+    ps = fma(ps, u, kInvFact[5]);
+    ps = fma(ps, u, kInvFact[3]);
     double sn = fma(r * u, ps, r);
-    double pc = inv_fact(16);
-    pc = fma(pc, u, inv_fact(14));
-    pc = fma(pc, u, inv_fact(12));
-    pc = fma(pc, u, inv_fact(10));
-    pc = fma(pc, u, inv_fact(8));
-    pc = fma(pc, u, inv_fact(6));
-    pc = fma(pc, u, inv_fact(4));
-    pc = fma(pc, u, inv_fact(2));
+    double pc = kInvFact[16];
+    pc = fma(pc, u, kInvFact[14]);
+    pc = fma(pc, u, kInvFact[12]);
+    pc = fma(pc, u, kInvFact[10]);
+    pc = fma(pc, u, kInvFact[8]);
+    pc = fma(pc, u, kInvFact[6]);
+    pc = fma(pc, u, kInvFact[4]);
+    pc = fma(pc, u, kInvFact[2]);
     double cs = fma(u, pc, 1.0);
     if (!hyper) {
         int q = (int)n & 3;
@@ -233,16 +244,16 @@ __device__ inline void gtrig(float a, bool hyper, float* C, float* S)
         r = ldexpf(a, -k);
     }
     float u = hyper ? r * r : -(r * r);
-    float ps = (float)inv_fact(9);
-    ps = fmaf(ps, u, (float)inv_fact(7));
-    ps = fmaf(ps, u, (float)inv_fact(5));
-    ps = fmaf(ps, u, (float)inv_fact(3));
+    float ps = kInvFactF[9];
+    ps = fmaf(ps, u, kInvFactF[7]);
+    ps = fmaf(ps, u, kInvFactF[5]);
+    ps = fmaf(ps, u, kInvFactF[3]);
     float sn = fmaf(r * u, ps, r);
-    float pc = (float)inv_fact(10);
-    pc = fmaf(pc, u, (float)inv_fact(8));
-    pc = fmaf(pc, u, (float)inv_fact(6));
-    pc = fmaf(pc, u, (float)inv_fact(4));
-    pc = fmaf(pc, u, (float)inv_fact(2));
+    float pc = kInvFactF[10];
+    pc = fmaf(pc, u, kInvFactF[8]);
+    pc = fmaf(pc, u, kInvFactF[6]);
+    pc = fmaf(pc, u, kInvFactF[4]);
+    pc = fmaf(pc, u, kInvFactF[2]);
     float cs = fmaf(u, pc, 1.0f);
     if (!hyper) {
         int q = (int)n & 3;
