@@ -250,38 +250,32 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
                                             double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
                                             double* grad_row, double* __restrict__ chk, int64_t cstride)
 {
-    // 1) exit -> incident sweep, checkpoints w_{kSeg}, w_{2 kSeg}, ...
-    //    (LDS reads run ahead: thickness and slot two layers, parameters one)
+    // 1) exit -> incident sweep, checkpoints w_{kSeg}, w_{2 kSeg}, ...: first
+    //    the L % kSeg layers above the last multiple of kSeg, then whole
+    //    groups of kSeg layers, each ending in a checkpoint (group 0 in none)
     if (L <= 0) return;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
     V2d vp = { 1.0, 0.0, eta0p, 0.0 };
-    {
-        const int dir = front ? -1 : 1;          // stack index step toward the incident side
-        int idx = front ? L - 1 : 0;
-        const int last = front ? 0 : L - 1;
-        double t0 = thk[idx];
-        double kq, xs, ys, xp, yp;
+    auto layer_fwd = [&](int jj) {
+        const int idx = front ? jj : (L - 1 - jj);
+        double kq, xs, ys, xp, yp, C, S;
         sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-        int idx1 = idx == last ? idx : idx + dir;
-        double t1 = thk[idx1];
-        int s1 = slot[idx1];
-        for (int jj = L - 1; jj >= 0; --jj) {
-            const int idx2 = idx1 == last ? idx1 : idx1 + dir;
-            const double t2 = thk[idx2];
-            const int s2 = slot[idx2];
-            double kq1, xs1, ys1, xp1, yp1, C, S;
-            sl.lossless(s1, kq1, xs1, ys1, xp1, yp1);
-            layer_cs(kq, t0, &C, &S);               // t = 0 gives the identity exactly
-            step_real_d(vs, C, S * xs, S * ys);
-            step_real_d(vp, C, S * xp, S * yp);
-            if (jj > 0 && (jj % kSeg) == 0) {
-                double* c = chk + (int64_t)(jj / kSeg) * 8 * cstride;
-                c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
-                c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
-            }
-            t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
-            t1 = t2; s1 = s2; idx1 = idx2;
-        }
+        layer_cs(kq, thk[idx], &C, &S);             // t = 0 gives the identity exactly
+        step_real_d(vs, C, S * xs, S * ys);
+        step_real_d(vp, C, S * xp, S * yp);
+    };
+    auto checkpoint = [&](int g) {
+        double* c = chk + (int64_t)g * 8 * cstride;
+        c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
+        c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
+    };
+    const int ng = L / kSeg;
+    for (int jj = L - 1; jj >= ng * kSeg; --jj) layer_fwd(jj);
+    if (ng > 0 && ng * kSeg < L) checkpoint(ng);     // w_{ng kSeg}, after the top layers
+    for (int g = ng - 1; g >= 0; --g) {
+#pragma unroll
+        for (int i = kSeg - 1; i >= 0; --i) layer_fwd(g * kSeg + i);
+        if (g > 0) checkpoint(g);
     }
     // 2) cotangent rows of the taken coefficients
     cd u1s, u2s, u1p, u2p;
@@ -315,32 +309,31 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             st[i] = jj < L ? thk[sidx[i]] : 0.0;
         }
         V2d segs[kSeg], segp[kSeg];
-        double segC[kSeg], segS[kSeg];
+        double segC[kSeg], sXs[kSeg], sYs[kSeg], sXp[kSeg], sYp[kSeg];
+        double cys[kSeg], gys[kSeg], cxp[kSeg], cyp[kSeg];   // y_s, sg y_s, x_p, y_p
 #pragma unroll
         for (int i = kSeg - 1; i >= 0; --i) {
             double kq, xs, ys, xp, yp, C, S;
             sl.lossless(sslot[i], kq, xs, ys, xp, yp);
             layer_cs(kq, st[i], &C, &S);
-            segC[i] = C; segS[i] = S;
-            step_real_d(ws, C, S * xs, S * ys);
-            step_real_d(wp, C, S * xp, S * yp);
+            segC[i] = C;
+            sXs[i] = S * xs; sYs[i] = S * ys; sXp[i] = S * xp; sYp[i] = S * yp;
+            cys[i] = ys; gys[i] = kq < 0.0 ? -ys : ys; cxp[i] = xp; cyp[i] = yp;
+            step_real_d(ws, C, sXs[i], sYs[i]);
+            step_real_d(wp, C, sXp[i], sYp[i]);
             segs[i] = ws; segp[i] = wp;
         }
 #pragma unroll
         for (int i = 0; i < kSeg; ++i) {
-            double kq, xs, ys, xp, yp;
-            sl.lossless(sslot[i], kq, xs, ys, xp, yp);
-            const double sg = kq < 0.0 ? -1.0 : 1.0;
             // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
             const double i_s1 = u1s.re * segs[i].ci + u1s.im * segs[i].cr;   // Im(u1s C_s)
             const double i_s2 = u2s.re * segs[i].bi + u2s.im * segs[i].br;   // Im(u2s B_s)
             const double i_p1 = u1p.re * segp[i].ci + u1p.im * segp[i].cr;   // Im(u1p C_p)
             const double i_p2 = u2p.re * segp[i].bi + u2p.im * segp[i].br;   // Im(u2p B_p)
-            const double g = k2 * (i_s1 + sg * ys * (ys * i_s2 + xp * i_p1 + yp * i_p2));
+            const double g = k2 * (i_s1 + gys[i] * (cys[i] * i_s2 + cxp[i] * i_p1 + cyp[i] * i_p2));
             if (lo + i < L) atomicAdd(&grad_row[sidx[i]], g);
-            const double C = segC[i], S = segS[i];
-            cov_step_real(u1s, u2s, C, S * xs, S * ys);
-            cov_step_real(u1p, u2p, C, S * xp, S * yp);
+            cov_step_real(u1s, u2s, segC[i], sXs[i], sYs[i]);
+            cov_step_real(u1p, u2p, segC[i], sXp[i], sYp[i]);
         }
     }
 }
