@@ -211,11 +211,14 @@ __device__ inline void gtrig(double a, bool hyper, double* C, double* S)
     pc = fma(pc, u, kInvFact[2]);
     double cs = fma(u, pc, 1.0);
     if (!hyper) {
-        int q = (int)n & 3;
-        double so = (q & 1) ? cs : sn;
-        double co = (q & 1) ? sn : cs;
-        *S = (q & 2) ? -so : so;
-        *C = ((q + 1) & 2) ? -co : co;
+        // quadrant q = n mod 4: swap for odd q, then flip signs through the
+        // sign bit (S negative for q = 2, 3; C negative for q = 1, 2)
+        const unsigned q = (unsigned)(int)n;
+        const double so = (q & 1u) ? cs : sn;
+        const double co = (q & 1u) ? sn : cs;
+        const unsigned fs = (q & 2u) << 30, fc = ((q + 1u) & 2u) << 30;
+        *S = __hiloint2double(__double2hiint(so) ^ (int)fs, __double2loint(so));
+        *C = __hiloint2double(__double2hiint(co) ^ (int)fc, __double2loint(co));
     } else {
         for (int i = 0; i < k; ++i) {
             double s2 = 2.0 * sn * cs;
@@ -256,11 +259,11 @@ __device__ inline void gtrig(float a, bool hyper, float* C, float* S)
     pc = fmaf(pc, u, kInvFactF[2]);
     float cs = fmaf(u, pc, 1.0f);
     if (!hyper) {
-        int q = (int)n & 3;
-        float so = (q & 1) ? cs : sn;
-        float co = (q & 1) ? sn : cs;
-        *S = (q & 2) ? -so : so;
-        *C = ((q + 1) & 2) ? -co : co;
+        const unsigned q = (unsigned)(int)n;
+        const float so = (q & 1u) ? cs : sn;
+        const float co = (q & 1u) ? sn : cs;
+        *S = __uint_as_float(__float_as_uint(so) ^ ((q & 2u) << 30));
+        *C = __uint_as_float(__float_as_uint(co) ^ (((q + 1u) & 2u) << 30));
     } else {
         for (int i = 0; i < k; ++i) {
             float s2 = 2.0f * sn * cs;
