@@ -200,8 +200,8 @@ typedef struct {
  * random numbers from Philox4x32-10 with key (seed_lo, seed_hi ^ step_lo),
  * counter (id_lo, id_hi, block, tag): tag 0 block 0 gives the birth words,
  * tag 1 block h/4 the word of the h-th mirror hit.  step < 2^32.
- * flags: 0 or GWG_FWD_GRAD.  With GWG_FWD_GRAD (a gwg_trace_backward will
- * follow) the trace also runs the path part of the adjoint for every ray
+ * flags: 0, GWG_FWD_GRAD, or GWG_FWD_GRAD | GWG_FWD_MEMO.  With GWG_FWD_GRAD
+ * (a gwg_trace_backward will follow) the trace also runs the path part of the adjoint for every ray
  * that reaches the eyebox and keeps one entry per mirror hit in the context
  * (about 48 bytes per hit, within a fixed memory budget); the backward then
  * only runs the thin-film adjoints.  Without it (or beyond the budget) the
@@ -212,6 +212,12 @@ typedef struct {
  * The context remembers the scene, seed, step, precision and thk pointer
  * for gwg_trace_backward; thk must not change in between. */
 #define GWG_FWD_GRAD 1u
+/* GWG_FWD_MEMO (with GWG_FWD_GRAD): the backward solves one thin-film
+ * adjoint per distinct (kappa, mirror, side, branch) key of each work item,
+ * with the key's summed cotangents, instead of one per mirror hit (exact by
+ * linearity, up to summation order; the sums run in a fixed order).  Within a
+ * work item of a FoV grid the hits share a few keys. */
+#define GWG_FWD_MEMO 2u
 int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
                       const gwg_materials* mats, const gwg_stacks* stacks,
                       const gwg_rays* rays, uint64_t seed, uint64_t step,

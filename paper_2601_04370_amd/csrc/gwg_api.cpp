@@ -96,6 +96,7 @@ struct gwg_ctx {
     // adjoint entries recorded by the last forward (GWG_FWD_GRAD)
     DevBuf adj_ent, adj_cnt, adj_ovf, fwd_tape;
     bool adj_valid = false;
+    bool memo = false;           // thin-film adjoints per distinct hit key (GWG_FWD_MEMO)
     AdjStore adj{};
     // tuning
     gwg_tuning tune{};
@@ -639,7 +640,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     if (!out || !out->q_bins || !out->counts) return fail(c, GWG_E_INVAL, "eyebox outputs are NULL");
     if (out->fp_shift < 0 || out->fp_shift > 40) return fail(c, GWG_E_INVAL, "fp_shift out of range");
     if (records && record_stride < 1) return fail(c, GWG_E_INVAL, "record_stride must be >= 1");
-    if (flags & ~(uint32_t)GWG_FWD_GRAD) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(uint32_t)(GWG_FWD_GRAD | GWG_FWD_MEMO)) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     const bool cap = stream_capturing(s);
@@ -726,6 +727,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     c->fwd = sc;
     c->have_forward = true;
     c->adj_valid = adj;
+    c->memo = (flags & GWG_FWD_MEMO) != 0;
     if (stats) {
         rc = read_stats(c, s, stats);
         if (rc) return rc;
@@ -761,8 +763,11 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     const int64_t grid = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, KIND_BWD_REGEN, sc.precision, wg, smem));
     const int kind_e = sc.slot_complex == 0u ? KIND_ADJ_LOSSLESS : KIND_ADJ_ENTRIES;
     const int64_t grid_e = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, kind_e, sc.precision, wg, smem));
+    const int kind_m = sc.slot_complex == 0u ? KIND_ADJ_MEMO_LOSSLESS : KIND_ADJ_MEMO;
+    const int64_t grid_m = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, kind_m, sc.precision, 64, memo_smem_bytes(sc)));
     const int ML = sc.M * sc.Lmax;
-    const int64_t scratch_d = std::max(bwd_scratch_doubles(sc, grid, wg), entries ? adj_scratch_doubles(sc, grid_e, wg) : 0);
+    int64_t scratch_d = std::max(bwd_scratch_doubles(sc, grid, wg), entries ? adj_scratch_doubles(sc, grid_e, wg) : 0);
+    if (entries && c->memo) scratch_d = std::max(scratch_d, adj_scratch_doubles(sc, grid_m, 64));
     rc = ensure_buf(c, c->scratch, sizeof(double) * (size_t)scratch_d, cap, "alloc adjoint scratch");
     if (rc) return rc;
     rc = ensure_buf(c, c->partial, sizeof(double) * (size_t)sc.n_items * ML, cap, "alloc partial gradients");
@@ -771,7 +776,11 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     if (rc) return rc;
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
     if (c->timing && !cap) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].begin(), s), "timing event");
-    if (entries)
+    if (entries && c->memo)
+        HIP_CHECK(c, launch_adj_memo(sc, (int)grid_m, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
+                                     c->adj, (double*)c->scratch.p, s),
+                  "memoized adjoint kernel");
+    else if (entries)
         HIP_CHECK(c, launch_adj_entries(sc, wg, (int)grid_e, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
                                         c->adj, (double*)c->scratch.p, s),
                   "adjoint entry kernel");
@@ -836,7 +845,7 @@ int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const g
     int rc = check_scene(c, slab, prma, mats, stacks, rays);
     if (rc) return rc;
     if (precision < GWG_FP64 || precision > GWG_FP32) return fail(c, GWG_E_INVAL, "precision out of range");
-    if (flags & ~(uint32_t)GWG_FWD_GRAD) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(uint32_t)(GWG_FWD_GRAD | GWG_FWD_MEMO)) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     if (stream_capturing(s)) return fail(c, GWG_E_STATE, "gwg_autotune cannot run during stream capture");

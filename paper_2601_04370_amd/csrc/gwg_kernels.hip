@@ -101,6 +101,7 @@ __device__ inline void decode_item(const SceneDev& sc, int64_t item, int64_t* po
 
 #include "gwg_fwd_kernel.h"
 #include "gwg_bwd_kernel.h"
+#include "gwg_memo_kernel.h"
 
 // Sum per-item partial gradients in item order: grad[d][k] = sum_items(d) partial[item][k].
 __global__ void k_grad_reduce(const double* __restrict__ partial, int64_t items_per_design, int ML,
@@ -338,6 +339,10 @@ int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem)
         return blocks_per_cu(k_trace_bwd<GWG_FP32>, wg, smem);
     case KIND_ADJ_LOSSLESS:
         return blocks_per_cu(k_adj_entries<true>, wg, smem);
+    case KIND_ADJ_MEMO:
+        return blocks_per_cu(k_adj_memo<false>, 64, smem);
+    case KIND_ADJ_MEMO_LOSSLESS:
+        return blocks_per_cu(k_adj_memo<true>, 64, smem);
     default:
         return blocks_per_cu(k_adj_entries<false>, wg, smem);
     }
@@ -406,6 +411,19 @@ hipError_t launch_adj_entries(const SceneDev& sc, int wg, int grid_blocks, const
                            scratch, stats);
     else
         hipLaunchKernelGGL(k_adj_entries<false>, dim3((unsigned)grid_blocks), dim3(wg), sm, s, sc, dLdI, partial, st,
+                           scratch, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_memo(const SceneDev& sc, int grid_blocks, const double* dLdI, unsigned long long* stats,
+                           double* partial, const AdjStore& st, double* scratch, hipStream_t s)
+{
+    const size_t sm = memo_smem_bytes(sc);
+    if (sc.slot_complex == 0u)
+        hipLaunchKernelGGL(k_adj_memo<true>, dim3((unsigned)grid_blocks), dim3(64), sm, s, sc, dLdI, partial, st,
+                           scratch, stats);
+    else
+        hipLaunchKernelGGL(k_adj_memo<false>, dim3((unsigned)grid_blocks), dim3(64), sm, s, sc, dLdI, partial, st,
                            scratch, stats);
     return hipGetLastError();
 }

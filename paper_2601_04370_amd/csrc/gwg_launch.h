@@ -16,7 +16,8 @@ size_t bwd_smem_bytes(const SceneDev& sc, int wg);
 size_t tmm_smem_bytes(int L, int n_slots, int wg);
 int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
-enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3, KIND_ADJ_LOSSLESS = 4 };
+enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3, KIND_ADJ_LOSSLESS = 4,
+       KIND_ADJ_MEMO = 5, KIND_ADJ_MEMO_LOSSLESS = 6 };
 int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem);
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 int64_t adj_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
@@ -29,6 +30,9 @@ hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const d
 hipError_t launch_adj_entries(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI,
                               unsigned long long* stats, double* partial, const AdjStore& st, double* scratch,
                               hipStream_t s);
+size_t memo_smem_bytes(const SceneDev& sc);
+hipError_t launch_adj_memo(const SceneDev& sc, int grid_blocks, const double* dLdI, unsigned long long* stats,
+                           double* partial, const AdjStore& st, double* scratch, hipStream_t s);
 hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D,
                               double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s);
 hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double* irr, hipStream_t s);

@@ -1,0 +1,193 @@
+// Memoized thin-film adjoint.  Included by gwg_kernels.hip inside namespace gwg.
+//
+// The FoV beams are collimated, so within one work item (one design,
+// wavelength and FoV point) the mirror hits share a handful of distinct
+// (kappa, mirror, side, branch) keys: kappa is computed from direction bits
+// that every ray with the same event history shares exactly.  The thin-film
+// part of the gradient is linear in the cotangents,
+//     sum_h 2 Re(G_h dc(kappa_h)/dt) = 2 Re((sum_{h in key} G_h) dc(kappa_key)/dt),
+// so the backward sums the (dL/dI-scaled) cotangents of each key in entry
+// order and runs one thin-film adjoint per key.  One wave per work item; the
+// sums run in a fixed order, so the gradient is deterministic.  An item with
+// more than kMemoKeys keys is drained hit by hit instead.
+
+constexpr int kMemoKeys = 256;
+
+struct MemoLds {
+    unsigned long long* kbits;   // [kMemoKeys] bits of kappa
+    int* kmeta;                  // [kMemoKeys] mirror | front << 8 | reflected << 9
+    double* gsum;                // [4][kMemoKeys] sums of G_s (re, im), G_p (re, im)
+    int* sidx;                   // [64] key of each lane's entry in the current chunk (-1: none)
+    double* sg;                  // [4][64] the lane's scaled cotangents
+};
+
+__host__ __device__ inline int memo_lds_bytes() { return kMemoKeys * (8 + 4 + 32) + 64 * (4 + 32) + 64; }
+
+// Entry v (in item order) -> index of its record; cnt: the item's region counts.
+__device__ inline int64_t entry_index(const AdjStore& st, int64_t item, const int32_t* cnt, int v)
+{
+    int rr = 0, k = v;
+    while (k >= cnt[rr]) { k -= cnt[rr]; ++rr; }
+    return (item * st.waves + rr) * st.cap_w + k;
+}
+
+template <bool LOSSLESS>
+__global__ void __launch_bounds__(64) k_adj_memo(SceneDev sc, const double* __restrict__ dLdI,
+                                                 double* __restrict__ partial, AdjStore st,
+                                                 double* __restrict__ scratch,
+                                                 unsigned long long* __restrict__ stats)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int B = sc.bins_x * sc.bins_y;
+    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, 64, B, false, 1);
+    PointLds* pl = (PointLds*)(smem + lay.off_pl);
+    double* s_thk = (double*)(smem + lay.off_thk);
+    uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
+    double* s_sp = (double*)(smem + lay.off_sp);
+    double* gw = (double*)(smem + lay.off_grad);
+    unsigned long long* s_st = (unsigned long long*)(smem + lay.off_st);
+    unsigned char* mb = smem + align16(lay.total);
+    MemoLds mt;
+    mt.kbits = (unsigned long long*)mb;
+    mt.gsum = (double*)(mb + 8 * kMemoKeys);
+    mt.sg = (double*)(mb + 40 * kMemoKeys);
+    mt.kmeta = (int*)(mb + 40 * kMemoKeys + 32 * 64);
+    mt.sidx = (int*)(mb + 44 * kMemoKeys + 32 * 64);
+    const int lane = threadIdx.x;
+    const int ML = sc.M * sc.Lmax;
+    const LaneSlots3 sl = { s_sp + lane, 64, pl->nsq, pl->in2 };
+    const int64_t nthreads = (int64_t)gridDim.x * 64;
+    double* chk = scratch + (int64_t)blockIdx.x * 64 + lane;
+    for (int k = lane; k < ST_WORDS; k += 64) s_st[k] = 0ull;
+    unsigned long long c_keys = 0, c_lay = 0;
+
+    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+        if (st.ovf[item] != 0) continue;
+        int64_t point, i0, i1;
+        int d, l, f;
+        decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
+        __syncthreads();
+        stage_point(sc, d, l, f, pl, s_thk, s_slot);
+        for (int k = lane; k < ML; k += 64) gw[k] = 0.0;
+        __syncthreads();
+        const double* g_bins = dLdI + point * B;
+        const int32_t* cnt = st.cnt + item * st.waves;
+        int total = 0;
+        for (int w = 0; w < st.waves; ++w) total += cnt[w];
+        const double invN = 1.0 / (double)sc.N;
+
+        // pass 1: the item's keys, first appearance in entry order
+        int U = 0;
+        bool overflow = false;
+        for (int c = 0; c < total && !overflow; c += 64) {
+            const int v = c + lane;
+            unsigned long long kb = 0ull;
+            int km = 0, idx = -1;
+            bool valid = false;
+            if (v < total) {
+                const int64_t e = entry_index(st, item, cnt, v);
+                const int64_t meta = (int64_t)st.ent[5 * st.total + e];
+                valid = g_bins[(int)(meta >> 10)] != 0.0;
+                kb = (unsigned long long)__double_as_longlong(st.ent[e]);
+                km = (int)(meta & 1023);
+            }
+            if (valid)
+                for (int u = 0; u < U; ++u)
+                    if (mt.kbits[u] == kb && mt.kmeta[u] == km) { idx = u; break; }
+            for (;;) {
+                const unsigned long long open = __ballot(valid && idx < 0);
+                if (open == 0ull) break;
+                if (U == kMemoKeys) { overflow = true; break; }
+                const int leader = __ffsll((long long)open) - 1;
+                const unsigned long long lkb = __shfl(kb, leader, 64);
+                const int lkm = __shfl(km, leader, 64);
+                if (lane == 0) { mt.kbits[U] = lkb; mt.kmeta[U] = lkm; }
+                if (valid && idx < 0 && kb == lkb && km == lkm) idx = U;
+                ++U;
+            }
+            __syncthreads();
+        }
+
+        if (overflow) {
+            // too many keys: one thin-film adjoint per entry
+            for (int c = 0; c < total; c += 64) {
+                const int v = c + lane;
+                if (v < total) {
+                    const int64_t e = entry_index(st, item, cnt, v);
+                    const int64_t meta = (int64_t)st.ent[5 * st.total + e];
+                    const double gscale = g_bins[(int)(meta >> 10)] * invN;
+                    if (gscale != 0.0) {
+                        const cd Gs = cscale(mk(st.ent[1 * st.total + e], st.ent[2 * st.total + e]), gscale);
+                        const cd Gp = cscale(mk(st.ent[3 * st.total + e], st.ent[4 * st.total + e]), gscale);
+                        const int mm = (int)(meta & 1023);
+                        adjoint_hit<LOSSLESS>(sc, *pl, s_thk, s_slot, sl, gw, st.ent[e], Gs, Gp, mm, chk, nthreads);
+                        c_keys += 1;
+                        c_lay += (unsigned long long)pl->nlay[mm & 255];
+                    }
+                }
+            }
+        } else {
+            // pass 2: per-key sums of the scaled cotangents, in entry order
+            for (int k = lane; k < 4 * kMemoKeys; k += 64) mt.gsum[k] = 0.0;
+            __syncthreads();
+            for (int c = 0; c < total; c += 64) {
+                const int v = c + lane;
+                int idx = -1;
+                double g4[4] = { 0.0, 0.0, 0.0, 0.0 };
+                if (v < total) {
+                    const int64_t e = entry_index(st, item, cnt, v);
+                    const int64_t meta = (int64_t)st.ent[5 * st.total + e];
+                    const double gscale = g_bins[(int)(meta >> 10)] * invN;
+                    if (gscale != 0.0) {
+                        const unsigned long long kb = (unsigned long long)__double_as_longlong(st.ent[e]);
+                        const int km = (int)(meta & 1023);
+                        for (int u = 0; u < U; ++u)
+                            if (mt.kbits[u] == kb && mt.kmeta[u] == km) { idx = u; break; }
+                        for (int q = 0; q < 4; ++q) g4[q] = st.ent[(1 + q) * st.total + e] * gscale;
+                    }
+                }
+                mt.sidx[lane] = idx;
+                for (int q = 0; q < 4; ++q) mt.sg[q * 64 + lane] = g4[q];
+                __syncthreads();
+                for (int k = lane; k < U; k += 64) {
+                    double a0 = mt.gsum[k], a1 = mt.gsum[kMemoKeys + k];
+                    double a2 = mt.gsum[2 * kMemoKeys + k], a3 = mt.gsum[3 * kMemoKeys + k];
+                    for (int j = 0; j < 64; ++j)
+                        if (mt.sidx[j] == k) {
+                            a0 += mt.sg[j]; a1 += mt.sg[64 + j]; a2 += mt.sg[128 + j]; a3 += mt.sg[192 + j];
+                        }
+                    mt.gsum[k] = a0; mt.gsum[kMemoKeys + k] = a1;
+                    mt.gsum[2 * kMemoKeys + k] = a2; mt.gsum[3 * kMemoKeys + k] = a3;
+                }
+                __syncthreads();
+            }
+            // one thin-film adjoint per key
+            for (int b = 0; b < U; b += 64) {
+                const int k = b + lane;
+                if (k < U) {
+                    const cd Gs = mk(mt.gsum[k], mt.gsum[kMemoKeys + k]);
+                    const cd Gp = mk(mt.gsum[2 * kMemoKeys + k], mt.gsum[3 * kMemoKeys + k]);
+                    const int mm = mt.kmeta[k];
+                    adjoint_hit<LOSSLESS>(sc, *pl, s_thk, s_slot, sl, gw, __longlong_as_double((long long)mt.kbits[k]),
+                                          Gs, Gp, mm, chk, nthreads);
+                    c_keys += 1;
+                    c_lay += (unsigned long long)pl->nlay[mm & 255];
+                }
+            }
+        }
+        __syncthreads();
+        double* out = partial + item * (int64_t)ML;
+        for (int k = lane; k < ML; k += 64) out[k] = gw[k];
+    }
+    if (c_keys) atomicAdd(&s_st[ST_ADJ_HITS], c_keys);
+    if (c_lay) atomicAdd(&s_st[ST_ADJ_LAYERS], c_lay);
+    __syncthreads();
+    for (int k = lane; k < ST_WORDS; k += 64)
+        if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
+}
+
+size_t memo_smem_bytes(const SceneDev& sc)
+{
+    return (size_t)align16(smem_layout(sc.M, sc.Lmax, sc.n_slots, 64, sc.bins_x * sc.bins_y, false, 1).total) +
+           (size_t)memo_lds_bytes();
+}

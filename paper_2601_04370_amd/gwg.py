@@ -103,6 +103,7 @@ EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gw
 
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 GWG_FWD_GRAD = 1
+GWG_FWD_MEMO = 2
 
 _lib = None
 
@@ -338,10 +339,12 @@ class Context:
     # ---------------------------------------------------------------- trace
     def trace_forward(self, scene: SceneSpec, thk, seed: int, step: int = 0, precision: int = FP64,
                       record_stride: int = 0, stats: bool = False, want_irradiance: bool = True,
-                      grad: bool = False):
+                      grad: bool = False, memo: bool = False):
         """Returns (q_bins u64-as-int64, counts int32, irradiance f64 or None,
         records or None, stats dict or None); tensors on the context's GPU.
-        grad=True prepares the adjoint entries for a following trace_backward."""
+        grad=True prepares the adjoint entries for a following trace_backward;
+        memo=True (with grad) makes that backward solve one thin-film adjoint
+        per distinct hit key of each work item."""
         torch = self.torch
         dev = torch.device("cuda", self.device)
         assert tuple(thk.shape) == scene.thk_shape and thk.dtype == torch.float64 and thk.is_contiguous()
@@ -361,7 +364,7 @@ class Context:
         self.forward_id += 1
         rc = self.lib.gwg_trace_forward(self.h, C.byref(s), C.byref(p), C.byref(m), C.byref(st), C.byref(r),
                                         seed & 0xFFFFFFFFFFFFFFFF, step, precision,
-                                        GWG_FWD_GRAD if grad else 0, C.byref(eb),
+                                        (GWG_FWD_GRAD if grad else 0) | (GWG_FWD_MEMO if memo else 0), C.byref(eb),
                                         rec.data_ptr() if rec is not None else None, int(record_stride or 1),
                                         C.byref(sts) if sts is not None else None, _stream(torch, dev))
         if rc == GWG_E_OVERFLOW:

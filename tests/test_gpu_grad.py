@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 # backward modes: adjoint entries recorded by the forward; paths regenerated
 # by the backward; entry regions too small for some items (both kernels run)
-MODES = {"entries": (True, 0), "regen": (False, 0), "mixed": (True, 2)}
+MODES = {"entries": (True, 0), "regen": (False, 0), "mixed": (True, 2), "memo": (True, 0)}
 
 
 def _grad_case(gctx, orc, w, inp, precision=0, stride=1, tile=0, bwd_wg=0, mode="entries"):
@@ -29,7 +29,7 @@ def _grad_case(gctx, orc, w, inp, precision=0, stride=1, tile=0, bwd_wg=0, mode=
     grad, per_ray = MODES[mode]
     gctx.set_tuning(bwd_rays_per_block=tile, bwd_block_threads=bwd_wg, adj_entries_per_ray=per_ray)
     try:
-        gctx.trace_forward(scene, thk, w.seed, 0, precision, grad=grad)
+        gctx.trace_forward(scene, thk, w.seed, 0, precision, grad=grad, memo=(mode == "memo"))
         assert gctx.forward_kept_entries() == grad
         g, st = gctx.trace_backward(torch.tensor(dLdI), scene, sample_stride=stride, stats=True)
         g = g.cpu().numpy()
@@ -67,19 +67,19 @@ def test_backward_fp64_matches_oracle(gctx, orc, name, kw, stride, tile, mode):
             assert np.all(g[d, m, inp["n_layers"][d, m]:] == 0.0)
 
 
-@pytest.mark.parametrize("grad", [True, False])
-def test_backward_is_deterministic(gctx, orc, grad):
+@pytest.mark.parametrize("grad,memo", [(True, False), (False, False), (True, True)])
+def test_backward_is_deterministic(gctx, orc, grad, memo):
     w = inputs.small_variant("diff_1200", rays_per_point=128, fov_n=3)
     inp = inputs.make_inputs(w)
     scene = gwg.SceneSpec.from_workload(w, inp)
     thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
     rng = np.random.default_rng(0)
     dLdI = torch.tensor(rng.standard_normal(scene.shape))
-    gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=grad)
+    gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=grad, memo=memo)
     a = gctx.trace_backward(dLdI, scene).cpu().numpy()
     b = gctx.trace_backward(dLdI, scene).cpu().numpy()
     assert np.array_equal(a, b)
-    gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=grad)
+    gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=grad, memo=memo)
     c = gctx.trace_backward(dLdI, scene).cpu().numpy()
     assert np.array_equal(a, c)
 
@@ -112,7 +112,12 @@ def test_backward_full_size_entries_match_regeneration(gctx):
     ge, st = gctx.trace_backward(dLdI, scene, stats=True)
     gctx.trace_forward(scene, thk, w.seed, 3, 0, grad=False)
     gr = gctx.trace_backward(dLdI, scene)
-    ge, gr = ge.cpu().numpy(), gr.cpu().numpy()
+    gctx.trace_forward(scene, thk, w.seed, 3, 0, grad=True, memo=True)
+    gm, sm = gctx.trace_backward(dLdI, scene, stats=True)
+    ge, gr, gm = ge.cpu().numpy(), gr.cpu().numpy(), gm.cpu().numpy()
+    print(f"memoized: {sm['adjoint_hits']} thin-film adjoints for {st['adjoint_hits']} hits, "
+          f"max diff {np.max(np.abs(gm - gr)):.2e}", flush=True)
+    assert np.all(np.abs(gm - gr) <= 1e-10 * np.maximum(np.abs(gr), 1e-3 * np.max(np.abs(gr))))
     scale = np.max(np.abs(gr))
     print(f"full size entries vs regeneration: max |g| {scale:.3e} max diff {np.max(np.abs(ge - gr)):.2e} "
           f"regenerated rays {st['rays']} adjoint hits {st['adjoint_hits']}", flush=True)
