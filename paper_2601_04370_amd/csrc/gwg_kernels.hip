@@ -340,9 +340,9 @@ int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem)
     case KIND_ADJ_LOSSLESS:
         return blocks_per_cu(k_adj_entries<true>, wg, smem);
     case KIND_ADJ_MEMO:
-        return blocks_per_cu(k_adj_memo<false>, 64, smem);
+        return blocks_per_cu(k_adj_memo<false>, 64 * kMemoWaves, smem);
     case KIND_ADJ_MEMO_LOSSLESS:
-        return blocks_per_cu(k_adj_memo<true>, 64, smem);
+        return blocks_per_cu(k_adj_memo<true>, 64 * kMemoWaves, smem);
     default:
         return blocks_per_cu(k_adj_entries<false>, wg, smem);
     }
@@ -420,10 +420,10 @@ hipError_t launch_adj_memo(const SceneDev& sc, int grid_blocks, const double* dL
 {
     const size_t sm = memo_smem_bytes(sc);
     if (sc.slot_complex == 0u)
-        hipLaunchKernelGGL(k_adj_memo<true>, dim3((unsigned)grid_blocks), dim3(64), sm, s, sc, dLdI, partial, st,
+        hipLaunchKernelGGL(k_adj_memo<true>, dim3((unsigned)grid_blocks), dim3(64 * kMemoWaves), sm, s, sc, dLdI, partial, st,
                            scratch, stats);
     else
-        hipLaunchKernelGGL(k_adj_memo<false>, dim3((unsigned)grid_blocks), dim3(64), sm, s, sc, dLdI, partial, st,
+        hipLaunchKernelGGL(k_adj_memo<false>, dim3((unsigned)grid_blocks), dim3(64 * kMemoWaves), sm, s, sc, dLdI, partial, st,
                            scratch, stats);
     return hipGetLastError();
 }
