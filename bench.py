@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="capture one step in a graph (device step counter) and time its replays")
     ap.add_argument("--autotune", action="store_true", help="autotune launch parameters first")
+    ap.add_argument("--memo", action="store_true",
+                    help="memoized thin-film backward: one adjoint per distinct hit key (reported separately "
+                         "from the per-hit metric)")
     ap.add_argument("--per-design", action="store_true",
                     help="also time one launch per design (the batched workload) for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -176,7 +179,7 @@ def main():
     def step(k, ev=None, sc=scene, th=thk):
         if ev:
             ev[0].record()
-        _, _, irr, _, _ = ctx.trace_forward(sc, th, w.seed, k, prec, grad=not fo)
+        _, _, irr, _, _ = ctx.trace_forward(sc, th, w.seed, k, prec, grad=not fo, memo=a.memo)
         if ev:
             ev[1].record()
         if fo:
@@ -243,7 +246,8 @@ def main():
     # counters of the timed steps (recomputed untimed: same seeds, same paths)
     inter = hits = lay_f = lay_b = lay_a = fp64h = 0
     for i in range(a.steps):
-        _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True, grad=not fo)
+        _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True, grad=not fo,
+                                             memo=a.memo)
         inter += st["interactions"]
         hits += st["prma_hits"]
         lay_f += st["layer_steps"]
@@ -284,7 +288,7 @@ def main():
     # the adjoint launch is the entry kernel (plus the regenerating kernel,
     # which only runs for items whose entry regions overflowed)
     if not fo and t_bwd >= t_fwd:
-        kname, flops, tk = "k_adj_entries", f_bwd, t_bwd
+        kname, flops, tk = ("k_adj_memo" if a.memo else "k_adj_entries"), f_bwd, t_bwd
     else:
         kname, flops, tk = "k_trace_fwd", f_fwd, t_fwd
     achieved = flops / tk / 1e12
@@ -299,7 +303,8 @@ def main():
     if not fo:
         extra.update({"bwd_kernel_ms": t_bwd * 1e3, "bwd_tflops": f_bwd / t_bwd / 1e12})
     out = {
-        "metric": METRIC if not fo else "fwd ray-surface interactions/s",
+        "metric": (METRIC if not a.memo else METRIC + " (memoized thin-film backward)") if not fo
+        else "fwd ray-surface interactions/s",
         "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == gwg.FP64 else "f32+f64", "data": "synthetic",
@@ -309,6 +314,7 @@ def main():
                    "rays_per_point": w.rays_per_point, "rays_per_step": w.n_rays,
                    "bins": list(w.bins), "max_events": w.max_events, "precision": a.precision,
                    "step": "forward" if fo else "forward+loss+adjoint",
+                   "thin_film_adjoint": "per distinct hit key" if a.memo else "per hit",
                    "launch": "graph" if a.graph else "eager"},
         "roofline": roof,
         "extra": extra,

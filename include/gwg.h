@@ -200,7 +200,7 @@ typedef struct {
  * random numbers from Philox4x32-10 with key (seed_lo, seed_hi ^ step_lo),
  * counter (id_lo, id_hi, block, tag): tag 0 block 0 gives the birth words,
  * tag 1 block h/4 the word of the h-th mirror hit.  step < 2^32.
- * flags: 0, GWG_FWD_GRAD, or GWG_FWD_GRAD | GWG_FWD_MEMO.  With GWG_FWD_GRAD
+ * flags: 0 or any of GWG_FWD_GRAD, GWG_FWD_MEMO.  With GWG_FWD_GRAD
  * (a gwg_trace_backward will follow) the trace also runs the path part of the adjoint for every ray
  * that reaches the eyebox and keeps one entry per mirror hit in the context
  * (about 48 bytes per hit, within a fixed memory budget); the backward then
@@ -212,11 +212,16 @@ typedef struct {
  * The context remembers the scene, seed, step, precision and thk pointer
  * for gwg_trace_backward; thk must not change in between. */
 #define GWG_FWD_GRAD 1u
-/* GWG_FWD_MEMO (with GWG_FWD_GRAD): the backward solves one thin-film
- * adjoint per distinct (kappa, mirror, side, branch) key of each work item,
- * with the key's summed cotangents, instead of one per mirror hit (exact by
- * linearity, up to summation order; the sums run in a fixed order).  Within a
- * work item of a FoV grid the hits share a few keys. */
+/* GWG_FWD_MEMO: hit keys are memoized per work item (one design, wavelength
+ * and FoV point; within it the collimated rays share a few keys).  The
+ * forward solves each distinct (kappa, mirror, side) key once and reuses its
+ * coefficients, which are those of the per-hit solve bit for bit, so the bins
+ * are identical (fov_mode 0 only; with fov_mode 1, or where the key tables do
+ * not fit in LDS, the forward solves per hit).  With GWG_FWD_GRAD the
+ * backward solves one thin-film adjoint per distinct (kappa, mirror, side,
+ * branch) key, with the key's summed cotangents, instead of one per mirror
+ * hit (exact by linearity, up to summation order; the sums run in a fixed
+ * order). */
 #define GWG_FWD_MEMO 2u
 int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
                       const gwg_materials* mats, const gwg_stacks* stacks,
@@ -259,13 +264,16 @@ int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t 
  * workgroup; block_threads is 64, 128 or 256 (adjoint: 64 or 128).
  * adj_entries_per_ray (0..64, 0 = 6) sizes the adjoint entry regions of
  * GWG_FWD_GRAD: a region holding more entries than this times its rays is
- * regenerated by the backward instead. */
+ * regenerated by the backward instead.  memo_keys (0..128, 0 = 128) is the
+ * capacity of each wave's key table in the memoized forward (GWG_FWD_MEMO):
+ * a wave meeting more keys in one work item solves the rest of it per hit. */
 typedef struct {
     int32_t block_threads;
     int64_t rays_per_block;
     int32_t bwd_block_threads;
     int64_t bwd_rays_per_block;
     int32_t adj_entries_per_ray;
+    int32_t memo_keys;
 } gwg_tuning;
 
 int gwg_set_tuning(gwg_ctx* ctx, const gwg_tuning* tuning);

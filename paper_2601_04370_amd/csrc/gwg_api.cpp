@@ -515,6 +515,7 @@ int gwg_set_tuning(gwg_ctx* c, const gwg_tuning* t)
     if (t->bwd_block_threads > 128) return fail(c, GWG_E_INVAL, "adjoint block size must be 64 or 128");
     if (t->rays_per_block < 0 || t->bwd_rays_per_block < 0) return fail(c, GWG_E_INVAL, "negative tile");
     if (t->adj_entries_per_ray < 0 || t->adj_entries_per_ray > 64) return fail(c, GWG_E_INVAL, "adj_entries_per_ray out of range");
+    if (t->memo_keys < 0 || t->memo_keys > kFwdMemoKeys) return fail(c, GWG_E_INVAL, "memo_keys out of range");
     c->tune = *t;
     return GWG_OK;
 }
@@ -660,7 +661,10 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     sc.precision = precision;
     const int B = sc.bins_x * sc.bins_y;
     const bool lds_bins = B <= 2048;
+    // memoized solves need collimated beams (shared hit keys) and room for the key tables
+    sc.memo = ((flags & GWG_FWD_MEMO) && sc.fov_mode == 0) ? (c->tune.memo_keys ? c->tune.memo_keys : kFwdMemoKeys) : 0;
     const int wg = pick_fwd_wg(c, sc, lds_bins);
+    if (sc.memo && fwd_smem_bytes(sc, wg, lds_bins) > 65536) sc.memo = 0;
     set_tiles(sc, c->tune.rays_per_block, wg, c->n_cu);
     if (fwd_smem_bytes(sc, wg, lds_bins) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
     if (sc.n_items > 0x7fffffff) return fail(c, GWG_E_INVAL, "too many work items; raise rays_per_block");
@@ -872,7 +876,7 @@ int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const g
                 }
             std::fclose(f);
             if (found) {
-                gwg_tuning t{ wg, rpb, bwg, brpb, adj };
+                gwg_tuning t{ wg, rpb, bwg, brpb, adj, c->tune.memo_keys };
                 if (gwg_set_tuning(c, &t) == GWG_OK) {
                     c->tuned[key] = t;
                     *out = t;

@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             __threadfence_block();
             if (active) {
                 ray_birth(sc, *pl, id, r);
-                walk_ray<true, true>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, hoff }, tape, &nt);
+                walk_ray<true, true>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, hoff, nullptr }, tape, &nt);
                 c_rays += 1;
                 c_ev += (unsigned long long)r.nev;
                 c_hits += (unsigned long long)r.nprma;

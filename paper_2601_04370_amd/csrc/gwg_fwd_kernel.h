@@ -16,6 +16,16 @@
 //      (AdjStore) for the backward.
 // Walks are cheap next to the thin-film solves (a few hundred operations per
 // event against tens of thousands per hit).
+//
+// Memoized solves (GWG_FWD_MEMO, collimated beams): a hit's coefficients
+// depend only on its kappa, mirror and side, and within one work item the
+// rays share a handful of such keys (kappa comes from direction bits that
+// every ray with the same event history shares exactly).  Each wave then
+// keeps a table of the item's keys with their coefficients: step 3 resolves
+// every queued hit to its key, solves only keys not seen before in the item,
+// and step 4 reads the coefficients by key.  The coefficients are those of
+// the per-hit solve bit for bit; an item with more than kFwdMemoKeys keys
+// per wave goes on hit by hit.
 
 // Thin-film coefficients of one hit for this lane (fills the lane's slot table).
 template <int MODE>
@@ -65,6 +75,125 @@ __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const 
     }
 }
 
+// ------------------------------------------------------- memoized solves
+constexpr int kFwdMemoHash = 256;   // open-addressing slots (at most half full)
+
+// One wave's key table: keys and hash slots in LDS, coefficients in global
+// scratch (field f of key u at coef[f * kFwdMemoKeys + u]).
+struct FwdMemo {
+    unsigned long long* kbits;   // [kFwdMemoKeys] bits of kappa
+    int* kmeta;                  // [kFwdMemoKeys] mirror | front << 8
+    int* ksrc;                   // [kFwdMemoKeys] queue entry of the key's first hit
+    int* hslot;                  // [kFwdMemoHash] key index, -1 if empty
+    double* coef;                // [8][kFwdMemoKeys]
+};
+
+__host__ __device__ inline int fwd_memo_wave_bytes() { return kFwdMemoKeys * (8 + 4 + 4) + kFwdMemoHash * 4; }
+
+__device__ inline FwdMemo fwd_memo(unsigned char* base, int w, double* coef)
+{
+    unsigned char* mb = base + w * fwd_memo_wave_bytes();
+    FwdMemo fm;
+    fm.kbits = (unsigned long long*)mb;
+    fm.kmeta = (int*)(mb + 8 * kFwdMemoKeys);
+    fm.ksrc = (int*)(mb + 12 * kFwdMemoKeys);
+    fm.hslot = (int*)(mb + 16 * kFwdMemoKeys);
+    fm.coef = coef;
+    return fm;
+}
+
+__device__ inline int fmemo_hash(unsigned long long kb, int km)
+{
+    uint32_t x = (uint32_t)kb ^ ((uint32_t)(kb >> 32) * 0x9E3779B1u) ^ ((uint32_t)km * 0x85EBCA77u);
+    x ^= x >> 15;
+    x *= 0x2C1B3C6Du;
+    x ^= x >> 12;
+    return (int)(x & (kFwdMemoHash - 1));
+}
+
+// Key index of (kb, km), or -1 - s with s the empty slot that ends its probe.
+__device__ inline int fmemo_find(const FwdMemo& fm, unsigned long long kb, int km)
+{
+    int h = fmemo_hash(kb, km);
+    for (;;) {
+        const int u = fm.hslot[h];
+        if (u < 0) return -1 - h;
+        if (fm.kbits[u] == kb && fm.kmeta[u] == km) return u;
+        h = (h + 1) & (kFwdMemoHash - 1);
+    }
+}
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);      // this wave's LDS operations have completed (lgkmcnt = 0)
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Resolve queue entries [0, total) to key indices, appending new keys to the
+// table (*U keys so far); entry p's index goes to its first coefficient field.
+// Returns false if the table would hold more than cap keys.
+__device__ inline bool fmemo_resolve(const HitQueue& hq, int total, const FwdMemo& fm, int cap, int* U)
+{
+    const int lane = wave_lane();
+    for (int b = 0; b < total; b += 64) {
+        const int p = b + lane;
+        const bool act = p < total;
+        unsigned long long kb = 0ull;
+        int km = 0, idx = 0;
+        if (act) {
+            kb = (unsigned long long)__double_as_longlong(hq.kappa(p));
+            km = hq.meta(p) & 511;
+            idx = fmemo_find(fm, kb, km);
+        }
+        for (;;) {
+            const unsigned long long open = __ballot(act && idx < 0);
+            if (open == 0ull) break;
+            if (*U == cap) return false;
+            const int leader = __ffsll((long long)open) - 1;
+            const int u = *U;
+            if (lane == leader) {
+                fm.kbits[u] = kb; fm.kmeta[u] = km; fm.ksrc[u] = p;
+                fm.hslot[-1 - idx] = u;
+            }
+            *U = u + 1;
+            wave_lds_sync();
+            // the others probe again: the new key may be theirs, or may have
+            // taken the slot their probe ended at
+            if (act && idx < 0) idx = fmemo_find(fm, kb, km);
+        }
+        if (act) hq.base[2 * hq.cap + p] = (double)idx;
+    }
+    return true;
+}
+
+// Solve keys [u0, u1) (one per lane) from their first hits into the table.
+template <int MODE>
+__device__ inline void fmemo_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
+                                   const uint8_t* s_slot, const LaneSlots3& sl, const HitQueue& hq,
+                                   const FwdMemo& fm, int u0, int u1, unsigned long long* n_fp64,
+                                   unsigned long long* n_lay)
+{
+    const int lane = wave_lane();
+    for (int b = u0; b < u1; b += 64) {
+        const int u = b + lane;
+        if (u < u1) {
+            const int p = fm.ksrc[u];
+            const double kappa = hq.kappa(p);
+            const int meta = hq.meta(p);
+            const int m = meta & 255;
+            bool u64 = false;
+            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64);
+            double* o = fm.coef + u;
+            o[0] = c.rs.re; o[kFwdMemoKeys] = c.rs.im; o[2 * kFwdMemoKeys] = c.rp.re; o[3 * kFwdMemoKeys] = c.rp.im;
+            o[4 * kFwdMemoKeys] = c.ts.re; o[5 * kFwdMemoKeys] = c.ts.im;
+            o[6 * kFwdMemoKeys] = c.tp.re; o[7 * kFwdMemoKeys] = c.tp.im;
+            *n_fp64 += u64 ? 1ull : 0ull;
+            *n_lay += (unsigned long long)pl.nlay[m];
+        }
+    }
+}
+
 struct NoHit {
     __device__ void operator()(int, double, int) const {}
 };
@@ -76,10 +205,21 @@ struct PutHit {
     int off;
     __device__ void operator()(int h, double kappa, int meta) const { q.put(off + h, kappa, meta); }
 };
+// Coefficients of the ray's hit h: from its queue entry, or (mc set) from
+// the key table at the index its queue entry holds.
 struct GetCoef {
     HitQueue q;
     int off;
-    __device__ Coef4 operator()(int h) const { return q.coef(off + h); }
+    const double* mc;
+    __device__ Coef4 operator()(int h) const
+    {
+        if (!mc) return q.coef(off + h);
+        const double* b = mc + (int)q.base[2 * q.cap + off + h];
+        Coef4 c;
+        c.rs = mk(b[0], b[kFwdMemoKeys]); c.rp = mk(b[2 * kFwdMemoKeys], b[3 * kFwdMemoKeys]);
+        c.ts = mk(b[4 * kFwdMemoKeys], b[5 * kFwdMemoKeys]); c.tp = mk(b[6 * kFwdMemoKeys], b[7 * kFwdMemoKeys]);
+        return c;
+    }
 };
 
 // Persistent workgroups walk the work items with a fixed stride; each wave
@@ -115,6 +255,8 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;
     const TapeRef tape = { tape_scratch + (int64_t)blockIdx.x * WG + tid, (int64_t)gridDim.x * WG };
+    const FwdMemo fm = fwd_memo(smem + lay.total, wave,
+                                scratch + (int64_t)gridDim.x * n_waves * kHitFields * cap + gwave * 8 * kFwdMemoKeys);
 
     for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
         int64_t point, i0, i1;
@@ -129,6 +271,12 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
         uint64_t* gq = q_out + point * B;
         uint32_t* gc = c_out + point * B;
         int64_t n_ent = 0;                                // this wave's entries in this item (uniform)
+        bool memo = sc.memo != 0;                         // this wave's key table is in use (uniform)
+        int n_keys = 0;
+        if (memo) {
+            for (int k = lane; k < kFwdMemoHash; k += 64) fm.hslot[k] = -1;
+            wave_lds_sync();
+        }
         const int64_t ent0 = (item * st.waves + wave) * st.cap_w;
         for (int64_t round = 0;; ++round) {
             const int64_t wave_first = i0 + (int64_t)wave * 64 + round * WG;
@@ -154,13 +302,18 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                 walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, off }, NoCoef{}, none, nullptr);
             }
             __threadfence_block();
-            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, &n_fp64, &n_lay);
+            const int u0 = n_keys;
+            if (memo && !fmemo_resolve(hq, total, fm, sc.memo, &n_keys)) memo = false;
+            if (memo)
+                fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
+            else
+                solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, &n_fp64, &n_lay);
             __threadfence_block();
             int nt = 0;
             if (active) {
                 ray_birth(sc, *pl, id, r);
                 const TapeRef rt = { to_eyebox ? tape.base : nullptr, tape.ts };
-                walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off }, rt, &nt);
+                walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off, memo ? fm.coef : nullptr }, rt, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
                 atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);
@@ -234,5 +387,5 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
 
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg)
 {
-    return grid_blocks * (wg / 64) * (int64_t)kHitFields * 64 * sc.Kmax;
+    return grid_blocks * (wg / 64) * ((int64_t)kHitFields * 64 * sc.Kmax + (sc.memo ? 8 * kFwdMemoKeys : 0));
 }

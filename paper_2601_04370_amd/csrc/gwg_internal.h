@@ -50,6 +50,7 @@ enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4
 // cnt[item * waves + wave] = entries of that region; ovf[item] != 0 when a
 // region of the item overflowed (the backward then regenerates that item).
 constexpr int kEntFields = 6;
+constexpr int kFwdMemoKeys = 128;      // largest key table per wave of the memoized forward
 struct AdjStore {
     double* ent;
     int32_t* cnt;
@@ -91,6 +92,7 @@ struct SceneDev {
     uint32_t seed_hi, step_host;      // with step_dev: key1 = seed_hi ^ (step_host + *step_dev)
     const uint32_t* step_dev;         // optional device step counter (graph replays)
     int32_t precision;
+    int32_t memo;                     // forward: key table capacity per wave (0: solve every hit)
     // work decomposition
     int64_t tiles_per_point;
     int64_t rays_per_tile;

@@ -305,7 +305,8 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
 
 size_t fwd_smem_bytes(const SceneDev& sc, int wg, bool lds_bins)
 {
-    return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, lds_bins, 0).total;
+    return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, lds_bins, 0).total
+           + (sc.memo ? (size_t)(wg / 64) * fwd_memo_wave_bytes() : 0);
 }
 size_t bwd_smem_bytes(const SceneDev& sc, int wg)
 {

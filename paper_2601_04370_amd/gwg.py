@@ -93,7 +93,7 @@ class Stats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("rays_per_block", C.c_int64),
                 ("bwd_block_threads", C.c_int32), ("bwd_rays_per_block", C.c_int64),
-                ("adj_entries_per_ray", C.c_int32)]
+                ("adj_entries_per_ray", C.c_int32), ("memo_keys", C.c_int32)]
 
 
 #: every function declared in include/gwg.h
@@ -272,8 +272,9 @@ class Context:
             raise GwgError(rc, self.lib.gwg_last_error(self.h).decode())
 
     def set_tuning(self, block_threads=0, rays_per_block=0, bwd_block_threads=0, bwd_rays_per_block=0,
-                   adj_entries_per_ray=0):
-        t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block, adj_entries_per_ray)
+                   adj_entries_per_ray=0, memo_keys=0):
+        t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block, adj_entries_per_ray,
+                   memo_keys)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
 
     def forward_kept_entries(self) -> bool:
@@ -343,8 +344,9 @@ class Context:
         """Returns (q_bins u64-as-int64, counts int32, irradiance f64 or None,
         records or None, stats dict or None); tensors on the context's GPU.
         grad=True prepares the adjoint entries for a following trace_backward;
-        memo=True (with grad) makes that backward solve one thin-film adjoint
-        per distinct hit key of each work item."""
+        memo=True solves each distinct hit key of a work item once (results
+        identical to the per-hit solves) and, with grad, makes that backward
+        solve one thin-film adjoint per distinct key."""
         torch = self.torch
         dev = torch.device("cuda", self.device)
         assert tuple(thk.shape) == scene.thk_shape and thk.dtype == torch.float64 and thk.is_contiguous()

@@ -120,6 +120,59 @@ def test_forward_tile_shape_does_not_change_results(gctx):
         assert np.array_equal(r[1], res[0][1]) and np.array_equal(r[2], res[0][2])
 
 
+MEMO_CASES = [
+    ("diff_1200", dict(rays_per_point=700, fov_n=3)),
+    ("precision_ag", dict(rays_per_point=400, fov_n=3, lambdas_nm=(460.0, 620.0))),
+    ("batched", dict(n_designs=2, rays_per_point=300, fov_n=3, lambdas_nm=(400.0, 700.0))),
+    ("plain_fp64", dict(rays_per_point=5000)),     # random FoV per ray: solved per hit
+]
+
+
+def _memo_pair(gctx, w, inp, precision, memo_keys=0, stride=7):
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    out = []
+    for memo in (False, True):
+        gctx.set_tuning(memo_keys=memo_keys)
+        try:
+            q, c, _, rec, st = gctx.trace_forward(scene, thk, w.seed, 3, precision, record_stride=stride,
+                                                  stats=True, memo=memo)
+        finally:
+            gctx.set_tuning()
+        out.append((q.cpu().numpy(), c.cpu().numpy(), gwg.records_view(rec), st))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("name,kw", MEMO_CASES)
+def test_forward_memo_identical_to_per_hit(gctx, name, kw, precision):
+    """Memoized solves give each hit the coefficients of its own solve bit for
+    bit: bins, counts and per-ray weights are identical."""
+    w = inputs.small_variant(name, **kw)
+    inp = inputs.make_inputs(w)
+    print(f"forward memo {name} {kw} precision {precision}", flush=True)
+    (q0, c0, r0, s0), (q1, c1, r1, s1) = _memo_pair(gctx, w, inp, precision)
+    assert np.array_equal(q0, q1) and np.array_equal(c0, c1)
+    assert np.array_equal(r0["w"], r1["w"]) and np.array_equal(r0["bin"], r1["bin"])
+    assert s0["interactions"] == s1["interactions"] and s0["prma_hits"] == s1["prma_hits"]
+    print(f"  layer steps per hit {s0['layer_steps']} -> memoized {s1['layer_steps']}", flush=True)
+    if w.fov_mode == 0:
+        assert s1["layer_steps"] < s0["layer_steps"] / 4
+    else:
+        assert s1["layer_steps"] == s0["layer_steps"]
+
+
+@pytest.mark.parametrize("memo_keys", [1, 3, 17])
+def test_forward_memo_table_overflow(gctx, memo_keys):
+    """Waves whose key table fills up solve the rest of the item per hit."""
+    w = inputs.small_variant("diff_1200", rays_per_point=900, fov_n=3)
+    inp = inputs.make_inputs(w)
+    (q0, c0, r0, s0), (q1, c1, r1, s1) = _memo_pair(gctx, w, inp, 0, memo_keys=memo_keys)
+    assert np.array_equal(q0, q1) and np.array_equal(c0, c1)
+    assert np.array_equal(r0["w"], r1["w"])
+    assert s1["layer_steps"] <= s0["layer_steps"]
+
+
 def test_full_size_sampled_rays(gctx, orc):
     """Differentiation workload at full size (6 mirrors x 200 layers, 3
     wavelengths, 21 x 21 FoV, 4096 rays per point) in the default launch
