@@ -133,8 +133,8 @@ def main():
                     help="capture one step in a graph (device step counter) and time its replays")
     ap.add_argument("--autotune", action="store_true", help="autotune launch parameters first")
     ap.add_argument("--memo", action="store_true",
-                    help="memoized thin-film backward: one adjoint per distinct hit key (reported separately "
-                         "from the per-hit metric)")
+                    help="memoized thin film: one solve per distinct hit key of a work item in the forward, one "
+                         "adjoint per key in the backward (reported separately from the per-hit metric)")
     ap.add_argument("--per-design", action="store_true",
                     help="also time one launch per design (the batched workload) for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -296,6 +296,7 @@ def main():
             "frac": achieved / PEAK_FP64, "traffic": load_traffic(kname, a.workload, a.precision),
             "kernel": kname, "kernel_ms": tk * 1e3}
     extra.update({"interactions_per_step": inter / K, "mirror_hits_per_step": hits / K,
+                  "fwd_layer_steps_per_step": lay_f / K, "adj_layer_steps_per_step": lay_a / K,
                   "mirror_hits_per_s": hits / wall, "fp64_hit_fraction": fp64h / max(hits, 1),
                   "fwd_ms": float(np.mean(fwd_ms)), "loss_ms": float(np.mean(loss_ms)),
                   "bwd_ms": float(np.mean(bwd_ms)), "fwd_kernel_ms": t_fwd * 1e3,

@@ -47,6 +47,7 @@ class Scene(C.Structure):
         ("fov_mode", C.c_int32), ("n_fov", C.c_int32), ("fov_deg", _dp),
         ("rays_per_point", C.c_int64), ("max_events", C.c_int32), ("fp_shift", C.c_int32),
         ("seed", C.c_uint64), ("step", C.c_uint64),
+        ("table_nodes", C.c_int32),
     ]
 
 
@@ -88,6 +89,7 @@ def lib():
     L.orc_loss.argtypes = [_dp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                            C.c_double, C.c_double, _dp]
     L.orc_loss.restype = C.c_double
+    L.orc_table_weights.argtypes = [C.c_double, C.c_int, _i32p, _dp]
     _lib = L
     return L
 
@@ -140,13 +142,21 @@ def tmm_dthk(thk, n_layers_complex, n_in: float, n_out: complex, lambda_nm: floa
     return o[:, :, 0] + 1j * o[:, :, 1]
 
 
+def table_weights(theta: float, n: int):
+    """Node indices and weights of the n-angle table at incidence angle theta."""
+    idx = np.zeros(4, dtype=np.int32)
+    w = np.zeros(4)
+    lib().orc_table_weights(C.c_double(theta), C.c_int(n), _ptr(idx, _i32p), _ptr(w, _dp))
+    return idx, w
+
+
 # ------------------------------------------------------------------- scene
 class OracleScene:
     """Holds the numpy arrays referenced by a Scene struct."""
 
     def __init__(self, w, inp: dict, seed: Optional[int] = None, step: int = 0,
                  thk: Optional[np.ndarray] = None, rays_per_point: Optional[int] = None,
-                 omega: Optional[np.ndarray] = None):
+                 omega: Optional[np.ndarray] = None, table_nodes: int = 0):
         from inputs import MAT_AIR, MAT_GLASS
         self.w = w
         self.arrays = {}
@@ -188,6 +198,7 @@ class OracleScene:
         s.max_events, s.fp_shift = w.max_events, w.fp_shift
         s.seed = w.seed if seed is None else seed
         s.step = step
+        s.table_nodes = table_nodes
         self.s = s
 
     @property

@@ -50,6 +50,15 @@ void orc_tmm_dthk(int n_layers, const double* thk_nm, const double* nre, const d
                   double n_in, double nout_re, double nout_im,
                   double lambda_nm, double kappa, double* d_out);
 
+/* Angle table (Methods, memory-saving strategies: the thin-film response is
+ * precomputed on a discrete set of incidence angles and interpolated,
+ * differentiably, in between).  Reading: n angles theta_j = j (pi/2)/(n-1)
+ * in the glass, a Catmull-Rom cubic in theta through the four angles around
+ * theta; the response is even in theta, so the angle before theta_0 is
+ * theta_1, and the last segment repeats theta_{n-1}.  A coefficient is
+ * sum_i w[i] c(theta_{idx[i]}).  n >= 4; theta in [0, pi/2]. */
+void orc_table_weights(double theta, int n, int idx[4], double w[4]);
+
 /* ------------------------------------------------------------------ scene */
 typedef struct {
     /* refractive-index table, [n_lambda][n_mat] */
@@ -82,6 +91,9 @@ typedef struct {
     int32_t max_events;
     int32_t fp_shift;
     uint64_t seed, step;
+    /* thin film per mirror hit: 0 = the exact response at the hit's angle;
+     * n >= 4 = interpolated from an n-angle table (orc_table_weights) */
+    int32_t table_nodes;
 } orc_scene;
 
 /* Termination categories. */

@@ -350,6 +350,82 @@ static int eyebox_bin(const orc_scene* sc, vec3 p, vec3 a)
 }
 
 /* Mirror event: stack response for this side, branch, Eq. 5/6 update. */
+void orc_table_weights(double theta, int n, int idx[4], double w[4])
+{
+    double h = (M_PI / 2.0) / (double)(n - 1);
+    double x = theta / h;
+    int j = (int)floor(x);
+    if (j > n - 2) j = n - 2;
+    if (j < 0) j = 0;
+    double t = x - (double)j;
+    /* cubic Hermite on [theta_j, theta_j+1] with central-difference slopes */
+    w[0] = 0.5 * (-t * t * t + 2.0 * t * t - t);
+    w[1] = 0.5 * (3.0 * t * t * t - 5.0 * t * t + 2.0);
+    w[2] = 0.5 * (-3.0 * t * t * t + 4.0 * t * t + t);
+    w[3] = 0.5 * (t * t * t - t * t);
+    idx[0] = j == 0 ? 1 : j - 1;
+    idx[1] = j;
+    idx[2] = j + 1;
+    idx[3] = j + 2 < n ? j + 2 : n - 1;
+}
+
+/* Incidence angle in the glass of a hit with kappa = n_g sin(theta). */
+static double hit_theta(double kappa, double ng)
+{
+    double s = kappa / ng;
+    return asin(s < 1.0 ? s : 1.0);
+}
+
+/* Node kappa of table angle j. */
+static double node_kappa(const ctx_t* c, int j)
+{
+    return c->ng * sin((double)j * ((M_PI / 2.0) / (double)(c->sc->table_nodes - 1)));
+}
+
+/* The four coefficients of mirror m's stack seen from `side` at kappa:
+ * exact, or interpolated from the angle table. */
+static void hit_coeffs(const ctx_t* c, int m, int side, double kappa, double complex co[4])
+{
+    size_t base = ((size_t)m * 2 + side) * c->sc->max_layers;
+    if (c->sc->table_nodes <= 0) {
+        orc__tmm_coeffs(c->s_len[m], c->s_thk + base, c->s_nre + base, c->s_nim + base,
+                        c->ng, c->lambda_nm, kappa, co);
+        return;
+    }
+    int idx[4];
+    double w[4];
+    orc_table_weights(hit_theta(kappa, c->ng), c->sc->table_nodes, idx, w);
+    for (int q = 0; q < 4; ++q) co[q] = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        double complex ci[4];
+        orc__tmm_coeffs(c->s_len[m], c->s_thk + base, c->s_nre + base, c->s_nim + base,
+                        c->ng, c->lambda_nm, node_kappa(c, idx[i]), ci);
+        for (int q = 0; q < 4; ++q) co[q] += w[i] * ci[q];
+    }
+}
+
+/* d c / d thk_j of the same coefficients (orc_tmm_dthk layout), exact or
+ * through the interpolation (linear in the table entries). */
+static void hit_dthk(const ctx_t* c, int m, int side, double kappa, double* dd, double* tmp)
+{
+    size_t base = ((size_t)m * 2 + side) * c->sc->max_layers;
+    int L = c->s_len[m];
+    if (c->sc->table_nodes <= 0) {
+        orc_tmm_dthk(L, c->s_thk + base, c->s_nre + base, c->s_nim + base, c->ng, c->ng, 0.0,
+                     c->lambda_nm, kappa, dd);
+        return;
+    }
+    int idx[4];
+    double w[4];
+    orc_table_weights(hit_theta(kappa, c->ng), c->sc->table_nodes, idx, w);
+    memset(dd, 0, sizeof(double) * 16 * (size_t)(L > 0 ? L : 1));
+    for (int i = 0; i < 4; ++i) {
+        orc_tmm_dthk(L, c->s_thk + base, c->s_nre + base, c->s_nim + base, c->ng, c->ng, 0.0,
+                     c->lambda_nm, node_kappa(c, idx[i]), tmp);
+        for (int k = 0; k < 16 * L; ++k) dd[k] += w[i] * tmp[k];
+    }
+}
+
 static void mirror_event(const ctx_t* c, ray_t* r, int m, int reflect, int mc_scale, tape_t* tp_out)
 {
     vec3 n = { c->nx, 0.0, c->nz };
@@ -359,10 +435,8 @@ static void mirror_event(const ctx_t* c, ray_t* r, int m, int reflect, int mc_sc
     double sin_i = sqrt(dot3(cr, cr));
     double kappa = c->ng * sin_i;
     int side = front ? 0 : 1;
-    size_t base = ((size_t)m * 2 + side) * c->sc->max_layers;
     double complex co[4];
-    orc__tmm_coeffs(c->s_len[m], c->s_thk + base, c->s_nre + base, c->s_nim + base,
-                    c->ng, c->lambda_nm, kappa, co);
+    hit_coeffs(c, m, side, kappa, co);
     double p = c->p_eff[m];
     vec3 dnew = r->d;
     if (reflect) {
@@ -656,6 +730,7 @@ int orc_trace_backward(const orc_scene* sc, const double* dL_dI, int64_t sample_
     if (sample_stride < 1) sample_stride = 1;
     tape_t* tape = (tape_t*)malloc(sizeof(tape_t) * (size_t)(sc->max_events + 1));
     double* dd = (double*)malloc(sizeof(double) * 16 * (size_t)(Lm > 0 ? Lm : 1));
+    double* tmp = (double*)malloc(sizeof(double) * 16 * (size_t)(Lm > 0 ? Lm : 1));
     for (int d = 0; d < sc->n_designs; ++d)
         for (int li = 0; li < sc->n_lsel; ++li)
             for (int f = 0; f < F; ++f) {
@@ -680,9 +755,7 @@ int orc_trace_backward(const orc_scene* sc, const double* dL_dI, int64_t sample_
                             int m = t->mirror;
                             int side = t->front ? 0 : 1;
                             int L = c.s_len[m];
-                            size_t base = ((size_t)m * 2 + side) * Lm;
-                            orc_tmm_dthk(L, c.s_thk + base, c.s_nre + base, c.s_nim + base,
-                                         c.ng, c.ng, 0.0, c.lambda_nm, t->kappa, dd);
+                            hit_dthk(&c, m, side, t->kappa, dd, tmp);
                             int cs_i = t->reflect ? 0 : 2, cp_i = t->reflect ? 1 : 3;
                             for (int j = 0; j < L; ++j) {
                                 double complex dcs = CMPLX(dd[j * 16 + 4 * cs_i], dd[j * 16 + 4 * cs_i + 1]);
@@ -704,6 +777,7 @@ int orc_trace_backward(const orc_scene* sc, const double* dL_dI, int64_t sample_
             }
     free(tape);
     free(dd);
+    free(tmp);
     ctx_free(&c);
     return 0;
 }
