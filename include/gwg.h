@@ -200,7 +200,8 @@ typedef struct {
  * random numbers from Philox4x32-10 with key (seed_lo, seed_hi ^ step_lo),
  * counter (id_lo, id_hi, block, tag): tag 0 block 0 gives the birth words,
  * tag 1 block h/4 the word of the h-th mirror hit.  step < 2^32.
- * flags: 0 or any of GWG_FWD_GRAD, GWG_FWD_MEMO.  With GWG_FWD_GRAD
+ * flags: 0 or GWG_FWD_GRAD with at most one of GWG_FWD_MEMO,
+ * GWG_FWD_TABLE.  With GWG_FWD_GRAD
  * (a gwg_trace_backward will follow) the trace also runs the path part of the adjoint for every ray
  * that reaches the eyebox and keeps one entry per mirror hit in the context
  * (about 48 bytes per hit, within a fixed memory budget); the backward then
@@ -223,6 +224,20 @@ typedef struct {
  * hit (exact by linearity, up to summation order; the sums run in a fixed
  * order). */
 #define GWG_FWD_MEMO 2u
+/* GWG_FWD_TABLE: the thin-film response is precomputed per (design,
+ * wavelength, mirror, side) at n = table_nodes incidence angles
+ * theta_j = j (pi/2)/(n-1) in the glass, and every hit interpolates it with a
+ * Catmull-Rom cubic in its angle (Methods, memory-saving strategies; the
+ * response is even in theta below theta_0, the last segment is clamped).
+ * The results are those of the interpolated model, not of the per-hit solve.
+ * The table takes 64 * D * n_lambda_sel * M * 2 * n bytes of device memory
+ * (GWG_E_INVAL if it does not fit in half of the free memory).  With
+ * GWG_FWD_GRAD, gwg_trace_backward returns the exact gradient of the
+ * interpolated model: the hits' cotangents are summed per table entry in
+ * 64-bit fixed point (exact, order-independent), and one thin-film adjoint
+ * runs per entry with a nonzero sum.  A table forward without GWG_FWD_GRAD
+ * has no backward (GWG_E_STATE).  Excludes GWG_FWD_MEMO. */
+#define GWG_FWD_TABLE 4u
 int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
                       const gwg_materials* mats, const gwg_stacks* stacks,
                       const gwg_rays* rays, uint64_t seed, uint64_t step,
@@ -266,7 +281,9 @@ int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t 
  * GWG_FWD_GRAD: a region holding more entries than this times its rays is
  * regenerated by the backward instead.  memo_keys (0..128, 0 = 128) is the
  * capacity of each wave's key table in the memoized forward (GWG_FWD_MEMO):
- * a wave meeting more keys in one work item solves the rest of it per hit. */
+ * a wave meeting more keys in one work item solves the rest of it per hit.
+ * table_nodes (0 = 8192, else 4..2^20) is the number of incidence angles of
+ * the angle table (GWG_FWD_TABLE). */
 typedef struct {
     int32_t block_threads;
     int64_t rays_per_block;
@@ -274,6 +291,7 @@ typedef struct {
     int64_t bwd_rays_per_block;
     int32_t adj_entries_per_ray;
     int32_t memo_keys;
+    int32_t table_nodes;
 } gwg_tuning;
 
 int gwg_set_tuning(gwg_ctx* ctx, const gwg_tuning* tuning);

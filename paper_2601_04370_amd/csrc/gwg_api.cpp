@@ -98,6 +98,9 @@ struct gwg_ctx {
     bool adj_valid = false;
     bool memo = false;           // thin-film adjoints per distinct hit key (GWG_FWD_MEMO)
     AdjStore adj{};
+    // angle table (GWG_FWD_TABLE): entries, fixed-point bound, backward accumulators
+    DevBuf tab, tab_scale, tab_acc;
+    bool tab_grad = false;       // the last forward was a table forward with GWG_FWD_GRAD
     // tuning
     gwg_tuning tune{};
     // kernel timing
@@ -497,7 +500,8 @@ int gwg_destroy(gwg_ctx* c)
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
         for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
-                           &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape })
+                           &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape,
+                           &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad })
             b->release();
         for (KernelTimer& t : c->timer) t.destroy();
     }
@@ -516,6 +520,8 @@ int gwg_set_tuning(gwg_ctx* c, const gwg_tuning* t)
     if (t->rays_per_block < 0 || t->bwd_rays_per_block < 0) return fail(c, GWG_E_INVAL, "negative tile");
     if (t->adj_entries_per_ray < 0 || t->adj_entries_per_ray > 64) return fail(c, GWG_E_INVAL, "adj_entries_per_ray out of range");
     if (t->memo_keys < 0 || t->memo_keys > kFwdMemoKeys) return fail(c, GWG_E_INVAL, "memo_keys out of range");
+    if (t->table_nodes != 0 && (t->table_nodes < 4 || t->table_nodes > kTableNodesMax))
+        return fail(c, GWG_E_INVAL, "table_nodes must be 0 or in [4, %d]", kTableNodesMax);
     c->tune = *t;
     return GWG_OK;
 }
@@ -641,13 +647,16 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     if (!out || !out->q_bins || !out->counts) return fail(c, GWG_E_INVAL, "eyebox outputs are NULL");
     if (out->fp_shift < 0 || out->fp_shift > 40) return fail(c, GWG_E_INVAL, "fp_shift out of range");
     if (records && record_stride < 1) return fail(c, GWG_E_INVAL, "record_stride must be >= 1");
-    if (flags & ~(uint32_t)(GWG_FWD_GRAD | GWG_FWD_MEMO)) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(uint32_t)(GWG_FWD_GRAD | GWG_FWD_MEMO | GWG_FWD_TABLE)) return fail(c, GWG_E_INVAL, "unknown flags 0x%x", flags);
+    if ((flags & GWG_FWD_MEMO) && (flags & GWG_FWD_TABLE))
+        return fail(c, GWG_E_INVAL, "GWG_FWD_MEMO and GWG_FWD_TABLE exclude each other");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     const bool cap = stream_capturing(s);
     if (cap && stats) return fail(c, GWG_E_STATE, "stats need a synchronization: not available during stream capture");
     c->adj_valid = false;
     c->have_forward = false;
+    c->tab_grad = false;
     rc = build_scene(c, slab, prma, mats, stacks, rays, s);
     if (rc) return rc;
     SceneDev sc = c->sc;
@@ -663,14 +672,37 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     const bool lds_bins = B <= 2048;
     // memoized solves need collimated beams (shared hit keys) and room for the key tables
     sc.memo = ((flags & GWG_FWD_MEMO) && sc.fov_mode == 0) ? (c->tune.memo_keys ? c->tune.memo_keys : kFwdMemoKeys) : 0;
+    sc.table = nullptr;
+    sc.table_n = 0;
+    sc.tab_scale = nullptr;
+    sc.tab_acc = nullptr;
     const int wg = pick_fwd_wg(c, sc, lds_bins);
     if (sc.memo && fwd_smem_bytes(sc, wg, lds_bins) > 65536) sc.memo = 0;
     set_tiles(sc, c->tune.rays_per_block, wg, c->n_cu);
     if (fwd_smem_bytes(sc, wg, lds_bins) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
     if (sc.n_items > 0x7fffffff) return fail(c, GWG_E_INVAL, "too many work items; raise rays_per_block");
     const int64_t nbins = (int64_t)sc.D * sc.n_lsel * sc.F * B;
+    const bool table = (flags & GWG_FWD_TABLE) != 0;
+    if (table) {
+        const int n = c->tune.table_nodes ? c->tune.table_nodes : kTableNodesDefault;
+        const size_t tab_b = sizeof(double) * 8 * (size_t)sc.D * sc.n_lsel * sc.M * 2 * (size_t)n;
+        if (!cap) {
+            size_t free_b = 0, total_b = 0;
+            (void)hipMemGetInfo(&free_b, &total_b);
+            if ((double)tab_b > 0.5 * (double)free_b + (double)c->tab.bytes)
+                return fail(c, GWG_E_INVAL, "angle table of %zu bytes does not fit in device memory; lower table_nodes", tab_b);
+        }
+        rc = ensure_buf(c, c->tab, tab_b, cap, "alloc angle table");
+        if (rc) return rc;
+        rc = ensure_buf(c, c->tab_scale, sizeof(uint64_t) * 4, cap, "alloc table scale");
+        if (rc) return rc;
+        sc.table = (const double*)c->tab.p;
+        sc.table_n = n;
+        sc.tab_scale = (unsigned long long*)c->tab_scale.p;
+    }
     // adjoint entries: per (item, wave) region of cap_w entries, if they fit the budget
     bool adj = false;
+    bool adj_sweep = false;      // the forward runs the path adjoint (with or without room for entries)
     if (flags & GWG_FWD_GRAD) {
         const int waves = wg / 64;
         const int64_t per_ray = c->tune.adj_entries_per_ray > 0 ? c->tune.adj_entries_per_ray : kAdjEntriesPerRay;
@@ -699,14 +731,24 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
             HIP_CHECK(c, launch_fill_u32((uint32_t*)c->adj_ovf.p, sc.n_items, 0u, s), "zero overflow flags");
             c->adj = AdjStore{ (double*)c->adj_ent.p, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, cap_w, total, waves };
             adj = true;
+        } else if (table) {
+            // the table backward needs the sweep's cotangent bound even when no
+            // entry can be kept: regions of zero entries, every item regenerated
+            rc = ensure_buf(c, c->adj_cnt, cnt_b, cap, "alloc entry counts");
+            if (rc) return rc;
+            rc = ensure_buf(c, c->adj_ovf, ovf_b, cap, "alloc overflow flags");
+            if (rc) return rc;
+            c->adj = AdjStore{ nullptr, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, 0, 0, waves };
         }
+        adj_sweep = adj || table;
     }
     // persistent grid: as many workgroups as fit on the device at once
-    const int per_cu = occupancy(c, adj ? KIND_FWD_ADJ : KIND_FWD, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
+    const int kind_f = adj_sweep ? (table ? KIND_FWD_ADJ_TAB : KIND_FWD_ADJ) : (table ? KIND_FWD_TAB : KIND_FWD);
+    const int per_cu = occupancy(c, kind_f, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
     const int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * per_cu);
     rc = ensure_buf(c, c->fwd_scratch, sizeof(double) * (size_t)fwd_scratch_doubles(sc, grid, wg), cap, "alloc hit queues");
     if (rc) return rc;
-    if (adj) {
+    if (adj_sweep) {
         rc = ensure_buf(c, c->fwd_tape, sizeof(double) * (size_t)(grid * wg * (int64_t)sc.Kmax * kTapeStride), cap,
                         "alloc forward tape");
         if (rc) return rc;
@@ -716,9 +758,14 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     HIP_CHECK(c, launch_fill_u64(out->q_bins, nbins, 0, s), "zero bins");
     HIP_CHECK(c, launch_fill_u32(out->counts, nbins, 0, s), "zero counts");
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
+    if (table) {
+        HIP_CHECK(c, launch_fill_u64((uint64_t*)c->tab_scale.p, 4, 0, s), "zero table scale");
+        HIP_CHECK(c, launch_table_build(sc, (double*)c->tab.p, c->n_cu, (unsigned long long*)c->stats.p, s),
+                  "angle table kernel");
+    }
     if (c->timing && !cap) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].begin(), s), "timing event");
     HIP_CHECK(c, launch_trace_fwd(sc, wg, (int)grid, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
-                                  records, record_stride, (double*)c->fwd_scratch.p, adj ? &c->adj : nullptr,
+                                  records, record_stride, (double*)c->fwd_scratch.p, adj_sweep ? &c->adj : nullptr,
                                   (double*)c->fwd_tape.p, s),
               "forward kernel");
     if (c->timing && !cap) {
@@ -732,6 +779,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     c->have_forward = true;
     c->adj_valid = adj;
     c->memo = (flags & GWG_FWD_MEMO) != 0;
+    c->tab_grad = table && adj_sweep;
     if (stats) {
         rc = read_stats(c, s, stats);
         if (rc) return rc;
@@ -754,6 +802,8 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     if (cap && stats) return fail(c, GWG_E_STATE, "stats need a synchronization: not available during stream capture");
     int rc = GWG_OK;
     SceneDev sc = c->fwd;
+    if (sc.table && !c->tab_grad)
+        return fail(c, GWG_E_STATE, "the angle-table backward needs a forward run with GWG_FWD_GRAD");
     const int wg = pick_bwd_wg(c, sc);
     // With entries from the forward, the backward keeps the forward's work
     // items: the entry kernel covers items whose regions fit, the
@@ -764,7 +814,8 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     // persistent grids: as many workgroups as fit on the device at once
     const size_t smem = bwd_smem_bytes(sc, wg);
     const int64_t n_cu = std::max(c->n_cu, 1);
-    const int64_t grid = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, KIND_BWD_REGEN, sc.precision, wg, smem));
+    const int64_t grid = std::min<int64_t>(
+        sc.n_items, n_cu * occupancy(c, sc.table ? KIND_BWD_REGEN_TAB : KIND_BWD_REGEN, sc.precision, wg, smem));
     const int kind_e = sc.slot_complex == 0u ? KIND_ADJ_LOSSLESS : KIND_ADJ_ENTRIES;
     const int64_t grid_e = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, kind_e, sc.precision, wg, smem));
     const int kind_m = sc.slot_complex == 0u ? KIND_ADJ_MEMO_LOSSLESS : KIND_ADJ_MEMO;
@@ -772,13 +823,43 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
     const int ML = sc.M * sc.Lmax;
     int64_t scratch_d = std::max(bwd_scratch_doubles(sc, grid, wg), entries ? adj_scratch_doubles(sc, grid_e, wg) : 0);
     if (entries && c->memo) scratch_d = std::max(scratch_d, adj_scratch_doubles(sc, grid_m, 64));
+    if (sc.table) scratch_d = std::max(scratch_d, adj_scratch_doubles(sc, table_adj_blocks(sc), 128));
     rc = ensure_buf(c, c->scratch, sizeof(double) * (size_t)scratch_d, cap, "alloc adjoint scratch");
     if (rc) return rc;
-    rc = ensure_buf(c, c->partial, sizeof(double) * (size_t)sc.n_items * ML, cap, "alloc partial gradients");
+    const int64_t partial_d = sc.table ? table_adj_blocks(sc) * sc.Lmax : sc.n_items * (int64_t)ML;
+    rc = ensure_buf(c, c->partial, sizeof(double) * (size_t)partial_d, cap, "alloc partial gradients");
     if (rc) return rc;
     rc = ensure_buf(c, c->stats, sizeof(uint64_t) * ST_WORDS, cap, "alloc stats");
     if (rc) return rc;
     HIP_CHECK(c, launch_fill_u64((uint64_t*)c->stats.p, ST_WORDS, 0, s), "zero stats");
+    if (sc.table) {
+        // angle table: cotangents of the table entries, then one adjoint per entry
+        if (table_adj_smem_bytes(sc) > 65536) return fail(c, GWG_E_INVAL, "scene too large for the table adjoint's LDS");
+        const int64_t n_acc = table_adj_blocks(sc) * (int64_t)sc.table_n * 4;
+        rc = ensure_buf(c, c->tab_acc, sizeof(int64_t) * (size_t)n_acc, cap, "alloc table cotangents");
+        if (rc) return rc;
+        sc.tab_acc = (long long*)c->tab_acc.p;
+        const int64_t nbins = (int64_t)sc.D * sc.n_lsel * sc.F * sc.bins_x * sc.bins_y;
+        const int64_t grid_t = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, KIND_TABLE_ACCUM, sc.precision, 256,
+                                                                              table_accum_smem_bytes()));
+        HIP_CHECK(c, launch_fill_u64((uint64_t*)c->tab_acc.p, n_acc, 0, s), "zero table cotangents");
+        HIP_CHECK(c, launch_fill_u64((uint64_t*)(sc.tab_scale + 2), 1, 0, s), "zero dL/dI bound");
+        HIP_CHECK(c, launch_absmax(d_dL_dI, nbins, sc.tab_scale + 2, s), "dL/dI bound");
+        if (c->timing && !cap) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].begin(), s), "timing event");
+        if (entries) HIP_CHECK(c, launch_table_accum(sc, (int)grid_t, d_dL_dI, c->adj, s), "table cotangent kernel");
+        HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
+                                      (double*)c->scratch.p, sample_stride, entries ? c->adj.ovf : nullptr, s),
+                  "adjoint kernel");
+        HIP_CHECK(c, launch_table_adj(sc, (double*)c->partial.p, (double*)c->scratch.p, (unsigned long long*)c->stats.p, s),
+                  "table adjoint kernel");
+        if (c->timing && !cap) {
+            HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].end(), s), "timing event");
+            ++c->timer[GWG_KERNEL_ADJOINT].recorded;
+        }
+        HIP_CHECK(c, launch_table_reduce((const double*)c->partial.p, sc, d_grad, s), "gradient reduction");
+        if (stats) return read_stats(c, s, stats);
+        return GWG_OK;
+    }
     if (c->timing && !cap) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].begin(), s), "timing event");
     if (entries && c->memo)
         HIP_CHECK(c, launch_adj_memo(sc, (int)grid_m, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
@@ -876,7 +957,7 @@ int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const g
                 }
             std::fclose(f);
             if (found) {
-                gwg_tuning t{ wg, rpb, bwg, brpb, adj, c->tune.memo_keys };
+                gwg_tuning t{ wg, rpb, bwg, brpb, adj, c->tune.memo_keys, c->tune.table_nodes };
                 if (gwg_set_tuning(c, &t) == GWG_OK) {
                     c->tuned[key] = t;
                     *out = t;

@@ -88,7 +88,7 @@ struct QueueEmit {
     }
 };
 
-template <int MODE>
+template <int MODE, bool TAB>
 __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double* __restrict__ dLdI,
                                                    double* __restrict__ partial,
                                                    double* __restrict__ scratch, int64_t sample_stride,
@@ -128,6 +128,10 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long c_rays = 0, c_ev = 0, c_hits = 0, c_lay = 0, c_fp64 = 0;
     unsigned long long c_arays = 0, c_ahits = 0, c_alay = 0;
+    // angle table: coefficients are interpolated and the sweep's cotangents go
+    // to the table accumulators instead of the thin-film adjoint
+    constexpr bool tabm = TAB;
+    const double fx = tabm ? table_fx_scale(sc) : 0.0;
 
     for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
         // regen (optional): only items whose stored entries overflowed
@@ -141,6 +145,9 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
         __syncthreads();
         const int64_t base = point * sc.N;
         const double* g_bins = dLdI + point * B;
+        const int64_t dl = (int64_t)d * sc.n_lsel + l;
+        const double* tab_dl = tabm ? sc.table + dl * sc.M * 2 * sc.table_n * 8 : nullptr;
+        long long* acc_dl = tabm ? sc.tab_acc + dl * sc.M * 4 * sc.table_n * 4 : nullptr;
         int qhead = 0, qcount = 0;            // wave-uniform
         for (int64_t round = 0;; ++round) {
             const int64_t wave_first = i0 + (int64_t)wave * 64 + round * WG;
@@ -166,23 +173,36 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
                 active = gscale != 0.0;
                 nh = active ? r.nprma : 0;
             }
-            int htotal;
-            const int hoff = wave_excl_scan(nh, &htotal);
-            if (active) {
-                ray_birth(sc, *pl, id, r);
-                walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, hoff }, NoCoef{}, none, nullptr);
+            int hoff = 0;
+            if (!tabm) {
+                int htotal;
+                hoff = wave_excl_scan(nh, &htotal);
+                if (active) {
+                    ray_birth(sc, *pl, id, r);
+                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, hoff }, NoCoef{}, none, nullptr);
+                }
+                __threadfence_block();
+                solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, htotal, &c_fp64, &c_lay);
+                __threadfence_block();
             }
-            __threadfence_block();
-            solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, htotal, &c_fp64, &c_lay);
-            __threadfence_block();
             if (active) {
                 ray_birth(sc, *pl, id, r);
-                walk_ray<true, true>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, hoff, nullptr }, tape, &nt);
+                if constexpr (TAB)
+                    walk_ray<true, true>(sc, *pl, r, o, NoHit{}, TabCoef{ tab_dl, sc.table_n, pl->ng, sc.nx, sc.nz }, tape, &nt);
+                else
+                    walk_ray<true, true>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, hoff, nullptr }, tape, &nt);
                 c_rays += 1;
                 c_ev += (unsigned long long)r.nev;
                 c_hits += (unsigned long long)r.nprma;
             }
             const bool contrib = active;
+            if constexpr (TAB) {
+                if (contrib) {
+                    c_arays += 1;
+                    reverse_sweep(sc, *pl, r.e, tape, nt, TableEmit{ acc_dl, sc.table_n, pl->ng, gscale, fx });
+                }
+                continue;
+            }
             int total;
             const int off = wave_excl_scan(contrib ? r.nprma : 0, &total);
             if (contrib) {
@@ -212,6 +232,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             qcount = 0;
         }
         __syncthreads();
+        if constexpr (TAB) continue;
         double* out = partial + item * (int64_t)ML;
         for (int k = tid; k < ML; k += WG) {
             double acc = 0.0;

@@ -198,7 +198,12 @@ struct NoHit {
     __device__ void operator()(int, double, int) const {}
 };
 struct NoCoef {
-    __device__ Coef4 operator()(int) const { Coef4 c; c.rs = c.rp = c.ts = c.tp = mk(0.0, 0.0); return c; }
+    __device__ Coef4 operator()(int, double, double, double, int, bool) const
+    {
+        Coef4 c;
+        c.rs = c.rp = c.ts = c.tp = mk(0.0, 0.0);
+        return c;
+    }
 };
 struct PutHit {
     HitQueue q;
@@ -211,7 +216,7 @@ struct GetCoef {
     HitQueue q;
     int off;
     const double* mc;
-    __device__ Coef4 operator()(int h) const
+    __device__ Coef4 operator()(int h, double, double, double, int, bool) const
     {
         if (!mc) return q.coef(off + h);
         const double* b = mc + (int)q.base[2 * q.cap + off + h];
@@ -226,7 +231,7 @@ struct GetCoef {
 // handles a strided share of the item's rays.  Eyebox bins of the current
 // point accumulate in LDS (integer atomics) and are flushed per item with
 // integer global atomics: the result does not depend on scheduling.
-template <int MODE, bool ADJ>
+template <int MODE, bool ADJ, bool TAB>
 __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __restrict__ q_out,
                                                    uint32_t* __restrict__ c_out,
                                                    unsigned long long* __restrict__ stats,
@@ -257,6 +262,9 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     const TapeRef tape = { tape_scratch + (int64_t)blockIdx.x * WG + tid, (int64_t)gridDim.x * WG };
     const FwdMemo fm = fwd_memo(smem + lay.total, wave,
                                 scratch + (int64_t)gridDim.x * n_waves * kHitFields * cap + gwave * 8 * kFwdMemoKeys);
+    constexpr bool tabm = TAB;                           // angle-table thin film: no hit queue
+    double t_gmax = 0.0;                                 // largest cotangent component (angle table)
+    unsigned long long t_ne = 0;                         // cotangent pairs emitted (angle table)
 
     for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
         int64_t point, i0, i1;
@@ -278,6 +286,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             wave_lds_sync();
         }
         const int64_t ent0 = (item * st.waves + wave) * st.cap_w;
+        const double* tab_dl = tabm ? sc.table + (int64_t)(d * sc.n_lsel + l) * sc.M * 2 * sc.table_n * 8 : nullptr;
         for (int64_t round = 0;; ++round) {
             const int64_t wave_first = i0 + (int64_t)wave * 64 + round * WG;
             if (wave_first >= i1) break;                  // uniform across the wave
@@ -289,31 +298,37 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             TapeRef none = { nullptr, 0 };
             int nh = 0;
             bool to_eyebox = false;                        // fixed by geometry alone
-            if (active) {
+            if (active && (!tabm || ADJ)) {
                 ray_birth(sc, *pl, id, r);
                 walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
                 nh = r.nprma;
                 to_eyebox = o.cat == CAT_EYEBOX;
             }
-            int total;
-            const int off = wave_excl_scan(nh, &total);
-            if (active) {
-                ray_birth(sc, *pl, id, r);
-                walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, off }, NoCoef{}, none, nullptr);
+            int off = 0;
+            if (!tabm) {
+                int total;
+                off = wave_excl_scan(nh, &total);
+                if (active) {
+                    ray_birth(sc, *pl, id, r);
+                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, off }, NoCoef{}, none, nullptr);
+                }
+                __threadfence_block();
+                const int u0 = n_keys;
+                if (memo && !fmemo_resolve(hq, total, fm, sc.memo, &n_keys)) memo = false;
+                if (memo)
+                    fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
+                else
+                    solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, &n_fp64, &n_lay);
+                __threadfence_block();
             }
-            __threadfence_block();
-            const int u0 = n_keys;
-            if (memo && !fmemo_resolve(hq, total, fm, sc.memo, &n_keys)) memo = false;
-            if (memo)
-                fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
-            else
-                solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, &n_fp64, &n_lay);
-            __threadfence_block();
             int nt = 0;
             if (active) {
                 ray_birth(sc, *pl, id, r);
                 const TapeRef rt = { to_eyebox ? tape.base : nullptr, tape.ts };
-                walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off, memo ? fm.coef : nullptr }, rt, &nt);
+                if constexpr (TAB)
+                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, TabCoef{ tab_dl, sc.table_n, pl->ng, sc.nx, sc.nz }, rt, &nt);
+                else
+                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off, memo ? fm.coef : nullptr }, rt, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
                 atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);
@@ -349,6 +364,11 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     const int64_t cap = st.cap_w;
                     const int64_t meta_bin = (int64_t)o.bin << 10;
                     reverse_sweep(sc, *pl, r.e, tape, nt, [&](double kappa, cd Gs, cd Gp, int meta) {
+                        if constexpr (TAB) {
+                            const double a = fmax(fmax(fabs(Gs.re), fabs(Gs.im)), fmax(fabs(Gp.re), fabs(Gp.im)));
+                            t_gmax = a > t_gmax ? a : t_gmax;
+                            ++t_ne;
+                        }
                         if (k < cap) {
                             const int64_t e = ent0 + k;
                             st.ent[e] = kappa;
@@ -380,6 +400,12 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     }
     if (n_fp64) atomicAdd(&s_st[ST_FP64], n_fp64);
     if (n_lay) atomicAdd(&s_st[ST_LAYERS], n_lay);
+    if constexpr (ADJ && TAB) {
+        // nonnegative doubles order like their bit patterns
+        const double gm = wave_max(t_gmax);
+        if (lane == 0 && gm > 0.0) atomicMax(&sc.tab_scale[0], (unsigned long long)__double_as_longlong(gm));
+        if (t_ne) atomicAdd(&sc.tab_scale[1], t_ne);
+    }
     __syncthreads();
     for (int k = tid; k < ST_WORDS; k += WG)
         if (s_st[k]) atomicAdd(&stats[k], s_st[k]);

@@ -51,6 +51,8 @@ enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4
 // region of the item overflowed (the backward then regenerates that item).
 constexpr int kEntFields = 6;
 constexpr int kFwdMemoKeys = 128;      // largest key table per wave of the memoized forward
+constexpr int kTableNodesDefault = 8192;
+constexpr int kTableNodesMax = 1 << 20;
 struct AdjStore {
     double* ent;
     int32_t* cnt;
@@ -93,6 +95,11 @@ struct SceneDev {
     const uint32_t* step_dev;         // optional device step counter (graph replays)
     int32_t precision;
     int32_t memo;                     // forward: key table capacity per wave (0: solve every hit)
+    // angle table (table_n = 0: exact per-hit thin film)
+    const double* table;              // [D][n_lsel][M][2 sides][table_n][8]
+    int32_t table_n;
+    unsigned long long* tab_scale;    // [maxG bits, cotangent pairs, maxD bits] (fixed-point scale)
+    long long* tab_acc;               // backward: [D][n_lsel][M][2][2 branches][table_n][4]
     // work decomposition
     int64_t tiles_per_point;
     int64_t rays_per_tile;

@@ -99,9 +99,11 @@ __device__ inline void decode_item(const SceneDev& sc, int64_t item, int64_t* po
     *i1 = e < sc.N ? e : sc.N;
 }
 
+#include "gwg_table.h"
 #include "gwg_fwd_kernel.h"
 #include "gwg_bwd_kernel.h"
 #include "gwg_memo_kernel.h"
+#include "gwg_table_kernel.h"
 
 // Sum per-item partial gradients in item order: grad[d][k] = sum_items(d) partial[item][k].
 __global__ void k_grad_reduce(const double* __restrict__ partial, int64_t items_per_design, int ML,
@@ -321,29 +323,39 @@ static int blocks_per_cu(K kernel, int wg, size_t smem)
     return n;
 }
 
-template <bool ADJ>
+template <bool ADJ, bool TAB>
 static int fwd_blocks_per_cu(int precision, int wg, size_t smem)
 {
-    if (precision == GWG_FP64) return blocks_per_cu(k_trace_fwd<GWG_FP64, ADJ>, wg, smem);
-    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_fwd<GWG_FP32_MIXED, ADJ>, wg, smem);
-    return blocks_per_cu(k_trace_fwd<GWG_FP32, ADJ>, wg, smem);
+    if (precision == GWG_FP64) return blocks_per_cu(k_trace_fwd<GWG_FP64, ADJ, TAB>, wg, smem);
+    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_fwd<GWG_FP32_MIXED, ADJ, TAB>, wg, smem);
+    return blocks_per_cu(k_trace_fwd<GWG_FP32, ADJ, TAB>, wg, smem);
+}
+
+template <bool TAB>
+static int bwd_blocks_per_cu(int precision, int wg, size_t smem)
+{
+    if (precision == GWG_FP64) return blocks_per_cu(k_trace_bwd<GWG_FP64, TAB>, wg, smem);
+    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_bwd<GWG_FP32_MIXED, TAB>, wg, smem);
+    return blocks_per_cu(k_trace_bwd<GWG_FP32, TAB>, wg, smem);
 }
 
 int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem)
 {
     switch (kind) {
-    case KIND_FWD: return fwd_blocks_per_cu<false>(precision, wg, smem);
-    case KIND_FWD_ADJ: return fwd_blocks_per_cu<true>(precision, wg, smem);
-    case KIND_BWD_REGEN:
-        if (precision == GWG_FP64) return blocks_per_cu(k_trace_bwd<GWG_FP64>, wg, smem);
-        if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_bwd<GWG_FP32_MIXED>, wg, smem);
-        return blocks_per_cu(k_trace_bwd<GWG_FP32>, wg, smem);
+    case KIND_FWD: return fwd_blocks_per_cu<false, false>(precision, wg, smem);
+    case KIND_FWD_ADJ: return fwd_blocks_per_cu<true, false>(precision, wg, smem);
+    case KIND_FWD_TAB: return fwd_blocks_per_cu<false, true>(precision, wg, smem);
+    case KIND_FWD_ADJ_TAB: return fwd_blocks_per_cu<true, true>(precision, wg, smem);
+    case KIND_BWD_REGEN: return bwd_blocks_per_cu<false>(precision, wg, smem);
+    case KIND_BWD_REGEN_TAB: return bwd_blocks_per_cu<true>(precision, wg, smem);
     case KIND_ADJ_LOSSLESS:
         return blocks_per_cu(k_adj_entries<true>, wg, smem);
     case KIND_ADJ_MEMO:
         return blocks_per_cu(k_adj_memo<false>, 64 * kMemoWaves, smem);
     case KIND_ADJ_MEMO_LOSSLESS:
         return blocks_per_cu(k_adj_memo<true>, 64 * kMemoWaves, smem);
+    case KIND_TABLE_ACCUM:
+        return blocks_per_cu(k_table_accum, 64 * kMemoWaves, smem);
     default:
         return blocks_per_cu(k_adj_entries<false>, wg, smem);
     }
@@ -354,11 +366,18 @@ static void launch_fwd_mode(const SceneDev& sc, dim3 grid, dim3 block, size_t sm
                             uint32_t* c, unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
                             double* scratch, const AdjStore* adj, double* tape, hipStream_t s)
 {
-    if (adj)
-        hipLaunchKernelGGL((k_trace_fwd<MODE, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+    const bool tab = sc.table != nullptr;
+    if (adj && tab)
+        hipLaunchKernelGGL((k_trace_fwd<MODE, true, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
                            (int)lds_bins, scratch, *adj, tape);
+    else if (adj)
+        hipLaunchKernelGGL((k_trace_fwd<MODE, true, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+                           (int)lds_bins, scratch, *adj, tape);
+    else if (tab)
+        hipLaunchKernelGGL((k_trace_fwd<MODE, false, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+                           (int)lds_bins, scratch, AdjStore{}, (double*)nullptr);
     else
-        hipLaunchKernelGGL((k_trace_fwd<MODE, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+        hipLaunchKernelGGL((k_trace_fwd<MODE, false, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
                            (int)lds_bins, scratch, AdjStore{}, (double*)nullptr);
 }
 
@@ -382,23 +401,37 @@ hipError_t launch_trace_fwd(const SceneDev& sc, int wg, int grid_blocks, bool ld
     return hipGetLastError();
 }
 
+template <bool TAB>
+static void launch_bwd_mode(const SceneDev& sc, dim3 grid, dim3 block, size_t sm, const double* dLdI, double* partial,
+                            double* scratch, int64_t sample_stride, const int32_t* regen, unsigned long long* stats,
+                            hipStream_t s)
+{
+    switch (sc.precision) {
+    case GWG_FP64:
+        hipLaunchKernelGGL((k_trace_bwd<GWG_FP64, TAB>), grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride,
+                           regen, stats);
+        break;
+    case GWG_FP32_MIXED:
+        hipLaunchKernelGGL((k_trace_bwd<GWG_FP32_MIXED, TAB>), grid, block, sm, s, sc, dLdI, partial, scratch,
+                           sample_stride, regen, stats);
+        break;
+    default:
+        hipLaunchKernelGGL((k_trace_bwd<GWG_FP32, TAB>), grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride,
+                           regen, stats);
+        break;
+    }
+}
+
 hipError_t launch_trace_bwd(const SceneDev& sc, int wg, int grid_blocks, const double* dLdI, unsigned long long* stats,
                             double* partial, double* scratch, int64_t sample_stride, const int32_t* regen,
                             hipStream_t s)
 {
     size_t sm = bwd_smem_bytes(sc, wg);
     dim3 grid((unsigned)grid_blocks), block(wg);
-    switch (sc.precision) {
-    case GWG_FP64:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP64>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, regen, stats);
-        break;
-    case GWG_FP32_MIXED:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32_MIXED>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, regen, stats);
-        break;
-    default:
-        hipLaunchKernelGGL(k_trace_bwd<GWG_FP32>, grid, block, sm, s, sc, dLdI, partial, scratch, sample_stride, regen, stats);
-        break;
-    }
+    if (sc.table)
+        launch_bwd_mode<true>(sc, grid, block, sm, dLdI, partial, scratch, sample_stride, regen, stats, s);
+    else
+        launch_bwd_mode<false>(sc, grid, block, sm, dLdI, partial, scratch, sample_stride, regen, stats, s);
     return hipGetLastError();
 }
 
@@ -426,6 +459,63 @@ hipError_t launch_adj_memo(const SceneDev& sc, int grid_blocks, const double* dL
     else
         hipLaunchKernelGGL(k_adj_memo<false>, dim3((unsigned)grid_blocks), dim3(64 * kMemoWaves), sm, s, sc, dLdI, partial, st,
                            scratch, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_build(const SceneDev& sc, double* tab, int n_cu, unsigned long long* stats, hipStream_t s)
+{
+    const int wg = 256;
+    const int64_t dls = (int64_t)sc.D * sc.n_lsel;
+    const int64_t per = (int64_t)sc.M * 2 * sc.table_n;
+    // enough workgroups to fill the device twice, each with at least one wave of entries
+    int64_t chunks = std::max<int64_t>(1, (2 * (int64_t)n_cu + dls - 1) / dls);
+    chunks = std::min<int64_t>(chunks, (per + wg - 1) / wg);
+    const size_t sm = (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, false, 0).total;
+    const dim3 grid((unsigned)(dls * chunks)), block(wg);
+    switch (sc.precision) {
+    case GWG_FP64:
+        hipLaunchKernelGGL(k_table_build<GWG_FP64>, grid, block, sm, s, sc, tab, (int)chunks, stats);
+        break;
+    case GWG_FP32_MIXED:
+        hipLaunchKernelGGL(k_table_build<GWG_FP32_MIXED>, grid, block, sm, s, sc, tab, (int)chunks, stats);
+        break;
+    default:
+        hipLaunchKernelGGL(k_table_build<GWG_FP32>, grid, block, sm, s, sc, tab, (int)chunks, stats);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax(const double* x, int64_t n, unsigned long long* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_accum(const SceneDev& sc, int grid_blocks, const double* dLdI, const AdjStore& st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_table_accum, dim3((unsigned)grid_blocks), dim3(64 * kMemoWaves), table_accum_smem_bytes(), s, sc,
+                       dLdI, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_adj(const SceneDev& sc, double* partial, double* scratch, unsigned long long* stats,
+                            hipStream_t s)
+{
+    const dim3 grid((unsigned)(table_adj_blocks(sc))), block(128);
+    const size_t sm = table_adj_smem_bytes(sc);
+    if (sc.slot_complex == 0u)
+        hipLaunchKernelGGL(k_table_adj<true>, grid, block, sm, s, sc, partial, scratch, stats);
+    else
+        hipLaunchKernelGGL(k_table_adj<false>, grid, block, sm, s, sc, partial, scratch, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_reduce(const double* partial, const SceneDev& sc, double* grad, hipStream_t s)
+{
+    const int64_t n = (int64_t)sc.D * sc.M * sc.Lmax;
+    hipLaunchKernelGGL(k_table_reduce, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, s, partial, sc.D, sc.n_lsel, sc.M,
+                       sc.Lmax, sc.nlay, grad);
     return hipGetLastError();
 }
 

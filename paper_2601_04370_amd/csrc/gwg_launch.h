@@ -17,7 +17,8 @@ size_t tmm_smem_bytes(int L, int n_slots, int wg);
 int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
 enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3, KIND_ADJ_LOSSLESS = 4,
-       KIND_ADJ_MEMO = 5, KIND_ADJ_MEMO_LOSSLESS = 6 };
+       KIND_ADJ_MEMO = 5, KIND_ADJ_MEMO_LOSSLESS = 6, KIND_TABLE_ACCUM = 7, KIND_FWD_TAB = 8, KIND_FWD_ADJ_TAB = 9,
+       KIND_BWD_REGEN_TAB = 10 };
 int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem);
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 int64_t adj_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
@@ -33,6 +34,15 @@ hipError_t launch_adj_entries(const SceneDev& sc, int wg, int grid_blocks, const
 size_t memo_smem_bytes(const SceneDev& sc);
 hipError_t launch_adj_memo(const SceneDev& sc, int grid_blocks, const double* dLdI, unsigned long long* stats,
                            double* partial, const AdjStore& st, double* scratch, hipStream_t s);
+hipError_t launch_table_build(const SceneDev& sc, double* tab, int n_cu, unsigned long long* stats, hipStream_t s);
+hipError_t launch_absmax(const double* x, int64_t n, unsigned long long* out, hipStream_t s);
+size_t table_accum_smem_bytes();
+hipError_t launch_table_accum(const SceneDev& sc, int grid_blocks, const double* dLdI, const AdjStore& st, hipStream_t s);
+int64_t table_adj_blocks(const SceneDev& sc);
+size_t table_adj_smem_bytes(const SceneDev& sc);
+hipError_t launch_table_adj(const SceneDev& sc, double* partial, double* scratch, unsigned long long* stats,
+                            hipStream_t s);
+hipError_t launch_table_reduce(const double* partial, const SceneDev& sc, double* grad, hipStream_t s);
 hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D,
                               double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s);
 hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double* irr, hipStream_t s);

@@ -117,6 +117,43 @@ __device__ inline int memo_collect(const SceneDev& sc, const AdjStore& st, int64
     return U;
 }
 
+// Wave 0 merges the key tables of waves 1.. into its own, in wave and key
+// order (nk[w]: wave w's key count, -1 if its table overflowed).  Returns the
+// merged key count, or -1 if a table overflowed or the merge would.
+__device__ inline int memo_merge(unsigned char* mbase, const int* nk)
+{
+    const int lane = wave_lane();
+    const MemoLds m0 = memo_table(mbase, 0);
+    for (int w = 0; w < kMemoWaves; ++w)
+        if (nk[w] < 0) return -1;
+    int U = nk[0];
+    for (int w = 1; w < kMemoWaves; ++w) {
+        const MemoLds mw = memo_table(mbase, w);
+        for (int u = 0; u < nk[w]; ++u) {
+            const unsigned long long kb = mw.kbits[u];
+            const int km = mw.kmeta[u];
+            int idx = -1;
+            for (int k = lane; k < U; k += 64)
+                if (m0.kbits[k] == kb && m0.kmeta[k] == km) idx = k;
+            const unsigned long long hit = __ballot(idx >= 0);
+            if (hit) idx = __shfl(idx, __ffsll((long long)hit) - 1, 64);
+            else {
+                if (U == kMemoKeys) return -1;
+                idx = U++;
+                if (lane == 0) {
+                    m0.kbits[idx] = kb; m0.kmeta[idx] = km;
+                    for (int q = 0; q < 4; ++q) m0.gsum[q * kMemoKeys + idx] = 0.0;
+                }
+            }
+            if (lane == 0)
+                for (int q = 0; q < 4; ++q) m0.gsum[q * kMemoKeys + idx] += mw.gsum[q * kMemoKeys + u];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+        }
+    }
+    return U;
+}
+
 template <bool LOSSLESS>
 __global__ void __launch_bounds__(64 * kMemoWaves) k_adj_memo(SceneDev sc, const double* __restrict__ dLdI,
                                                               double* __restrict__ partial, AdjStore st,
@@ -162,38 +199,9 @@ __global__ void __launch_bounds__(64 * kMemoWaves) k_adj_memo(SceneDev sc, const
         const int nk = memo_collect(sc, st, item, cnt, g_bins, v0, v1, mt);
         if (lane == 0) s_nkeys[wave] = nk;
         __syncthreads();
-        // wave 0 merges the tables of waves 1.. into its own, in wave and key order
-        bool overflow = false;
-        for (int w = 0; w < kMemoWaves; ++w) overflow |= s_nkeys[w] < 0;
-        int U = s_nkeys[0];
-        if (wave == 0 && !overflow) {
-            for (int w = 1; w < kMemoWaves && !overflow; ++w) {
-                const MemoLds mw = memo_table(mbase, w);
-                for (int u = 0; u < s_nkeys[w]; ++u) {
-                    const unsigned long long kb = mw.kbits[u];
-                    const int km = mw.kmeta[u];
-                    int idx = -1;
-                    for (int k = lane; k < U; k += 64)
-                        if (m0.kbits[k] == kb && m0.kmeta[k] == km) idx = k;
-                    const unsigned long long hit = __ballot(idx >= 0);
-                    if (hit) idx = __shfl(idx, __ffsll((long long)hit) - 1, 64);
-                    else {
-                        if (U == kMemoKeys) { overflow = true; break; }
-                        idx = U++;
-                        if (lane == 0) {
-                            m0.kbits[idx] = kb; m0.kmeta[idx] = km;
-                            for (int q = 0; q < 4; ++q) m0.gsum[q * kMemoKeys + idx] = 0.0;
-                        }
-                    }
-                    if (lane == 0)
-                        for (int q = 0; q < 4; ++q) m0.gsum[q * kMemoKeys + idx] += mw.gsum[q * kMemoKeys + u];
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_s_waitcnt(0xc07f);
-                }
-            }
-        }
         if (wave == 0) {
-            if (overflow) {
+            const int U = memo_merge(mbase, s_nkeys);
+            if (U < 0) {
                 // too many keys: one thin-film adjoint per entry
                 const double invN = 1.0 / (double)sc.N;
                 for (int c = 0; c < total; c += 64) {

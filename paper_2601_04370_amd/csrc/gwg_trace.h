@@ -310,7 +310,8 @@ struct Outcome { int cat; int bin; double w; double w_in; };
 // FIELD = false: geometry and branch decisions only; every mirror hit h calls
 //   on_hit(h, kappa, meta).
 // FIELD = true: also the polarization field (Eq. 5 at every event, Eq. 6 at
-//   mirrors); mirror hit h takes its coefficients from get_coef(h); with
+//   mirrors); mirror hit h takes its coefficients from
+//   get_coef(h, direction, mirror, front); with
 //   TAPE and a non-null tape, field-changing events are recorded for the
 //   adjoint.
 // Both modes perform the same geometric operations, so they visit the same
@@ -394,7 +395,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
         double ndx = r.dx, ndz = r.dz;
         if (refl) mirror_reflect(nx, nz, r.dx, r.dz, &ndx, &ndz);
         if (FIELD) {
-            const Coef4 co = get_coef(h);
+            const Coef4 co = get_coef(h, r.dx, r.dy, r.dz, m, front);
             double sv[3], pin[3], pout[3];
             s_basis(r.dx, r.dy, r.dz, nx, 0.0, nz, sv);
             cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);

@@ -93,7 +93,7 @@ class Stats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("rays_per_block", C.c_int64),
                 ("bwd_block_threads", C.c_int32), ("bwd_rays_per_block", C.c_int64),
-                ("adj_entries_per_ray", C.c_int32), ("memo_keys", C.c_int32)]
+                ("adj_entries_per_ray", C.c_int32), ("memo_keys", C.c_int32), ("table_nodes", C.c_int32)]
 
 
 #: every function declared in include/gwg.h
@@ -104,6 +104,7 @@ EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gw
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 GWG_FWD_GRAD = 1
 GWG_FWD_MEMO = 2
+GWG_FWD_TABLE = 4
 
 _lib = None
 
@@ -272,9 +273,9 @@ class Context:
             raise GwgError(rc, self.lib.gwg_last_error(self.h).decode())
 
     def set_tuning(self, block_threads=0, rays_per_block=0, bwd_block_threads=0, bwd_rays_per_block=0,
-                   adj_entries_per_ray=0, memo_keys=0):
+                   adj_entries_per_ray=0, memo_keys=0, table_nodes=0):
         t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block, adj_entries_per_ray,
-                   memo_keys)
+                   memo_keys, table_nodes)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
 
     def forward_kept_entries(self) -> bool:
@@ -340,13 +341,14 @@ class Context:
     # ---------------------------------------------------------------- trace
     def trace_forward(self, scene: SceneSpec, thk, seed: int, step: int = 0, precision: int = FP64,
                       record_stride: int = 0, stats: bool = False, want_irradiance: bool = True,
-                      grad: bool = False, memo: bool = False):
+                      grad: bool = False, memo: bool = False, table: bool = False):
         """Returns (q_bins u64-as-int64, counts int32, irradiance f64 or None,
         records or None, stats dict or None); tensors on the context's GPU.
         grad=True prepares the adjoint entries for a following trace_backward;
         memo=True solves each distinct hit key of a work item once (results
         identical to the per-hit solves) and, with grad, makes that backward
-        solve one thin-film adjoint per distinct key."""
+        solve one thin-film adjoint per distinct key.  table=True interpolates
+        the thin film from the angle table (tuning table_nodes angles)."""
         torch = self.torch
         dev = torch.device("cuda", self.device)
         assert tuple(thk.shape) == scene.thk_shape and thk.dtype == torch.float64 and thk.is_contiguous()
@@ -366,7 +368,8 @@ class Context:
         self.forward_id += 1
         rc = self.lib.gwg_trace_forward(self.h, C.byref(s), C.byref(p), C.byref(m), C.byref(st), C.byref(r),
                                         seed & 0xFFFFFFFFFFFFFFFF, step, precision,
-                                        (GWG_FWD_GRAD if grad else 0) | (GWG_FWD_MEMO if memo else 0), C.byref(eb),
+                                        (GWG_FWD_GRAD if grad else 0) | (GWG_FWD_MEMO if memo else 0)
+                                        | (GWG_FWD_TABLE if table else 0), C.byref(eb),
                                         rec.data_ptr() if rec is not None else None, int(record_stride or 1),
                                         C.byref(sts) if sts is not None else None, _stream(torch, dev))
         if rc == GWG_E_OVERFLOW:
