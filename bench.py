@@ -135,6 +135,10 @@ def main():
     ap.add_argument("--memo", action="store_true",
                     help="memoized thin film: one solve per distinct hit key of a work item in the forward, one "
                          "adjoint per key in the backward (reported separately from the per-hit metric)")
+    ap.add_argument("--table", action="store_true",
+                    help="angle-table thin film (interpolated model, reported separately with its error against "
+                         "the per-hit solve)")
+    ap.add_argument("--table-nodes", type=int, default=0, help="incidence angles of the table (0: library default)")
     ap.add_argument("--per-design", action="store_true",
                     help="also time one launch per design (the batched workload) for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -176,10 +180,17 @@ def main():
         extra["tuning"] = ctx.autotune(scene, thk, w.seed, prec, grad=not fo)
         extra["autotune_s"] = time.perf_counter() - t
 
-    def step(k, ev=None, sc=scene, th=thk):
+    if a.memo and a.table:
+        sys.exit("--memo and --table exclude each other")
+    if a.table and a.table_nodes:
+        t = ctx.get_tuning()
+        t["table_nodes"] = a.table_nodes
+        ctx.set_tuning(**t)
+
+    def step(k, ev=None, sc=scene, th=thk, table=a.table):
         if ev:
             ev[0].record()
-        _, _, irr, _, _ = ctx.trace_forward(sc, th, w.seed, k, prec, grad=not fo, memo=a.memo)
+        _, _, irr, _, _ = ctx.trace_forward(sc, th, w.seed, k, prec, grad=not fo, memo=a.memo, table=table)
         if ev:
             ev[1].record()
         if fo:
@@ -243,11 +254,31 @@ def main():
         extra["graph_ms_per_step"] = g_wall / a.steps * 1e3
         extra["eager_ms_per_step"] = wall / a.steps * 1e3
 
+    if a.table:
+        # the interpolated model against the per-hit solve on the same paths
+        # (untimed): irradiance and, for a full step, the gradient
+        k = a.warmup
+        _, _, irr_t, _, _ = ctx.trace_forward(scene, thk, w.seed, k, prec, grad=not fo, table=True)
+        irr_t = irr_t.clone()
+        g_t = None
+        if not fo:
+            _, dLdI_t = ctx.loss(irr_t, 0)
+        _, _, irr_e, _, _ = ctx.trace_forward(scene, thk, w.seed, k, prec, grad=not fo)
+        e_irr = float((irr_t - irr_e).abs().max() / irr_e.abs().max())
+        tab = {"nodes": ctx.get_tuning()["table_nodes"] or 8192, "irradiance_max_rel_err": e_irr,
+               "irradiance_mean_abs_rel_err": float((irr_t - irr_e).abs().sum() / irr_e.abs().sum())}
+        if not fo:
+            g_e = ctx.trace_backward(dLdI_t, scene).clone()
+            ctx.trace_forward(scene, thk, w.seed, k, prec, grad=True, table=True)
+            g_t = ctx.trace_backward(dLdI_t, scene)
+            tab["grad_max_rel_err"] = float((g_t - g_e).abs().max() / g_e.abs().max())
+        extra["table"] = tab
+
     # counters of the timed steps (recomputed untimed: same seeds, same paths)
     inter = hits = lay_f = lay_b = lay_a = fp64h = 0
     for i in range(a.steps):
         _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True, grad=not fo,
-                                             memo=a.memo)
+                                             memo=a.memo, table=a.table)
         inter += st["interactions"]
         hits += st["prma_hits"]
         lay_f += st["layer_steps"]
@@ -288,7 +319,7 @@ def main():
     # the adjoint launch is the entry kernel (plus the regenerating kernel,
     # which only runs for items whose entry regions overflowed)
     if not fo and t_bwd >= t_fwd:
-        kname, flops, tk = ("k_adj_memo" if a.memo else "k_adj_entries"), f_bwd, t_bwd
+        kname, flops, tk = ("k_adj_memo" if a.memo else "k_table_adj" if a.table else "k_adj_entries"), f_bwd, t_bwd
     else:
         kname, flops, tk = "k_trace_fwd", f_fwd, t_fwd
     achieved = flops / tk / 1e12
@@ -304,8 +335,8 @@ def main():
     if not fo:
         extra.update({"bwd_kernel_ms": t_bwd * 1e3, "bwd_tflops": f_bwd / t_bwd / 1e12})
     out = {
-        "metric": (METRIC if not a.memo else METRIC + " (memoized thin-film backward)") if not fo
-        else "fwd ray-surface interactions/s",
+        "metric": (METRIC + (" (memoized thin film)" if a.memo else " (angle-table thin film)" if a.table else ""))
+        if not fo else "fwd ray-surface interactions/s",
         "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == gwg.FP64 else "f32+f64", "data": "synthetic",
@@ -315,7 +346,8 @@ def main():
                    "rays_per_point": w.rays_per_point, "rays_per_step": w.n_rays,
                    "bins": list(w.bins), "max_events": w.max_events, "precision": a.precision,
                    "step": "forward" if fo else "forward+loss+adjoint",
-                   "thin_film_adjoint": "per distinct hit key" if a.memo else "per hit",
+                   "thin_film": ("memoized per distinct hit key" if a.memo else
+                                 "angle table, Catmull-Rom interpolation" if a.table else "per hit"),
                    "launch": "graph" if a.graph else "eager"},
         "roofline": roof,
         "extra": extra,

@@ -278,6 +278,11 @@ class Context:
                    memo_keys, table_nodes)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
 
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(self.lib.gwg_get_tuning(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
     def forward_kept_entries(self) -> bool:
         """True if the last forward stored adjoint entries for the backward."""
         v = C.c_int32(0)
