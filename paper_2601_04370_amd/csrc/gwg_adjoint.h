@@ -250,10 +250,12 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
                                             double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
                                             double* grad_row, double* __restrict__ chk, int64_t cstride)
 {
-    // 1) exit -> incident sweep, checkpoints w_{kSeg}, w_{2 kSeg}, ...: first
-    //    the L % kSeg layers above the last multiple of kSeg, then whole
-    //    groups of kSeg layers, each ending in a checkpoint (group 0 in none)
+    // 1) exit -> incident sweep v_j = M_j v_{j+1}, checkpoints v_K, v_2K, ...
+    //    (K = kSegL): first the L % K layers above the last multiple of K,
+    //    then whole groups of K layers, each ending in a checkpoint (group 0
+    //    in none: v_0 stays in registers)
     if (L <= 0) return;
+    constexpr int K = kSegL;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
     V2d vp = { 1.0, 0.0, eta0p, 0.0 };
     auto layer_fwd = [&](int jj) {
@@ -269,71 +271,68 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
         c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
         c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
     };
-    const int ng = L / kSeg;
-    for (int jj = L - 1; jj >= ng * kSeg; --jj) layer_fwd(jj);
-    if (ng > 0 && ng * kSeg < L) checkpoint(ng);     // w_{ng kSeg}, after the top layers
+    const int ng = L / K;
+    for (int jj = L - 1; jj >= ng * K; --jj) layer_fwd(jj);
+    if (ng > 0 && ng * K < L) checkpoint(ng);        // v_{ng K}, after the top layers
     for (int g = ng - 1; g >= 0; --g) {
-#pragma unroll
-        for (int i = kSeg - 1; i >= 0; --i) layer_fwd(g * kSeg + i);
+#pragma unroll 2
+        for (int i = K - 1; i >= 0; --i) layer_fwd(g * K + i);
         if (g > 0) checkpoint(g);
     }
     // 2) cotangent rows of the taken coefficients
     cd u1s, u2s, u1p, u2p;
     coef_cotangent(vs, eta0s, reflect, false, Gs, &u1s, &u2s);
     coef_cotangent(vp, eta0p, reflect, true, Gp, &u1p, &u2p);
-    // 3) incident -> exit covector sweep, segment by segment.  Every segment
-    //    has kSeg layers: layers past the end of the stack get t = 0 (the
-    //    identity, C = 1, S = 0 exactly) and add no gradient, so all loads of
-    //    a segment are independent of the arithmetic and issued first.
+    // 3) incident -> exit covector sweep.  The state a layer's contraction
+    //    needs, v_j, is walked down from the top of its segment (v_0 from the
+    //    sweep, v_{kK} from checkpoint k) with the inverse layer matrix: a
+    //    lossless layer, circular or hyperbolic, is unimodular with
+    //    M^-1 = [[C, iX], [iY, C]], so one sine/cosine per layer serves the
+    //    contraction, the covector step and the inverse step, and no
+    //    per-segment state is kept.  Checkpoint k + 1 is loaded while segment
+    //    k runs; each layer's LDS operands are loaded one layer ahead.
     const double k2 = 2.0 * k0;
-    const int nseg = (L + kSeg - 1) / kSeg;
-    for (int k = 0; k < nseg; ++k) {
-        const int lo = k * kSeg;
-        V2d ws, wp;
-        if (lo + kSeg >= L) {
-            ws = V2d{ 1.0, 0.0, eta0s, 0.0 };
-            wp = V2d{ 1.0, 0.0, eta0p, 0.0 };
-        } else {
-            const double* c = chk + (int64_t)((lo + kSeg) / kSeg) * 8 * cstride;
-            ws = V2d{ c[0], c[cstride], c[2 * cstride], c[3 * cstride] };
-            wp = V2d{ c[4 * cstride], c[5 * cstride], c[6 * cstride], c[7 * cstride] };
+    V2d ws = vs, wp = vp, nws = vs, nwp = vp;
+    auto load_chk = [&](int k) {
+        const double* c = chk + (int64_t)k * 8 * cstride;
+        nws = V2d{ c[0], c[cstride], c[2 * cstride], c[3 * cstride] };
+        nwp = V2d{ c[4 * cstride], c[5 * cstride], c[6 * cstride], c[7 * cstride] };
+    };
+    if (K < L) load_chk(1);
+    int idx = front ? 0 : L - 1;
+    const int step = front ? 1 : -1;
+    double t0 = thk[idx];
+    double kq, xs, ys, xp, yp;
+    sl.lossless(slot[idx], kq, xs, ys, xp, yp);
+    for (int lo = 0; lo < L; lo += K) {
+        if (lo > 0) {
+            ws = nws;
+            wp = nwp;
+            if (lo + K < L) load_chk(lo / K + 1);
         }
-        int sidx[kSeg], sslot[kSeg];
-        double st[kSeg];
-#pragma unroll
-        for (int i = 0; i < kSeg; ++i) {
-            const int jj = lo + i;
-            const int jc = jj < L ? jj : L - 1;
-            sidx[i] = front ? jc : (L - 1 - jc);
-            sslot[i] = slot[sidx[i]];
-            st[i] = jj < L ? thk[sidx[i]] : 0.0;
-        }
-        V2d segs[kSeg], segp[kSeg];
-        double segC[kSeg], sXs[kSeg], sYs[kSeg], sXp[kSeg], sYp[kSeg];
-        double cys[kSeg], gys[kSeg], cxp[kSeg], cyp[kSeg];   // y_s, sg y_s, x_p, y_p
-#pragma unroll
-        for (int i = kSeg - 1; i >= 0; --i) {
-            double kq, xs, ys, xp, yp, C, S;
-            sl.lossless(sslot[i], kq, xs, ys, xp, yp);
-            layer_cs(kq, st[i], &C, &S);
-            segC[i] = C;
-            sXs[i] = S * xs; sYs[i] = S * ys; sXp[i] = S * xp; sYp[i] = S * yp;
-            cys[i] = ys; gys[i] = kq < 0.0 ? -ys : ys; cxp[i] = xp; cyp[i] = yp;
-            step_real_d(ws, C, sXs[i], sYs[i]);
-            step_real_d(wp, C, sXp[i], sYp[i]);
-            segs[i] = ws; segp[i] = wp;
-        }
-#pragma unroll
-        for (int i = 0; i < kSeg; ++i) {
+        const int hi = lo + K < L ? lo + K : L;
+#pragma unroll 2
+        for (int j = lo; j < hi; ++j) {
+            const int idn = j + 1 < L ? idx + step : idx;
+            const double t1 = thk[idn];
+            double kq1, xs1, ys1, xp1, yp1;
+            sl.lossless(slot[idn], kq1, xs1, ys1, xp1, yp1);
+            double C, S;
+            layer_cs(kq, t0, &C, &S);
+            const double sXs = S * xs, sYs = S * ys, sXp = S * xp, sYp = S * yp;
+            const double gys = kq < 0.0 ? -ys : ys;
             // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
-            const double i_s1 = u1s.re * segs[i].ci + u1s.im * segs[i].cr;   // Im(u1s C_s)
-            const double i_s2 = u2s.re * segs[i].bi + u2s.im * segs[i].br;   // Im(u2s B_s)
-            const double i_p1 = u1p.re * segp[i].ci + u1p.im * segp[i].cr;   // Im(u1p C_p)
-            const double i_p2 = u2p.re * segp[i].bi + u2p.im * segp[i].br;   // Im(u2p B_p)
-            const double g = k2 * (i_s1 + gys[i] * (cys[i] * i_s2 + cxp[i] * i_p1 + cyp[i] * i_p2));
-            if (lo + i < L) atomicAdd(&grad_row[sidx[i]], g);
-            cov_step_real(u1s, u2s, segC[i], sXs[i], sYs[i]);
-            cov_step_real(u1p, u2p, segC[i], sXp[i], sYp[i]);
+            const double i_s1 = u1s.re * ws.ci + u1s.im * ws.cr;   // Im(u1s C_s)
+            const double i_s2 = u2s.re * ws.bi + u2s.im * ws.br;   // Im(u2s B_s)
+            const double i_p1 = u1p.re * wp.ci + u1p.im * wp.cr;   // Im(u1p C_p)
+            const double i_p2 = u2p.re * wp.bi + u2p.im * wp.br;   // Im(u2p B_p)
+            const double g = k2 * (i_s1 + gys * (ys * i_s2 + xp * i_p1 + yp * i_p2));
+            atomicAdd(&grad_row[idx], g);
+            cov_step_real(u1s, u2s, C, sXs, sYs);
+            cov_step_real(u1p, u2p, C, sXp, sYp);
+            step_real_d(ws, C, -sXs, -sYs);
+            step_real_d(wp, C, -sXp, -sYp);
+            idx = idn; t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
         }
     }
 }

@@ -29,6 +29,7 @@ constexpr int LT_NSLOT = 40;          // number of slots (as double)
 
 constexpr int kTapeStride = 15;       // doubles per tape entry (backward)
 constexpr int kSeg = 4;               // layers per recomputation segment (backward)
+constexpr int kSegL = 16;             // checkpoint interval of the lossless adjoint (multiple of kSeg)
 
 enum EventType { EV_NONE = 0, EV_TIR = 1, EV_EXIT = 2, EV_LEAK = 3, EV_END = 4, EV_MIRROR = 5 };
 enum Category { CAT_EYEBOX = 0, CAT_MISS = 1, CAT_LEAK = 2, CAT_END = 3, CAT_TRUNC = 4,

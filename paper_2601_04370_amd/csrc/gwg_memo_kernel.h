@@ -155,7 +155,7 @@ __device__ inline int memo_merge(unsigned char* mbase, const int* nk)
 }
 
 template <bool LOSSLESS>
-__global__ void __launch_bounds__(64 * kMemoWaves) k_adj_memo(SceneDev sc, const double* __restrict__ dLdI,
+__global__ void __launch_bounds__(64 * kMemoWaves, 2) k_adj_memo(SceneDev sc, const double* __restrict__ dLdI,
                                                               double* __restrict__ partial, AdjStore st,
                                                               double* __restrict__ scratch,
                                                               unsigned long long* __restrict__ stats)

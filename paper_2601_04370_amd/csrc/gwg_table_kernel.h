@@ -142,7 +142,7 @@ size_t table_accum_smem_bytes()
 // One workgroup (two waves) per (design, wavelength, mirror, side, branch):
 // block b covers accumulators [b n, (b + 1) n) and writes partial row b.
 template <bool LOSSLESS>
-__global__ void __launch_bounds__(128) k_table_adj(SceneDev sc, double* __restrict__ partial,
+__global__ void __launch_bounds__(128, 2) k_table_adj(SceneDev sc, double* __restrict__ partial,
                                                  double* __restrict__ scratch,
                                                  unsigned long long* __restrict__ stats)
 {
