@@ -11,11 +11,10 @@ struct V2d { double br, bi, cr, ci; };
 
 __device__ inline void step_real_d(V2d& v, double C, double X, double Y)
 {
-#pragma clang fp contract(fast)
-    double br = C * v.br + X * v.ci;
-    double bi = C * v.bi - X * v.cr;
-    double cr = Y * v.bi + C * v.cr;
-    double ci = C * v.ci - Y * v.br;
+    double br = fma(C, v.br, X * v.ci);
+    double bi = fma(C, v.bi, -(X * v.cr));
+    double cr = fma(C, v.cr, Y * v.bi);
+    double ci = fma(C, v.ci, -(Y * v.br));
     v.br = br; v.bi = bi; v.cr = cr; v.ci = ci;
 }
 
@@ -77,9 +76,8 @@ __device__ inline void cov_step(cd& u1, cd& u2, cd C, cd X, cd Y)
 // u^T <- u^T M for a lossless layer, M = [[C, -iX], [-iY, C]] with real C, X, Y.
 __device__ inline void cov_step_real(cd& u1, cd& u2, double C, double X, double Y)
 {
-#pragma clang fp contract(fast)
-    const double a = u1.re * C + Y * u2.im, b = u1.im * C - Y * u2.re;
-    const double c = u2.re * C + X * u1.im, d = u2.im * C - X * u1.re;
+    const double a = fma(u1.re, C, Y * u2.im), b = fma(u1.im, C, -(Y * u2.re));
+    const double c = fma(u2.re, C, X * u1.im), d = fma(u2.im, C, -(X * u1.re));
     u1 = mk(a, b);
     u2 = mk(c, d);
 }
@@ -240,11 +238,13 @@ __device__ inline void coef_cotangent(const V2d& v, double eta0, bool reflect, b
 }
 
 // Adjoint of one mirror hit whose stack has no absorbing layer (every layer
-// matrix has real C, X, Y).  Same contract as tmm_adjoint.  The contraction
+// matrix has real C, X, Y).  Same contract as tmm_adjoint.  HC = false: no
+// lane of the calling wave has an evanescent slot.  The contraction
 // uses the slot parameters (x_s, y_s, x_p, y_p) = (1/q, q, q/N^2, N^2/q) for a
 // propagating layer or (1/Q, -Q, -Q/N^2, N^2/Q) for an evanescent one
 // (q = iQ), with sg = +1 or -1 respectively:
 //     z = sg y_s^2,  z / N^2 = sg y_s x_p,  N^2 = sg y_s y_p.
+template <bool HC = true>
 __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, const uint8_t* __restrict__ slot,
                                             int L, bool front, const LaneSlots3& sl, double k0,
                                             double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
@@ -262,7 +262,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
         const int idx = front ? jj : (L - 1 - jj);
         double kq, xs, ys, xp, yp, C, S;
         sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-        layer_cs(kq, thk[idx], &C, &S);             // t = 0 gives the identity exactly
+        layer_cs<double, HC>(kq, thk[idx], &C, &S);             // t = 0 gives the identity exactly
         step_real_d(vs, C, S * xs, S * ys);
         step_real_d(vp, C, S * xp, S * yp);
     };
@@ -318,7 +318,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             double kq1, xs1, ys1, xp1, yp1;
             sl.lossless(slot[idn], kq1, xs1, ys1, xp1, yp1);
             double C, S;
-            layer_cs(kq, t0, &C, &S);
+            layer_cs<double, HC>(kq, t0, &C, &S);
             const double sXs = S * xs, sYs = S * ys, sXp = S * xp, sYp = S * yp;
             const double gys = kq < 0.0 ? -ys : ys;
             // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]

@@ -51,16 +51,25 @@ __device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const
 {
     const int m = meta & 255;
     const bool front = (meta >> 8) & 1, refl = (meta >> 9) & 1;
+    bool hyp = false;                       // an evanescent lossless slot at this kappa
     for (int s = 0; s < sc.n_slots; ++s) {
         double P[NPF];
         slot_params(pl.slotN[2 * s], pl.slotN[2 * s + 1], kappa, pl.k0, P);
         sl.put(s, P);
+        hyp |= !((sc.slot_complex >> s) & 1u) && P[0] < 0.0;
     }
     const double z0 = pl.ng * pl.ng - kappa * kappa;
     const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
-    if (LOSSLESS || sc.slot_complex == 0u)
-        tmm_adjoint_lossless(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
-                             pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride);
+    if (LOSSLESS || sc.slot_complex == 0u) {
+        // waves whose lanes all see circular layers take the sweep without
+        // the hyperbolic case (same results)
+        if (__ballot(hyp) == 0ull)
+            tmm_adjoint_lossless<false>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
+                                        pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride);
+        else
+            tmm_adjoint_lossless<true>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
+                                       pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride);
+    }
     else if (!LOSSLESS)
         tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, sc.slot_complex,
                     pl.k0, kappa * kappa, q0, pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk,

@@ -175,9 +175,13 @@ __constant__ float kInvFactF[11] = {
     (float)inv_fact(5), (float)inv_fact(6), (float)inv_fact(7), (float)inv_fact(8), (float)inv_fact(9),
     (float)inv_fact(10) };
 
-__device__ inline void gtrig(double a, bool hyper, double* C, double* S)
+// HC = false compiles the circular case alone (hyper must then be false):
+// the same operations, so the same results, without the hyperbolic branch.
+template <bool HC = true>
+__device__ inline void gtrig(double a, bool hyper_in, double* C, double* S)
 {
 #pragma clang fp contract(fast)
+    const bool hyper = HC && hyper_in;
     const double two_over_pi = 0.63661977236758134308;
     const double pio2_hi = 1.5707963267948966;
     const double pio2_lo = 6.123233995736766e-17;
@@ -230,9 +234,11 @@ __device__ inline void gtrig(double a, bool hyper, double* C, double* S)
     }
 }
 
-__device__ inline void gtrig(float a, bool hyper, float* C, float* S)
+template <bool HC = true>
+__device__ inline void gtrig(float a, bool hyper_in, float* C, float* S)
 {
 #pragma clang fp contract(fast)
+    const bool hyper = HC && hyper_in;
     const float two_over_pi = 0.636619772f;
     const float pio2_hi = 1.57079637f;
     const float pio2_lo = -4.37113883e-8f;
@@ -383,11 +389,12 @@ template <typename T> struct CTv { T re, im; };
 template <typename T>
 __device__ inline void step_real(V2<T>& v, T C, T X, T Y)
 {
-#pragma clang fp contract(fast)
-    T br = C * v.br + X * v.ci;
-    T bi = C * v.bi - X * v.cr;
-    T cr = Y * v.bi + C * v.cr;
-    T ci = C * v.ci - Y * v.br;
+    // explicit fused operations: the rounding does not depend on how the
+    // compiler contracts each inlined copy
+    T br = fma(C, v.br, X * v.ci);
+    T bi = fma(C, v.bi, -(X * v.cr));
+    T cr = fma(C, v.cr, Y * v.bi);
+    T ci = fma(C, v.ci, -(Y * v.br));
     v.br = br; v.bi = bi; v.cr = cr; v.ci = ci;
 }
 
@@ -415,12 +422,13 @@ __device__ inline void step_cplx(V2<T>& v, CTv<T> C, CTv<T> X, CTv<T> Y)
     v.cr = c1.re + c2.re; v.ci = c1.im + c2.im;
 }
 
-// Trig part of a lossless layer: circular or hyperbolic by the sign of kq.
-template <typename T>
+// Trig part of a lossless layer: circular or hyperbolic by the sign of kq
+// (HC = false: the caller knows every layer is circular).
+template <typename T, bool HC = true>
 __device__ inline void layer_cs(T kq, T t, T* C, T* S)
 {
-    const bool hyper = kq < (T)0;
-    gtrig(hyper ? -kq * t : kq * t, hyper, C, S);
+    const bool hyper = HC && kq < (T)0;
+    gtrig<HC>(hyper ? -kq * t : kq * t, hyper, C, S);
 }
 
 // Entries of an absorbing layer: returns C, X_s, Y_s, X_p, Y_p.
@@ -474,15 +482,52 @@ __device__ inline Coef4 finish_coeffs(const V2<T>& vs, const V2<T>& vp, int es, 
     return o;
 }
 
+// Lossless stack: one loop body for every layer.  The LDS reads run ahead of
+// the arithmetic: thickness and slot two layers ahead, the slot's parameters
+// one layer ahead.  HC = false: no layer of any lane is evanescent.
+template <typename T, bool HC, class SL>
+__device__ __attribute__((always_inline)) inline void lossless_sweep(const double* __restrict__ thk,
+                                                                     const uint8_t* __restrict__ slot, int L,
+                                                                     bool front, const SL& sl, V2<T>& vs, V2<T>& vp,
+                                                                     int& es, int& ep)
+{
+    const int dir = front ? -1 : 1;
+    const int last = front ? 0 : L - 1;
+    const int idx = front ? L - 1 : 0;
+    double t0 = thk[idx];
+    double kq, xs, ys, xp, yp;
+    sl.lossless(slot[idx], kq, xs, ys, xp, yp);
+    int idx1 = idx == last ? idx : idx + dir;
+    double t1 = thk[idx1];
+    int s1 = slot[idx1];
+#pragma unroll 2
+    for (int j = 0; j < L; ++j) {
+        const int idx2 = idx1 == last ? idx1 : idx1 + dir;
+        const double t2 = thk[idx2];
+        const int s2 = slot[idx2];
+        double kq1, xs1, ys1, xp1, yp1;
+        sl.lossless(s1, kq1, xs1, ys1, xp1, yp1);
+        T C, S;
+        layer_cs<T, HC>((T)kq, (T)t0, &C, &S);    // t = 0 gives the identity exactly
+        step_real(vs, C, S * (T)xs, S * (T)ys);
+        step_real(vp, C, S * (T)xp, S * (T)yp);
+        if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
+        t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+        t1 = t2; s1 = s2; idx1 = idx2;
+    }
+}
+
 // Forward solve of one hit.  thk/slot: this mirror's layers in stack order
 // (LDS); `front` selects incidence order 0..L-1 (else reversed).  sl: this
 // lane's slot table.  Exit medium admittances (es, ep) are complex in general.
 // The stack thicknesses and slot parameters are read in double precision
-// and rounded to the chain precision T once per layer.
+// and rounded to the chain precision T once per layer.  circ: no lane of the
+// calling wave has an evanescent lossless slot (the sweep then skips the
+// hyperbolic case; the results are the same).
 template <typename T, class SL>
 __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t* __restrict__ slot, int L,
                                   bool front, const SL& sl, uint32_t cplx_mask, double k0d, double eta0s,
-                                  double eta0p, cd etaEs, cd etaEp, cd tp_factor)
+                                  double eta0p, cd etaEs, cd etaEp, cd tp_factor, bool circ = false)
 {
     const T k0 = (T)k0d;
     V2<T> vs = { (T)1, (T)0, (T)etaEs.re, (T)etaEs.im };
@@ -490,33 +535,12 @@ __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* _
     int es = 0, ep = 0;
     if (L <= 0) return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
     const int dir = front ? -1 : 1;
-    const int last = front ? 0 : L - 1;
     int idx = front ? L - 1 : 0;
     if (cplx_mask == 0u) {
-        // Lossless stack: one loop body for every layer.  The LDS reads run
-        // ahead of the arithmetic: thickness and slot two layers ahead, the
-        // slot's parameters one layer ahead.
-        double t0 = thk[idx];
-        double kq, xs, ys, xp, yp;
-        sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-        int idx1 = idx == last ? idx : idx + dir;
-        double t1 = thk[idx1];
-        int s1 = slot[idx1];
-#pragma unroll 2
-        for (int j = 0; j < L; ++j) {
-            const int idx2 = idx1 == last ? idx1 : idx1 + dir;
-            const double t2 = thk[idx2];
-            const int s2 = slot[idx2];
-            double kq1, xs1, ys1, xp1, yp1;
-            sl.lossless(s1, kq1, xs1, ys1, xp1, yp1);
-            T C, S;
-            layer_cs((T)kq, (T)t0, &C, &S);    // t = 0 gives the identity exactly
-            step_real(vs, C, S * (T)xs, S * (T)ys);
-            step_real(vp, C, S * (T)xp, S * (T)yp);
-            if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
-            t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
-            t1 = t2; s1 = s2; idx1 = idx2;
-        }
+        if (circ)
+            lossless_sweep<T, false>(thk, slot, L, front, sl, vs, vp, es, ep);
+        else
+            lossless_sweep<T, true>(thk, slot, L, front, sl, vs, vp, es, ep);
         return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
     }
     for (int j = 0; j < L; ++j, idx += dir) {

@@ -33,11 +33,14 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
                                   const uint8_t* s_slot, const LaneSlots3& sl, int m, bool front, double kappa,
                                   bool* used_fp64)
 {
+    bool hyp = false;                       // an evanescent lossless slot at this kappa
     for (int s = 0; s < sc.n_slots; ++s) {
         double P[NPF];
         slot_params(pl.slotN[2 * s], pl.slotN[2 * s + 1], kappa, pl.k0, P);
         sl.put(s, P);
+        hyp |= !((sc.slot_complex >> s) & 1u) && P[0] < 0.0;
     }
+    const bool circ = __ballot(hyp) == 0ull;
     const double z0 = pl.ng * pl.ng - kappa * kappa;
     const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
     const double eta0s = q0, eta0p = pl.ng * pl.ng / q0;
@@ -48,9 +51,9 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
     *used_fp64 = fp64;
     if (fp64)
         return tmm_solve<double>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
-                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
+                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
     return tmm_solve<float>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
-                            mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0));
+                            mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
 }
 
 // Solve queue entries [0, total) in batches of 64 (one per lane).
