@@ -10,9 +10,9 @@
 // asked to prepare a gradient it ran this sweep itself and stored one entry
 // per hit (AdjStore); otherwise, or for work items whose entry regions
 // overflowed, k_trace_bwd regenerates the paths: a geometry-only walk finds
-// each ray's bin, rays in a bin with nonzero dL/dI are walked again with
-// their thin-film solves and a tape of their field-changing events, and the
-// sweep runs on the tape.
+// each ray's bin and queues its hits, the hits of rays in a bin with nonzero
+// dL/dI are solved, those rays are walked again with the field and a tape of
+// their field-changing events, and the sweep runs on the tape.
 //
 // Thin-film part.  Entries are drained 64 at a time, one per lane, so every
 // lane runs the same layer loop whatever the length of its ray: the adjoint
@@ -172,9 +172,13 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             TapeRef none = { nullptr, 0 };
             int nh = 0;
             double gscale = 0.0;
+            const int own = lane * sc.Kmax;      // this lane's slots of the hit queue
             if (active) {
                 ray_birth(sc, *pl, id, r);
-                walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
+                if constexpr (TAB)
+                    walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
+                else
+                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, own }, NoCoef{}, none, nullptr);
                 // the bin is fixed by geometry alone: rays that end outside the
                 // eyebox or in a bin with dL/dI = 0 carry no gradient and are
                 // not regenerated further
@@ -182,16 +186,11 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
                 active = gscale != 0.0;
                 nh = active ? r.nprma : 0;
             }
-            int hoff = 0;
             if (!tabm) {
                 int htotal;
-                hoff = wave_excl_scan(nh, &htotal);
-                if (active) {
-                    ray_birth(sc, *pl, id, r);
-                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, hoff }, NoCoef{}, none, nullptr);
-                }
+                const int hoff = wave_excl_scan(nh, &htotal);
                 __threadfence_block();
-                solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, htotal, &c_fp64, &c_lay);
+                solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, htotal, hoff, &c_fp64, &c_lay);
                 __threadfence_block();
             }
             if (active) {
@@ -199,7 +198,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
                 if constexpr (TAB)
                     walk_ray<true, true>(sc, *pl, r, o, NoHit{}, TabCoef{ tab_dl, sc.table_n, pl->ng, sc.nx, sc.nz }, tape, &nt);
                 else
-                    walk_ray<true, true>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, hoff, nullptr }, tape, &nt);
+                    walk_ray<true, true>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, own, nullptr }, tape, &nt);
                 c_rays += 1;
                 c_ev += (unsigned long long)r.nev;
                 c_hits += (unsigned long long)r.nprma;

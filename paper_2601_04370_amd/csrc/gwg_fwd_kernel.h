@@ -3,14 +3,15 @@
 // Two-pass intersection (Methods, memory-saving strategies): the path of a
 // ray (surfaces, branch decisions) does not depend on the coatings, so each
 // wave processes its rays in rounds of one ray per lane:
-//   1. a geometry-only walk counts each ray's mirror hits; a wave prefix sum
-//      gives each ray a contiguous range of the wave's hit queue;
-//   2. a second geometry-only walk writes each hit's kappa, mirror and side;
-//   3. the hits are solved in batches of 64, one per lane, so every lane of
+//   1. a geometry-only walk writes each hit's kappa, mirror and side to the
+//      ray's lane's slots of the wave's hit queue and finds the ray's fate;
+//   2. a wave prefix sum of the hit counts orders the wave's hits densely,
+//      and they are solved in batches of 64, one per lane, so every lane of
 //      the wave runs the same layer loop whatever the path lengths;
-//   4. a third walk replays the path with the polarization field, taking the
-//      coefficients from the queue, and scatters into the eyebox bins;
-//   5. with ADJ (a gradient will follow), the third walk also writes a tape
+//   3. a second walk replays the path with the polarization field, taking
+//      the coefficients from the ray's own slots, and scatters into the
+//      eyebox bins;
+//   4. with ADJ (a gradient will follow), the second walk also writes a tape
 //      of the field-changing events and every ray that reached the eyebox
 //      runs the reverse field sweep, storing one adjoint entry per mirror hit
 //      (AdjStore) for the backward.
@@ -21,9 +22,9 @@
 // depend only on its kappa, mirror and side, and within one work item the
 // rays share a handful of such keys (kappa comes from direction bits that
 // every ray with the same event history shares exactly).  Each wave then
-// keeps a table of the item's keys with their coefficients: step 3 resolves
+// keeps a table of the item's keys with their coefficients: step 2 resolves
 // every queued hit to its key, solves only keys not seen before in the item,
-// and step 4 reads the coefficients by key.  The coefficients are those of
+// and step 3 reads the coefficients by key.  The coefficients are those of
 // the per-hit solve bit for bit; an item with more than kFwdMemoKeys keys
 // per wave goes on hit by hit.
 
@@ -56,22 +57,40 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
                             mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
 }
 
-// Solve queue entries [0, total) in batches of 64 (one per lane).
+// The wave's hit queue keeps each ray's hits in its lane's own slots,
+// lane * kmax + h.  Dense hit p (the wave's hits in ray order) belongs to the
+// largest lane whose exclusive prefix sum of hit counts (off) is <= p: lanes
+// without hits share the next lane's offset and lose the search to it.
+// Called by all lanes of the wave (shuffles).
+__device__ inline int dense_slot(int p, int off, int kmax)
+{
+    int l = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int c = l + step;
+        if (__shfl(off, c, 64) <= p) l = c;
+    }
+    return l * kmax + (p - __shfl(off, l, 64));
+}
+
+// Solve the wave's `total` queued hits in batches of 64 (one per lane);
+// off: this lane's exclusive prefix sum of hit counts.
 template <int MODE>
 __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
                                   const uint8_t* s_slot, const LaneSlots3& sl, const HitQueue& hq, int total,
-                                  unsigned long long* n_fp64, unsigned long long* n_lay)
+                                  int off, unsigned long long* n_fp64, unsigned long long* n_lay)
 {
     const int lane = wave_lane();
     for (int b = 0; b < total; b += 64) {
         const int p = b + lane;
+        const int q = dense_slot(p < total ? p : total - 1, off, sc.Kmax);
         if (p < total) {
-            const double kappa = hq.kappa(p);
-            const int meta = hq.meta(p);
+            const double kappa = hq.kappa(q);
+            const int meta = hq.meta(q);
             const int m = meta & 255;
             bool u64 = false;
             const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64);
-            hq.put_coef(p, c);
+            hq.put_coef(q, c);
             *n_fp64 += u64 ? 1ull : 0ull;
             *n_lay += (unsigned long long)pl.nlay[m];
         }
@@ -133,15 +152,17 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Resolve queue entries [0, total) to key indices, appending new keys to the
-// table (*U keys so far); entry p's index goes to its first coefficient field.
-// Returns false if the table would hold more than cap keys.
-__device__ inline bool fmemo_resolve(const HitQueue& hq, int total, const FwdMemo& fm, int cap, int* U)
+// Resolve the wave's `total` queued hits to key indices, appending new keys
+// to the table (*U keys so far); a hit's index goes to its first coefficient
+// field.  Returns false if the table would hold more than cap keys.
+__device__ inline bool fmemo_resolve(const HitQueue& hq, int total, int off, int kmax, const FwdMemo& fm, int cap,
+                                     int* U)
 {
     const int lane = wave_lane();
     for (int b = 0; b < total; b += 64) {
-        const int p = b + lane;
-        const bool act = p < total;
+        const int p0 = b + lane;
+        const bool act = p0 < total;
+        const int p = dense_slot(act ? p0 : total - 1, off, kmax);
         unsigned long long kb = 0ull;
         int km = 0, idx = 0;
         if (act) {
@@ -301,27 +322,29 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             TapeRef none = { nullptr, 0 };
             int nh = 0;
             bool to_eyebox = false;                        // fixed by geometry alone
+            // geometry walk: the hits go to this lane's slots of the queue
+            // (the angle table needs no queue: the walk only finds the rays
+            // bound for the eyebox, whose fields the adjoint tapes)
+            const int own = lane * sc.Kmax;
             if (active && (!tabm || ADJ)) {
                 ray_birth(sc, *pl, id, r);
-                walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
+                if (tabm)
+                    walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
+                else
+                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, own }, NoCoef{}, none, nullptr);
                 nh = r.nprma;
                 to_eyebox = o.cat == CAT_EYEBOX;
             }
-            int off = 0;
             if (!tabm) {
                 int total;
-                off = wave_excl_scan(nh, &total);
-                if (active) {
-                    ray_birth(sc, *pl, id, r);
-                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, off }, NoCoef{}, none, nullptr);
-                }
+                const int off = wave_excl_scan(nh, &total);
                 __threadfence_block();
                 const int u0 = n_keys;
-                if (memo && !fmemo_resolve(hq, total, fm, sc.memo, &n_keys)) memo = false;
+                if (memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
                 if (memo)
                     fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
                 else
-                    solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, &n_fp64, &n_lay);
+                    solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, off, &n_fp64, &n_lay);
                 __threadfence_block();
             }
             int nt = 0;
@@ -331,7 +354,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                 if constexpr (TAB)
                     walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, TabCoef{ tab_dl, sc.table_n, pl->ng, sc.nx, sc.nz }, rt, &nt);
                 else
-                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, off, memo ? fm.coef : nullptr }, rt, &nt);
+                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, own, memo ? fm.coef : nullptr }, rt, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
                 atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);
