@@ -30,8 +30,10 @@ PEAK_FP64 = 78.6
 # FMA as two and one sine/cosine pair as zero (reported separately):
 #   forward solve 29 = phase 1 + four X/Y products 4 + two real-coefficient
 #     complex 2x2 matrix-vector products 2 x 12;
-#   adjoint 125 = exit-to-incident sweep 29 + segment recomputation 29 +
-#     contraction u^T D w for s and p 39 + covector step for s and p 28.
+#   adjoint 125 = exit-to-incident sweep 29 + inverse step back down 29 +
+#     contraction u^T D w for s and p 39 + covector step for s and p 28;
+#     96 where the forward solve stored the sweep's checkpoints (its 29 are
+#     then part of the forward's work).
 # Adjoint layer steps are counted per hit that enters the thin-film adjoint;
 # regenerated hits (items whose entry regions overflowed) add 29 each.
 FLOP_FWD_LAYER = 29.0
@@ -275,7 +277,7 @@ def main():
         extra["table"] = tab
 
     # counters of the timed steps (recomputed untimed: same seeds, same paths)
-    inter = hits = lay_f = lay_b = lay_a = fp64h = 0
+    inter = hits = lay_f = lay_b = lay_a = lay_s = fp64h = 0
     for i in range(a.steps):
         _, _, irr, _, st = ctx.trace_forward(scene, thk, w.seed, a.warmup + i, prec, stats=True, grad=not fo,
                                              memo=a.memo, table=a.table)
@@ -288,6 +290,7 @@ def main():
             _, bst = ctx.trace_backward(dLdI, scene, stats=True)
             lay_b += bst["layer_steps"]
             lay_a += bst["adjoint_layer_steps"]
+            lay_s += bst["adjoint_stored_layer_steps"]
     K = a.steps
     if a.graph:
         wall = extra["graph_ms_per_step"] * 1e-3 * K
@@ -313,7 +316,7 @@ def main():
         extra["batched_speedup_vs_per_design"] = pd_wall / wall
 
     f_fwd = FLOP_FWD_LAYER * lay_f / K
-    f_bwd = (FLOP_FWD_LAYER * lay_b + FLOP_ADJ_LAYER * lay_a) / K
+    f_bwd = (FLOP_FWD_LAYER * lay_b + FLOP_ADJ_LAYER * lay_a - FLOP_FWD_LAYER * lay_s) / K
     t_fwd = float(np.mean(kfwd_ms)) * 1e-3
     t_bwd = float(np.mean(kbwd_ms)) * 1e-3
     # the adjoint launch is the entry kernel (plus the regenerating kernel,
@@ -328,6 +331,7 @@ def main():
             "kernel": kname, "kernel_ms": tk * 1e3}
     extra.update({"interactions_per_step": inter / K, "mirror_hits_per_step": hits / K,
                   "fwd_layer_steps_per_step": lay_f / K, "adj_layer_steps_per_step": lay_a / K,
+                  "adj_stored_sweep_layer_steps_per_step": lay_s / K,
                   "mirror_hits_per_s": hits / wall, "fp64_hit_fraction": fp64h / max(hits, 1),
                   "fwd_ms": float(np.mean(fwd_ms)), "loss_ms": float(np.mean(loss_ms)),
                   "bwd_ms": float(np.mean(bwd_ms)), "fwd_kernel_ms": t_fwd * 1e3,

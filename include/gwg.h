@@ -187,12 +187,14 @@ enum { GWG_CAT_EYEBOX = 0, GWG_CAT_MISS = 1, GWG_CAT_LEAK = 2, GWG_CAT_END = 3,
  * and final power per category.  Backward: the same for the regenerated
  * paths (only rays that end in a bin with nonzero dL/dI are regenerated past
  * their geometry), plus rays / hits / layer steps that went through the
- * adjoint. */
+ * adjoint, and of those layer steps the ones whose exit-to-incident sweep
+ * the forward had stored (ck_entries_per_ray). */
 typedef struct {
     int64_t rays, interactions, prma_hits, layer_steps, fp64_hits, saturated;
     int64_t adjoint_rays, adjoint_hits, adjoint_layer_steps;
     int64_t n_cat[GWG_NCAT];
     double power[GWG_NCAT];     /* summed final |E|^2 per category (fixed-point, 2^-24) */
+    int64_t adjoint_stored_layer_steps;
 } gwg_stats;
 
 /* Forward Monte Carlo trace of the whole batch (Methods; Eq. 5, Eq. 6).
@@ -283,7 +285,12 @@ int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t 
  * capacity of each wave's key table in the memoized forward (GWG_FWD_MEMO):
  * a wave meeting more keys in one work item solves the rest of it per hit.
  * table_nodes (0 = 8192, else 4..2^20) is the number of incidence angles of
- * the angle table (GWG_FWD_TABLE). */
+ * the angle table (GWG_FWD_TABLE).  ck_entries_per_ray (0 = 4, -1 = none,
+ * else 1..64): with GWG_FWD_GRAD at FP64 on lossless stacks, the forward
+ * solve keeps the adjoint's sweep checkpoints (8 doubles every 16 layers)
+ * for up to this many entries per ray of each entry region, within a memory
+ * budget (the smaller of 48 GiB and half the free memory), so the backward
+ * skips that sweep for them; the gradient is the same bit for bit. */
 typedef struct {
     int32_t block_threads;
     int64_t rays_per_block;
@@ -292,6 +299,7 @@ typedef struct {
     int32_t adj_entries_per_ray;
     int32_t memo_keys;
     int32_t table_nodes;
+    int32_t ck_entries_per_ray;
 } gwg_tuning;
 
 int gwg_set_tuning(gwg_ctx* ctx, const gwg_tuning* tuning);

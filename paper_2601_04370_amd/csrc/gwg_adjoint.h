@@ -248,12 +248,15 @@ template <bool HC = true>
 __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, const uint8_t* __restrict__ slot,
                                             int L, bool front, const LaneSlots3& sl, double k0,
                                             double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
-                                            double* grad_row, double* __restrict__ chk, int64_t cstride)
+                                            double* grad_row, double* __restrict__ chk, int64_t cstride,
+                                            bool stored = false)
 {
     // 1) exit -> incident sweep v_j = M_j v_{j+1}, checkpoints v_K, v_2K, ...
     //    (K = kSegL): first the L % K layers above the last multiple of K,
     //    then whole groups of K layers, each ending in a checkpoint (group 0
-    //    in none: v_0 stays in registers)
+    //    in none: v_0 stays in registers).  stored: the forward solve ran
+    //    this sweep and left v_0 in block 0 and the checkpoints in blocks
+    //    1.. of chk, with the same arithmetic.
     if (L <= 0) return;
     constexpr int K = kSegL;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
@@ -271,13 +274,18 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
         c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
         c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
     };
-    const int ng = L / K;
-    for (int jj = L - 1; jj >= ng * K; --jj) layer_fwd(jj);
-    if (ng > 0 && ng * K < L) checkpoint(ng);        // v_{ng K}, after the top layers
-    for (int g = ng - 1; g >= 0; --g) {
+    if (stored) {
+        vs = V2d{ chk[0], chk[cstride], chk[2 * cstride], chk[3 * cstride] };
+        vp = V2d{ chk[4 * cstride], chk[5 * cstride], chk[6 * cstride], chk[7 * cstride] };
+    } else {
+        const int ng = L / K;
+        for (int jj = L - 1; jj >= ng * K; --jj) layer_fwd(jj);
+        if (ng > 0 && ng * K < L) checkpoint(ng);    // v_{ng K}, after the top layers
+        for (int g = ng - 1; g >= 0; --g) {
 #pragma unroll 2
-        for (int i = K - 1; i >= 0; --i) layer_fwd(g * K + i);
-        if (g > 0) checkpoint(g);
+            for (int i = K - 1; i >= 0; --i) layer_fwd(g * K + i);
+            if (g > 0) checkpoint(g);
+        }
     }
     // 2) cotangent rows of the taken coefficients
     cd u1s, u2s, u1p, u2p;

@@ -94,7 +94,7 @@ struct gwg_ctx {
     bool have_forward = false;
     SceneDev fwd{};
     // adjoint entries recorded by the last forward (GWG_FWD_GRAD)
-    DevBuf adj_ent, adj_cnt, adj_ovf, fwd_tape;
+    DevBuf adj_ent, adj_cnt, adj_ovf, fwd_tape, adj_ck;
     bool adj_valid = false;
     bool memo = false;           // thin-film adjoints per distinct hit key (GWG_FWD_MEMO)
     AdjStore adj{};
@@ -461,6 +461,7 @@ int read_stats(gwg_ctx* c, hipStream_t s, gwg_stats* stats)
     stats->adjoint_rays = (int64_t)w[ST_ADJ_RAYS];
     stats->adjoint_hits = (int64_t)w[ST_ADJ_HITS];
     stats->adjoint_layer_steps = (int64_t)w[ST_ADJ_LAYERS];
+    stats->adjoint_stored_layer_steps = (int64_t)w[ST_ADJ_STORED];
     for (int k = 0; k < GWG_NCAT; ++k) {
         stats->n_cat[k] = (int64_t)w[ST_CAT + k];
         stats->power[k] = (double)w[ST_POW + k] / 16777216.0;
@@ -501,7 +502,8 @@ int gwg_destroy(gwg_ctx* c)
         (void)hipDeviceSynchronize();
         for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape,
-                           &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad })
+                           &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad,
+                           &c->adj_ck })
             b->release();
         for (KernelTimer& t : c->timer) t.destroy();
     }
@@ -520,6 +522,8 @@ int gwg_set_tuning(gwg_ctx* c, const gwg_tuning* t)
     if (t->rays_per_block < 0 || t->bwd_rays_per_block < 0) return fail(c, GWG_E_INVAL, "negative tile");
     if (t->adj_entries_per_ray < 0 || t->adj_entries_per_ray > 64) return fail(c, GWG_E_INVAL, "adj_entries_per_ray out of range");
     if (t->memo_keys < 0 || t->memo_keys > kFwdMemoKeys) return fail(c, GWG_E_INVAL, "memo_keys out of range");
+    if (t->ck_entries_per_ray < -1 || t->ck_entries_per_ray > 64)
+        return fail(c, GWG_E_INVAL, "ck_entries_per_ray must be -1, 0 or in [1, 64]");
     if (t->table_nodes != 0 && (t->table_nodes < 4 || t->table_nodes > kTableNodesMax))
         return fail(c, GWG_E_INVAL, "table_nodes must be 0 or in [4, %d]", kTableNodesMax);
     c->tune = *t;
@@ -729,8 +733,37 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
             rc = ensure_buf(c, c->adj_ovf, ovf_b, cap, "alloc overflow flags");
             if (rc) return rc;
             HIP_CHECK(c, launch_fill_u32((uint32_t*)c->adj_ovf.p, sc.n_items, 0u, s), "zero overflow flags");
-            c->adj = AdjStore{ (double*)c->adj_ent.p, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, cap_w, total, waves };
+            c->adj = AdjStore{ (double*)c->adj_ent.p, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, cap_w, total, waves,
+                               nullptr, 0, 0 };
             adj = true;
+            // The FP64 solve can keep the adjoint's sweep checkpoints of the
+            // first ck_cap entries of every region (kCkEntriesPerRay per ray,
+            // fewer if memory is short); the adjoint then skips that sweep.
+            const int64_t ck_per = c->tune.ck_entries_per_ray == 0 ? kCkEntriesPerRay : c->tune.ck_entries_per_ray;
+            if (precision == GWG_FP64 && !(flags & GWG_FWD_MEMO) && sc.slot_complex == 0u && ck_per > 0) {
+                const int64_t blocks = sc.Lmax / kSegL + 1;
+                const int64_t rays_w = (sc.rays_per_tile + wg - 1) / wg * 64;
+                for (int64_t per = ck_per; per >= 1; --per) {
+                    const int64_t ck_cap = std::min<int64_t>(cap_w, rays_w * per);
+                    const int64_t ck_total = sc.n_items * waves * ck_cap;
+                    const size_t ck_b = sizeof(double) * 8 * (size_t)blocks * (size_t)ck_total;
+                    bool ok;
+                    if (cap) {
+                        ok = c->adj_ck.p && c->adj_ck.bytes >= ck_b;
+                    } else {
+                        size_t free_b = 0, total_b = 0;
+                        (void)hipMemGetInfo(&free_b, &total_b);
+                        ok = (double)ck_b <= std::min<double>(kCkBudgetBytes, 0.5 * (double)free_b + (double)c->adj_ck.bytes);
+                    }
+                    if (!ok) continue;
+                    rc = ensure_buf(c, c->adj_ck, ck_b, cap, "alloc sweep checkpoints");
+                    if (rc) return rc;
+                    c->adj.ck = (double*)c->adj_ck.p;
+                    c->adj.ck_cap = ck_cap;
+                    c->adj.ck_total = ck_total;
+                    break;
+                }
+            }
         } else if (table) {
             // the table backward needs the sweep's cotangent bound even when no
             // entry can be kept: regions of zero entries, every item regenerated
@@ -738,7 +771,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
             if (rc) return rc;
             rc = ensure_buf(c, c->adj_ovf, ovf_b, cap, "alloc overflow flags");
             if (rc) return rc;
-            c->adj = AdjStore{ nullptr, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, 0, 0, waves };
+            c->adj = AdjStore{ nullptr, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, 0, 0, waves, nullptr, 0, 0 };
         }
         adj_sweep = adj || table;
     }
@@ -957,7 +990,7 @@ int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const g
                 }
             std::fclose(f);
             if (found) {
-                gwg_tuning t{ wg, rpb, bwg, brpb, adj, c->tune.memo_keys, c->tune.table_nodes };
+                gwg_tuning t{ wg, rpb, bwg, brpb, adj, c->tune.memo_keys, c->tune.table_nodes, c->tune.ck_entries_per_ray };
                 if (gwg_set_tuning(c, &t) == GWG_OK) {
                     c->tuned[key] = t;
                     *out = t;

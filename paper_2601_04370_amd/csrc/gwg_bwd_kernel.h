@@ -44,10 +44,12 @@ __device__ inline void q_put(const Queue& q, int pos, double kappa, cd Gs, cd Gp
 // Adjoint thin-film solve of one mirror hit (one per lane): kappa, the
 // scaled cotangents and meta = mirror | front << 8 | reflected << 9.
 // LOSSLESS: the scene has no absorbing slot (compiled without the general path).
+// stored: chk is the entry's checkpoint block written by the forward solve
+// (lossless stacks; the sweep is not run again).
 template <bool LOSSLESS = false>
 __device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const double* s_thk,
                                    const uint8_t* s_slot, const LaneSlots3& sl, double* gw, double kappa, cd Gs,
-                                   cd Gp, int meta, double* chk, int64_t cstride)
+                                   cd Gp, int meta, double* chk, int64_t cstride, bool stored = false)
 {
     const int m = meta & 255;
     const bool front = (meta >> 8) & 1, refl = (meta >> 9) & 1;
@@ -65,10 +67,10 @@ __device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const
         // the hyperbolic case (same results)
         if (__ballot(hyp) == 0ull)
             tmm_adjoint_lossless<false>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
-                                        pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride);
+                                        pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored);
         else
             tmm_adjoint_lossless<true>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
-                                       pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride);
+                                       pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored);
     }
     else if (!LOSSLESS)
         tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, sc.slot_complex,
@@ -285,7 +287,7 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
     const int64_t nthreads = (int64_t)gridDim.x * WG;
     double* chk = scratch + (int64_t)blockIdx.x * WG + tid;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
-    unsigned long long c_ahits = 0, c_alay = 0;
+    unsigned long long c_ahits = 0, c_alay = 0, c_astored = 0;
 
     for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
         if (st.ovf[item] != 0) continue;
@@ -314,9 +316,14 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
                     const cd Gs = cscale(mk(st.ent[1 * st.total + e], st.ent[2 * st.total + e]), gscale);
                     const cd Gp = cscale(mk(st.ent[3 * st.total + e], st.ent[4 * st.total + e]), gscale);
                     const int mm = (int)(meta & 1023);
-                    adjoint_hit<LOSSLESS>(sc, *pl, s_thk, s_slot, sl, gw, kappa, Gs, Gp, mm, chk, nthreads);
+                    // the forward stored this entry's sweep (lossless FP64 stacks)
+                    const bool stored = LOSSLESS && st.ck && k < st.ck_cap;
+                    double* c = stored ? st.ck + (item * st.waves + rr) * st.ck_cap + k : chk;
+                    adjoint_hit<LOSSLESS>(sc, *pl, s_thk, s_slot, sl, gw, kappa, Gs, Gp, mm, c,
+                                          stored ? st.ck_total : nthreads, stored);
                     c_ahits += 1;
                     c_alay += (unsigned long long)pl->nlay[mm & 255];
+                    if (stored) c_astored += (unsigned long long)pl->nlay[mm & 255];
                 }
             }
         }
@@ -330,6 +337,7 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
     }
     if (c_ahits) atomicAdd(&s_st[ST_ADJ_HITS], c_ahits);
     if (c_alay) atomicAdd(&s_st[ST_ADJ_LAYERS], c_alay);
+    if (c_astored) atomicAdd(&s_st[ST_ADJ_STORED], c_astored);
     __syncthreads();
     for (int k = tid; k < ST_WORDS; k += WG)
         if (s_st[k]) atomicAdd(&stats[k], s_st[k]);

@@ -489,8 +489,16 @@ template <typename T, bool HC, class SL>
 __device__ __attribute__((always_inline)) inline void lossless_sweep(const double* __restrict__ thk,
                                                                      const uint8_t* __restrict__ slot, int L,
                                                                      bool front, const SL& sl, V2<T>& vs, V2<T>& vp,
-                                                                     int& es, int& ep)
+                                                                     int& es, int& ep, double* ck, int64_t cks)
 {
+    // ck (T = double only): the adjoint's sweep checkpoints v_{g kSegL}
+    // (incidence-order layer g kSegL and below) go to block g, field f at
+    // ck[(g * 8 + f) * cks]; v_0 goes to block 0 after the loop.
+    auto store = [&](int g) {
+        double* c = ck + (int64_t)g * 8 * cks;
+        c[0] = (double)vs.br; c[cks] = (double)vs.bi; c[2 * cks] = (double)vs.cr; c[3 * cks] = (double)vs.ci;
+        c[4 * cks] = (double)vp.br; c[5 * cks] = (double)vp.bi; c[6 * cks] = (double)vp.cr; c[7 * cks] = (double)vp.ci;
+    };
     const int dir = front ? -1 : 1;
     const int last = front ? 0 : L - 1;
     const int idx = front ? L - 1 : 0;
@@ -512,9 +520,14 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(const doubl
         step_real(vs, C, S * (T)xs, S * (T)ys);
         step_real(vp, C, S * (T)xp, S * (T)yp);
         if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
+        if (sizeof(T) == 8 && ck) {
+            const int jj = L - 1 - j;                  // incidence-order index of this layer
+            if (jj > 0 && (jj % kSegL) == 0) store(jj / kSegL);
+        }
         t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
         t1 = t2; s1 = s2; idx1 = idx2;
     }
+    if (sizeof(T) == 8 && ck) store(0);
 }
 
 // Forward solve of one hit.  thk/slot: this mirror's layers in stack order
@@ -523,11 +536,13 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(const doubl
 // The stack thicknesses and slot parameters are read in double precision
 // and rounded to the chain precision T once per layer.  circ: no lane of the
 // calling wave has an evanescent lossless slot (the sweep then skips the
-// hyperbolic case; the results are the same).
+// hyperbolic case; the results are the same).  ck (lossless FP64 stacks):
+// where the sweep's checkpoints for the adjoint go, or null.
 template <typename T, class SL>
 __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t* __restrict__ slot, int L,
                                   bool front, const SL& sl, uint32_t cplx_mask, double k0d, double eta0s,
-                                  double eta0p, cd etaEs, cd etaEp, cd tp_factor, bool circ = false)
+                                  double eta0p, cd etaEs, cd etaEp, cd tp_factor, bool circ = false,
+                                  double* ck = nullptr, int64_t cks = 0)
 {
     const T k0 = (T)k0d;
     V2<T> vs = { (T)1, (T)0, (T)etaEs.re, (T)etaEs.im };
@@ -538,9 +553,9 @@ __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* _
     int idx = front ? L - 1 : 0;
     if (cplx_mask == 0u) {
         if (circ)
-            lossless_sweep<T, false>(thk, slot, L, front, sl, vs, vp, es, ep);
+            lossless_sweep<T, false>(thk, slot, L, front, sl, vs, vp, es, ep, ck, cks);
         else
-            lossless_sweep<T, true>(thk, slot, L, front, sl, vs, vp, es, ep);
+            lossless_sweep<T, true>(thk, slot, L, front, sl, vs, vp, es, ep, ck, cks);
         return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
     }
     for (int j = 0; j < L; ++j, idx += dir) {

@@ -32,7 +32,7 @@
 template <int MODE>
 __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
                                   const uint8_t* s_slot, const LaneSlots3& sl, int m, bool front, double kappa,
-                                  bool* used_fp64)
+                                  bool* used_fp64, double* ck = nullptr, int64_t cks = 0)
 {
     bool hyp = false;                       // an evanescent lossless slot at this kappa
     for (int s = 0; s < sc.n_slots; ++s) {
@@ -52,7 +52,8 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
     *used_fp64 = fp64;
     if (fp64)
         return tmm_solve<double>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
-                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
+                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ, MODE == GWG_FP64 ? ck : nullptr,
+                                 cks);
     return tmm_solve<float>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                             mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
 }
@@ -75,10 +76,13 @@ __device__ inline int dense_slot(int p, int off, int kmax)
 
 // Solve the wave's `total` queued hits in batches of 64 (one per lane);
 // off: this lane's exclusive prefix sum of hit counts.
+// ck (non-null): checkpoint store of the adjoint entries; a hit whose
+// queue field 10 holds a slot c >= 0 stores its sweep checkpoints there.
 template <int MODE>
 __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
                                   const uint8_t* s_slot, const LaneSlots3& sl, const HitQueue& hq, int total,
-                                  int off, unsigned long long* n_fp64, unsigned long long* n_lay)
+                                  int off, unsigned long long* n_fp64, unsigned long long* n_lay,
+                                  double* ck = nullptr, int64_t cks = 0)
 {
     const int lane = wave_lane();
     for (int b = 0; b < total; b += 64) {
@@ -89,7 +93,12 @@ __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const 
             const int meta = hq.meta(q);
             const int m = meta & 255;
             bool u64 = false;
-            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64);
+            double* ckp = nullptr;
+            if (ck) {
+                const double c = hq.base[10 * (int64_t)hq.cap + q];
+                if (c >= 0.0) ckp = ck + (int64_t)c;
+            }
+            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64, ckp, cks);
             hq.put_coef(q, c);
             *n_fp64 += u64 ? 1ull : 0ull;
             *n_lay += (unsigned long long)pl.nlay[m];
@@ -338,13 +347,28 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             if (!tabm) {
                 int total;
                 const int off = wave_excl_scan(nh, &total);
+                // FP64 with a checkpoint store: the hits of rays bound for the
+                // eyebox learn the slots of their future adjoint entries (the
+                // sweep emits a ray's hits last to first)
+                const bool cks = ADJ && MODE == GWG_FP64 && st.ck != nullptr && !memo;
+                if (cks) {
+                    int etot;
+                    const int eoff = wave_excl_scan(to_eyebox ? nh : 0, &etot);
+                    for (int h = 0; h < nh; ++h) {
+                        const int64_t k = n_ent + eoff + (nh - 1 - h);
+                        double c = -1.0;
+                        if (to_eyebox && k < st.ck_cap) c = (double)((item * st.waves + wave) * st.ck_cap + k);
+                        hq.base[10 * (int64_t)cap + own + h] = c;
+                    }
+                }
                 __threadfence_block();
                 const int u0 = n_keys;
                 if (memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
                 if (memo)
                     fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
                 else
-                    solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, off, &n_fp64, &n_lay);
+                    solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, off, &n_fp64, &n_lay,
+                                     cks ? st.ck : nullptr, st.ck_total);
                 __threadfence_block();
             }
             int nt = 0;

@@ -41,7 +41,8 @@ enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4
                 ST_LAYERS = 5, ST_ADJ_RAYS = 6, ST_ADJ_HITS = 7, ST_ADJ_LAYERS = 8,
                 ST_CAT = 9,           // 8 words of counts
                 ST_POW = 17,          // 8 words of power (fixed point 2^-24)
-                ST_WORDS = 25 };
+                ST_ADJ_STORED = 25,   // adjoint layer steps whose sweep the forward stored
+                ST_WORDS = 26 };
 
 // Adjoint entries recorded by the forward trace for the backward: per
 // (work item, forward wave) a region of cap_w entries, field f of entry e at
@@ -53,6 +54,8 @@ enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4
 constexpr int kEntFields = 6;
 constexpr int kFwdMemoKeys = 128;      // largest key table per wave of the memoized forward
 constexpr int kTableNodesDefault = 8192;
+constexpr int kCkEntriesPerRay = 4;        // sweep checkpoints kept per ray (entry regions)
+constexpr double kCkBudgetBytes = 48.0 * (1ull << 30);
 constexpr int kTableNodesMax = 1 << 20;
 struct AdjStore {
     double* ent;
@@ -61,6 +64,13 @@ struct AdjStore {
     int64_t cap_w;
     int64_t total;
     int32_t waves;
+    // Sweep checkpoints of the first ck_cap entries of every region, stored
+    // by the FP64 forward solve (null: the adjoint recomputes them).  Block g
+    // of entry slot c (c = region * ck_cap + k): field f at
+    // ck[(g * 8 + f) * ck_total + c]; g = 0 holds v_0, g >= 1 v_{g kSegL}.
+    double* ck;
+    int64_t ck_cap;
+    int64_t ck_total;
 };
 
 struct SceneDev {

@@ -257,9 +257,10 @@ __device__ inline int wave_excl_scan(int x, int* total)
 }
 
 // ------------------------------------------------------------ hit queue
-// Mirror hits of one wave's current round of rays, in ray order: entry p
-// holds the hit's kappa and meta (mirror | front << 8) and, after the solve,
-// its four coefficients.  Field f of entry p at base[f * cap + p].
+// Mirror hits of one wave's current round of rays: entry p holds the hit's
+// kappa and meta (mirror | front << 8), after the solve its four
+// coefficients, and (field 10) the checkpoint slot of its adjoint entry or
+// -1.  Field f of entry p at base[f * cap + p].
 struct HitQueue {
     double* base;
     int cap;
@@ -285,7 +286,7 @@ struct HitQueue {
         return c;
     }
 };
-constexpr int kHitFields = 10;
+constexpr int kHitFields = 11;
 
 // ------------------------------------------------------------ tape
 // Field-changing events of one ray for the adjoint (this lane's doubles, stride ts).

@@ -81,7 +81,7 @@ class Stats(C.Structure):
                 ("layer_steps", C.c_int64), ("fp64_hits", C.c_int64), ("saturated", C.c_int64),
                 ("adjoint_rays", C.c_int64), ("adjoint_hits", C.c_int64),
                 ("adjoint_layer_steps", C.c_int64), ("n_cat", C.c_int64 * 8),
-                ("power", C.c_double * 8)]
+                ("power", C.c_double * 8), ("adjoint_stored_layer_steps", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("n_cat", "power")}
@@ -93,7 +93,8 @@ class Stats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("rays_per_block", C.c_int64),
                 ("bwd_block_threads", C.c_int32), ("bwd_rays_per_block", C.c_int64),
-                ("adj_entries_per_ray", C.c_int32), ("memo_keys", C.c_int32), ("table_nodes", C.c_int32)]
+                ("adj_entries_per_ray", C.c_int32), ("memo_keys", C.c_int32), ("table_nodes", C.c_int32),
+                ("ck_entries_per_ray", C.c_int32)]
 
 
 #: every function declared in include/gwg.h
@@ -273,9 +274,9 @@ class Context:
             raise GwgError(rc, self.lib.gwg_last_error(self.h).decode())
 
     def set_tuning(self, block_threads=0, rays_per_block=0, bwd_block_threads=0, bwd_rays_per_block=0,
-                   adj_entries_per_ray=0, memo_keys=0, table_nodes=0):
+                   adj_entries_per_ray=0, memo_keys=0, table_nodes=0, ck_entries_per_ray=0):
         t = Tuning(block_threads, rays_per_block, bwd_block_threads, bwd_rays_per_block, adj_entries_per_ray,
-                   memo_keys, table_nodes)
+                   memo_keys, table_nodes, ck_entries_per_ray)
         self._check(self.lib.gwg_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self) -> dict:

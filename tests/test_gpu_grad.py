@@ -162,3 +162,29 @@ def test_backward_requires_forward(orc):
         ctx.trace_backward(_t.zeros(scene.shape, dtype=_t.float64), scene)
     assert e.value.code == 4
     ctx.close()
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("diff_1200", dict(rays_per_point=160, fov_n=3)),
+    ("plain_fp64", dict(rays_per_point=3000)),
+    ("batched", dict(n_designs=2, rays_per_point=64, fov_n=3, lambdas_nm=(420.0, 680.0))),
+])
+def test_stored_sweep_checkpoints_give_the_same_gradient(gctx, name, kw):
+    """The FP64 forward keeps the adjoint's sweep checkpoints for (some or
+    all) entries; the adjoint then skips that sweep.  Same arithmetic, so
+    the gradient is identical bit for bit to the recomputing adjoint."""
+    w = inputs.small_variant(name, **kw)
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    rng = np.random.default_rng(11)
+    dLdI = torch.tensor(rng.standard_normal(scene.shape))
+    out = []
+    for per in (-1, 0, 1):
+        gctx.set_tuning(ck_entries_per_ray=per)
+        try:
+            gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=True)
+            out.append(gctx.trace_backward(dLdI, scene).cpu().numpy())
+        finally:
+            gctx.set_tuning()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
