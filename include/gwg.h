@@ -247,6 +247,25 @@ int gwg_trace_forward(gwg_ctx* ctx, const gwg_slab* slab, const gwg_prma* prma,
                       gwg_ray_record* records, int64_t record_stride,
                       gwg_stats* stats, void* stream);
 
+/* Learned reflection probabilities (Methods): gradient, with respect to
+ * every mirror's reflection probability omega_m, of
+ *     J = sum over (design, wavelength, FoV) points and bins of W * I
+ * in the scalar-reflectance model (each coating idealised as reflecting the
+ * fraction omega_m of the incident energy, geometry only, no polarization),
+ * whose irradiance is I = counts / rays_per_point.  Score-function
+ * estimator on the paths of the last gwg_trace_forward (same seed, step and
+ * decisions; its thk must still be valid):
+ *     dJ/domega_m = sum_points 1/N sum_rays (W_bin - beta) S_m,
+ * S_m = sum over the ray's hits on mirror m of 1/omega_m (reflected) or
+ * -1/(1 - omega_m) (transmitted), beta = the point's J (an unbiased
+ * baseline since E[S_m] = 0), omega_m = the sampling probability
+ * floor(omega 2^32) / 2^32; a ray outside the eyebox has W = 0.
+ * d_W: device f64 [D][n_lambda_sel][F][bins_y][bins_x] (1 for throughput, or
+ * dL/dI of any loss of I); d_counts: device u32 counts of that forward;
+ * d_grad: device f64 [M].  Deterministic (fixed-order sums). */
+int gwg_omega_gradient(gwg_ctx* ctx, const double* d_W, const uint32_t* d_counts, double* d_grad,
+                       void* stream);
+
 /* *kept = 1 if the last gwg_trace_forward (or the one recorded by a stream
  * capture) stored adjoint entries, so that gwg_trace_backward runs the
  * thin-film adjoints only; 0 if the backward will regenerate the paths. */

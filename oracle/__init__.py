@@ -267,6 +267,69 @@ class OracleScene:
         return b, w.value, p.value, nu.value
 
 
+# ------------------------------------------- learned reflection probabilities
+# (Methods, learned reflection probabilities) Each coating is idealised as a
+# scalar reflectance equal to the mirror's reflection probability omega, so a
+# sampled path carries weight one and a ray adds 1 / N to the bin it reaches.
+_EV_MIRROR = 5
+
+
+def p_eff(omega) -> np.ndarray:
+    """Sampling probability floor(omega 2^32) / 2^32 of each mirror."""
+    t = np.floor(np.asarray(omega, dtype=np.float64) * 4294967296.0)
+    return np.clip(t, 0.0, 4294967295.0) / 4294967296.0
+
+
+def omega_score_gradient(osc: "OracleScene", W: np.ndarray, counts: np.ndarray, ray_ids=None):
+    """Score-function estimate of dJ/domega for J = sum_points sum_b W I,
+    I = counts / N: per ray, (W_bin - beta) S_m with S_m = sum over its hits
+    on mirror m of 1/omega_m (reflected) or -1/(1 - omega_m) (transmitted),
+    beta = the point's J; summed per point with 1/N.  Returns (gradient,
+    per-ray contributions [n, M]).  ray_ids: all rays by default."""
+    s = osc.s
+    D, nl, F, by, bx = osc.shape
+    B, N, M = by * bx, s.rays_per_point, s.n_mirrors
+    p = p_eff(osc.arrays["omega"])
+    Wf = np.asarray(W, dtype=np.float64).reshape(-1, B)
+    cf = np.asarray(counts, dtype=np.float64).reshape(-1, B)
+    ids = np.arange(D * nl * F * N) if ray_ids is None else np.asarray(ray_ids, dtype=np.int64)
+    recs = osc.trace_rays(ids)
+    contrib = np.zeros((len(ids), M))
+    for k, (i, r) in enumerate(zip(ids, recs)):
+        pt = int(i) // N
+        beta = float(np.dot(Wf[pt], cf[pt])) / N
+        S = np.zeros(M)
+        for e in osc.events(int(i)):
+            if int(e[0]) == _EV_MIRROR:
+                m = int(e[1])
+                S[m] += 1.0 / p[m] if e[9] != 0.0 else -1.0 / (1.0 - p[m])
+        f = (Wf[pt][r.bin] if r.category == ORC_EYEBOX else 0.0) - beta
+        contrib[k] = f * S / N
+    return contrib.sum(axis=0), contrib
+
+
+def scalar_expectation(osc: "OracleScene", W: np.ndarray, ray_ids) -> float:
+    """Exact expectation over the reflect/transmit decisions of
+    sum_rays W_bin / N for fixed births (scalar reflectance): every decision
+    sequence of every ray is traced with forced decisions and weighted by its
+    probability.  A sequence is enumerated from its first unset decision on."""
+    s = osc.s
+    D, nl, F, by, bx = osc.shape
+    B, N = by * bx, s.rays_per_point
+    Wf = np.asarray(W, dtype=np.float64).reshape(-1, B)
+    total = 0.0
+    for i in np.asarray(ray_ids, dtype=np.int64):
+        pt = int(i) // N
+        stack = [(0, 0)]
+        while stack:
+            bits, k = stack.pop()
+            b, _, prob, used = osc.forced(int(i), bits, 64)
+            total += prob * (Wf[pt][b] if b >= 0 else 0.0)
+            for j in range(k, min(used, 64)):
+                stack.append((bits | (1 << j), j + 1))
+    return total / N
+
+
 def loss(irr: np.ndarray, kind: int = 0, w_f: float = 1.0, w_e: float = 1.0):
     """Loss and dL/dI for irradiance [D][n_l][F][By][Bx]."""
     I = np.ascontiguousarray(irr, dtype=np.float64)

@@ -938,6 +938,28 @@ int gwg_loss(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
     return GWG_OK;
 }
 
+int gwg_omega_gradient(gwg_ctx* c, const double* d_W, const uint32_t* d_counts, double* d_grad, void* stream)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    if (!c->have_forward) return fail(c, GWG_E_STATE, "gwg_omega_gradient called before gwg_trace_forward");
+    if (!d_W || !d_counts || !d_grad) return fail(c, GWG_E_INVAL, "NULL pointer");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool cap = stream_capturing(s);
+    const SceneDev sc = c->fwd;                    // the forward's items, seeds and decisions
+    const int wg = 256;
+    const size_t smem = omega_smem_bytes(sc, wg);
+    if (smem > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
+    const int64_t n_cu = std::max(c->n_cu, 1);
+    const int64_t grid = std::min<int64_t>(sc.n_items, n_cu * occupancy(c, KIND_OMEGA, sc.precision, wg, smem));
+    int rc = ensure_buf(c, c->partial, sizeof(double) * (size_t)sc.n_items * sc.M, cap, "alloc partial gradients");
+    if (rc) return rc;
+    HIP_CHECK(c, launch_omega_grad(sc, (int)grid, wg, d_W, d_counts, (double*)c->partial.p, d_grad, s),
+              "reflection-probability gradient kernel");
+    return GWG_OK;
+}
+
 int gwg_forward_kept_entries(const gwg_ctx* c, int32_t* kept)
 {
     if (!c || !kept) return GWG_E_INVAL;

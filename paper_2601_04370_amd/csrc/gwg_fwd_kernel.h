@@ -229,6 +229,7 @@ __device__ inline void fmemo_solve(const SceneDev& sc, const PointLds& pl, const
 
 struct NoHit {
     __device__ void operator()(int, double, int) const {}
+    __device__ void branch(int, bool) const {}
 };
 struct NoCoef {
     __device__ Coef4 operator()(int, double, double, double, int, bool) const
@@ -242,6 +243,7 @@ struct PutHit {
     HitQueue q;
     int off;
     __device__ void operator()(int h, double kappa, int meta) const { q.put(off + h, kappa, meta); }
+    __device__ void branch(int, bool) const {}
 };
 // Coefficients of the ray's hit h: from its queue entry, or (mc set) from
 // the key table at the index its queue entry holds.

@@ -104,6 +104,7 @@ __device__ inline void decode_item(const SceneDev& sc, int64_t item, int64_t* po
 #include "gwg_bwd_kernel.h"
 #include "gwg_memo_kernel.h"
 #include "gwg_table_kernel.h"
+#include "gwg_omega_kernel.h"
 
 // Sum per-item partial gradients in item order: grad[d][k] = sum_items(d) partial[item][k].
 __global__ void k_grad_reduce(const double* __restrict__ partial, int64_t items_per_design, int ML,
@@ -356,6 +357,8 @@ int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem)
         return blocks_per_cu(k_adj_memo<true>, 64 * kMemoWaves, smem);
     case KIND_TABLE_ACCUM:
         return blocks_per_cu(k_table_accum, 64 * kMemoWaves, smem);
+    case KIND_OMEGA:
+        return blocks_per_cu(k_omega_grad, wg, smem);
     default:
         return blocks_per_cu(k_adj_entries<false>, wg, smem);
     }
@@ -516,6 +519,15 @@ hipError_t launch_table_reduce(const double* partial, const SceneDev& sc, double
     const int64_t n = (int64_t)sc.D * sc.M * sc.Lmax;
     hipLaunchKernelGGL(k_table_reduce, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, s, partial, sc.D, sc.n_lsel, sc.M,
                        sc.Lmax, sc.nlay, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_omega_grad(const SceneDev& sc, int grid_blocks, int wg, const double* W, const uint32_t* counts,
+                             double* partial, double* grad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_omega_grad, dim3((unsigned)grid_blocks), dim3(wg), omega_smem_bytes(sc, wg), s, sc, W, counts,
+                       partial);
+    hipLaunchKernelGGL(k_omega_reduce, dim3(1), dim3(64), 0, s, (const double*)partial, sc.n_items, sc.M, grad);
     return hipGetLastError();
 }
 

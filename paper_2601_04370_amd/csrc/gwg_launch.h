@@ -18,7 +18,7 @@ int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
 enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3, KIND_ADJ_LOSSLESS = 4,
        KIND_ADJ_MEMO = 5, KIND_ADJ_MEMO_LOSSLESS = 6, KIND_TABLE_ACCUM = 7, KIND_FWD_TAB = 8, KIND_FWD_ADJ_TAB = 9,
-       KIND_BWD_REGEN_TAB = 10 };
+       KIND_BWD_REGEN_TAB = 10, KIND_OMEGA = 11 };
 int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem);
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 int64_t adj_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
@@ -43,6 +43,9 @@ size_t table_adj_smem_bytes(const SceneDev& sc);
 hipError_t launch_table_adj(const SceneDev& sc, double* partial, double* scratch, unsigned long long* stats,
                             hipStream_t s);
 hipError_t launch_table_reduce(const double* partial, const SceneDev& sc, double* grad, hipStream_t s);
+size_t omega_smem_bytes(const SceneDev& sc, int wg);
+hipError_t launch_omega_grad(const SceneDev& sc, int grid_blocks, int wg, const double* W, const uint32_t* counts,
+                             double* partial, double* grad, hipStream_t s);
 hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D,
                               double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s);
 hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double* irr, hipStream_t s);

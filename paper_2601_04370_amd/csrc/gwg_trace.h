@@ -309,7 +309,7 @@ struct Outcome { int cat; int bin; double w; double w_in; };
 
 // Walk one ray (already born) from its current state to termination.
 // FIELD = false: geometry and branch decisions only; every mirror hit h calls
-//   on_hit(h, kappa, meta).
+//   on_hit(h, kappa, meta) and, once the branch is drawn, on_hit.branch(m, refl).
 // FIELD = true: also the polarization field (Eq. 5 at every event, Eq. 6 at
 //   mirrors); mirror hit h takes its coefficients from
 //   get_coef(h, direction, mirror, front); with
@@ -393,6 +393,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
         const int hw = h & 3;
         const uint32_t word = hw == 0 ? r.w4[0] : hw == 1 ? r.w4[1] : hw == 2 ? r.w4[2] : r.w4[3];
         const bool refl = word < pl.thr[m];
+        if (!FIELD) on_hit.branch(m, refl);
         double ndx = r.dx, ndz = r.dz;
         if (refl) mirror_reflect(nx, nz, r.dx, r.dz, &ndx, &ndz);
         if (FIELD) {

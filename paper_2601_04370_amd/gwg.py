@@ -100,7 +100,8 @@ class Tuning(C.Structure):
 #: every function declared in include/gwg.h
 EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gwg_tmm_rt",
            "gwg_trace_forward", "gwg_trace_backward", "gwg_loss", "gwg_set_tuning", "gwg_get_tuning",
-           "gwg_set_timing", "gwg_kernel_times", "gwg_set_step_source", "gwg_autotune", "gwg_forward_kept_entries"]
+           "gwg_set_timing", "gwg_kernel_times", "gwg_set_step_source", "gwg_autotune", "gwg_forward_kept_entries",
+           "gwg_omega_gradient"]
 
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 GWG_FWD_GRAD = 1
@@ -137,6 +138,7 @@ def load_library(path: str = LIB_PATH):
     L.gwg_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.gwg_set_step_source.argtypes = [C.c_void_p, C.c_void_p]
     L.gwg_forward_kept_entries.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+    L.gwg_omega_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.gwg_autotune.argtypes = [C.c_void_p, C.POINTER(Slab), C.POINTER(Prma), C.POINTER(Materials),
                                C.POINTER(Stacks), C.POINTER(Rays), C.c_uint64, C.c_int32, C.c_uint32,
                                C.c_char_p, C.POINTER(Tuning), C.c_void_p]
@@ -283,6 +285,20 @@ class Context:
         t = Tuning()
         self._check(self.lib.gwg_get_tuning(self.h, C.byref(t)))
         return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def omega_gradient(self, W, counts, scene: "SceneSpec"):
+        """d/domega [M] of sum W * counts / N in the scalar-reflectance model,
+        score-function estimate on the paths of the last forward (whose
+        counts tensor is passed; its thk must still be alive)."""
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+        W = W.to(dev, torch.float64).contiguous()
+        counts = counts.to(dev).contiguous()
+        assert W.numel() == int(np.prod(scene.shape)) and counts.numel() == W.numel() and counts.element_size() == 4
+        g = torch.empty(scene.n_mirrors, dtype=torch.float64, device=dev)
+        self._check(self.lib.gwg_omega_gradient(self.h, W.data_ptr(), counts.data_ptr(), g.data_ptr(),
+                                                _stream(torch, dev)))
+        return g
 
     def forward_kept_entries(self) -> bool:
         """True if the last forward stored adjoint entries for the backward."""

@@ -1,4 +1,11 @@
-"""Coating optimisation with discrete thickness constraints and layer pruning.
+"""Coating optimisation with discrete thickness constraints and layer pruning,
+and the pre-optimisation of the mirrors' reflection probabilities.
+
+``learn_reflection_probabilities`` is the step before the trace (Methods,
+learned reflection probabilities): omega per mirror is optimised for eyebox
+throughput with every coating idealised as a scalar reflectance, using the
+library's score-function gradient (``gwg_omega_gradient``); the learned
+omega then drives the Monte Carlo sampling of the polarization trace.
 
 The step after the differentiable trace (Results: stacks are optimised from a
 random start inside thickness bounds, over-parameterised stacks are pruned by
@@ -169,6 +176,60 @@ class CoatingOptimizer:
                 acc[key] += m[key] / len(seeds)
             acc["loss"] += float(L) / len(seeds)
         return acc
+
+
+def learn_reflection_probabilities(ctx: Context, w, inp: dict, iters: int = 100, lr: float = 0.2, seed: int = 0,
+                                   objective: str = "throughput", w_f: float = 10.0, w_e: float = 3.0,
+                                   omega0: Optional[np.ndarray] = None, p_min: float = 0.02, p_max: float = 0.98,
+                                   callback: Optional[Callable[[dict], None]] = None) -> np.ndarray:
+    """Pre-optimisation of the mirrors' reflection probabilities (Methods,
+    learned reflection probabilities): every coating idealised as a scalar
+    reflectance equal to omega, geometry only.  Each iteration traces fresh
+    paths (the forward's bin counts are geometry, so the cheapest thin-film
+    mode serves), forms the scalar irradiance I = counts / N, and takes an
+    Adam step on logit(omega) with the score-function gradient of the
+    objective (gwg_omega_gradient):
+      - "throughput" (the paper's): maximise the mean eyebox throughput;
+      - "eq1": minimise Eq. 1 (w_f, w_e) at the scalar irradiance.
+    omega stays in [p_min, p_max].  Returns omega [M]."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    om = np.clip(np.asarray(inp["omega"] if omega0 is None else omega0, dtype=np.float64), p_min, p_max)
+    theta = np.log(om / (1.0 - om))
+    m1, m2 = np.zeros_like(theta), np.zeros_like(theta)
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device=dev)
+    saved = ctx.get_tuning()
+    try:
+        ctx.set_tuning(**{**saved, "table_nodes": 4})
+        for k in range(iters):
+            om = np.clip(1.0 / (1.0 + np.exp(-theta)), p_min, p_max)
+            scene = SceneSpec.from_workload(w, {**inp, "omega": om})
+            _, counts, _, _, _ = ctx.trace_forward(scene, thk, seed, k, FP64, table=True, want_irradiance=False)
+            I = counts.to(torch.float64) / float(w.rays_per_point)
+            n_pts = I.shape[0] * I.shape[1] * I.shape[2]
+            if objective == "throughput":
+                W = torch.ones_like(I)
+                value = float(I.sum()) / n_pts
+                sign = -1.0                               # ascent
+            elif objective == "eq1":
+                L, W = ctx.loss(I, 1, w_f, w_e)
+                value = float(L)
+                sign = 1.0
+            else:
+                raise ValueError(f"unknown objective {objective!r}")
+            g = ctx.omega_gradient(W, counts, scene).cpu().numpy()
+            if objective == "throughput":
+                g = g / n_pts
+            gt = sign * g * om * (1.0 - om)               # d/dlogit, as a descent direction
+            m1 = b1 * m1 + (1 - b1) * gt
+            m2 = b2 * m2 + (1 - b2) * gt * gt
+            theta = theta - lr * (m1 / (1 - b1 ** (k + 1))) / (np.sqrt(m2 / (1 - b2 ** (k + 1))) + eps)
+            if callback:
+                callback({"iter": k, "objective": value, "omega": om.tolist()})
+    finally:
+        ctx.set_tuning(**saved)
+    return np.clip(1.0 / (1.0 + np.exp(-theta)), p_min, p_max)
 
 
 def main():

@@ -56,6 +56,7 @@ def test_null_context_is_rejected(lib):
     assert lib.gwg_kernel_times(None, 0, 1, None) == gwg.GWG_E_INVAL
     assert lib.gwg_set_step_source(None, None) == gwg.GWG_E_INVAL
     assert lib.gwg_forward_kept_entries(None, None) == gwg.GWG_E_INVAL
+    assert lib.gwg_omega_gradient(None, None, None, None, None) == gwg.GWG_E_INVAL
     assert lib.gwg_autotune(None, None, None, None, None, None, 0, 0, 0, None, None, None) == gwg.GWG_E_INVAL
 
 
