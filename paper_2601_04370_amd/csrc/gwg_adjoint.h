@@ -256,7 +256,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     //    then whole groups of K layers, each ending in a checkpoint (group 0
     //    in none: v_0 stays in registers).  stored: the forward solve ran
     //    this sweep and left v_0 in block 0 and the checkpoints in blocks
-    //    1.. of chk, with the same arithmetic.
+    //    1.. of chk (64-byte blocks, cstride 1), with the same arithmetic.
     if (L <= 0) return;
     constexpr int K = kSegL;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
@@ -274,9 +274,15 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
         c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
         c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
     };
+    // a stored block is 64 contiguous bytes (cstride 1), read whole
+    auto read_block = [&](const double* c, V2d& a, V2d& b) {
+        const double2* p = (const double2*)c;
+        const double2 x0 = p[0], x1 = p[1], x2 = p[2], x3 = p[3];
+        a = V2d{ x0.x, x0.y, x1.x, x1.y };
+        b = V2d{ x2.x, x2.y, x3.x, x3.y };
+    };
     if (stored) {
-        vs = V2d{ chk[0], chk[cstride], chk[2 * cstride], chk[3 * cstride] };
-        vp = V2d{ chk[4 * cstride], chk[5 * cstride], chk[6 * cstride], chk[7 * cstride] };
+        read_block(chk, vs, vp);
     } else {
         const int ng = L / K;
         for (int jj = L - 1; jj >= ng * K; --jj) layer_fwd(jj);
@@ -303,8 +309,12 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     V2d ws = vs, wp = vp, nws = vs, nwp = vp;
     auto load_chk = [&](int k) {
         const double* c = chk + (int64_t)k * 8 * cstride;
-        nws = V2d{ c[0], c[cstride], c[2 * cstride], c[3 * cstride] };
-        nwp = V2d{ c[4 * cstride], c[5 * cstride], c[6 * cstride], c[7 * cstride] };
+        if (stored) {
+            read_block(c, nws, nwp);
+        } else {
+            nws = V2d{ c[0], c[cstride], c[2 * cstride], c[3 * cstride] };
+            nwp = V2d{ c[4 * cstride], c[5 * cstride], c[6 * cstride], c[7 * cstride] };
+        }
     };
     if (K < L) load_chk(1);
     int idx = front ? 0 : L - 1;

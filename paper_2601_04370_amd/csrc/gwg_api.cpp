@@ -741,7 +741,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
             // fewer if memory is short); the adjoint then skips that sweep.
             const int64_t ck_per = c->tune.ck_entries_per_ray == 0 ? kCkEntriesPerRay : c->tune.ck_entries_per_ray;
             if (precision == GWG_FP64 && !(flags & GWG_FWD_MEMO) && sc.slot_complex == 0u && ck_per > 0) {
-                const int64_t blocks = sc.Lmax / kSegL + 1;
+                const int64_t blocks = ck_blocks(sc.Lmax);
                 const int64_t rays_w = (sc.rays_per_tile + wg - 1) / wg * 64;
                 for (int64_t per = ck_per; per >= 1; --per) {
                     const int64_t ck_cap = std::min<int64_t>(cap_w, rays_w * per);

@@ -30,6 +30,8 @@ constexpr int LT_NSLOT = 40;          // number of slots (as double)
 constexpr int kTapeStride = 15;       // doubles per tape entry (backward)
 constexpr int kSeg = 4;               // layers per recomputation segment (backward)
 constexpr int kSegL = 16;             // checkpoint interval of the lossless adjoint (multiple of kSeg)
+// checkpoint blocks per stored adjoint entry: v_0 and v_{g kSegL}, g >= 1
+__host__ __device__ inline int64_t ck_blocks(int lmax) { return lmax / kSegL + 1; }
 
 enum EventType { EV_NONE = 0, EV_TIR = 1, EV_EXIT = 2, EV_LEAK = 3, EV_END = 4, EV_MIRROR = 5 };
 enum Category { CAT_EYEBOX = 0, CAT_MISS = 1, CAT_LEAK = 2, CAT_END = 3, CAT_TRUNC = 4,
@@ -65,9 +67,10 @@ struct AdjStore {
     int64_t total;
     int32_t waves;
     // Sweep checkpoints of the first ck_cap entries of every region, stored
-    // by the FP64 forward solve (null: the adjoint recomputes them).  Block g
-    // of entry slot c (c = region * ck_cap + k): field f at
-    // ck[(g * 8 + f) * ck_total + c]; g = 0 holds v_0, g >= 1 v_{g kSegL}.
+    // by the FP64 forward solve (null: the adjoint recomputes them).  Entry
+    // slot c (c = region * ck_cap + k) owns ck_blocks(Lmax) contiguous blocks
+    // of 8 doubles (64 bytes, written and read whole): field f of block g at
+    // ck[(c * ck_blocks + g) * 8 + f]; g = 0 holds v_0, g >= 1 v_{g kSegL}.
     double* ck;
     int64_t ck_cap;
     int64_t ck_total;
