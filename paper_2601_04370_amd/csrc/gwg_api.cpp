@@ -431,10 +431,11 @@ void set_tiles(SceneDev& s, int64_t rays_per_tile, int wg, int n_cu)
     const int64_t points = (int64_t)s.D * s.n_lsel * s.F;
     int64_t rpt = rays_per_tile;
     if (rpt <= 0) {
-        // Whole points while there are at least ~2 per resident workgroup
-        // (two per CU); otherwise split every point into equal tiles of at
-        // least 4 rays per lane.
-        const int64_t target = (int64_t)std::max(n_cu, 1) * 4;
+        // Whole points while there are at least ~16 per CU (about 8 rounds
+        // of two resident workgroups per CU, so the last, partly filled
+        // round costs little); otherwise split every point into equal tiles
+        // of at least 4 rays per lane.
+        const int64_t target = (int64_t)std::max(n_cu, 1) * 16;
         const int64_t tiles = points >= target ? 1 : (target + points - 1) / points;
         rpt = (s.N + tiles - 1) / tiles;
         rpt = std::max<int64_t>(rpt, (int64_t)wg * 4);

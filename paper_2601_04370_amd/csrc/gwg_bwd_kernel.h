@@ -144,13 +144,12 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     constexpr bool tabm = TAB;
     const double fx = tabm ? table_fx_scale(sc) : 0.0;
 
-    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+    for (int64_t item = draw_item(stats + ST_NEXT1); item < sc.n_items; item = draw_item(stats + ST_NEXT1)) {
         // regen (optional): only items whose stored entries overflowed
         if (regen && regen[item] == 0) continue;
         int64_t point, i0, i1;
         int d, l, f;
         decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
-        __syncthreads();
         stage_point(sc, d, l, f, pl, s_thk, s_slot);
         for (int k = tid; k < n_waves * ML; k += WG) s_grad[k] = 0.0;
         __syncthreads();
@@ -289,12 +288,11 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long c_ahits = 0, c_alay = 0, c_astored = 0;
 
-    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+    for (int64_t item = draw_item(stats + ST_NEXT0); item < sc.n_items; item = draw_item(stats + ST_NEXT0)) {
         if (st.ovf[item] != 0) continue;
         int64_t point, i0, i1;
         int d, l, f;
         decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
-        __syncthreads();
         stage_point(sc, d, l, f, pl, s_thk, s_slot);
         for (int k = tid; k < n_waves * ML; k += WG) s_grad[k] = 0.0;
         __syncthreads();

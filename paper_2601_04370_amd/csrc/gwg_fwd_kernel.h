@@ -300,11 +300,10 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     double t_gmax = 0.0;                                 // largest cotangent component (angle table)
     unsigned long long t_ne = 0;                         // cotangent pairs emitted (angle table)
 
-    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+    for (int64_t item = draw_item(stats + ST_NEXT0); item < sc.n_items; item = draw_item(stats + ST_NEXT0)) {
         int64_t point, i0, i1;
         int d, l, f;
         decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
-        __syncthreads();
         stage_point(sc, d, l, f, pl, s_thk, s_slot);
         if (lds_bins)
             for (int k = tid; k < B; k += WG) { s_q[k] = 0ull; s_c[k] = 0u; }

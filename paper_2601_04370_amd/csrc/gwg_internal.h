@@ -44,7 +44,9 @@ enum StatWord { ST_RAYS = 0, ST_EVENTS = 1, ST_PRMA = 2, ST_FP64 = 3, ST_SAT = 4
                 ST_CAT = 9,           // 8 words of counts
                 ST_POW = 17,          // 8 words of power (fixed point 2^-24)
                 ST_ADJ_STORED = 25,   // adjoint layer steps whose sweep the forward stored
-                ST_WORDS = 26 };
+                ST_NEXT0 = 26,        // work-item counter of the call's first item kernel
+                ST_NEXT1 = 27,        // ... and of its second (the backward's regenerating kernel)
+                ST_WORDS = 28 };
 
 // Adjoint entries recorded by the forward trace for the backward: per
 // (work item, forward wave) a region of cap_w entries, field f of entry e at

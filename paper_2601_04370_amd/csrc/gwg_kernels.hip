@@ -99,6 +99,21 @@ __device__ inline void decode_item(const SceneDev& sc, int64_t item, int64_t* po
     *i1 = e < sc.N ? e : sc.N;
 }
 
+// Work items are drawn from a launch-wide counter (a stats word cleared
+// before the launch) rather than by a fixed stride over blocks: a block that
+// drew cheap items goes on to the next one, so the launch ends within about
+// one item of the mean.  Every output is indexed by item, never by block,
+// so results do not depend on which block ran an item.  Called by the whole
+// block.
+__device__ inline int64_t draw_item(unsigned long long* ctr)
+{
+    __shared__ long long s_item;
+    __syncthreads();                                   // the previous draw has been read
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(ctr, 1ull);
+    __syncthreads();
+    return s_item;
+}
+
 #include "gwg_table.h"
 #include "gwg_fwd_kernel.h"
 #include "gwg_bwd_kernel.h"

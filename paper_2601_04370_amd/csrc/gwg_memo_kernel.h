@@ -181,12 +181,11 @@ __global__ void __launch_bounds__(64 * kMemoWaves, 2) k_adj_memo(SceneDev sc, co
     for (int k = tid; k < ST_WORDS; k += 64 * kMemoWaves) s_st[k] = 0ull;
     unsigned long long c_keys = 0, c_lay = 0;
 
-    for (int64_t item = blockIdx.x; item < sc.n_items; item += gridDim.x) {
+    for (int64_t item = draw_item(stats + ST_NEXT0); item < sc.n_items; item = draw_item(stats + ST_NEXT0)) {
         if (st.ovf[item] != 0) continue;
         int64_t point, i0, i1;
         int d, l, f;
         decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
-        __syncthreads();
         stage_point(sc, d, l, f, pl, s_thk, s_slot);
         for (int k = tid; k < ML; k += 64 * kMemoWaves) gw[k] = 0.0;
         const double* g_bins = dLdI + point * B;
