@@ -777,7 +777,8 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
         adj_sweep = adj || table;
     }
     // persistent grid: as many workgroups as fit on the device at once
-    const int kind_f = adj_sweep ? (table ? KIND_FWD_ADJ_TAB : KIND_FWD_ADJ) : (table ? KIND_FWD_TAB : KIND_FWD);
+    const int kind_f = adj_sweep ? (table ? KIND_FWD_ADJ_TAB : sc.memo ? KIND_FWD_ADJ_MEMO : KIND_FWD_ADJ)
+                                 : (table ? KIND_FWD_TAB : sc.memo ? KIND_FWD_MEMO : KIND_FWD);
     const int per_cu = occupancy(c, kind_f, precision, wg, fwd_smem_bytes(sc, wg, lds_bins));
     const int64_t grid = std::min<int64_t>(sc.n_items, (int64_t)std::max(c->n_cu, 1) * per_cu);
     rc = ensure_buf(c, c->fwd_scratch, sizeof(double) * (size_t)fwd_scratch_doubles(sc, grid, wg), cap, "alloc hit queues");

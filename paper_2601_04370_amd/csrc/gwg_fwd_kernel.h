@@ -265,7 +265,7 @@ struct GetCoef {
 // handles a strided share of the item's rays.  Eyebox bins of the current
 // point accumulate in LDS (integer atomics) and are flushed per item with
 // integer global atomics: the result does not depend on scheduling.
-template <int MODE, bool ADJ, bool TAB>
+template <int MODE, bool ADJ, bool TAB, bool MEMO>
 __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __restrict__ q_out,
                                                    uint32_t* __restrict__ c_out,
                                                    unsigned long long* __restrict__ stats,
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
         uint64_t* gq = q_out + point * B;
         uint32_t* gc = c_out + point * B;
         int64_t n_ent = 0;                                // this wave's entries in this item (uniform)
-        bool memo = sc.memo != 0;                         // this wave's key table is in use (uniform)
+        bool memo = MEMO && sc.memo != 0;                 // this wave's key table is in use (uniform)
         int n_keys = 0;
         if (memo) {
             for (int k = lane; k < kFwdMemoHash; k += 64) fm.hslot[k] = -1;
@@ -363,8 +363,8 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                 }
                 __threadfence_block();
                 const int u0 = n_keys;
-                if (memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
-                if (memo)
+                if (MEMO && memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
+                if (MEMO && memo)
                     fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
                 else
                     solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, off, &n_fp64, &n_lay,
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                 if constexpr (TAB)
                     walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, TabCoef{ tab_dl, sc.table_n, pl->ng, sc.nx, sc.nz }, rt, &nt);
                 else
-                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, own, memo ? fm.coef : nullptr }, rt, &nt);
+                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, own, MEMO && memo ? fm.coef : nullptr }, rt, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
                 atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);

@@ -339,12 +339,12 @@ static int blocks_per_cu(K kernel, int wg, size_t smem)
     return n;
 }
 
-template <bool ADJ, bool TAB>
+template <bool ADJ, bool TAB, bool MEMO = false>
 static int fwd_blocks_per_cu(int precision, int wg, size_t smem)
 {
-    if (precision == GWG_FP64) return blocks_per_cu(k_trace_fwd<GWG_FP64, ADJ, TAB>, wg, smem);
-    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_fwd<GWG_FP32_MIXED, ADJ, TAB>, wg, smem);
-    return blocks_per_cu(k_trace_fwd<GWG_FP32, ADJ, TAB>, wg, smem);
+    if (precision == GWG_FP64) return blocks_per_cu(k_trace_fwd<GWG_FP64, ADJ, TAB, MEMO>, wg, smem);
+    if (precision == GWG_FP32_MIXED) return blocks_per_cu(k_trace_fwd<GWG_FP32_MIXED, ADJ, TAB, MEMO>, wg, smem);
+    return blocks_per_cu(k_trace_fwd<GWG_FP32, ADJ, TAB, MEMO>, wg, smem);
 }
 
 template <bool TAB>
@@ -362,6 +362,8 @@ int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem)
     case KIND_FWD_ADJ: return fwd_blocks_per_cu<true, false>(precision, wg, smem);
     case KIND_FWD_TAB: return fwd_blocks_per_cu<false, true>(precision, wg, smem);
     case KIND_FWD_ADJ_TAB: return fwd_blocks_per_cu<true, true>(precision, wg, smem);
+    case KIND_FWD_MEMO: return fwd_blocks_per_cu<false, false, true>(precision, wg, smem);
+    case KIND_FWD_ADJ_MEMO: return fwd_blocks_per_cu<true, false, true>(precision, wg, smem);
     case KIND_BWD_REGEN: return bwd_blocks_per_cu<false>(precision, wg, smem);
     case KIND_BWD_REGEN_TAB: return bwd_blocks_per_cu<true>(precision, wg, smem);
     case KIND_ADJ_LOSSLESS:
@@ -384,18 +386,24 @@ static void launch_fwd_mode(const SceneDev& sc, dim3 grid, dim3 block, size_t sm
                             uint32_t* c, unsigned long long* stats, gwg_ray_record* rec, int64_t rec_stride,
                             double* scratch, const AdjStore* adj, double* tape, hipStream_t s)
 {
-    const bool tab = sc.table != nullptr;
+    const bool tab = sc.table != nullptr, memo = sc.memo != 0;
     if (adj && tab)
-        hipLaunchKernelGGL((k_trace_fwd<MODE, true, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+        hipLaunchKernelGGL((k_trace_fwd<MODE, true, true, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+                           (int)lds_bins, scratch, *adj, tape);
+    else if (adj && memo)
+        hipLaunchKernelGGL((k_trace_fwd<MODE, true, false, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
                            (int)lds_bins, scratch, *adj, tape);
     else if (adj)
-        hipLaunchKernelGGL((k_trace_fwd<MODE, true, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+        hipLaunchKernelGGL((k_trace_fwd<MODE, true, false, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
                            (int)lds_bins, scratch, *adj, tape);
     else if (tab)
-        hipLaunchKernelGGL((k_trace_fwd<MODE, false, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+        hipLaunchKernelGGL((k_trace_fwd<MODE, false, true, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+                           (int)lds_bins, scratch, AdjStore{}, (double*)nullptr);
+    else if (memo)
+        hipLaunchKernelGGL((k_trace_fwd<MODE, false, false, true>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
                            (int)lds_bins, scratch, AdjStore{}, (double*)nullptr);
     else
-        hipLaunchKernelGGL((k_trace_fwd<MODE, false, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
+        hipLaunchKernelGGL((k_trace_fwd<MODE, false, false, false>), grid, block, sm, s, sc, q, c, stats, rec, rec_stride,
                            (int)lds_bins, scratch, AdjStore{}, (double*)nullptr);
 }
 

@@ -18,7 +18,7 @@ int64_t bwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 
 enum { KIND_FWD = 0, KIND_FWD_ADJ = 1, KIND_BWD_REGEN = 2, KIND_ADJ_ENTRIES = 3, KIND_ADJ_LOSSLESS = 4,
        KIND_ADJ_MEMO = 5, KIND_ADJ_MEMO_LOSSLESS = 6, KIND_TABLE_ACCUM = 7, KIND_FWD_TAB = 8, KIND_FWD_ADJ_TAB = 9,
-       KIND_BWD_REGEN_TAB = 10, KIND_OMEGA = 11 };
+       KIND_BWD_REGEN_TAB = 10, KIND_OMEGA = 11, KIND_FWD_MEMO = 12, KIND_FWD_ADJ_MEMO = 13 };
 int trace_blocks_per_cu(int kind, int precision, int wg, size_t smem);
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
 int64_t adj_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg);
