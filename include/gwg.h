@@ -338,9 +338,11 @@ int gwg_set_step_source(gwg_ctx* ctx, const uint32_t* d_step);
 
 /* Autotuner.  Times the forward trace of this scene (same arguments as
  * gwg_trace_forward, step 0) for workgroup sizes 256/128 and ray tiles of
- * 1/4 to 4 times the automatic tile, checks that the eyebox bins are
- * bit-identical across them (scenes of up to 2^24 bins), then times the
- * adjoint (dL/dI = 1) for adjoint workgroup sizes 128/64, and keeps the
+ * 1/4 to 4 times the automatic tile (with GWG_FWD_GRAD: forward plus
+ * adjoint with dL/dI = 1, since the adjoint runs on the forward's tiles),
+ * checks that the eyebox bins are bit-identical across them (scenes of up
+ * to 2^24 bins), then times the adjoint for adjoint workgroup sizes 128/64,
+ * and keeps the
  * fastest as the context's tuning (*out).  Results are cached in the
  * context by scene signature (scene tables, precision, flags, device) and,
  * with cache_path != NULL, read from and appended to that text file.  Runs

@@ -1056,6 +1056,14 @@ int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const g
         return gwg_trace_forward(c, slab, prma, mats, stacks, rays, seed, 0, precision, flags, &eb, nullptr, 1,
                                  nullptr, stream);
     };
+    // with a gradient to follow, a tile is timed over forward + backward: the
+    // adjoint takes its work items from the forward's decomposition
+    const bool with_bwd = (flags & GWG_FWD_GRAD) != 0;
+    auto step = [&]() {
+        const int r = forward();
+        if (r != GWG_OK || !with_bwd) return r;
+        return gwg_trace_backward(c, (const double*)c->tune_g.p, (double*)c->tune_grad.p, 1, nullptr, stream);
+    };
     // forward candidates: block size x ray tile; bins must not depend on them
     std::vector<gwg_tuning> cands;
     for (int wg : { 256, 128 }) {
@@ -1081,7 +1089,7 @@ int gwg_autotune(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, const g
     gwg_tuning best = saved;
     for (size_t i = 0; i < cands.size(); ++i) {
         c->tune = cands[i];
-        const double ms = timed(forward);
+        const double ms = timed(step);
         if (ms < 0.0) continue;
         if (verify) {
             cur.resize((size_t)nbins);

@@ -510,7 +510,7 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(const doubl
     int idx1 = idx == last ? idx : idx + dir;
     double t1 = thk[idx1];
     int s1 = slot[idx1];
-#pragma unroll 2
+#pragma unroll 4
     for (int j = 0; j < L; ++j) {
         const int idx2 = idx1 == last ? idx1 : idx1 + dir;
         const double t2 = thk[idx2];
