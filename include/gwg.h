@@ -298,7 +298,7 @@ int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t 
 /* Launch parameters of the trace kernels (0 = automatic).  rays_per_block
  * is the tile of rays of one (design, wavelength, FoV) point handled by a
  * workgroup; block_threads is 64, 128 or 256 (adjoint: 64 or 128).
- * adj_entries_per_ray (0..64, 0 = 6) sizes the adjoint entry regions of
+ * adj_entries_per_ray (0..64, 0 = 8) sizes the adjoint entry regions of
  * GWG_FWD_GRAD: a region holding more entries than this times its rays is
  * regenerated by the backward instead.  memo_keys (0..128, 0 = 128) is the
  * capacity of each wave's key table in the memoized forward (GWG_FWD_MEMO):

@@ -73,7 +73,7 @@ struct KernelTimer {
 
 // Adjoint entry capacity: entries per ray of a (work item, wave) region, and
 // the most device memory the entries may take.
-constexpr int64_t kAdjEntriesPerRay = 6;
+constexpr int64_t kAdjEntriesPerRay = 8;
 constexpr double kAdjBudgetBytes = 32.0 * 1024 * 1024 * 1024;
 
 struct gwg_ctx {
@@ -87,7 +87,7 @@ struct gwg_ctx {
     DevBuf lam_tab, dir_tab, slot, nlay;
     std::vector<int32_t> h_nlay;
     // per-call buffers
-    DevBuf stats, partial, scratch, fwd_scratch, loss_work;
+    DevBuf stats, partial, scratch, fwd_scratch, loss_work, grad_tmp;
     // thin-film queries
     DevBuf tmm_tab, tmm_slot;
     // last forward
@@ -504,7 +504,7 @@ int gwg_destroy(gwg_ctx* c)
         for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape,
                            &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad,
-                           &c->adj_ck })
+                           &c->adj_ck, &c->grad_tmp })
             b->release();
         for (KernelTimer& t : c->timer) t.destroy();
     }
@@ -911,8 +911,11 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
         HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_ADJOINT].end(), s), "timing event");
         ++c->timer[GWG_KERNEL_ADJOINT].recorded;
     }
-    HIP_CHECK(c, launch_grad_reduce((const double*)c->partial.p, sc.n_items / sc.D, ML, sc.D, d_grad, sc.nlay, sc.M,
-                                    sc.Lmax, s),
+    rc = ensure_buf(c, c->grad_tmp, sizeof(double) * (size_t)grad_reduce_tmp_doubles(ML, sc.D), cap,
+                    "alloc gradient reduction");
+    if (rc) return rc;
+    HIP_CHECK(c, launch_grad_reduce((const double*)c->partial.p, sc.n_items / sc.D, ML, sc.D, (double*)c->grad_tmp.p,
+                                    d_grad, sc.nlay, sc.M, sc.Lmax, s),
               "gradient reduction");
     if (stats) return read_stats(c, s, stats);
     return GWG_OK;

@@ -122,17 +122,37 @@ __device__ inline int64_t draw_item(unsigned long long* ctr)
 #include "gwg_omega_kernel.h"
 
 // Sum per-item partial gradients in item order: grad[d][k] = sum_items(d) partial[item][k].
-__global__ void k_grad_reduce(const double* __restrict__ partial, int64_t items_per_design, int ML,
-                              int D, double* __restrict__ grad)
+// Gradient reduction over the per-item partials, in two launches with a
+// fixed order of additions (the gradient is the same bit for bit from run to
+// run): range r of kGradRanges contiguous item ranges of a design is summed
+// in item order, then the range sums in range order.
+constexpr int kGradRanges = 64;
+
+__global__ void k_grad_ranges(const double* __restrict__ partial, int64_t items_per_design, int ML,
+                              double* __restrict__ tmp)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y, d = blockIdx.z;
+    if (k >= ML) return;
+    const int64_t a = items_per_design * r / kGradRanges, b = items_per_design * (r + 1) / kGradRanges;
+    const double* p = partial + (int64_t)d * items_per_design * ML + k;
+    double acc = 0.0;
+    for (int64_t it = a; it < b; ++it) acc += p[it * ML];
+    tmp[((int64_t)d * kGradRanges + r) * ML + k] = acc;
+}
+
+__global__ void k_grad_reduce(const double* __restrict__ tmp, int ML, int D, double* __restrict__ grad)
 {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (int64_t)D * ML) return;
     int d = (int)(gid / ML), k = (int)(gid % ML);
-    const double* p = partial + (int64_t)d * items_per_design * ML + k;
+    const double* p = tmp + (int64_t)d * kGradRanges * ML + k;
     double acc = 0.0;
-    for (int64_t it = 0; it < items_per_design; ++it) acc += p[it * ML];
+    for (int r = 0; r < kGradRanges; ++r) acc += p[(int64_t)r * ML];
     grad[gid] = acc;
 }
+
+int64_t grad_reduce_tmp_doubles(int ML, int D) { return (int64_t)D * kGradRanges * ML; }
 
 __global__ void k_mask_padding(double* grad, const int32_t* nlay, int D, int M, int Lmax)
 {
@@ -554,11 +574,13 @@ hipError_t launch_omega_grad(const SceneDev& sc, int grid_blocks, int wg, const 
     return hipGetLastError();
 }
 
-hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D,
+hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D, double* tmp,
                               double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s)
 {
     int64_t n = (int64_t)D * ML;
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, s, partial, items_per_design, ML, D, grad);
+    hipLaunchKernelGGL(k_grad_ranges, dim3((unsigned)((ML + 255) / 256), kGradRanges, (unsigned)D), dim3(256), 0, s,
+                       partial, items_per_design, ML, tmp);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, s, (const double*)tmp, ML, D, grad);
     hipLaunchKernelGGL(k_mask_padding, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, s, grad, nlay, D, M, Lmax);
     return hipGetLastError();
 }
