@@ -240,60 +240,98 @@ __global__ void __launch_bounds__(256) k_loss_eta(const double* __restrict__ I, 
     if (threadIdx.x == 0) eta[blockIdx.x] = red[0];
 }
 
-// E[d][b] = mean over (l, f) of I  (one thread per (d, b), fixed order)
-__global__ void k_loss_eyeb(const double* __restrict__ I, int D, int nlf, int B, double* __restrict__ E)
+// E[d][b] = mean over (l, f) of I.  One block of 1024 threads per (design,
+// 64 bins): wave w sums the rows k = w, w + 16, ... in order, then lane b's
+// 16 wave sums are added in wave order (a fixed order).
+__global__ void __launch_bounds__(1024) k_loss_eyeb(const double* __restrict__ I, int D, int nlf, int B,
+                                                    double* __restrict__ E)
 {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)D * B) return;
-    int d = (int)(gid / B), b = (int)(gid % B);
-    const double* p = I + (int64_t)d * nlf * B + b;
+    __shared__ double part[16][64];
+    const int tiles = (B + 63) / 64;
+    const int d = blockIdx.x / tiles, b = (blockIdx.x % tiles) * 64 + (threadIdx.x & 63), w = threadIdx.x >> 6;
     double acc = 0.0;
-    for (int k = 0; k < nlf; ++k) acc += p[(int64_t)k * B] / (double)nlf;
-    E[gid] = acc;
+    if (b < B) {
+        const double* p = I + (int64_t)d * nlf * B + b;
+        for (int k = w; k < nlf; k += 16) acc += p[(int64_t)k * B] / (double)nlf;
+    }
+    part[w][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (w == 0 && b < B) {
+        double e = 0.0;
+        for (int k = 0; k < 16; ++k) e += part[k][threadIdx.x];
+        E[(int64_t)d * B + b] = e;
+    }
 }
 
-// Per design: moments and the coefficients of dL/dI (one thread per design).
-// coef[d] = { L_d, a_e, a_f, m_e, m_f, ebar, ibar } ; phi[d][f] written too.
-__global__ void k_loss_scalar(const double* __restrict__ eta, const double* __restrict__ E, int D, int nl,
-                              int F, int B, int kind, double w_f, double w_e, double* __restrict__ phi,
-                              double* __restrict__ coef, double* __restrict__ loss)
+// Sum over the block of each thread's v: a fixed tree over the 256 threads.
+__device__ inline double block_sum256(double v, double* red)
+{
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// Per design (one block of 256 threads each): moments and the coefficients
+// of dL/dI.  coef[d] = { L_d, a_e, a_f, m_e, m_f, ebar, ibar }; phi[d][f]
+// written too.  Sums are strided per thread, then a fixed tree.
+__global__ void __launch_bounds__(256) k_loss_scalar(const double* __restrict__ eta, const double* __restrict__ E,
+                                                     int nl, int F, int B, int kind, double w_f, double w_e,
+                                                     double* __restrict__ phi, double* __restrict__ coef)
+{
+    __shared__ double red[256];
+    const int d = blockIdx.x, t = threadIdx.x;
+    const double* et = eta + (int64_t)d * nl * F;
+    double* ph = phi + (int64_t)d * F;
+    const double npts = (double)nl * (double)F;
+    double part = 0.0;
+    for (int f = t; f < F; f += 256) {
+        double a = 0.0;
+        for (int l = 0; l < nl; ++l) {
+            const double v = et[(int64_t)l * F + f];
+            a += v / (double)nl;
+            part += v / npts;
+        }
+        ph[f] = a;
+    }
+    const double ibar = block_sum256(part, red);
+    const double* Ed = E + (int64_t)d * B;
+    part = 0.0;
+    for (int b = t; b < B; b += 256) part += Ed[b] / (double)B;
+    const double ebar = block_sum256(part, red);
+    part = 0.0;
+    for (int b = t; b < B; b += 256) part += (Ed[b] - ebar) * (Ed[b] - ebar) / (double)B;
+    const double ve = block_sum256(part, red);
+    part = 0.0;
+    for (int f = t; f < F; f += 256) part += (ph[f] - ibar) * (ph[f] - ibar) / (double)F;   // this thread's own ph[f]
+    const double vf = block_sum256(part, red);
+    if (t != 0) return;
+    double L, ae, af, me, mf;
+    if (kind == 0) {
+        L = -ibar + w_e * ve + w_f * vf;
+        ae = w_e; af = w_f; me = 0.0; mf = 0.0;
+    } else {
+        double se = sqrt(ve), sf = sqrt(vf);
+        L = -ibar + w_f * (sf / ibar) + w_e * (se / ebar);
+        ae = se > 0.0 ? w_e / (2.0 * se * ebar) : 0.0;
+        af = sf > 0.0 ? w_f / (2.0 * sf * ibar) : 0.0;
+        me = -w_e * se / (ebar * ebar);
+        mf = -w_f * sf / (ibar * ibar);
+    }
+    double* c = coef + (int64_t)d * 8;
+    c[0] = L; c[1] = ae; c[2] = af; c[3] = me; c[4] = mf; c[5] = ebar; c[6] = ibar;
+}
+
+// Total loss: the designs' L_d in design order.
+__global__ void k_loss_total(const double* __restrict__ coef, int D, double* __restrict__ loss)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     double total = 0.0;
-    for (int d = 0; d < D; ++d) {
-        const double* et = eta + (int64_t)d * nl * F;
-        double* ph = phi + (int64_t)d * F;
-        double npts = (double)nl * (double)F;
-        double ibar = 0.0;
-        for (int f = 0; f < F; ++f) ph[f] = 0.0;
-        for (int l = 0; l < nl; ++l)
-            for (int f = 0; f < F; ++f) {
-                double v = et[(int64_t)l * F + f];
-                ph[f] += v / (double)nl;
-                ibar += v / npts;
-            }
-        const double* Ed = E + (int64_t)d * B;
-        double ebar = 0.0;
-        for (int b = 0; b < B; ++b) ebar += Ed[b] / (double)B;
-        double ve = 0.0, vf = 0.0;
-        for (int b = 0; b < B; ++b) ve += (Ed[b] - ebar) * (Ed[b] - ebar) / (double)B;
-        for (int f = 0; f < F; ++f) vf += (ph[f] - ibar) * (ph[f] - ibar) / (double)F;
-        double L, ae, af, me, mf;
-        if (kind == 0) {
-            L = -ibar + w_e * ve + w_f * vf;
-            ae = w_e; af = w_f; me = 0.0; mf = 0.0;
-        } else {
-            double se = sqrt(ve), sf = sqrt(vf);
-            L = -ibar + w_f * (sf / ibar) + w_e * (se / ebar);
-            ae = se > 0.0 ? w_e / (2.0 * se * ebar) : 0.0;
-            af = sf > 0.0 ? w_f / (2.0 * sf * ibar) : 0.0;
-            me = -w_e * se / (ebar * ebar);
-            mf = -w_f * sf / (ibar * ibar);
-        }
-        double* c = coef + (int64_t)d * 8;
-        c[0] = L; c[1] = ae; c[2] = af; c[3] = me; c[4] = mf; c[5] = ebar; c[6] = ibar;
-        total += L;
-    }
+    for (int d = 0; d < D; ++d) total += coef[(int64_t)d * 8];
     loss[0] = total;
 }
 
@@ -626,8 +664,9 @@ hipError_t launch_loss(const double* I, int D, int nl, int F, int B, int kind, d
     double* phi = E + (int64_t)D * B;
     double* coef = phi + (int64_t)D * F;
     hipLaunchKernelGGL(k_loss_eta, dim3((unsigned)((int64_t)D * nl * F)), dim3(256), 0, s, I, B, eta);
-    hipLaunchKernelGGL(k_loss_eyeb, dim3(grid_for((int64_t)D * B, 256, 1 << 30)), dim3(256), 0, s, I, D, nl * F, B, E);
-    hipLaunchKernelGGL(k_loss_scalar, dim3(1), dim3(64), 0, s, eta, E, D, nl, F, B, kind, w_f, w_e, phi, coef, loss);
+    hipLaunchKernelGGL(k_loss_eyeb, dim3((unsigned)((int64_t)D * ((B + 63) / 64))), dim3(1024), 0, s, I, D, nl * F, B, E);
+    hipLaunchKernelGGL(k_loss_scalar, dim3((unsigned)D), dim3(256), 0, s, eta, E, nl, F, B, kind, w_f, w_e, phi, coef);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, (const double*)coef, D, loss);
     if (G) hipLaunchKernelGGL(k_loss_grad, dim3(grid_for((int64_t)D * nl * F * B, 256)), dim3(256), 0, s, E, phi, coef, D, nl, F, B, G);
     return hipGetLastError();
 }
