@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             TapeRef none = { nullptr, 0 };
             int nh = 0;
             double gscale = 0.0;
-            const int own = lane * sc.Kmax;      // this lane's slots of the hit queue
+            const int own = lane;                // this lane's column of the hit queue
             if (active) {
                 ray_birth(sc, *pl, id, r);
                 if constexpr (TAB)

@@ -57,12 +57,11 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
                             mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
 }
 
-// The wave's hit queue keeps each ray's hits in its lane's own slots,
-// lane * kmax + h.  Dense hit p (the wave's hits in ray order) belongs to the
-// largest lane whose exclusive prefix sum of hit counts (off) is <= p: lanes
-// without hits share the next lane's offset and lose the search to it.
-// Called by all lanes of the wave (shuffles).
-__device__ inline int dense_slot(int p, int off, int kmax)
+// Dense hit p (the wave's hits in ray order) belongs to the largest lane
+// whose exclusive prefix sum of hit counts (off) is <= p: lanes without hits
+// share the next lane's offset and lose the search to it.  Returns its queue
+// slot.  Called by all lanes of the wave (shuffles).
+__device__ inline int dense_slot(int p, int off, int)
 {
     int l = 0;
 #pragma unroll
@@ -70,7 +69,7 @@ __device__ inline int dense_slot(int p, int off, int kmax)
         const int c = l + step;
         if (__shfl(off, c, 64) <= p) l = c;
     }
-    return l * kmax + (p - __shfl(off, l, 64));
+    return hq_slot(l, p - __shfl(off, l, 64));
 }
 
 // Solve the wave's `total` queued hits in batches of 64 (one per lane);
@@ -241,7 +240,7 @@ struct NoCoef {
 struct PutHit {
     HitQueue q;
     int off;
-    __device__ void operator()(int h, double kappa, int meta) const { q.put(off + h, kappa, meta); }
+    __device__ void operator()(int h, double kappa, int meta) const { q.put(hq_slot(off, h), kappa, meta); }
     __device__ void branch(int, bool) const {}
 };
 // Coefficients of the ray's hit h: from its queue entry, or (mc set) from
@@ -252,8 +251,8 @@ struct GetCoef {
     const double* mc;
     __device__ Coef4 operator()(int h, double, double, double, int, bool) const
     {
-        if (!mc) return q.coef(off + h);
-        const double* b = mc + (int)q.base[2 * q.cap + off + h];
+        if (!mc) return q.coef(hq_slot(off, h));
+        const double* b = mc + (int)q.base[2 * q.cap + hq_slot(off, h)];
         Coef4 c;
         c.rs = mk(b[0], b[kFwdMemoKeys]); c.rp = mk(b[2 * kFwdMemoKeys], b[3 * kFwdMemoKeys]);
         c.ts = mk(b[4 * kFwdMemoKeys], b[5 * kFwdMemoKeys]); c.tp = mk(b[6 * kFwdMemoKeys], b[7 * kFwdMemoKeys]);
@@ -334,7 +333,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             // geometry walk: the hits go to this lane's slots of the queue
             // (the angle table needs no queue: the walk only finds the rays
             // bound for the eyebox, whose fields the adjoint tapes)
-            const int own = lane * sc.Kmax;
+            const int own = lane;                          // this lane's column of the hit queue
             if (active && (!tabm || ADJ)) {
                 ray_birth(sc, *pl, id, r);
                 if (tabm)
@@ -358,7 +357,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                         const int64_t k = n_ent + eoff + (nh - 1 - h);
                         double c = -1.0;
                         if (to_eyebox && k < st.ck_cap) c = (double)((item * st.waves + wave) * st.ck_cap + k);
-                        hq.base[10 * (int64_t)cap + own + h] = c;
+                        hq.base[10 * (int64_t)cap + hq_slot(own, h)] = c;
                     }
                 }
                 __threadfence_block();

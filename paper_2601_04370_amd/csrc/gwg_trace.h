@@ -261,6 +261,11 @@ __device__ inline int wave_excl_scan(int x, int* total)
 // kappa and meta (mirror | front << 8), after the solve its four
 // coefficients, and (field 10) the checkpoint slot of its adjoint entry or
 // -1.  Field f of entry p at base[f * cap + p].
+// A wave's hit queue holds up to Kmax hits per lane; hit h of lane l is in
+// slot h * 64 + l, so the lanes' h-th hits share 512 contiguous bytes per
+// field (the walks touch the lanes' hits in step).
+__device__ inline int hq_slot(int lane, int h) { return h * 64 + lane; }
+
 struct HitQueue {
     double* base;
     int cap;
