@@ -77,6 +77,9 @@ __device__ inline void stage_point(const SceneDev& sc, int d, int l, int f, Poin
             pl->thr[m] = sc.thr[m];
             pl->nlay[m] = sc.nlay[(int64_t)d * sc.M + m];
         }
+        pl->T = sc.T; pl->Lx = sc.Lx; pl->nx = sc.nx; pl->nz = sc.nz; pl->ER = sc.ER;
+        pl->ex0 = sc.ex0; pl->ew = sc.ew; pl->ey0 = sc.ey0; pl->eh = sc.eh;
+        pl->M = sc.M; pl->Kmax = sc.Kmax; pl->bins_x = sc.bins_x; pl->bins_y = sc.bins_y;
     }
     const int n = sc.M * sc.Lmax;
     const double* gthk = sc.thk + (int64_t)d * n;

@@ -37,6 +37,10 @@ struct PointLds {
     double h[kMaxMirrors], sc_r[kMaxMirrors], sc_t[kMaxMirrors];
     uint32_t thr[kMaxMirrors];
     int32_t nlay[kMaxMirrors];
+    // the walk's scene constants, read from LDS where they are used rather
+    // than held in scalar registers across the walk
+    double T, Lx, nx, nz, ER, ex0, ew, ey0, eh;
+    int32_t M, Kmax, bins_x, bins_y;
 };
 
 __device__ inline void cross3(double ax, double ay, double az, double bx, double by, double bz,
@@ -137,15 +141,15 @@ __device__ inline int next_surface(const SceneDev& sc, const PointLds& pl, Ray& 
     double best = 0.0;
     int hit = -1;
     if (r.dz > 0.0 && r.last != SURF_TOP) {
-        double t = (sc.T - r.pz) / r.dz;
+        double t = (pl.T - r.pz) / r.dz;
         if (hit < 0 || t < best) { best = t; hit = SURF_TOP; }
     }
     if (r.dz < 0.0 && r.last != SURF_BOTTOM) {
         double t = (0.0 - r.pz) / r.dz;
         if (hit < 0 || t < best) { best = t; hit = SURF_BOTTOM; }
     }
-    double dn = sc.nx * r.dx + sc.nz * r.dz;
-    double pn = sc.nx * r.px + sc.nz * r.pz;
+    double dn = pl.nx * r.dx + pl.nz * r.dz;
+    double pn = pl.nx * r.px + pl.nz * r.pz;
     if (r.cell == 0) {
         if (r.dx < 0.0 && r.last != SURF_END0) {
             double t = (0.0 - r.px) / r.dx;
@@ -158,9 +162,9 @@ __device__ inline int next_surface(const SceneDev& sc, const PointLds& pl, Ray& 
             if (hit < 0 || t < best) { best = t; hit = m; }
         }
     }
-    if (r.cell == sc.M) {
+    if (r.cell == pl.M) {
         if (r.dx > 0.0 && r.last != SURF_END1) {
-            double t = (sc.Lx - r.px) / r.dx;
+            double t = (pl.Lx - r.px) / r.dx;
             if (hit < 0 || t < best) { best = t; hit = SURF_END1; }
         }
     } else {
@@ -174,10 +178,10 @@ __device__ inline int next_surface(const SceneDev& sc, const PointLds& pl, Ray& 
     r.px = r.px + best * r.dx;
     r.py = r.py + best * r.dy;
     r.pz = r.pz + best * r.dz;
-    if (hit == SURF_TOP) r.pz = sc.T;
+    if (hit == SURF_TOP) r.pz = pl.T;
     if (hit == SURF_BOTTOM) r.pz = 0.0;
     if (hit == SURF_END0) r.px = 0.0;
-    if (hit == SURF_END1) r.px = sc.Lx;
+    if (hit == SURF_END1) r.px = pl.Lx;
     return hit;
 }
 
@@ -204,15 +208,15 @@ __device__ inline FaceCoef face_coeffs(double ng, double na, double dx, double d
 }
 
 // Eyebox bin of a ray leaving the top face at (px, py) along air direction a.
-__device__ inline int eyebox_bin(const SceneDev& sc, double px, double py, const double* a)
+__device__ inline int eyebox_bin(const SceneDev& sc, const PointLds& pl, double px, double py, const double* a)
 {
-    double xe = px + sc.ER * (a[0] / a[2]);
-    double ye = py + sc.ER * (a[1] / a[2]);
-    double fx = ((xe - sc.ex0) / sc.ew) * (double)sc.bins_x;
-    double fy = ((ye - sc.ey0) / sc.eh) * (double)sc.bins_y;
-    if (!(fx >= 0.0 && fx < (double)sc.bins_x && fy >= 0.0 && fy < (double)sc.bins_y)) return -1;
+    double xe = px + pl.ER * (a[0] / a[2]);
+    double ye = py + pl.ER * (a[1] / a[2]);
+    double fx = ((xe - pl.ex0) / pl.ew) * (double)pl.bins_x;
+    double fy = ((ye - pl.ey0) / pl.eh) * (double)pl.bins_y;
+    if (!(fx >= 0.0 && fx < (double)pl.bins_x && fy >= 0.0 && fy < (double)pl.bins_y)) return -1;
     int bx = (int)fx, by = (int)fy;
-    return by * sc.bins_x + bx;
+    return by * pl.bins_x + bx;
 }
 
 __device__ inline void exit_direction(double ng, double na, const Ray& r, double st2, double* a)
@@ -326,9 +330,9 @@ template <bool FIELD, bool TAPE, class OnHit, class GetCoef>
 __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, Outcome& o,
                                 OnHit on_hit, GetCoef get_coef, TapeRef tape, int* ntape)
 {
-    const double nx = sc.nx, nz = sc.nz;
+    const double nx = pl.nx, nz = pl.nz;
     for (;;) {
-        if (r.nev >= sc.Kmax) {
+        if (r.nev >= pl.Kmax) {
             o.cat = CAT_TRUNC; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
             return;
         }
@@ -368,7 +372,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
                     o.w = norm2(r.e);
                 }
                 r.dx = a[0]; r.dy = a[1]; r.dz = a[2];
-                o.bin = eyebox_bin(sc, r.px, r.py, a);
+                o.bin = eyebox_bin(sc, pl, r.px, r.py, a);
                 o.cat = o.bin >= 0 ? CAT_EYEBOX : CAT_MISS;
                 return;
             }
@@ -445,10 +449,10 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
         const int front = (meta >> 12) & 1, refl = (meta >> 13) & 1;
         double sv[3], pin[3], pout[3];
         if (type == EV_MIRROR) {
-            s_basis(dx, dy, dz, sc.nx, 0.0, sc.nz, sv);
+            s_basis(dx, dy, dz, pl.nx, 0.0, pl.nz, sv);
             cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
             double ndx = dx, ndz = dz;
-            if (refl) mirror_reflect(sc.nx, sc.nz, dx, dz, &ndx, &ndz);
+            if (refl) mirror_reflect(pl.nx, pl.nz, dx, dz, &ndx, &ndz);
             cross3(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
             cd E[3];
             for (int c = 0; c < 3; ++c) E[c] = mk(b[(3 + 2 * c) * ts], b[(4 + 2 * c) * ts]);
@@ -459,7 +463,7 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
             const cd Gs = cscale(cmul(cconj(ls), es), scale);
             const cd Gp = cscale(cmul(cconj(lp), ep), scale);
             double c3[3];
-            cross3(dx, dy, dz, sc.nx, 0.0, sc.nz, c3);
+            cross3(dx, dy, dz, pl.nx, 0.0, pl.nz, c3);
             const double kappa = pl.ng * sqrt(c3[0] * c3[0] + c3[1] * c3[1] + c3[2] * c3[2]);
             emit(kappa, Gs, Gp, m | (front << 8) | (refl << 9));
         } else {
