@@ -308,7 +308,7 @@ int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t 
  * else 1..64): with GWG_FWD_GRAD at FP64 on lossless stacks, the forward
  * solve keeps the adjoint's sweep checkpoints (8 doubles every 16 layers)
  * for up to this many entries per ray of each entry region, within a memory
- * budget (the smaller of 48 GiB and half the free memory), so the backward
+ * budget (the smaller of 128 GiB and half the free memory), so the backward
  * skips that sweep for them; the gradient is the same bit for bit. */
 typedef struct {
     int32_t block_threads;

@@ -74,7 +74,7 @@ struct KernelTimer {
 // Adjoint entry capacity: entries per ray of a (work item, wave) region, and
 // the most device memory the entries may take.
 constexpr int64_t kAdjEntriesPerRay = 8;
-constexpr double kAdjBudgetBytes = 32.0 * 1024 * 1024 * 1024;
+constexpr double kAdjBudgetBytes = 96.0 * 1024 * 1024 * 1024;
 
 struct gwg_ctx {
     int device = -1;
@@ -431,11 +431,11 @@ void set_tiles(SceneDev& s, int64_t rays_per_tile, int wg, int n_cu)
     const int64_t points = (int64_t)s.D * s.n_lsel * s.F;
     int64_t rpt = rays_per_tile;
     if (rpt <= 0) {
-        // Whole points while there are at least ~16 per CU (about 8 rounds
-        // of two resident workgroups per CU, so the last, partly filled
-        // round costs little); otherwise split every point into equal tiles
-        // of at least 4 rays per lane.
-        const int64_t target = (int64_t)std::max(n_cu, 1) * 16;
+        // Whole points while there are at least ~32 per CU (about 16 items
+        // per resident workgroup at two per CU, so the launch's tail, at
+        // most about one item, costs little); otherwise split every point
+        // into equal tiles of at least 4 rays per lane.
+        const int64_t target = (int64_t)std::max(n_cu, 1) * 32;
         const int64_t tiles = points >= target ? 1 : (target + points - 1) / points;
         rpt = (s.N + tiles - 1) / tiles;
         rpt = std::max<int64_t>(rpt, (int64_t)wg * 4);
@@ -744,8 +744,9 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
             if (precision == GWG_FP64 && !(flags & GWG_FWD_MEMO) && sc.slot_complex == 0u && ck_per > 0) {
                 const int64_t blocks = ck_blocks(sc.Lmax);
                 const int64_t rays_w = (sc.rays_per_tile + wg - 1) / wg * 64;
-                for (int64_t per = ck_per; per >= 1; --per) {
-                    const int64_t ck_cap = std::min<int64_t>(cap_w, rays_w * per);
+                // in quarter entries per ray, down to a quarter
+                for (int64_t per4 = 4 * ck_per; per4 >= 1; --per4) {
+                    const int64_t ck_cap = std::min<int64_t>(cap_w, rays_w * per4 / 4);
                     const int64_t ck_total = sc.n_items * waves * ck_cap;
                     const size_t ck_b = sizeof(double) * 8 * (size_t)blocks * (size_t)ck_total;
                     bool ok;

@@ -59,7 +59,7 @@ constexpr int kEntFields = 6;
 constexpr int kFwdMemoKeys = 128;      // largest key table per wave of the memoized forward
 constexpr int kTableNodesDefault = 8192;
 constexpr int kCkEntriesPerRay = 4;        // sweep checkpoints kept per ray (entry regions)
-constexpr double kCkBudgetBytes = 48.0 * (1ull << 30);
+constexpr double kCkBudgetBytes = 128.0 * (1ull << 30);
 constexpr int kTableNodesMax = 1 << 20;
 struct AdjStore {
     double* ent;
