@@ -256,7 +256,8 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     //    then whole groups of K layers, each ending in a checkpoint (group 0
     //    in none: v_0 stays in registers).  stored: the forward solve ran
     //    this sweep and left v_0 in block 0 and the checkpoints in blocks
-    //    1.. of chk (64-byte blocks, cstride 1), with the same arithmetic.
+    //    1.. (64-byte blocks, block g at chk + g cstride), with the same
+    //    arithmetic.
     if (L <= 0) return;
     constexpr int K = kSegL;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
@@ -274,7 +275,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
         c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
         c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
     };
-    // a stored block is 64 contiguous bytes (cstride 1), read whole
+    // a stored block is 64 contiguous bytes, read whole
     auto read_block = [&](const double* c, V2d& a, V2d& b) {
         const double2* p = (const double2*)c;
         const double2 x0 = p[0], x1 = p[1], x2 = p[2], x3 = p[3];
@@ -308,7 +309,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     const double k2 = 2.0 * k0;
     V2d ws = vs, wp = vp, nws = vs, nwp = vp;
     auto load_chk = [&](int k) {
-        const double* c = chk + (int64_t)k * 8 * cstride;
+        const double* c = chk + (int64_t)k * (stored ? cstride : 8 * cstride);
         if (stored) {
             read_block(c, nws, nwp);
         } else {

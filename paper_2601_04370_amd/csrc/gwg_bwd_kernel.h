@@ -316,9 +316,9 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
                     const int mm = (int)(meta & 1023);
                     // the forward stored this entry's sweep (lossless FP64 stacks)
                     const bool stored = LOSSLESS && st.ck && k < st.ck_cap;
-                    double* c = stored ? st.ck + ((item * st.waves + rr) * st.ck_cap + k) * ck_blocks(sc.Lmax) * 8 : chk;
+                    double* c = stored ? st.ck + ((item * st.waves + rr) * st.ck_cap + k) * 8 : chk;
                     adjoint_hit<LOSSLESS>(sc, *pl, s_thk, s_slot, sl, gw, kappa, Gs, Gp, mm, c,
-                                          stored ? 1 : nthreads, stored);
+                                          stored ? 8 * st.ck_total : nthreads, stored);
                     c_ahits += 1;
                     c_alay += (unsigned long long)pl->nlay[mm & 255];
                     if (stored) c_astored += (unsigned long long)pl->nlay[mm & 255];

@@ -489,13 +489,13 @@ template <typename T, bool HC, class SL>
 __device__ __attribute__((always_inline)) inline void lossless_sweep(const double* __restrict__ thk,
                                                                      const uint8_t* __restrict__ slot, int L,
                                                                      bool front, const SL& sl, V2<T>& vs, V2<T>& vp,
-                                                                     int& es, int& ep, double* ck)
+                                                                     int& es, int& ep, double* ck, int64_t ckb)
 {
     // ck (T = double only): the adjoint's sweep checkpoints v_{g kSegL}
     // (incidence-order layer g kSegL and below) go to the 64-byte block g at
-    // ck + 8 g, whole; v_0 goes to block 0 after the loop.
+    // ck + g ckb, whole; v_0 goes to block 0 after the loop.
     auto store = [&](int g) {
-        double2* c = (double2*)(ck + (int64_t)g * 8);
+        double2* c = (double2*)(ck + (int64_t)g * ckb);
         c[0] = make_double2((double)vs.br, (double)vs.bi);
         c[1] = make_double2((double)vs.cr, (double)vs.ci);
         c[2] = make_double2((double)vp.br, (double)vp.bi);
@@ -539,12 +539,13 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(const doubl
 // and rounded to the chain precision T once per layer.  circ: no lane of the
 // calling wave has an evanescent lossless slot (the sweep then skips the
 // hyperbolic case; the results are the same).  ck (lossless FP64 stacks):
-// the entry's checkpoint blocks for the adjoint's sweep, or null.
+// the entry's checkpoint blocks for the adjoint's sweep (block g at ck + g
+// ckb), or null.
 template <typename T, class SL>
 __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t* __restrict__ slot, int L,
                                   bool front, const SL& sl, uint32_t cplx_mask, double k0d, double eta0s,
                                   double eta0p, cd etaEs, cd etaEp, cd tp_factor, bool circ = false,
-                                  double* ck = nullptr)
+                                  double* ck = nullptr, int64_t ckb = 8)
 {
     const T k0 = (T)k0d;
     V2<T> vs = { (T)1, (T)0, (T)etaEs.re, (T)etaEs.im };
@@ -555,9 +556,9 @@ __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* _
     int idx = front ? L - 1 : 0;
     if (cplx_mask == 0u) {
         if (circ)
-            lossless_sweep<T, false>(thk, slot, L, front, sl, vs, vp, es, ep, ck);
+            lossless_sweep<T, false>(thk, slot, L, front, sl, vs, vp, es, ep, ck, ckb);
         else
-            lossless_sweep<T, true>(thk, slot, L, front, sl, vs, vp, es, ep, ck);
+            lossless_sweep<T, true>(thk, slot, L, front, sl, vs, vp, es, ep, ck, ckb);
         return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
     }
     for (int j = 0; j < L; ++j, idx += dir) {

@@ -32,7 +32,7 @@
 template <int MODE>
 __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
                                   const uint8_t* s_slot, const LaneSlots3& sl, int m, bool front, double kappa,
-                                  bool* used_fp64, double* ck = nullptr)
+                                  bool* used_fp64, double* ck = nullptr, int64_t ckb = 8)
 {
     bool hyp = false;                       // an evanescent lossless slot at this kappa
     for (int s = 0; s < sc.n_slots; ++s) {
@@ -52,7 +52,8 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
     *used_fp64 = fp64;
     if (fp64)
         return tmm_solve<double>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
-                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ, MODE == GWG_FP64 ? ck : nullptr);
+                                 mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ, MODE == GWG_FP64 ? ck : nullptr,
+                                 ckb);
     return tmm_solve<float>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                             mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
 }
@@ -80,7 +81,7 @@ template <int MODE>
 __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
                                   const uint8_t* s_slot, const LaneSlots3& sl, const HitQueue& hq, int total,
                                   int off, unsigned long long* n_fp64, unsigned long long* n_lay,
-                                  double* ck = nullptr)
+                                  double* ck = nullptr, int64_t ck_total = 0)
 {
     const int lane = wave_lane();
     for (int b = 0; b < total; b += 64) {
@@ -94,9 +95,10 @@ __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const 
             double* ckp = nullptr;
             if (ck) {
                 const double c = hq.base[10 * (int64_t)hq.cap + q];
-                if (c >= 0.0) ckp = ck + (int64_t)c * ck_blocks(sc.Lmax) * 8;
+                if (c >= 0.0) ckp = ck + (int64_t)c * 8;
             }
-            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64, ckp);
+            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64, ckp,
+                                            8 * ck_total);
             hq.put_coef(q, c);
             *n_fp64 += u64 ? 1ull : 0ull;
             *n_lay += (unsigned long long)pl.nlay[m];
@@ -230,6 +232,8 @@ struct NoHit {
     __device__ void branch(int, bool) const {}
 };
 struct NoCoef {
+    static constexpr bool kStoredBranch = false;
+    __device__ bool refl(int) const { return false; }
     __device__ Coef4 operator()(int, double, double, double, int, bool) const
     {
         Coef4 c;
@@ -249,6 +253,8 @@ struct GetCoef {
     HitQueue q;
     int off;
     const double* mc;
+    static constexpr bool kStoredBranch = true;   // the geometry walk stored the branch in the meta word
+    __device__ bool refl(int h) const { return (((int)q.base[q.cap + hq_slot(off, h)]) >> 9) & 1; }
     __device__ Coef4 operator()(int h, double, double, double, int, bool) const
     {
         if (!mc) return q.coef(hq_slot(off, h));
@@ -367,7 +373,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
                 else
                     solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, off, &n_fp64, &n_lay,
-                                     cks ? st.ck : nullptr);
+                                     cks ? st.ck : nullptr, st.ck_total);
                 __threadfence_block();
             }
             int nt = 0;

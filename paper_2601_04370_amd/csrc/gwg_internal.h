@@ -70,9 +70,11 @@ struct AdjStore {
     int32_t waves;
     // Sweep checkpoints of the first ck_cap entries of every region, stored
     // by the FP64 forward solve (null: the adjoint recomputes them).  Entry
-    // slot c (c = region * ck_cap + k) owns ck_blocks(Lmax) contiguous blocks
-    // of 8 doubles (64 bytes, written and read whole): field f of block g at
-    // ck[(c * ck_blocks + g) * 8 + f]; g = 0 holds v_0, g >= 1 v_{g kSegL}.
+    // slot c (c = region * ck_cap + k) owns ck_blocks(Lmax) blocks of 8
+    // doubles (64 bytes, written and read whole), block-major so that the
+    // consecutive entries a wave solves or adjoins share lines: field f of
+    // block g at ck[(g * ck_total + c) * 8 + f]; g = 0 holds v_0, g >= 1
+    // v_{g kSegL}.
     double* ck;
     int64_t ck_cap;
     int64_t ck_total;

@@ -84,6 +84,8 @@ struct TabCoef {
     const double* tab;
     int tn;
     double ng, nx, nz;
+    static constexpr bool kStoredBranch = false;
+    __device__ bool refl(int) const { return false; }
     __device__ Coef4 operator()(int, double dx, double dy, double dz, int m, bool front) const
     {
         double c3[3];

@@ -318,14 +318,19 @@ struct Outcome { int cat; int bin; double w; double w_in; };
 
 // Walk one ray (already born) from its current state to termination.
 // FIELD = false: geometry and branch decisions only; every mirror hit h calls
-//   on_hit(h, kappa, meta) and, once the branch is drawn, on_hit.branch(m, refl).
+//   on_hit(h, kappa, meta) once its branch is drawn (meta = mirror | front
+//   << 8 | reflected << 9) and on_hit.branch(m, refl).
 // FIELD = true: also the polarization field (Eq. 5 at every event, Eq. 6 at
 //   mirrors); mirror hit h takes its coefficients from
-//   get_coef(h, direction, mirror, front); with
-//   TAPE and a non-null tape, field-changing events are recorded for the
-//   adjoint.
+//   get_coef(h, direction, mirror, front) and, where GetCoef::kStoredBranch,
+//   its branch from get_coef.refl(h) (the decision the geometry walk drew and
+//   stored) instead of drawing it again; with TAPE and a non-null tape,
+//   field-changing events are recorded for the adjoint.
 // Both modes perform the same geometric operations, so they visit the same
-// surfaces and take the same branches.
+// surfaces and take the same branches.  A total internal reflection and a
+// mirror hit update the field with the same code (basis about the surface
+// normal, Eq. 5 with the event's coefficients), so a wave whose lanes meet
+// both runs it once.
 template <bool FIELD, bool TAPE, class OnHit, class GetCoef>
 __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, Outcome& o,
                                 OnHit on_hit, GetCoef get_coef, TapeRef tape, int* ntape)
@@ -342,86 +347,98 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
             return;
         }
         r.nev++;
+        // the event's field update: coefficients, scale, surface normal
+        // (bnx, 0, bnz) and the direction after it
+        cd cs = mk(0.0, 0.0), cp = mk(0.0, 0.0);
+        double scale = 1.0, bnx = 0.0, bnz = 1.0;
+        double ndx = r.dx, ndz = r.dz;
+        int ev = EV_TIR, m = 0, front = 0, refl = 0;
         if (s == SURF_TOP || s == SURF_BOTTOM) {
             FaceCoef fc = face_coeffs(pl.ng, pl.na, r.dx, r.dy, r.dz);
-            double sv[3], pin[3], pout[3];
-            if (FIELD) {
-                s_basis(r.dx, r.dy, r.dz, 0.0, 0.0, 1.0, sv);
-                cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
-            }
-            if (fc.tir) {
-                if (FIELD) {
-                    cross3(r.dx, r.dy, -r.dz, sv[0], sv[1], sv[2], pout);
-                    if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, fc.rs, fc.rp, 1.0, EV_TIR, 0, 0, 0);
-                    apply_sp(r.e, sv, pin, pout, fc.rs, fc.rp, 1.0);
+            if (!fc.tir) {
+                if (s == SURF_TOP) {
+                    double sv[3], pin[3], pout[3];
+                    double a[3];
+                    exit_direction(pl.ng, pl.na, r, fc.st2, a);
+                    o.w_in = 0.0;
+                    o.w = 0.0;
+                    if (FIELD) {
+                        s_basis(r.dx, r.dy, r.dz, 0.0, 0.0, 1.0, sv);
+                        cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
+                        cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
+                        o.w_in = norm2(r.e);
+                        if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, fc.ts, fc.tp, fc.flux, EV_EXIT, 0, 0, 0);
+                        apply_sp(r.e, sv, pin, pout, fc.ts, fc.tp, fc.flux);
+                        o.w = norm2(r.e);
+                    }
+                    r.dx = a[0]; r.dy = a[1]; r.dz = a[2];
+                    o.bin = eyebox_bin(sc, pl, r.px, r.py, a);
+                    o.cat = o.bin >= 0 ? CAT_EYEBOX : CAT_MISS;
+                    return;
                 }
-                r.dz = -r.dz;
-                r.last = s;
-                continue;
-            }
-            if (s == SURF_TOP) {
-                double a[3];
-                exit_direction(pl.ng, pl.na, r, fc.st2, a);
-                o.w_in = 0.0;
-                o.w = 0.0;
-                if (FIELD) {
-                    cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
-                    o.w_in = norm2(r.e);
-                    if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, fc.ts, fc.tp, fc.flux, EV_EXIT, 0, 0, 0);
-                    apply_sp(r.e, sv, pin, pout, fc.ts, fc.tp, fc.flux);
-                    o.w = norm2(r.e);
-                }
-                r.dx = a[0]; r.dy = a[1]; r.dz = a[2];
-                o.bin = eyebox_bin(sc, pl, r.px, r.py, a);
-                o.cat = o.bin >= 0 ? CAT_EYEBOX : CAT_MISS;
+                o.cat = CAT_LEAK; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
                 return;
             }
-            o.cat = CAT_LEAK; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
-            return;
-        }
-        if (s == SURF_END0 || s == SURF_END1) {
+            // total internal reflection at a face
+            cs = fc.rs; cp = fc.rp;
+            ndz = -r.dz;
+        } else if (s == SURF_END0 || s == SURF_END1) {
             o.cat = CAT_END; o.bin = -1; o.w = FIELD ? norm2(r.e) : 0.0; o.w_in = o.w;
             return;
+        } else {
+            // mirror hit
+            m = s;
+            const double dn = nx * r.dx + nz * r.dz;
+            front = dn < 0.0 ? 1 : 0;
+            const int h = r.nprma;
+            bool rf;
+            if constexpr (FIELD && GetCoef::kStoredBranch) {
+                rf = get_coef.refl(h);
+            } else {
+                if ((h & 3) == 0) {
+                    u32x4 w = philox10((uint32_t)(uint64_t)r.id, (uint32_t)((uint64_t)r.id >> 32), (uint32_t)(h >> 2),
+                                       1u, sc.key0, r.key1);
+                    r.w4[0] = w.x; r.w4[1] = w.y; r.w4[2] = w.z; r.w4[3] = w.w;
+                }
+                const int hw = h & 3;
+                const uint32_t word = hw == 0 ? r.w4[0] : hw == 1 ? r.w4[1] : hw == 2 ? r.w4[2] : r.w4[3];
+                rf = word < pl.thr[m];
+            }
+            refl = rf ? 1 : 0;
+            if (!FIELD) {
+                double c[3];
+                cross3(r.dx, r.dy, r.dz, nx, 0.0, nz, c);
+                double kappa = pl.ng * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+                on_hit(h, kappa, m | (front << 8) | (refl << 9));
+                on_hit.branch(m, rf);
+            }
+            if (rf) mirror_reflect(nx, nz, r.dx, r.dz, &ndx, &ndz);
+            if (FIELD) {
+                const Coef4 co = get_coef(h, r.dx, r.dy, r.dz, m, front != 0);
+                cs = rf ? co.rs : co.ts;
+                cp = rf ? co.rp : co.tp;
+                scale = rf ? pl.sc_r[m] : pl.sc_t[m];
+            }
+            bnx = nx; bnz = nz;
+            ev = EV_MIRROR;
         }
-        // mirror hit
-        const int m = s;
-        const double dn = nx * r.dx + nz * r.dz;
-        const bool front = dn < 0.0;
-        const int h = r.nprma;
-        if (!FIELD) {
-            double c[3];
-            cross3(r.dx, r.dy, r.dz, nx, 0.0, nz, c);
-            double kappa = pl.ng * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-            on_hit(h, kappa, m | ((front ? 1 : 0) << 8));
-        }
-        if ((h & 3) == 0) {
-            u32x4 w = philox10((uint32_t)(uint64_t)r.id, (uint32_t)((uint64_t)r.id >> 32), (uint32_t)(h >> 2), 1u,
-                               sc.key0, r.key1);
-            r.w4[0] = w.x; r.w4[1] = w.y; r.w4[2] = w.z; r.w4[3] = w.w;
-        }
-        const int hw = h & 3;
-        const uint32_t word = hw == 0 ? r.w4[0] : hw == 1 ? r.w4[1] : hw == 2 ? r.w4[2] : r.w4[3];
-        const bool refl = word < pl.thr[m];
-        if (!FIELD) on_hit.branch(m, refl);
-        double ndx = r.dx, ndz = r.dz;
-        if (refl) mirror_reflect(nx, nz, r.dx, r.dz, &ndx, &ndz);
         if (FIELD) {
-            const Coef4 co = get_coef(h, r.dx, r.dy, r.dz, m, front);
             double sv[3], pin[3], pout[3];
-            s_basis(r.dx, r.dy, r.dz, nx, 0.0, nz, sv);
+            s_basis(r.dx, r.dy, r.dz, bnx, 0.0, bnz, sv);
             cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
             cross3(ndx, r.dy, ndz, sv[0], sv[1], sv[2], pout);
-            const cd cs = refl ? co.rs : co.ts;
-            const cd cp = refl ? co.rp : co.tp;
-            const double scale = refl ? pl.sc_r[m] : pl.sc_t[m];
-            if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, cs, cp, scale, EV_MIRROR, m, front ? 1 : 0, refl ? 1 : 0);
+            if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, cs, cp, scale, ev, m, front, refl);
             apply_sp(r.e, sv, pin, pout, cs, cp, scale);
         }
         r.dx = ndx;
         r.dz = ndz;
-        if (!refl) r.cell += (m == r.cell) ? 1 : -1;
-        r.last = m;
-        r.nprma++;
+        if (ev == EV_MIRROR) {
+            if (!refl) r.cell += (m == r.cell) ? 1 : -1;
+            r.last = m;
+            r.nprma++;
+        } else {
+            r.last = s;
+        }
     }
 }
 
