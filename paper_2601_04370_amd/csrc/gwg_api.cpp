@@ -94,7 +94,7 @@ struct gwg_ctx {
     bool have_forward = false;
     SceneDev fwd{};
     // adjoint entries recorded by the last forward (GWG_FWD_GRAD)
-    DevBuf adj_ent, adj_cnt, adj_ovf, fwd_tape, adj_ck;
+    DevBuf adj_ent, adj_cnt, adj_ovf, fwd_tape, adj_ck, adj_order;
     bool adj_valid = false;
     bool memo = false;           // thin-film adjoints per distinct hit key (GWG_FWD_MEMO)
     AdjStore adj{};
@@ -504,7 +504,7 @@ int gwg_destroy(gwg_ctx* c)
         for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape,
                            &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad,
-                           &c->adj_ck, &c->grad_tmp })
+                           &c->adj_ck, &c->grad_tmp, &c->adj_order })
             b->release();
         for (KernelTimer& t : c->timer) t.destroy();
     }
@@ -735,7 +735,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
             if (rc) return rc;
             HIP_CHECK(c, launch_fill_u32((uint32_t*)c->adj_ovf.p, sc.n_items, 0u, s), "zero overflow flags");
             c->adj = AdjStore{ (double*)c->adj_ent.p, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, cap_w, total, waves,
-                               nullptr, 0, 0 };
+                               nullptr, 0, 0, nullptr };
             adj = true;
             // The FP64 solve can keep the adjoint's sweep checkpoints of the
             // first ck_cap entries of every region (kCkEntriesPerRay per ray,
@@ -773,7 +773,7 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
             if (rc) return rc;
             rc = ensure_buf(c, c->adj_ovf, ovf_b, cap, "alloc overflow flags");
             if (rc) return rc;
-            c->adj = AdjStore{ nullptr, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, 0, 0, waves, nullptr, 0, 0 };
+            c->adj = AdjStore{ nullptr, (int32_t*)c->adj_cnt.p, (int32_t*)c->adj_ovf.p, 0, 0, waves, nullptr, 0, 0, nullptr };
         }
         adj_sweep = adj || table;
     }
@@ -901,10 +901,18 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
         HIP_CHECK(c, launch_adj_memo(sc, (int)grid_m, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
                                      c->adj, (double*)c->scratch.p, s),
                   "memoized adjoint kernel");
-    else if (entries)
+    else if (entries) {
+        // the entry kernel takes items largest first (entry counts from the
+        // forward), so its workgroups finish together
+        rc = ensure_buf(c, c->adj_order, sizeof(int32_t) * (size_t)sc.n_items, cap, "alloc item order");
+        if (rc) return rc;
+        AdjStore st = c->adj;
+        st.order = (const int32_t*)c->adj_order.p;
+        HIP_CHECK(c, launch_item_order(st, sc.n_items, (int32_t*)c->adj_order.p, s), "item order");
         HIP_CHECK(c, launch_adj_entries(sc, wg, (int)grid_e, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
-                                        c->adj, (double*)c->scratch.p, s),
+                                        st, (double*)c->scratch.p, s),
                   "adjoint entry kernel");
+    }
     HIP_CHECK(c, launch_trace_bwd(sc, wg, (int)grid, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
                                   (double*)c->scratch.p, sample_stride, entries ? c->adj.ovf : nullptr, s),
               "adjoint kernel");

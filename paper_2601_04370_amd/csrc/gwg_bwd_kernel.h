@@ -288,7 +288,8 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long c_ahits = 0, c_alay = 0, c_astored = 0;
 
-    for (int64_t item = draw_item(stats + ST_NEXT0); item < sc.n_items; item = draw_item(stats + ST_NEXT0)) {
+    for (int64_t it = draw_item(stats + ST_NEXT0); it < sc.n_items; it = draw_item(stats + ST_NEXT0)) {
+        const int64_t item = st.order ? (int64_t)st.order[it] : it;
         if (st.ovf[item] != 0) continue;
         int64_t point, i0, i1;
         int d, l, f;

@@ -78,6 +78,9 @@ struct AdjStore {
     double* ck;
     int64_t ck_cap;
     int64_t ck_total;
+    // Order in which the entry kernel takes items (null: item order); set by
+    // the backward, largest entry regions first.
+    const int32_t* order;
 };
 
 struct SceneDev {

@@ -157,6 +157,56 @@ __global__ void k_grad_reduce(const double* __restrict__ tmp, int ML, int D, dou
 
 int64_t grad_reduce_tmp_doubles(int ML, int D) { return (int64_t)D * kGradRanges * ML; }
 
+// Work items in decreasing order of their adjoint entry counts (the sum over
+// the item's wave regions), by a counting sort over count >> shift in one
+// workgroup.  Items in one bucket are placed in no particular order; the
+// entry kernel's outputs are indexed by item, so its results do not depend
+// on it.
+constexpr int kOrderBuckets = 2048;
+
+__global__ void __launch_bounds__(1024) k_item_order(const int32_t* __restrict__ cnt, int waves, int64_t n_items,
+                                                     int shift, int32_t* __restrict__ order)
+{
+    __shared__ int hist[kOrderBuckets];
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    auto bucket = [&](int64_t it) {
+        int n = 0;
+        for (int w = 0; w < waves; ++w) n += cnt[it * waves + w];
+        const int b = n >> shift;
+        return kOrderBuckets - 1 - (b < kOrderBuckets ? b : kOrderBuckets - 1);   // largest first
+    };
+    for (int k = t; k < kOrderBuckets; k += 1024) hist[k] = 0;
+    __syncthreads();
+    for (int64_t it = t; it < n_items; it += 1024) atomicAdd(&hist[bucket(it)], 1);
+    __syncthreads();
+    // exclusive prefix sum over the buckets: two per thread, then a scan of
+    // the 1024 pair sums
+    const int a0 = hist[2 * t], a1 = hist[2 * t + 1];
+    part[t] = a0 + a1;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const int base = part[t] - (a0 + a1);
+    hist[2 * t] = base;
+    hist[2 * t + 1] = base + a0;
+    __syncthreads();
+    for (int64_t it = t; it < n_items; it += 1024) order[atomicAdd(&hist[bucket(it)], 1)] = (int32_t)it;
+}
+
+hipError_t launch_item_order(const AdjStore& st, int64_t n_items, int32_t* order, hipStream_t s)
+{
+    int shift = 0;
+    while ((((int64_t)st.waves * st.cap_w) >> shift) >= kOrderBuckets) ++shift;
+    hipLaunchKernelGGL(k_item_order, dim3(1), dim3(1024), 0, s, (const int32_t*)st.cnt, (int)st.waves, n_items, shift,
+                       order);
+    return hipGetLastError();
+}
+
 __global__ void k_mask_padding(double* grad, const int32_t* nlay, int D, int M, int Lmax)
 {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
