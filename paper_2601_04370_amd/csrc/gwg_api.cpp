@@ -95,6 +95,11 @@ struct gwg_ctx {
     SceneDev fwd{};
     // adjoint entries recorded by the last forward (GWG_FWD_GRAD)
     DevBuf adj_ent, adj_cnt, adj_ovf, fwd_tape, adj_ck, adj_order;
+    // per-(item, wave) mirror hits of the last forward, and the order the
+    // next forward of the same decomposition takes its items in
+    DevBuf item_work, fwd_order;
+    int64_t work_items = -1;
+    int work_waves = 0;
     bool adj_valid = false;
     bool memo = false;           // thin-film adjoints per distinct hit key (GWG_FWD_MEMO)
     AdjStore adj{};
@@ -504,7 +509,7 @@ int gwg_destroy(gwg_ctx* c)
         for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape,
                            &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad,
-                           &c->adj_ck, &c->grad_tmp, &c->adj_order })
+                           &c->adj_ck, &c->grad_tmp, &c->adj_order, &c->item_work, &c->fwd_order })
             b->release();
         for (KernelTimer& t : c->timer) t.destroy();
     }
@@ -799,6 +804,26 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
         HIP_CHECK(c, launch_table_build(sc, (double*)c->tab.p, c->n_cu, (unsigned long long*)c->stats.p, s),
                   "angle table kernel");
     }
+    {
+        // items are taken in decreasing order of the mirror hits that the last
+        // forward of the same decomposition recorded (its first call: item
+        // order), so the workgroups finish together; results do not depend on it
+        const int waves_f = wg / 64;
+        rc = ensure_buf(c, c->item_work, sizeof(int32_t) * (size_t)(sc.n_items * waves_f), cap, "alloc item work");
+        if (rc) return rc;
+        rc = ensure_buf(c, c->fwd_order, sizeof(int32_t) * (size_t)sc.n_items, cap, "alloc forward order");
+        if (rc) return rc;
+        sc.fwd_order = nullptr;
+        if (c->work_items == sc.n_items && c->work_waves == waves_f) {
+            HIP_CHECK(c, launch_item_order((const int32_t*)c->item_work.p, waves_f, sc.n_items,
+                                           sc.rays_per_tile * (int64_t)sc.Kmax, (int32_t*)c->fwd_order.p, s),
+                      "forward item order");
+            sc.fwd_order = (const int32_t*)c->fwd_order.p;
+        }
+        sc.item_work = (int32_t*)c->item_work.p;
+        c->work_items = sc.n_items;
+        c->work_waves = waves_f;
+    }
     if (c->timing && !cap) HIP_CHECK(c, hipEventRecord(c->timer[GWG_KERNEL_FORWARD].begin(), s), "timing event");
     HIP_CHECK(c, launch_trace_fwd(sc, wg, (int)grid, lds_bins, out->q_bins, out->counts, (unsigned long long*)c->stats.p,
                                   records, record_stride, (double*)c->fwd_scratch.p, adj_sweep ? &c->adj : nullptr,
@@ -908,7 +933,9 @@ int gwg_trace_backward(gwg_ctx* c, const double* d_dL_dI, double* d_grad, int64_
         if (rc) return rc;
         AdjStore st = c->adj;
         st.order = (const int32_t*)c->adj_order.p;
-        HIP_CHECK(c, launch_item_order(st, sc.n_items, (int32_t*)c->adj_order.p, s), "item order");
+        HIP_CHECK(c, launch_item_order(st.cnt, st.waves, sc.n_items, (int64_t)st.waves * st.cap_w,
+                                       (int32_t*)c->adj_order.p, s),
+                  "item order");
         HIP_CHECK(c, launch_adj_entries(sc, wg, (int)grid_e, d_dL_dI, (unsigned long long*)c->stats.p, (double*)c->partial.p,
                                         st, (double*)c->scratch.p, s),
                   "adjoint entry kernel");

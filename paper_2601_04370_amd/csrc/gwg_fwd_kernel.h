@@ -305,11 +305,13 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     double t_gmax = 0.0;                                 // largest cotangent component (angle table)
     unsigned long long t_ne = 0;                         // cotangent pairs emitted (angle table)
 
-    for (int64_t item = draw_item(stats + ST_NEXT0); item < sc.n_items; item = draw_item(stats + ST_NEXT0)) {
+    for (int64_t it = draw_item(stats + ST_NEXT0); it < sc.n_items; it = draw_item(stats + ST_NEXT0)) {
+        const int64_t item = sc.fwd_order ? (int64_t)sc.fwd_order[it] : it;
         int64_t point, i0, i1;
         int d, l, f;
         decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
         stage_point(sc, d, l, f, pl, s_thk, s_slot);
+        int64_t n_work = 0;                               // this wave's mirror hits in this item (uniform)
         if (lds_bins)
             for (int k = tid; k < B; k += WG) { s_q[k] = 0ull; s_c[k] = 0u; }
         __syncthreads();
@@ -352,6 +354,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             if (!tabm) {
                 int total;
                 const int off = wave_excl_scan(nh, &total);
+                n_work += total;
                 // FP64 with a checkpoint store: the hits of rays bound for the
                 // eyebox learn the slots of their future adjoint entries (the
                 // sweep emits a ray's hits last to first)
@@ -443,6 +446,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             st.cnt[item * st.waves + wave] = (int32_t)(n_ent < st.cap_w ? n_ent : st.cap_w);
             if (n_ent > st.cap_w) st.ovf[item] = 1;
         }
+        if (sc.item_work && lane == 0) sc.item_work[item * n_waves + wave] = (int32_t)n_work;
         __syncthreads();
         if (lds_bins) {
             for (int k = tid; k < B; k += WG) {

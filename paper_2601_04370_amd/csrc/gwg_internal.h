@@ -125,6 +125,11 @@ struct SceneDev {
     int64_t tiles_per_point;
     int64_t rays_per_tile;
     int64_t n_items;
+    // forward: order in which items are taken (null: item order), and the
+    // per-(item, wave) mirror-hit counts it records for the next forward's
+    // order (null: none)
+    const int32_t* fwd_order;
+    int32_t* item_work;
 };
 
 }  // namespace gwg

@@ -157,11 +157,11 @@ __global__ void k_grad_reduce(const double* __restrict__ tmp, int ML, int D, dou
 
 int64_t grad_reduce_tmp_doubles(int ML, int D) { return (int64_t)D * kGradRanges * ML; }
 
-// Work items in decreasing order of their adjoint entry counts (the sum over
-// the item's wave regions), by a counting sort over count >> shift in one
-// workgroup.  Items in one bucket are placed in no particular order; the
-// entry kernel's outputs are indexed by item, so its results do not depend
-// on it.
+// Work items in decreasing order of a per-(item, wave) work count summed
+// over the item's waves (adjoint entries; mirror hits of the last forward),
+// by a counting sort over count >> shift in one workgroup.  Items in one
+// bucket are placed in no particular order; the kernels' outputs are indexed
+// by item, so their results do not depend on it.
 constexpr int kOrderBuckets = 2048;
 
 __global__ void __launch_bounds__(1024) k_item_order(const int32_t* __restrict__ cnt, int waves, int64_t n_items,
@@ -198,12 +198,12 @@ __global__ void __launch_bounds__(1024) k_item_order(const int32_t* __restrict__
     for (int64_t it = t; it < n_items; it += 1024) order[atomicAdd(&hist[bucket(it)], 1)] = (int32_t)it;
 }
 
-hipError_t launch_item_order(const AdjStore& st, int64_t n_items, int32_t* order, hipStream_t s)
+hipError_t launch_item_order(const int32_t* cnt, int waves, int64_t n_items, int64_t max_count, int32_t* order,
+                             hipStream_t s)
 {
     int shift = 0;
-    while ((((int64_t)st.waves * st.cap_w) >> shift) >= kOrderBuckets) ++shift;
-    hipLaunchKernelGGL(k_item_order, dim3(1), dim3(1024), 0, s, (const int32_t*)st.cnt, (int)st.waves, n_items, shift,
-                       order);
+    while ((max_count >> shift) >= kOrderBuckets) ++shift;
+    hipLaunchKernelGGL(k_item_order, dim3(1), dim3(1024), 0, s, cnt, waves, n_items, shift, order);
     return hipGetLastError();
 }
 

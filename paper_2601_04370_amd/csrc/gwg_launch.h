@@ -49,7 +49,8 @@ hipError_t launch_omega_grad(const SceneDev& sc, int grid_blocks, int wg, const 
 hipError_t launch_grad_reduce(const double* partial, int64_t items_per_design, int ML, int D, double* tmp,
                               double* grad, const int32_t* nlay, int M, int Lmax, hipStream_t s);
 int64_t grad_reduce_tmp_doubles(int ML, int D);
-hipError_t launch_item_order(const AdjStore& st, int64_t n_items, int32_t* order, hipStream_t s);
+hipError_t launch_item_order(const int32_t* cnt, int waves, int64_t n_items, int64_t max_count, int32_t* order,
+                             hipStream_t s);
 hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double* irr, hipStream_t s);
 hipError_t launch_tmm_rt(int precision, const double* thk, const uint8_t* slot, int L,
                          const double* lam_tab, int n_lambda, int n_slots, uint32_t cplx_mask,
