@@ -141,6 +141,8 @@ def main():
                     help="angle-table thin film (interpolated model, reported separately with its error against "
                          "the per-hit solve)")
     ap.add_argument("--table-nodes", type=int, default=0, help="incidence angles of the table (0: library default)")
+    ap.add_argument("--rays-per-block", type=int, default=0,
+                    help="rays per work item (tuning rays_per_block; 0: the library's choice)")
     ap.add_argument("--per-design", action="store_true",
                     help="also time one launch per design (the batched workload) for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -182,6 +184,11 @@ def main():
         extra["tuning"] = ctx.autotune(scene, thk, w.seed, prec, grad=not fo)
         extra["autotune_s"] = time.perf_counter() - t
 
+    if a.rays_per_block:
+        t = ctx.get_tuning()
+        t["rays_per_block"] = a.rays_per_block
+        ctx.set_tuning(**t)
+        extra["rays_per_block"] = a.rays_per_block
     if a.memo and a.table:
         sys.exit("--memo and --table exclude each other")
     if a.table and a.table_nodes:

@@ -439,8 +439,9 @@ void set_tiles(SceneDev& s, int64_t rays_per_tile, int wg, int n_cu)
         // Whole points while there are at least ~32 per CU (about 16 items
         // per resident workgroup at two per CU, so the launch's tail, at
         // most about one item, costs little); otherwise split every point
-        // into equal tiles of at least 4 rays per lane.
-        const int64_t target = (int64_t)std::max(n_cu, 1) * 32;
+        // into equal tiles of at least 4 rays per lane.  Memoized solves
+        // share keys within an item, and take half as many, larger items.
+        const int64_t target = (int64_t)std::max(n_cu, 1) * (s.memo ? 16 : 32);
         const int64_t tiles = points >= target ? 1 : (target + points - 1) / points;
         rpt = (s.N + tiles - 1) / tiles;
         rpt = std::max<int64_t>(rpt, (int64_t)wg * 4);
