@@ -381,6 +381,33 @@ struct LaneSlots3 {
     }
 };
 
+// LaneSlots3x: the values LaneSlots3 returns, all five kept per lane (x_p
+// and y_p formed once, by the same products, when the slot is put), so a
+// layer reads them instead of multiplying again.  Same results as LaneSlots3.
+struct LaneSlots3x {
+    static constexpr int kPer = 5;
+    double* sp;
+    int ls;
+    const double* nsq;          // N^2 (re, im) per slot
+    const double* in2;          // 1 / Re N^2 per lossless slot
+    __device__ void put(int s, const double* P) const
+    {
+        double* Q = sp + s * 5 * ls;
+        Q[0] = P[0]; Q[ls] = P[1]; Q[2 * ls] = P[2];
+        Q[3 * ls] = P[2] * in2[s]; Q[4 * ls] = P[1] * nsq[2 * s];
+    }
+    __device__ void lossless(int s, double& kq, double& xs, double& ys, double& xp, double& yp) const
+    {
+        const double* P = sp + s * 5 * ls;
+        kq = P[0]; xs = P[ls]; ys = P[2 * ls]; xp = P[3 * ls]; yp = P[4 * ls];
+    }
+    __device__ void absorbing(int s, double* Pl) const
+    {
+        const double* P = sp + s * 5 * ls;
+        Pl[0] = P[0]; Pl[1] = P[ls]; Pl[2] = nsq[2 * s]; Pl[3] = nsq[2 * s + 1];
+    }
+};
+
 // ------------------------------------------------------------ chain steps
 template <typename T> struct V2 { T br, bi, cr, ci; };   // [B; C] of one polarization
 template <typename T> struct CTv { T re, im; };

@@ -29,9 +29,9 @@
 // per wave goes on hit by hit.
 
 // Thin-film coefficients of one hit for this lane (fills the lane's slot table).
-template <int MODE>
+template <int MODE, class SL>
 __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                  const uint8_t* s_slot, const LaneSlots3& sl, int m, bool front, double kappa,
+                                  const uint8_t* s_slot, const SL& sl, int m, bool front, double kappa,
                                   bool* used_fp64, double* ck = nullptr, int64_t ckb = 8)
 {
     bool hyp = false;                       // an evanescent lossless slot at this kappa
@@ -77,9 +77,9 @@ __device__ inline int dense_slot(int p, int off, int)
 // off: this lane's exclusive prefix sum of hit counts.
 // ck (non-null): checkpoint store of the adjoint entries; a hit whose
 // queue field 10 holds a slot c >= 0 stores its sweep checkpoints there.
-template <int MODE>
+template <int MODE, class SL>
 __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                  const uint8_t* s_slot, const LaneSlots3& sl, const HitQueue& hq, int total,
+                                  const uint8_t* s_slot, const SL& sl, const HitQueue& hq, int total,
                                   int off, unsigned long long* n_fp64, unsigned long long* n_lay,
                                   double* ck = nullptr, int64_t ck_total = 0)
 {
@@ -201,9 +201,9 @@ __device__ inline bool fmemo_resolve(const HitQueue& hq, int total, int off, int
 }
 
 // Solve keys [u0, u1) (one per lane) from their first hits into the table.
-template <int MODE>
+template <int MODE, class SL>
 __device__ inline void fmemo_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                   const uint8_t* s_slot, const LaneSlots3& sl, const HitQueue& hq,
+                                   const uint8_t* s_slot, const SL& sl, const HitQueue& hq,
                                    const FwdMemo& fm, int u0, int u1, unsigned long long* n_fp64,
                                    unsigned long long* n_lay)
 {
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     const int B = sc.bins_x * sc.bins_y;
     const int WG = blockDim.x;
     const int n_waves = WG / 64;
-    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, lds_bins != 0, 0);
+    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, lds_bins != 0, 0, LaneSlots3x::kPer);
     PointLds* pl = (PointLds*)(smem + lay.off_pl);
     double* s_thk = (double*)(smem + lay.off_thk);
     uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
     const int cap = 64 * sc.Kmax;
     const HitQueue hq = { scratch + gwave * (int64_t)kHitFields * cap, cap };
-    const LaneSlots3 sl = { s_sp + tid, WG, pl->nsq, pl->in2 };
+    const LaneSlots3x sl = { s_sp + tid, WG, pl->nsq, pl->in2 };
     const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;

@@ -35,14 +35,14 @@ struct SmemLayout {
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
 __host__ __device__ inline SmemLayout smem_layout(int M, int Lmax, int n_slots, int wg, int B,
-                                                  bool lds_bins, int n_grad_regions)
+                                                  bool lds_bins, int n_grad_regions, int slot_per = LaneSlots3::kPer)
 {
     SmemLayout s;
     int o = 0;
     s.off_pl = o; o = align16(o + (int)sizeof(PointLds));
     s.off_thk = o; o = align16(o + 8 * M * Lmax);
     s.off_slot = o; o = align16(o + M * Lmax);
-    s.off_sp = o; o = align16(o + 8 * n_slots * LaneSlots3::kPer * wg);
+    s.off_sp = o; o = align16(o + 8 * n_slots * slot_per * wg);
     s.off_q = o; o = align16(o + (lds_bins ? 8 * B : 0));
     s.off_c = o; o = align16(o + (lds_bins ? 4 * B : 0));
     s.off_st = o; o = align16(o + 8 * ST_WORDS);
@@ -434,7 +434,7 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
 
 size_t fwd_smem_bytes(const SceneDev& sc, int wg, bool lds_bins)
 {
-    return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, lds_bins, 0).total
+    return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, lds_bins, 0, LaneSlots3x::kPer).total
            + (sc.memo ? (size_t)(wg / 64) * fwd_memo_wave_bytes() : 0);
 }
 size_t bwd_smem_bytes(const SceneDev& sc, int wg)
