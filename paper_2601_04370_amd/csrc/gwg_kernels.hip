@@ -171,10 +171,10 @@ __global__ void __launch_bounds__(1024) k_item_order(const int32_t* __restrict__
     __shared__ int part[1024];
     const int t = threadIdx.x;
     auto bucket = [&](int64_t it) {
-        int n = 0;
+        long long n = 0;
         for (int w = 0; w < waves; ++w) n += cnt[it * waves + w];
-        const int b = n >> shift;
-        return kOrderBuckets - 1 - (b < kOrderBuckets ? b : kOrderBuckets - 1);   // largest first
+        const long long b = n > 0 ? n >> shift : 0;     // any count maps into the histogram
+        return kOrderBuckets - 1 - (int)(b < kOrderBuckets ? b : kOrderBuckets - 1);   // largest first
     };
     for (int k = t; k < kOrderBuckets; k += 1024) hist[k] = 0;
     __syncthreads();
