@@ -687,8 +687,11 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     sc.table_n = 0;
     sc.tab_scale = nullptr;
     sc.tab_acc = nullptr;
-    const int wg = pick_fwd_wg(c, sc, lds_bins);
-    if (sc.memo && fwd_smem_bytes(sc, wg, lds_bins) > 65536) sc.memo = 0;
+    int wg = pick_fwd_wg(c, sc, lds_bins);
+    if (sc.memo && fwd_smem_bytes(sc, wg, lds_bins) > 65536) {
+        sc.memo = 0;                                   // per-hit solves (their own slot table size)
+        wg = pick_fwd_wg(c, sc, lds_bins);
+    }
     set_tiles(sc, c->tune.rays_per_block, wg, c->n_cu);
     if (fwd_smem_bytes(sc, wg, lds_bins) > 65536) return fail(c, GWG_E_INVAL, "scene too large for one workgroup's LDS");
     if (sc.n_items > 0x7fffffff) return fail(c, GWG_E_INVAL, "too many work items; raise rays_per_block");

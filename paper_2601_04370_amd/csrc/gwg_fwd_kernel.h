@@ -282,7 +282,10 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     const int B = sc.bins_x * sc.bins_y;
     const int WG = blockDim.x;
     const int n_waves = WG / 64;
-    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, lds_bins != 0, 0, LaneSlots3x::kPer);
+    // slot table: all five values per lane, except with the memoized solves,
+    // whose key tables need the LDS (they solve few hits)
+    using SlotTable = typename std::conditional<MEMO, LaneSlots3, LaneSlots3x>::type;
+    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, lds_bins != 0, 0, SlotTable::kPer);
     PointLds* pl = (PointLds*)(smem + lay.off_pl);
     double* s_thk = (double*)(smem + lay.off_thk);
     uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
@@ -294,7 +297,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
     const int cap = 64 * sc.Kmax;
     const HitQueue hq = { scratch + gwave * (int64_t)kHitFields * cap, cap };
-    const LaneSlots3x sl = { s_sp + tid, WG, pl->nsq, pl->in2 };
+    const SlotTable sl = { s_sp + tid, WG, pl->nsq, pl->in2 };
     const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;

@@ -2,6 +2,8 @@
 // with fixed-point eyebox scatter, adjoint trace, gradient reduction,
 // irradiance and loss.  Launch wrappers at the end are the only entry points
 // used by the host API (gwg_api.cpp).
+#include <type_traits>
+
 #include "gwg_internal.h"
 #include "gwg_device.h"
 #include "gwg_adjoint.h"
@@ -434,7 +436,8 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
 
 size_t fwd_smem_bytes(const SceneDev& sc, int wg, bool lds_bins)
 {
-    return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, lds_bins, 0, LaneSlots3x::kPer).total
+    return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, lds_bins, 0,
+                               sc.memo ? LaneSlots3::kPer : LaneSlots3x::kPer).total
            + (sc.memo ? (size_t)(wg / 64) * fwd_memo_wave_bytes() : 0);
 }
 size_t bwd_smem_bytes(const SceneDev& sc, int wg)
