@@ -196,13 +196,19 @@ __device__ inline FaceCoef face_coeffs(double ng, double na, double dx, double d
     double qi = ng * fabs(dz);
     f.tir = f.st2 > na2;
     cd qt = f.tir ? mk(0.0, sqrt(f.st2 - na2)) : mk(sqrt(na2 - f.st2), 0.0);
-    cd den_s = cadd(mk(qi, 0.0), qt);
-    f.rs = cdiv(csub(mk(qi, 0.0), qt), den_s);
-    f.ts = cdiv(mk(2.0 * qi, 0.0), den_s);
-    cd a = mk(na2 * qi, 0.0), b = cscale(qt, ng2);
-    cd den_p = cadd(a, b);
-    f.rp = cdiv(csub(a, b), den_p);
-    f.tp = cdiv(mk(2.0 * ng * na * qi, 0.0), den_p);
+    // r and t of each polarization share their denominator: one reciprocal
+    // 1/den = conj(den) / |den|^2 each (|den| is of order one here)
+    const cd den_s = cadd(mk(qi, 0.0), qt);
+    const double is = 1.0 / (den_s.re * den_s.re + den_s.im * den_s.im);
+    const cd inv_s = mk(den_s.re * is, -den_s.im * is);
+    f.rs = cmul(csub(mk(qi, 0.0), qt), inv_s);
+    f.ts = cscale(inv_s, 2.0 * qi);
+    const cd a = mk(na2 * qi, 0.0), b = cscale(qt, ng2);
+    const cd den_p = cadd(a, b);
+    const double ip = 1.0 / (den_p.re * den_p.re + den_p.im * den_p.im);
+    const cd inv_p = mk(den_p.re * ip, -den_p.im * ip);
+    f.rp = cmul(csub(a, b), inv_p);
+    f.tp = cscale(inv_p, 2.0 * ng * na * qi);
     f.flux = f.tir ? 0.0 : sqrt(qt.re / qi);
     return f;
 }
