@@ -334,14 +334,24 @@ __device__ inline void slot_params(double nre, double nim, double kappa, double 
 // what the layer loops read and returns, for slot s,
 //   lossless(s, kq, xs, ys, xp, yp)   P0..P4 of a lossless slot,
 //   absorbing(s, Pl)                  Pl = q (re, im), N^2 (re, im).
+// Slot tables are laid out per wave: value p of slot s of lane l of wave w
+// at base[((w n_slots + s) kPer + p) 64 + l].  The lane stride is the
+// compile-time 64, so the reads of one slot's values take immediate offsets
+// from one address; consecutive lanes read consecutive doubles.
+constexpr int kSlotLanes = 64;
+__device__ inline double* slot_lane_base(double* base, int n_slots, int per, int tid)
+{
+    return base + (tid / kSlotLanes) * n_slots * per * kSlotLanes + (tid % kSlotLanes);
+}
+
 // LaneSlots5 keeps all five values per lane (lanes may differ in
 // wavelength).  LaneSlots3 keeps kq, x_s, y_s per lane and takes N^2 of the
 // slot from arrays shared by the workgroup (one wavelength per workgroup):
 // x_p = y_s / N^2 and y_p = N^2 x_s for both lossless kinds.
 struct LaneSlots5 {
     static constexpr int kPer = 5;
-    double* sp;
-    int ls;
+    double* sp;                 // this lane's value 0 of slot 0 (slot_lane_base)
+    static constexpr int ls = kSlotLanes;
     __device__ void put(int s, const double* P) const
     {
 #pragma unroll
@@ -360,8 +370,8 @@ struct LaneSlots5 {
 };
 struct LaneSlots3 {
     static constexpr int kPer = 3;
-    double* sp;
-    int ls;
+    double* sp;                 // this lane's value 0 of slot 0 (slot_lane_base)
+    static constexpr int ls = kSlotLanes;
     const double* nsq;          // N^2 (re, im) per slot
     const double* in2;          // 1 / Re N^2 per lossless slot
     __device__ void put(int s, const double* P) const
@@ -386,8 +396,8 @@ struct LaneSlots3 {
 // layer reads them instead of multiplying again.  Same results as LaneSlots3.
 struct LaneSlots3x {
     static constexpr int kPer = 5;
-    double* sp;
-    int ls;
+    double* sp;                 // this lane's value 0 of slot 0 (slot_lane_base)
+    static constexpr int ls = kSlotLanes;
     const double* nsq;          // N^2 (re, im) per slot
     const double* in2;          // 1 / Re N^2 per lossless slot
     __device__ void put(int s, const double* P) const

@@ -44,7 +44,7 @@ __host__ __device__ inline SmemLayout smem_layout(int M, int Lmax, int n_slots, 
     s.off_pl = o; o = align16(o + (int)sizeof(PointLds));
     s.off_thk = o; o = align16(o + 8 * M * Lmax);
     s.off_slot = o; o = align16(o + M * Lmax);
-    s.off_sp = o; o = align16(o + 8 * n_slots * slot_per * wg);
+    s.off_sp = o; o = align16(o + 8 * n_slots * slot_per * ((wg + 63) / 64 * 64));   // whole waves
     s.off_q = o; o = align16(o + (lds_bins ? 8 * B : 0));
     s.off_c = o; o = align16(o + (lds_bins ? 4 * B : 0));
     s.off_st = o; o = align16(o + 8 * ST_WORDS);
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(256) k_tmm_rt(const double* __restrict__ thk, 
     double* s_sp = (double*)(smem + align16(8 * L) + align16(L > 0 ? L : 1));
     for (int i = threadIdx.x; i < L; i += blockDim.x) { s_thk[i] = thk[i]; s_slot[i] = slot[i]; }
     __syncthreads();
-    const LaneSlots5 sl = { s_sp + threadIdx.x, (int)blockDim.x };
+    const LaneSlots5 sl = { slot_lane_base(s_sp, n_slots, LaneSlots5::kPer, threadIdx.x) };
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
         int li = lidx[q];
         double th = theta[q];
@@ -687,7 +687,7 @@ hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double*
 
 size_t tmm_smem_bytes(int L, int n_slots, int wg)
 {
-    return (size_t)(align16(8 * L) + align16(L > 0 ? L : 1) + 8 * n_slots * LaneSlots5::kPer * wg);
+    return (size_t)(align16(8 * L) + align16(L > 0 ? L : 1) + 8 * n_slots * LaneSlots5::kPer * ((wg + 63) / 64 * 64));
 }
 
 hipError_t launch_tmm_rt(int precision, const double* thk, const uint8_t* slot, int L,
