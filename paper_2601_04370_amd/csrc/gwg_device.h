@@ -195,6 +195,7 @@ __device__ inline void gtrig(double a, bool hyper_in, double* C, double* S)
         frexp(a * 1.2732395447351628, &e);      // a / (pi/4) = m 2^e, m in [0.5, 1)
         k = e > 0 ? e : 0;
         r = ldexp(a, -k);
+        n = 0.0;                                 // the quadrant rotation below is then the identity
     }
     double u = hyper ? r * r : -(r * r);
     double ps = kInvFact[15];
@@ -214,24 +215,24 @@ __device__ inline void gtrig(double a, bool hyper_in, double* C, double* S)
     pc = fma(pc, u, kInvFact[4]);
     pc = fma(pc, u, kInvFact[2]);
     double cs = fma(u, pc, 1.0);
-    if (!hyper) {
-        // quadrant q = n mod 4: swap for odd q, then flip signs through the
-        // sign bit (S negative for q = 2, 3; C negative for q = 1, 2)
-        const unsigned q = (unsigned)(int)n;
-        const double so = (q & 1u) ? cs : sn;
-        const double co = (q & 1u) ? sn : cs;
-        const unsigned fs = (q & 2u) << 30, fc = ((q + 1u) & 2u) << 30;
-        *S = __hiloint2double(__double2hiint(so) ^ (int)fs, __double2loint(so));
-        *C = __hiloint2double(__double2hiint(co) ^ (int)fc, __double2loint(co));
-    } else {
-        for (int i = 0; i < k; ++i) {
-            double s2 = 2.0 * sn * cs;
-            cs = fma(cs, cs, sn * sn);
-            sn = s2;
-        }
-        *S = sn;
-        *C = cs;
+    // Both kinds run the same straight-line code (no divergent branch): the
+    // quadrant rotation (the identity for hyperbolic lanes, whose n is 0),
+    // then the doublings (none for circular lanes, whose k is 0).
+    // Quadrant q = n mod 4: swap for odd q, then flip signs through the sign
+    // bit (S negative for q = 2, 3; C negative for q = 1, 2).
+    const unsigned q = (unsigned)(int)n;
+    const double so = (q & 1u) ? cs : sn;
+    const double co = (q & 1u) ? sn : cs;
+    const unsigned fs = (q & 2u) << 30, fc = ((q + 1u) & 2u) << 30;
+    sn = __hiloint2double(__double2hiint(so) ^ (int)fs, __double2loint(so));
+    cs = __hiloint2double(__double2hiint(co) ^ (int)fc, __double2loint(co));
+    for (int i = 0; i < k; ++i) {
+        double s2 = 2.0 * sn * cs;
+        cs = fma(cs, cs, sn * sn);
+        sn = s2;
     }
+    *S = sn;
+    *C = cs;
 }
 
 template <bool HC = true>
@@ -251,6 +252,7 @@ __device__ inline void gtrig(float a, bool hyper_in, float* C, float* S)
         frexpf(a * 1.27323954f, &e);
         k = e > 0 ? e : 0;
         r = ldexpf(a, -k);
+        n = 0.0f;
     }
     float u = hyper ? r * r : -(r * r);
     float ps = kInvFactF[9];
@@ -264,21 +266,18 @@ __device__ inline void gtrig(float a, bool hyper_in, float* C, float* S)
     pc = fmaf(pc, u, kInvFactF[4]);
     pc = fmaf(pc, u, kInvFactF[2]);
     float cs = fmaf(u, pc, 1.0f);
-    if (!hyper) {
-        const unsigned q = (unsigned)(int)n;
-        const float so = (q & 1u) ? cs : sn;
-        const float co = (q & 1u) ? sn : cs;
-        *S = __uint_as_float(__float_as_uint(so) ^ ((q & 2u) << 30));
-        *C = __uint_as_float(__float_as_uint(co) ^ (((q + 1u) & 2u) << 30));
-    } else {
-        for (int i = 0; i < k; ++i) {
-            float s2 = 2.0f * sn * cs;
-            cs = fmaf(cs, cs, sn * sn);
-            sn = s2;
-        }
-        *S = sn;
-        *C = cs;
+    const unsigned q = (unsigned)(int)n;
+    const float so = (q & 1u) ? cs : sn;
+    const float co = (q & 1u) ? sn : cs;
+    sn = __uint_as_float(__float_as_uint(so) ^ ((q & 2u) << 30));
+    cs = __uint_as_float(__float_as_uint(co) ^ (((q + 1u) & 2u) << 30));
+    for (int i = 0; i < k; ++i) {
+        float s2 = 2.0f * sn * cs;
+        cs = fmaf(cs, cs, sn * sn);
+        sn = s2;
     }
+    *S = sn;
+    *C = cs;
 }
 
 // cosh and sinh of x >= 0 from expm1 (no cancellation for small x)
@@ -547,6 +546,10 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(const doubl
     int idx1 = idx == last ? idx : idx + dir;
     double t1 = thk[idx1];
     int s1 = slot[idx1];
+    // loop index j of the next checkpoint (incidence-order layer L-1-j a
+    // positive multiple of kSegL), or L when none is left
+    int jck = (L - 1) % kSegL;
+    if (jck >= L - 1) jck = L;
 #pragma unroll 4
     for (int j = 0; j < L; ++j) {
         const int idx2 = idx1 == last ? idx1 : idx1 + dir;
@@ -559,9 +562,9 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(const doubl
         step_real(vs, C, S * (T)xs, S * (T)ys);
         step_real(vp, C, S * (T)xp, S * (T)yp);
         if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
-        if (sizeof(T) == 8 && ck) {
-            const int jj = L - 1 - j;                  // incidence-order index of this layer
-            if (jj > 0 && (jj % kSegL) == 0) store(jj / kSegL);
+        if (sizeof(T) == 8 && ck && j == jck) {
+            store((L - 1 - j) / kSegL);
+            jck = jck + kSegL < L - 1 ? jck + kSegL : L;
         }
         t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
         t1 = t2; s1 = s2; idx1 = idx2;
