@@ -186,17 +186,19 @@ __device__ inline void gtrig(double a, bool hyper_in, double* C, double* S)
     const double pio2_hi = 1.5707963267948966;
     const double pio2_lo = 6.123233995736766e-17;
     double n = rint(a * two_over_pi);
-    double r = fma(-n, pio2_hi, a);
-    r = fma(-n, pio2_lo, r);
     int k = 0;
     if (hyper) {
         // smallest k with a / 2^k <= pi/4 (a is finite and moderate)
         int e;
         frexp(a * 1.2732395447351628, &e);      // a / (pi/4) = m 2^e, m in [0.5, 1)
         k = e > 0 ? e : 0;
-        r = ldexp(a, -k);
         n = 0.0;                                 // the quadrant rotation below is then the identity
     }
+    // r = a - n pi/2; exactly a on hyperbolic lanes (n = 0), which then
+    // scale it by 2^-k (k = 0 leaves circular lanes unchanged)
+    double r = fma(-n, pio2_hi, a);
+    r = fma(-n, pio2_lo, r);
+    if (HC) r = ldexp(r, -k);
     double u = hyper ? r * r : -(r * r);
     double ps = kInvFact[15];
     ps = fma(ps, u, kInvFact[13]);
@@ -244,16 +246,16 @@ __device__ inline void gtrig(float a, bool hyper_in, float* C, float* S)
     const float pio2_hi = 1.57079637f;
     const float pio2_lo = -4.37113883e-8f;
     float n = rintf(a * two_over_pi);
-    float r = fmaf(-n, pio2_hi, a);
-    r = fmaf(-n, pio2_lo, r);
     int k = 0;
     if (hyper) {
         int e;
         frexpf(a * 1.27323954f, &e);
         k = e > 0 ? e : 0;
-        r = ldexpf(a, -k);
         n = 0.0f;
     }
+    float r = fmaf(-n, pio2_hi, a);
+    r = fmaf(-n, pio2_lo, r);
+    if (HC) r = ldexpf(r, -k);
     float u = hyper ? r * r : -(r * r);
     float ps = kInvFactF[9];
     ps = fmaf(ps, u, kInvFactF[7]);
