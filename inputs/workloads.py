@@ -200,7 +200,8 @@ def _cfg(i: int, **kw) -> Workload:
     return Workload(seed=20260100 + i, **kw)
 
 
-#: The five workloads.  Sizes follow the survey of the paper's configurations.
+#: The five workloads, shaped like the configurations the paper describes (stack sizes,
+#: materials, wavelengths, field of view, ray counts).
 WORKLOADS = {
     "plain_fp64": _cfg(
         1, name="plain_fp64", n_mirrors=4, n_layers=8, thk_range=(0.0, 200.0),
