@@ -190,6 +190,34 @@ def test_stored_sweep_checkpoints_give_the_same_gradient(gctx, name, kw):
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
+@pytest.mark.parametrize("n_layers", [1, 15, 16, 17, 33])
+def test_checkpoint_schedule_layer_counts(gctx, orc, n_layers):
+    """Stacks with no checkpoint (L <= 16) and with L - 1 just below, at and
+    above a multiple of the 16-layer checkpoint interval: the gradient with
+    the forward's stored sweep checkpoints matches the oracle and equals the
+    recomputing adjoint's bit for bit."""
+    w = inputs.small_variant("diff_1200", rays_per_point=96, fov_n=3, n_layers=n_layers)
+    inp = inputs.make_inputs(w)
+    print(f"checkpoint schedule diff_1200 n_layers={n_layers}", flush=True)
+    g, og = _grad_case(gctx, orc, w, inp, 0, 1, 0, mode="entries")
+    scale = np.max(np.abs(og))
+    assert scale > 0
+    err = np.abs(g - og)
+    assert np.all(err <= 1e-4 * np.maximum(np.abs(og), 1e-3 * scale))
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    dLdI = torch.tensor(np.random.default_rng(5).standard_normal(scene.shape))
+    out = []
+    for per in (-1, 0):
+        gctx.set_tuning(ck_entries_per_ray=per)
+        try:
+            gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=True)
+            out.append(gctx.trace_backward(dLdI, scene).cpu().numpy())
+        finally:
+            gctx.set_tuning()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_work_order_does_not_change_results(gctx):
     """Work items are taken largest first: the forward by the mirror hits its
     previous forward of the same decomposition recorded, the adjoint by the
