@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     const int lane = wave_lane();
     const int ML = sc.M * sc.Lmax;
     double* gw = s_grad + (int64_t)wave * ML;
-    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->in2 };
+    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->pxy };
     const int64_t nthreads = (int64_t)gridDim.x * WG;
     const int64_t gtid = (int64_t)blockIdx.x * WG + tid;
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
     const int lane = wave_lane();
     const int ML = sc.M * sc.Lmax;
     double* gw = s_grad + (int64_t)wave * ML;
-    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->in2 };
+    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->pxy };
     const int64_t nthreads = (int64_t)gridDim.x * WG;
     double* chk = scratch + (int64_t)blockIdx.x * WG + tid;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;

@@ -374,7 +374,7 @@ struct LaneSlots3 {
     double* sp;                 // this lane's value 0 of slot 0 (slot_lane_base)
     static constexpr int ls = kSlotLanes;
     const double* nsq;          // N^2 (re, im) per slot
-    const double* in2;          // 1 / Re N^2 per lossless slot
+    const double* pxy;          // per slot (1 / Re N^2 if lossless, Re N^2), 16-byte aligned pairs
     __device__ void put(int s, const double* P) const
     {
         sp[(s * 3) * ls] = P[0]; sp[(s * 3 + 1) * ls] = P[1]; sp[(s * 3 + 2) * ls] = P[2];
@@ -383,7 +383,8 @@ struct LaneSlots3 {
     {
         const double* P = sp + s * 3 * ls;
         kq = P[0]; xs = P[ls]; ys = P[2 * ls];
-        xp = ys * in2[s]; yp = xs * nsq[2 * s];
+        const double2 c = reinterpret_cast<const double2*>(pxy)[s];   // one paired LDS read
+        xp = ys * c.x; yp = xs * c.y;
     }
     __device__ void absorbing(int s, double* Pl) const
     {
@@ -400,12 +401,13 @@ struct LaneSlots3x {
     double* sp;                 // this lane's value 0 of slot 0 (slot_lane_base)
     static constexpr int ls = kSlotLanes;
     const double* nsq;          // N^2 (re, im) per slot
-    const double* in2;          // 1 / Re N^2 per lossless slot
+    const double* pxy;          // per slot (1 / Re N^2 if lossless, Re N^2), 16-byte aligned pairs
     __device__ void put(int s, const double* P) const
     {
         double* Q = sp + s * 5 * ls;
         Q[0] = P[0]; Q[ls] = P[1]; Q[2 * ls] = P[2];
-        Q[3 * ls] = P[2] * in2[s]; Q[4 * ls] = P[1] * nsq[2 * s];
+        const double2 c = reinterpret_cast<const double2*>(pxy)[s];
+        Q[3 * ls] = P[2] * c.x; Q[4 * ls] = P[1] * c.y;
     }
     __device__ void lossless(int s, double& kq, double& xs, double& ys, double& xp, double& yp) const
     {

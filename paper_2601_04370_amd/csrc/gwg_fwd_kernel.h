@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
     const int cap = 64 * sc.Kmax;
     const HitQueue hq = { scratch + gwave * (int64_t)kHitFields * cap, cap };
-    const SlotTable sl = { slot_lane_base(s_sp, sc.n_slots, SlotTable::kPer, tid), pl->nsq, pl->in2 };
+    const SlotTable sl = { slot_lane_base(s_sp, sc.n_slots, SlotTable::kPer, tid), pl->nsq, pl->pxy };
     const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;

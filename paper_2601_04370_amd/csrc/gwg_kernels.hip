@@ -71,7 +71,8 @@ __device__ inline void stage_point(const SceneDev& sc, int d, int l, int f, Poin
             double nr = lt[LT_SLOT + 2 * s], ni = lt[LT_SLOT + 2 * s + 1];
             pl->slotN[2 * s] = nr; pl->slotN[2 * s + 1] = ni;
             pl->nsq[2 * s] = nr * nr - ni * ni; pl->nsq[2 * s + 1] = 2.0 * nr * ni;
-            pl->in2[s] = (ni == 0.0 && nr != 0.0) ? 1.0 / (nr * nr) : 0.0;
+            pl->pxy[2 * s] = (ni == 0.0 && nr != 0.0) ? 1.0 / (nr * nr) : 0.0;
+            pl->pxy[2 * s + 1] = nr * nr - ni * ni;
             pl->crit[2 * s] = lt[LT_CRIT + 2 * s]; pl->crit[2 * s + 1] = lt[LT_CRIT + 2 * s + 1];
         }
         for (int m = 0; m < sc.M; ++m) {

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(64 * kMemoWaves, 2) k_adj_memo(SceneDev sc, co
     const MemoLds mt = memo_table(mbase, wave);
     const MemoLds m0 = memo_table(mbase, 0);
     const int ML = sc.M * sc.Lmax;
-    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, lane), pl->nsq, pl->in2 };     // wave 0's lanes
+    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, lane), pl->nsq, pl->pxy };     // wave 0's lanes
     const int64_t nthreads = (int64_t)gridDim.x * 64;
     double* chk = scratch + (int64_t)blockIdx.x * 64 + lane;
     for (int k = tid; k < ST_WORDS; k += 64 * kMemoWaves) s_st[k] = 0ull;

@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(256) k_table_build(SceneDev sc, double* __rest
     uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
     double* s_sp = (double*)(smem + lay.off_sp);
     const int tid = threadIdx.x;
-    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->in2 };
+    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->pxy };
     const int64_t dl = blockIdx.x / chunks;
     const int chunk = blockIdx.x % chunks;
     const int d = (int)(dl / sc.n_lsel), l = (int)(dl % sc.n_lsel);
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(128, 2) k_table_adj(SceneDev sc, double* __res
     const int ML = sc.M * sc.Lmax;
     double* gw = s_grad + (int64_t)wave * ML;
     int* lst = s_list + wave * 128;
-    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->in2 };
+    const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->pxy };
     double* chk = scratch + (int64_t)blockIdx.x * WG + tid;
     const int64_t cstride = (int64_t)gridDim.x * WG;
     const int64_t b = blockIdx.x;

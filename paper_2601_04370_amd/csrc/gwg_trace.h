@@ -12,6 +12,7 @@
 // so a CPU implementation with the same operation sequence reproduces every
 // path decision bit for bit (integer bin counts are compared exactly).
 #pragma once
+#include <stddef.h>
 #include "gwg_internal.h"
 #include "gwg_device.h"
 
@@ -32,7 +33,7 @@ struct PointLds {
     double dir[3];
     double slotN[2 * kMaxSlots];     // (re, im) per slot
     double nsq[2 * kMaxSlots];       // N^2 (re, im) per slot
-    double in2[kMaxSlots];           // 1 / N^2 per lossless slot
+    double pxy[2 * kMaxSlots];       // per slot: 1 / Re N^2 (lossless slot, else 0), Re N^2
     double crit[2 * kMaxSlots];      // near-critical kappa interval per slot
     double h[kMaxMirrors], sc_r[kMaxMirrors], sc_t[kMaxMirrors];
     uint32_t thr[kMaxMirrors];
@@ -42,6 +43,8 @@ struct PointLds {
     double T, Lx, nx, nz, ER, ex0, ew, ey0, eh;
     int32_t M, Kmax, bins_x, bins_y;
 };
+// the slot tables read pxy in pairs (16-byte loads)
+static_assert(offsetof(PointLds, pxy) % 16 == 0, "pxy pairs must be 16-byte aligned");
 
 __device__ inline void cross3(double ax, double ay, double az, double bx, double by, double bz,
                               double* o)
