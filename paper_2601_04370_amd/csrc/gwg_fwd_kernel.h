@@ -74,19 +74,21 @@ __device__ inline int dense_slot(int p, int off, int)
 }
 
 // Solve the wave's `total` queued hits in batches of 64 (one per lane);
-// off: this lane's exclusive prefix sum of hit counts.
+// off: this lane's exclusive prefix sum of hit counts.  perm: take the hits
+// in the order queue field 11 lists (else lane by lane).
 // ck (non-null): checkpoint store of the adjoint entries; a hit whose
 // queue field 10 holds a slot c >= 0 stores its sweep checkpoints there.
 template <int MODE, class SL>
 __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
                                   const uint8_t* s_slot, const SL& sl, const HitQueue& hq, int total,
                                   int off, unsigned long long* n_fp64, unsigned long long* n_lay,
-                                  double* ck = nullptr, int64_t ck_total = 0)
+                                  double* ck = nullptr, int64_t ck_total = 0, bool perm = false)
 {
     const int lane = wave_lane();
     for (int b = 0; b < total; b += 64) {
         const int p = b + lane;
-        const int q = dense_slot(p < total ? p : total - 1, off, sc.Kmax);
+        const int pp = p < total ? p : total - 1;
+        const int q = perm ? (int)hq.base[11 * (int64_t)hq.cap + pp] : dense_slot(pp, off, sc.Kmax);
         if (p < total) {
             const double kappa = hq.kappa(q);
             const int meta = hq.meta(q);
@@ -372,6 +374,26 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                         hq.base[10 * (int64_t)cap + hq_slot(own, h)] = c;
                     }
                 }
+                // solve order: first the hits that may meet an evanescent
+                // layer (kappa^2 above the smallest lossless Re N^2), then the
+                // rest, so that most batches of 64 take the circular-only sweep
+                // (a batch's kind is still decided from its hits' own layers)
+                if (!MEMO) {
+                    int ne = 0;
+                    for (int h = 0; h < nh; ++h) {
+                        const double k = hq.kappa(hq_slot(own, h));
+                        ne += k * k > pl->kap2_evan ? 1 : 0;
+                    }
+                    int net;
+                    const int eo = wave_excl_scan(ne, &net);
+                    int pe = eo, pc = net + (off - eo);    // positions < total
+                    for (int h = 0; h < nh; ++h) {
+                        const int q = hq_slot(own, h);
+                        const double k = hq.kappa(q);
+                        const int pos = k * k > pl->kap2_evan ? pe++ : pc++;
+                        hq.base[11 * (int64_t)cap + pos] = (double)q;
+                    }
+                }
                 __threadfence_block();
                 const int u0 = n_keys;
                 if (MEMO && memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
@@ -379,7 +401,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
                 else
                     solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, off, &n_fp64, &n_lay,
-                                     cks ? st.ck : nullptr, st.ck_total);
+                                     cks ? st.ck : nullptr, st.ck_total, !MEMO);
                 __threadfence_block();
             }
             int nt = 0;

@@ -67,6 +67,13 @@ __device__ inline void stage_point(const SceneDev& sc, int d, int l, int f, Poin
             const double* dv = sc.dir_tab + ((int64_t)l * sc.F + f) * 4;
             pl->dir[0] = dv[0]; pl->dir[1] = dv[1]; pl->dir[2] = dv[2];
         }
+        double k2e = 1e300;
+        for (int s = 0; s < sc.n_slots; ++s)
+            if (!((sc.slot_complex >> s) & 1u)) {
+                const double nr = lt[LT_SLOT + 2 * s];
+                k2e = fmin(k2e, nr * nr);
+            }
+        pl->kap2_evan = k2e;
         for (int s = 0; s < kMaxSlots; ++s) {
             double nr = lt[LT_SLOT + 2 * s], ni = lt[LT_SLOT + 2 * s + 1];
             pl->slotN[2 * s] = nr; pl->slotN[2 * s + 1] = ni;

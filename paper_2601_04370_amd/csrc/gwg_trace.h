@@ -42,6 +42,9 @@ struct PointLds {
     // than held in scalar registers across the walk
     double T, Lx, nx, nz, ER, ex0, ew, ey0, eh;
     int32_t M, Kmax, bins_x, bins_y;
+    // smallest Re N^2 of a lossless slot: a hit whose kappa^2 exceeds it may
+    // meet an evanescent layer (+huge without lossless slots)
+    double kap2_evan;
 };
 // the slot tables read pxy in pairs (16-byte loads)
 static_assert(offsetof(PointLds, pxy) % 16 == 0, "pxy pairs must be 16-byte aligned");
@@ -304,7 +307,9 @@ struct HitQueue {
         return c;
     }
 };
-constexpr int kHitFields = 11;
+// Field 11 (non-memoized forward): the solve order, the slot of the wave's
+// p-th solved hit at position p.
+constexpr int kHitFields = 12;
 
 // ------------------------------------------------------------ tape
 // Field-changing events of one ray for the adjoint (this lane's doubles, stride ts).
