@@ -90,6 +90,8 @@ def lib():
                            C.c_double, C.c_double, _dp]
     L.orc_loss.restype = C.c_double
     L.orc_table_weights.argtypes = [C.c_double, C.c_int, _i32p, _dp]
+    L.orc_event_probe.argtypes = [C.POINTER(Scene), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  _dp, _dp, _dp, _dp]
     _lib = L
     return L
 
@@ -258,6 +260,19 @@ class OracleScene:
         assert rc == 0
         return bp, npaths.value
 
+    def event(self, surface, dir_in, E_in, reflect=0, d=0, li=0):
+        """One field-changing event in isolation (no Monte Carlo rescaling):
+        returns (event type, outgoing direction, outgoing complex field)."""
+        di = np.ascontiguousarray(dir_in, dtype=np.float64)
+        Ec = np.asarray(E_in, dtype=np.complex128)
+        ei = np.ascontiguousarray(np.stack([Ec.real, Ec.imag], -1).reshape(6))
+        do = np.zeros(3)
+        eo = np.zeros(6)
+        ev = lib().orc_event_probe(C.byref(self.s), int(d), int(li), int(surface), int(reflect),
+                                   _ptr(di, _dp), _ptr(ei, _dp), _ptr(do, _dp), _ptr(eo, _dp))
+        assert ev > 0, ev
+        return ev, do, eo[0::2] + 1j * eo[1::2]
+
     def forced(self, ray_id, bits, n_bits):
         w = C.c_double(0)
         p = C.c_double(0)
@@ -272,6 +287,7 @@ class OracleScene:
 # scalar reflectance equal to the mirror's reflection probability omega, so a
 # sampled path carries weight one and a ray adds 1 / N to the bin it reaches.
 _EV_MIRROR = 5
+SURF_TOP, SURF_BOTTOM = 1000, 1001
 
 
 def p_eff(omega) -> np.ndarray:

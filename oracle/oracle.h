@@ -153,6 +153,17 @@ int orc_split_bruteforce(const orc_scene* sc, int32_t d, int32_t lsel, int32_t f
 int orc_trace_forced(const orc_scene* sc, int64_t ray_id, uint64_t decisions, int n_decisions,
                      double* w, double* prob, int* n_used);
 
+/* One field-changing event in isolation (polarization pins): a ray of point
+ * (d, li, fov 0) with direction dir_in[3] and field E_in[6] ((re, im) of x,
+ * y, z) meets `surface`: a mirror index (branch `reflect`, no Monte Carlo
+ * rescaling) or ORC_SURF_TOP / ORC_SURF_BOTTOM (total internal reflection,
+ * exit or leak, as in the trace).  Writes the outgoing direction and field;
+ * returns the event type (1 TIR, 2 exit, 3 leak, 5 mirror), < 0 on a bad
+ * argument. */
+enum { ORC_SURF_TOP = 1000, ORC_SURF_BOTTOM = 1001 };
+int orc_event_probe(const orc_scene* sc, int32_t d, int32_t li, int32_t surface, int32_t reflect,
+                    const double dir_in[3], const double E_in[6], double dir_out[3], double E_out[6]);
+
 /* --------------------------------------------------------------- the loss */
 /* irr: [D][n_l][F][B] irradiance.  kind 0: -mean eta + w_e Var_eyebox + w_f Var_fov;
  * kind 1: -mean eta + w_f CV_fov + w_e CV_eyebox (Eq. 1).  Returns L, writes dL/dI. */

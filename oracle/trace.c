@@ -321,6 +321,52 @@ static int face_coeffs(const ctx_t* c, vec3 d, double complex* rs, double comple
     return tir;
 }
 
+/* Face event at the top or bottom face (Eq. 3 at a bare glass/air
+ * interface, Eq. 5 for the field, basis recomputed for this interface).
+ * Total internal reflection keeps the ray in the glass: the field's s and p
+ * components are multiplied by r_s and r_p and re-assembled on the reflected
+ * basis.  Otherwise the top face emits the ray: the components are
+ * multiplied by t_s and t_p and by the square root of the flux ratio, so
+ * |E|^2 is the transmitted power, and the direction becomes the refracted
+ * one in air; the bottom face loses the ray with its field unchanged.
+ * Returns EV_TIR, EV_EXIT or EV_LEAK; t (optional) receives the tape entry
+ * of a field-changing event. */
+static int face_event(const ctx_t* c, ray_t* r, int s, tape_t* t)
+{
+    double complex rs, rp, ts, tp;
+    double flux;
+    int tir = face_coeffs(c, r->d, &rs, &rp, &ts, &tp, &flux);
+    vec3 zhat = { 0.0, 0.0, 1.0 };
+    vec3 sv = s_basis(r->d, zhat);
+    vec3 pin = cross3(r->d, sv);
+    if (tir) {
+        vec3 dnew = { r->d.x, r->d.y, -r->d.z };
+        vec3 pout = cross3(dnew, sv);
+        if (t) {
+            memset(t, 0, sizeof(*t));
+            t->type = EV_TIR; t->s = sv; t->pin = pin; t->pout = pout;
+            t->cs = rs; t->cp = rp; t->scale = 1.0; t->E_before = r->E;
+        }
+        r->E = apply_sp(r->E, sv, pin, pout, rs, rp, 1.0);
+        r->d = dnew;
+        r->last = s;
+        return EV_TIR;
+    }
+    if (s != SURF_TOP) return EV_LEAK;
+    double rn = c->ng / c->na;
+    double st2 = (c->ng * c->ng) * (r->d.x * r->d.x + r->d.y * r->d.y);
+    vec3 a = { rn * r->d.x, rn * r->d.y, sqrt(1.0 - st2 / (c->na * c->na)) };
+    vec3 pout = cross3(a, sv);
+    if (t) {
+        memset(t, 0, sizeof(*t));
+        t->type = EV_EXIT; t->s = sv; t->pin = pin; t->pout = pout;
+        t->cs = ts; t->cp = tp; t->scale = flux; t->E_before = r->E;
+    }
+    r->E = apply_sp(r->E, sv, pin, pout, ts, tp, flux);
+    r->d = a;
+    return EV_EXIT;
+}
+
 /* Outcome of one event. */
 typedef struct {
     int terminal;      /* 0 continue, else category + 1 */
@@ -495,47 +541,16 @@ static outcome_t trace_one(const ctx_t* c, int64_t ray_id, decider_t* dc,
         int branch = -1;
         int evtype = EV_MIRROR;
         if (s == SURF_TOP || s == SURF_BOTTOM) {
-            double complex rs, rp, ts, tp;
-            double flux;
-            int tir = face_coeffs(c, r.d, &rs, &rp, &ts, &tp, &flux);
-            vec3 zhat = { 0.0, 0.0, 1.0 };
-            vec3 sv = s_basis(r.d, zhat);
-            vec3 pin = cross3(r.d, sv);
-            if (tir) {
-                vec3 dnew = { r.d.x, r.d.y, -r.d.z };
-                vec3 pout = cross3(dnew, sv);
-                if (tape) {
-                    tape_t* t = &tape[nt++];
-                    memset(t, 0, sizeof(*t));
-                    t->type = EV_TIR; t->s = sv; t->pin = pin; t->pout = pout;
-                    t->cs = rs; t->cp = rp; t->scale = 1.0; t->E_before = r.E;
-                }
-                r.E = apply_sp(r.E, sv, pin, pout, rs, rp, 1.0);
-                r.d = dnew;
-                r.last = s;
-                evtype = EV_TIR;
-            } else if (s == SURF_TOP) {
-                evtype = EV_EXIT;
-                double rn = c->ng / c->na;
-                double st2 = (c->ng * c->ng) * (r.d.x * r.d.x + r.d.y * r.d.y);
-                vec3 a = { rn * r.d.x, rn * r.d.y, sqrt(1.0 - st2 / (c->na * c->na)) };
-                vec3 pout = cross3(a, sv);
-                double w_in = norm2c(r.E);
-                if (tape) {
-                    tape_t* t = &tape[nt++];
-                    memset(t, 0, sizeof(*t));
-                    t->type = EV_EXIT; t->s = sv; t->pin = pin; t->pout = pout;
-                    t->cs = ts; t->cp = tp; t->scale = flux; t->E_before = r.E;
-                }
-                r.E = apply_sp(r.E, sv, pin, pout, ts, tp, flux);
-                r.d = a;
-                o.a = a;
+            double w_in = norm2c(r.E);
+            evtype = face_event(c, &r, s, tape ? &tape[nt] : NULL);
+            if (tape && evtype != EV_LEAK) nt++;
+            if (evtype == EV_EXIT) {
+                o.a = r.d;
                 o.w = norm2c(r.E);
                 if (st) st->power[ORC_FACE_R] += w_in - o.w;
-                o.bin = eyebox_bin(sc, r.p, a);
+                o.bin = eyebox_bin(sc, r.p, r.d);
                 o.terminal = (o.bin >= 0 ? ORC_EYEBOX : ORC_MISS) + 1;
-            } else {
-                evtype = EV_LEAK;
+            } else if (evtype == EV_LEAK) {
                 o.terminal = ORC_LEAK + 1;
                 o.w = norm2c(r.E);
             }
@@ -800,26 +815,11 @@ static void split_rec(split_t* S, ray_t r, int k)
         if (s < 0) { S->paths++; return; }
         r.n_events++;
         if (s == SURF_TOP || s == SURF_BOTTOM) {
-            double complex rs, rp, ts, tp;
-            double flux;
-            int tir = face_coeffs(c, r.d, &rs, &rp, &ts, &tp, &flux);
-            vec3 zhat = { 0.0, 0.0, 1.0 };
-            vec3 sv = s_basis(r.d, zhat);
-            vec3 pin = cross3(r.d, sv);
-            if (tir) {
-                vec3 dnew = { r.d.x, r.d.y, -r.d.z };
-                r.E = apply_sp(r.E, sv, pin, cross3(dnew, sv), rs, rp, 1.0);
-                r.d = dnew;
-                r.last = s;
-                continue;
-            }
-            if (s == SURF_TOP) {
-                double rn = c->ng / c->na;
-                double st2 = (c->ng * c->ng) * (r.d.x * r.d.x + r.d.y * r.d.y);
-                vec3 a = { rn * r.d.x, rn * r.d.y, sqrt(1.0 - st2 / (c->na * c->na)) };
-                cvec3 E = apply_sp(r.E, sv, pin, cross3(a, sv), ts, tp, flux);
-                int b = eyebox_bin(sc, r.p, a);
-                if (b >= 0) S->bin_power[b] += norm2c(E);
+            int ev = face_event(c, &r, s, NULL);
+            if (ev == EV_TIR) continue;
+            if (ev == EV_EXIT) {
+                int b = eyebox_bin(sc, r.p, r.d);
+                if (b >= 0) S->bin_power[b] += norm2c(r.E);
             }
             S->paths++;
             return;
@@ -855,4 +855,44 @@ int orc_split_bruteforce(const orc_scene* sc, int32_t d, int32_t lsel, int32_t f
     if (n_paths) *n_paths = S.paths;
     ctx_free(&c);
     return 0;
+}
+
+/* ------------------------------------------------------ single-event probe */
+/* One field-changing event in isolation, for the polarization pins: a ray of
+ * point (d, li, fov 0) in the glass with direction dir_in and complex field
+ * E_in (x, y, z as (re, im) pairs) meets `surface` (a mirror index, or
+ * ORC_SURF_TOP / ORC_SURF_BOTTOM).  A mirror applies the branch `reflect`
+ * without the Monte Carlo 1/sqrt(p) factor; a face reflects totally or emits
+ * the ray (top) exactly as in the trace.  Returns the event type (1 TIR,
+ * 2 exit, 3 leak, 5 mirror) or a negative value for a bad argument. */
+int orc_event_probe(const orc_scene* sc, int32_t d, int32_t li, int32_t surface, int32_t reflect,
+                    const double dir_in[3], const double E_in[6], double dir_out[3], double E_out[6])
+{
+    if (d < 0 || d >= sc->n_designs || li < 0 || li >= sc->n_lsel) return -2;
+    if (!(surface == SURF_TOP || surface == SURF_BOTTOM || (surface >= 0 && surface < sc->n_mirrors)))
+        return -3;
+    ctx_t c;
+    if (ctx_init(&c, sc)) return -1;
+    ctx_point(&c, d, li, 0);
+    ray_t r;
+    memset(&r, 0, sizeof(r));
+    r.d.x = dir_in[0]; r.d.y = dir_in[1]; r.d.z = dir_in[2];
+    r.E.x = CMPLX(E_in[0], E_in[1]);
+    r.E.y = CMPLX(E_in[2], E_in[3]);
+    r.E.z = CMPLX(E_in[4], E_in[5]);
+    r.last = -1;
+    int ev;
+    if (surface == SURF_TOP || surface == SURF_BOTTOM) {
+        ev = face_event(&c, &r, surface, NULL);
+    } else {
+        r.cell = surface;
+        mirror_event(&c, &r, surface, reflect ? 1 : 0, 0, NULL);
+        ev = EV_MIRROR;
+    }
+    dir_out[0] = r.d.x; dir_out[1] = r.d.y; dir_out[2] = r.d.z;
+    E_out[0] = creal(r.E.x); E_out[1] = cimag(r.E.x);
+    E_out[2] = creal(r.E.y); E_out[3] = cimag(r.E.y);
+    E_out[4] = creal(r.E.z); E_out[5] = cimag(r.E.z);
+    ctx_free(&c);
+    return ev;
 }

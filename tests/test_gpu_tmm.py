@@ -1,24 +1,25 @@
 """Parity of gwg_tmm_rt (per-hit thin-film solve on the GPU) with the oracle.
 
-FP64: within 1e-10 (1e-12 for short stacks) of the oracle's recursive-Airy
-solve (an independent formulation).  FP32: the error distribution is measured and bounded at the
-level single precision can reach; the tracer's re-solve rule is exercised
-through the mixed mode.
+FP64: within 1e-12 of the oracle's recursive-Airy solve (an independent
+formulation) on lossless stacks of 0 to 200 layers, and within 2e-11 on the
+201-layer stack with an absorbing Ag layer, where two independent CPU
+formulations already differ by 4.2e-12 (`tmm_cases.FP64_TOL`).  FP32: the
+error distribution is measured and reported; the tracer's re-solve rule is
+exercised through the mixed mode.
 """
 import numpy as np
 import pytest
 import torch
 
 import inputs
+import tmm_cases
 from inputs import MAT_AG, MAT_AIR, MAT_AL2O3, MAT_GLASS, MAT_SIO2, MAT_TIO2
 
 pytestmark = pytest.mark.gpu
 
 
 def _tables(lams=(460.0, 530.0, 620.0)):
-    w = inputs.small_variant("diff_1200", lambdas_nm=lams)
-    inp = inputs.make_inputs(w)
-    return inp["lambda_nm"], inp["n_re"], inp["n_im"]
+    return tmm_cases.tables(lams)
 
 
 def _oracle(orc, thk, mat, nre, nim, lam, mat_in, mat_out, li, th):
@@ -27,35 +28,25 @@ def _oracle(orc, thk, mat, nre, nim, lam, mat_in, mat_out, li, th):
     return orc.tmm_rt(thk, N, nre[li, mat_in], n_out, lam[li], theta=th)
 
 
-def _queries(rng, n, nlam, crit_frac=0.2, lo=0.0, hi=89.0):
-    li = rng.integers(0, nlam, size=n).astype(np.int32)
-    th = np.radians(rng.uniform(lo, hi, size=n))
-    k = int(crit_frac * n)
-    # near the SiO2/glass critical angle (about 73.9 deg)
-    th[:k] = np.radians(rng.uniform(71.5, 76.5, size=k))
-    return li, th
+_queries = tmm_cases.queries
 
 
 @pytest.mark.parametrize("L,with_ag", [(0, False), (1, False), (8, False), (40, False), (200, False), (201, True)])
 def test_tmm_fp64_matches_oracle(gctx, orc, L, with_ag):
-    rng = np.random.default_rng(L)
     lam, nre, nim = _tables()
-    cyc = [MAT_SIO2, MAT_TIO2, MAT_AL2O3]
-    mat = np.array([cyc[j % 3] for j in range(L)], dtype=np.uint8)
-    thk = rng.uniform(0, 300, L)
-    if with_ag:
-        mat[100] = MAT_AG
-        thk[100] = 25.0
-    n = 256 * 5 + 37          # several workgroups and a ragged tail
-    li, th = _queries(rng, n, len(lam))
-    print(f"tmm fp64 L={L} ag={with_ag} n={n}", flush=True)
+    mat, thk, li, th, sample = tmm_cases.fp64_case(L, with_ag)
+    tol = tmm_cases.FP64_TOL[(L, with_ag)]
+    n = len(li)
+    print(f"tmm fp64 L={L} ag={with_ag} n={n} tol={tol:g}", flush=True)
     got = gctx.tmm_rt(torch.tensor(thk), mat, MAT_GLASS, MAT_GLASS, lam, nre, nim,
                       torch.tensor(li), torch.tensor(th), precision=0).cpu().numpy()
-    for q in range(0, n, 7):
+    worst = 0.0
+    for q in sample:
         ref = _oracle(orc, thk, mat, nre, nim, lam, MAT_GLASS, MAT_GLASS, li[q], th[q])
-        # two independent FP64 formulations; 201 layers with a metal layer near
-        # grazing incidence are conditioned at about 1e3
-        assert np.max(np.abs(got[q] - ref)) < 1e-10 * max(1.0, np.max(np.abs(ref))), (q, got[q], ref)
+        err = np.max(np.abs(got[q] - ref)) / max(1.0, np.max(np.abs(ref)))
+        worst = max(worst, err)
+        assert err < tol, (q, got[q], ref)
+    print(f"  max rel error {worst:.3e}", flush=True)
 
 
 def test_tmm_exit_media(gctx, orc):

@@ -13,40 +13,9 @@ import os
 import numpy as np
 import pytest
 
+from numpy_ref import charmatrix, maxwell_event, qz
+
 HERE = os.path.dirname(os.path.abspath(__file__))
-
-
-def qz(N, kappa):
-    q = np.sqrt(np.complex128(N) ** 2 - kappa ** 2)
-    if q.imag < 0 or (q.imag == 0 and q.real < 0):
-        q = -q
-    return q
-
-
-def charmatrix(thk, N, n0, ns, lam, kappa):
-    """Characteristic-matrix solve (exp(-i w t)), converted to Eq. 3 amplitudes."""
-    k0 = 2 * np.pi / lam
-    q0, qs = qz(n0, kappa), qz(ns, kappa)
-    out = []
-    for pol in (0, 1):
-        eta0 = q0 if pol == 0 else n0 ** 2 / q0
-        etas = qs if pol == 0 else ns ** 2 / qs
-        Mt = np.eye(2, dtype=np.complex128)
-        for d, n in zip(thk, N):
-            q = qz(n, kappa)
-            eta = q if pol == 0 else n ** 2 / q
-            dl = k0 * q * d
-            Mj = np.array([[np.cos(dl), -1j * np.sin(dl) / eta], [-1j * eta * np.sin(dl), np.cos(dl)]])
-            Mt = Mt @ Mj
-        B, Cc = Mt @ np.array([1.0, etas])
-        r = (eta0 * B - Cc) / (eta0 * B + Cc)
-        t = 2 * eta0 / (eta0 * B + Cc)
-        if pol == 1:
-            r = -r
-            t = t * (q0 / n0) / (qs / ns)
-        out.append((r, t))
-    (rs, ts), (rp, tp) = out
-    return np.array([rs, rp, ts, tp])
 
 
 def rand_stack(rng, L, mats=(1.46, 2.35, 1.63), hi=300.0):
@@ -186,12 +155,37 @@ def test_single_interface_limits(orc):
     # below critical: no TIR
     c = orc.tmm_rt([], [], 1.52, 1.0, 550.0, theta=np.radians(40.0))
     assert abs(c[0]) < 0.9
-    # the s-phase on TIR: tan(phi_s / 2) = sqrt(sin^2 - n^2) / cos  (n = n2/n1), our sign
+    # the s-phase on TIR: with exp(-i w t) and a transmitted wave that decays
+    # into the air (Im q >= 0), r_s = (a - i b)/(a + i b), a = cos, b =
+    # sqrt(sin^2 - n^2) (n = n2/n1), so arg r_s = -2 atan(b / a): signed
     th = np.radians(55.0)
     nrel = 1.0 / 1.52
     phi = 2 * np.arctan(np.sqrt(np.sin(th) ** 2 - nrel ** 2) / np.cos(th))
     c = orc.tmm_rt([], [], 1.52, 1.0, 550.0, theta=th)
-    assert abs(abs(np.angle(c[0])) - phi) < 1e-13
+    assert abs(np.angle(c[0]) + phi) < 1e-13
+
+
+@pytest.mark.parametrize("n_out", [1.0, 1.46, 2.35, 0.12 + 3.3j])
+def test_single_interface_solves_maxwell(orc, n_out):
+    """0 layers: r_s, r_p, t_s, t_p (Eq. 3 amplitudes, p = k x s) equal the
+    field ratios of a laboratory-frame solve of Maxwell's boundary conditions,
+    signs and phases included, below and above the critical angle."""
+    n0, lam = 1.52, 550.0
+    for deg in np.linspace(0.5, 88.0, 23):
+        th = np.radians(deg)
+        d = np.array([np.sin(th), 0.0, np.cos(th)])
+        u = np.array([0.0, 0.0, 1.0])
+        s = np.cross(d, u) / np.linalg.norm(np.cross(d, u))
+        c = orc.tmm_rt([], [], n0, n_out, lam, theta=th)
+        Er, kr, Et, kt = maxwell_event(d, s.astype(complex), u, n0, [], n_out, lam)
+        assert abs(Er @ s - c[0]) < 1e-14 and abs(Et @ s - c[2]) < 1e-14, deg
+        p_in = np.cross(d, s)
+        Er, kr, Et, kt = maxwell_event(d, p_in.astype(complex), u, n0, [], n_out, lam)
+        # outgoing p = k x s on each wave's own (possibly complex) unit wave vector
+        p_r = np.cross(kr / n0, s)
+        p_t = np.cross(kt / np.sqrt(kt @ kt), s)
+        assert abs(Er @ p_r - c[1]) < 1e-14, deg
+        assert abs(Et @ p_t / (p_t @ p_t) - c[3]) < 1e-13, deg
 
 
 def test_single_layer_is_conjugate_airy(orc):
@@ -297,3 +291,23 @@ def test_quarter_wave_stationarity(orc):
     assert np.max(np.abs(dR)) < 1e-13
     # but the phase of r is not stationary
     assert np.max(np.abs(g[:, 0])) > 1e-4
+
+
+@pytest.mark.parametrize("case", [(40, False), (200, False), (201, True)])
+def test_fp64_formulation_spread(orc, case):
+    """Sizes the GPU thin-film tolerance: on the GPU parity test's own queries,
+    two independent double-precision formulations (the oracle's Rouard
+    recursion and the numpy characteristic-matrix product) differ by at most a
+    quarter of the tolerance that test applies (`tmm_cases.FP64_TOL`)."""
+    import tmm_cases
+    from inputs import MAT_GLASS
+    lam, nre, nim = tmm_cases.tables()
+    mat, thk, li, th, sample = tmm_cases.fp64_case(*case)
+    worst = 0.0
+    for q in sample:
+        N = nre[li[q], mat] + 1j * nim[li[q], mat]
+        ng = nre[li[q], MAT_GLASS]
+        a = orc.tmm_rt(thk, N, ng, ng + 0j, lam[li[q]], theta=th[q])
+        b = charmatrix(thk, N, ng, ng, lam[li[q]], ng * np.sin(th[q]))
+        worst = max(worst, np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a))))
+    assert worst <= tmm_cases.FP64_TOL[case] / 4, worst
