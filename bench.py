@@ -12,7 +12,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mix
 Prints one JSON line.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -41,13 +40,9 @@ FLOP_ADJ_LAYER = 125.0
 
 
 def source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2601_04370_amd", "csrc")
-    for n in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, n), "rb") as f:
-            h.update(n.encode())
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the library's sources (the one compiled into libgwg.so)."""
+    from paper_2601_04370_amd import build
+    return build.source_hash()
 
 
 def load_traffic(kernel: str, workload: str, precision: str):
@@ -64,41 +59,91 @@ def load_traffic(kernel: str, workload: str, precision: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(w, inp, budget_s: float, forward_only: bool = False):
-    """The FP64 oracle (single-threaded C) on a bounded sample of the same
-    workload: every s-th ray, forward + loss + adjoint (or forward only)."""
-    import numpy as np
-    import oracle
-    osc = oracle.OracleScene(w, inp)
-    n_rays = w.n_rays
-
-    def run(stride):
-        irr = osc.forward_sampled(stride)
-        if not forward_only:
-            _, g = oracle.loss(irr, 0)
-            osc.backward(g, stride)
-
-    # calibrate on a tiny sample
-    s0 = max(1, n_rays // 60)
-    t = time.perf_counter()
-    run(s0)
-    per_ray = (time.perf_counter() - t) / max(1, n_rays // s0)
-    # two passes: the first corrects the calibration (cold caches, tiny sample)
-    for _ in range(2):
-        stride = max(1, int(n_rays / max(1.0, budget_s / max(per_ray, 1e-9))))
-        ids = np.arange(0, n_rays, stride)
+def _oracle_workers(name, rays_per_point, chunks, forward_only):
+    """Run the oracle on each chunk of whole points in its own process
+    (`oracle.points`), all released together once every one has built its
+    scenes; returns the wall time from release to the last result and the
+    per-process results."""
+    import subprocess
+    procs = []
+    try:
+        for pts in chunks:
+            arg = json.dumps({"workload": name, "rays_per_point": rays_per_point,
+                              "points": [list(p) for p in pts], "forward_only": forward_only})
+            procs.append(subprocess.Popen([sys.executable, "-m", "oracle.points", arg], cwd=ROOT,
+                                          stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True))
+        for p in procs:
+            if p.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle worker failed to start")
         t = time.perf_counter()
-        run(stride)
-        el = time.perf_counter() - t
-        per_ray = el / len(ids)
-        if el >= 0.5 * budget_s:
-            break
-    recs = osc.trace_rays(ids)
-    n_int = int(sum(r.n_events for r in recs))
+        for p in procs:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        res = [json.loads(p.stdout.readline()) for p in procs]
+        wall = time.perf_counter() - t
+        for p in procs:
+            if p.wait(timeout=60) != 0:
+                raise RuntimeError("oracle worker failed")
+        return wall, res
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, inp, name: str, rays_per_point: int, interactions_per_point: float,
+                 forward_only: bool = False, min_interactions: float = 1e6, max_cores: int = 16):
+    """The FP64 oracle (plain C, as it stands) on whole (wavelength, FoV)
+    points of the same workload, forward + loss + adjoint (or forward only):
+
+    - one thread: the fewest points spread over the grid that hold at least
+      `min_interactions` interactions;
+    - all host cores: one worker process per core (at most `max_cores`, the
+      host's share for one GPU), each running whole points of its own, the
+      same number of points per core, released together and timed by the
+      wall clock from release to the last result.
+
+    The point loop runs the oracle's own calls; only the points differ
+    between workers (each point's rays are those of a workload holding that
+    point alone)."""
+    import math
+    n_l = len(w.lambdas_nm)
+    F = w.n_fov
+    n_pts = n_l * F
+    ipp = max(interactions_per_point, 1.0)
+    k1 = max(1, min(n_pts, math.ceil(min_interactions / ipp)))
+    pts = [divmod(int(j * n_pts / k1), F) for j in range(k1)]
+    el1, r1 = _oracle_workers(name, rays_per_point, [pts], forward_only)
+    int1 = r1[0]["interactions"]
+    el1 = r1[0]["seconds"]
+    cores = max(1, min(len(os.sched_getaffinity(0)), max_cores))
+    per_core = max(1, math.ceil(min_interactions / (ipp * cores)))
+    total = min(n_pts, per_core * cores)
+    allpts = [divmod(int(j * n_pts / total), F) for j in range(total)]
+    chunks = [allpts[c::cores] for c in range(cores)]
+    chunks = [c for c in chunks if c]
+    wall, res = _oracle_workers(name, rays_per_point, chunks, forward_only)
+    intn = sum(r["interactions"] for r in res)
     what = "forward" if forward_only else "forward + loss + adjoint"
-    return {"value": n_int / el, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"every {stride}th ray of the workload ({len(ids)} rays, {n_int} interactions), "
-                      f"{what}, {el:.1f} s single-threaded FP64 C"}
+    return {"value": intn / wall, "unit": UNIT, "cores": len(chunks), "kind": "oracle",
+            "sample": f"{len(allpts)} whole (wavelength, FoV) points of the workload ({intn} interactions, "
+                      f"{w.rays_per_point} rays each), {what}, FP64 C, one worker process per core, "
+                      f"{wall:.1f} s wall",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "single_thread": {"value": int1 / el1, "unit": UNIT, "cores": 1,
+                              "sample": f"{len(pts)} whole points ({int1} interactions), {what}, "
+                                        f"{el1:.1f} s"}}
 
 
 def copy_probe(torch, mib: int = 1024, reps: int = 5):
@@ -145,7 +190,8 @@ def main():
                     help="rays per work item (tuning rays_per_block; 0: the library's choice)")
     ap.add_argument("--per-design", action="store_true",
                     help="also time one launch per design (the batched workload) for comparison")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-interactions", type=float, default=1e6,
+                    help="interactions in each CPU-baseline sample (whole points)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (calibrates HBM byte counters)")
@@ -359,12 +405,14 @@ def main():
                    "step": "forward" if fo else "forward+loss+adjoint",
                    "thin_film": ("memoized per distinct hit key" if a.memo else
                                  "angle table, Catmull-Rom interpolation" if a.table else "per hit"),
-                   "launch": "graph" if a.graph else "eager"},
+                   "launch": "graph" if a.graph else "eager",
+                   "library_source_hash": gwg.source_hash()},
         "roofline": roof,
         "extra": extra,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, inp, a.cpu_seconds, forward_only=fo)
+        out["cpu_baseline"] = cpu_baseline(w, inp, a.workload, a.rays_per_point, inter / K / w.n_points,
+                                           forward_only=fo, min_interactions=a.cpu_interactions)
     print(json.dumps(out), flush=True)
 
 

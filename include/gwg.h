@@ -59,9 +59,13 @@ typedef enum {
 typedef enum {
     GWG_FP64 = 0,           /* every step in double precision */
     GWG_FP32_MIXED = 1,     /* thin-film solve in single precision, re-solved in
-                               double precision for flagged hits (near-critical
-                               angle or large estimated conditioning); geometry,
-                               fields and reductions in double precision */
+                               double precision for hits within 2 degrees of the
+                               critical angle of a layer material (the only
+                               re-solve rule); geometry, fields, the adjoint and
+                               reductions in double precision.  Does not reach
+                               |dR| <= 1e-5 on every hit of long stacks: their
+                               resonances, not the critical angle, carry the
+                               largest single-precision errors */
     GWG_FP32 = 2            /* thin-film solve in single precision, no re-solve
                                (diagnostics: measures the single-precision error) */
 } gwg_precision;
@@ -85,6 +89,11 @@ int gwg_destroy(gwg_ctx* ctx);
 const char* gwg_last_error(const gwg_ctx* ctx);
 /* ABI version (GWG_ABI_VERSION). */
 int32_t gwg_abi_version(void);
+/* Hash of the sources this library was built from: 16 hex digits of the
+ * SHA-256 over its kernel, host and header files and compile flags (fixed
+ * order), so that a caller can check that the library matches the sources
+ * beside it.  Static string, never NULL. */
+const char* gwg_source_hash(void);
 
 /* ------------------------------------------------------------ thin film */
 /* One coating stack in incidence order. */
@@ -273,9 +282,13 @@ int gwg_forward_kept_entries(const gwg_ctx* ctx, int32_t* kept);
 
 /* Gradient of a loss with respect to every layer thickness, given
  * d_dL_dI (device f64, the eyebox shape of the last forward).  The sampled
- * paths of the last forward are regenerated (same seed and step), so the
- * result is the pathwise derivative of the unquantized estimator
- * I = sum w / rays_per_point.  d_grad: device f64 [D][M][max_layers],
+ * paths of the last forward are used: when that forward ran with
+ * GWG_FWD_GRAD, the backward reads the adjoint entries it stored (and their
+ * stored sweep checkpoints) and runs only the thin-film adjoints; items whose
+ * entries did not fit, or a forward without GWG_FWD_GRAD, have their paths
+ * regenerated from the same seed and step.  Either way the result is the
+ * pathwise derivative of the unquantized estimator I = sum w /
+ * rays_per_point.  d_grad: device f64 [D][M][max_layers],
  * overwritten (padding slots get 0).  sample_stride >= 1: only rays with
  * id % sample_stride == 0 contribute (1 = all rays).  Deterministic: the
  * same inputs give bit-identical gradients.  stats: optional host struct

@@ -8,5 +8,5 @@ this package only marshals arguments to it.
 from .gwg import (  # noqa: F401
     FP64, FP32_MIXED, FP32, PRECISIONS, Context, GwgError, SceneSpec, load_library,
     make_trace_function, records_view, EXPORTS, LIB_PATH, KERNEL_FORWARD, KERNEL_ADJOINT,
-    TIMING_RING, GWG_FWD_GRAD, GWG_FWD_MEMO, GWG_FWD_TABLE,
+    TIMING_RING, GWG_FWD_GRAD, GWG_FWD_MEMO, GWG_FWD_TABLE, source_hash,
 )

@@ -3,8 +3,11 @@
 hipcc compiles the kernels and the host C ABI into one shared library.  The
 flags disable packed-FP32 instruction selection and FMA contraction (the
 thin-film kernels opt back into contraction locally), and keep
-IEEE-conforming division and square root.
+IEEE-conforming division and square root.  The library carries the hash of
+the sources it was built from (gwg_source_hash), so a loader can refuse a
+library that does not match the sources beside it.
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -35,9 +38,24 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over every source file of the
+    library (kernels, host code, the C header) and the compile flags, in a
+    fixed order."""
+    h = hashlib.sha256()
+    for path in sources():
+        h.update(os.path.relpath(path, ROOT).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+        h.update(b"\0")
+    h.update(" ".join(FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + srcs
+    cmd = ([hipcc()] + FLAGS + ['-DGWG_SOURCE_HASH="%s"' % source_hash()]
+           + ["-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + srcs)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

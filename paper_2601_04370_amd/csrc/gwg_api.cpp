@@ -483,6 +483,11 @@ extern "C" {
 
 int32_t gwg_abi_version(void) { return GWG_ABI_VERSION; }
 
+#ifndef GWG_SOURCE_HASH
+#error "GWG_SOURCE_HASH must be defined by the build (hash of the library's sources)"
+#endif
+const char* gwg_source_hash(void) { return GWG_SOURCE_HASH; }
+
 int gwg_create(gwg_ctx** out, int32_t device)
 {
     if (!out) return fail(nullptr, GWG_E_INVAL, "out is NULL");

@@ -101,7 +101,7 @@ class Tuning(C.Structure):
 EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gwg_tmm_rt",
            "gwg_trace_forward", "gwg_trace_backward", "gwg_loss", "gwg_set_tuning", "gwg_get_tuning",
            "gwg_set_timing", "gwg_kernel_times", "gwg_set_step_source", "gwg_autotune", "gwg_forward_kept_entries",
-           "gwg_omega_gradient"]
+           "gwg_omega_gradient", "gwg_source_hash"]
 
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 GWG_FWD_GRAD = 1
@@ -119,6 +119,14 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
     L = C.CDLL(path)
+    L.gwg_source_hash.restype = C.c_char_p
+    built = L.gwg_source_hash().decode()
+    if path == LIB_PATH:
+        from . import build as _build
+        want = _build.source_hash()
+        if built != want:
+            raise ImportError(f"{path} was built from other sources (library {built}, sources {want}): "
+                              "rebuild it with `python -c 'import __graft_entry__ as g; g.build()'`")
     L.gwg_abi_version.restype = C.c_int32
     L.gwg_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32]
     L.gwg_destroy.argtypes = [C.c_void_p]
@@ -145,6 +153,11 @@ def load_library(path: str = LIB_PATH):
     L.gwg_kernel_times.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     _lib = L
     return L
+
+
+def source_hash() -> str:
+    """Source hash compiled into the loaded library (equal to the sources' own)."""
+    return load_library().gwg_source_hash().decode()
 
 
 def _np_ptr(a: np.ndarray, t):
@@ -443,8 +456,12 @@ def make_trace_function():
     class GWGTrace(torch.autograd.Function):
         @staticmethod
         def forward(fctx, thk, context: Context, scene: SceneSpec, seed: int, step: int, precision: int):
-            q, c, irr, _, _ = context.trace_forward(scene, thk.detach().contiguous(), seed, step, precision,
+            # the library keeps this pointer and reads the thicknesses again in
+            # the backward, so the contiguous copy must outlive this call
+            thk_c = thk.detach().contiguous()
+            q, c, irr, _, _ = context.trace_forward(scene, thk_c, seed, step, precision,
                                                     grad=thk.requires_grad)
+            fctx.thk_c = thk_c
             fctx.context = context
             fctx.scene = scene
             fctx.forward_id = context.forward_id
@@ -457,6 +474,7 @@ def make_trace_function():
             if fctx.context.forward_id != fctx.forward_id:
                 raise GwgError(GWG_E_STATE, "another forward ran on this context before this backward")
             g = fctx.context.trace_backward(grad_irr, fctx.scene)
+            fctx.thk_c = None
             return g, None, None, None, None, None
 
     return GWGTrace

@@ -73,3 +73,11 @@ def test_create_reports_missing_device(lib):
     assert len(lib.gwg_last_error(None)) > 0
     with pytest.raises(Exception):
         gwg.Context(0)
+
+
+def test_library_matches_its_sources(lib):
+    """The loaded library carries the hash of the sources beside it."""
+    from paper_2601_04370_amd import build, gwg
+    h = lib.gwg_source_hash()
+    assert h.decode() == build.source_hash() == gwg.source_hash()
+    assert len(h) == 16

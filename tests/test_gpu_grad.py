@@ -140,6 +140,35 @@ def test_autograd_function(gctx, orc):
     assert np.max(np.abs(g - og)) <= 1e-6 * np.max(np.abs(og))
 
 
+def test_autograd_function_non_contiguous_leaf(gctx):
+    """A non-contiguous thickness leaf: the library reads a contiguous copy in
+    the forward and again in the backward; the copy must stay alive in
+    between even when the allocator is busy, so the gradient equals that of
+    a contiguous leaf bit for bit."""
+    w = inputs.small_variant("diff_1200", rays_per_point=64, fov_n=3)
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    GWGTrace = gwg.make_trace_function()
+    grads = []
+    for contiguous in (True, False):
+        if contiguous:
+            thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0", requires_grad=True)
+        else:
+            base = torch.tensor(np.ascontiguousarray(inp["thk"].transpose(2, 1, 0)), dtype=torch.float64,
+                                device="cuda:0")
+            thk = base.permute(2, 1, 0).detach().requires_grad_(True)
+            assert not thk.is_contiguous() and thk.is_leaf
+            del base
+        irr = GWGTrace.apply(thk, gctx, scene, w.seed, 0, gwg.FP64)
+        # churn the caching allocator between forward and backward
+        junk = [torch.full(inp["thk"].shape, 1e3, dtype=torch.float64, device="cuda:0") for _ in range(8)]
+        weights = torch.linspace(0.5, 1.5, irr.numel(), dtype=torch.float64, device="cuda:0").view_as(irr)
+        (irr * weights).sum().backward()
+        del junk
+        grads.append(thk.grad.cpu().numpy())
+    assert np.array_equal(grads[0], grads[1])
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 def test_loss_matches_oracle(gctx, orc, kind):
     rng = np.random.default_rng(kind)

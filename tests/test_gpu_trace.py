@@ -16,11 +16,11 @@ import paper_2601_04370_amd as gwg
 pytestmark = pytest.mark.gpu
 
 
-def _run(gctx, w, inp, precision=0, stride=1, step=0, stats=True):
+def _run(gctx, w, inp, precision=0, stride=1, step=0, stats=True, grad=False):
     scene = gwg.SceneSpec.from_workload(w, inp)
     thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
     q, c, irr, rec, st = gctx.trace_forward(scene, thk, w.seed, step, precision, record_stride=stride,
-                                            stats=stats)
+                                            stats=stats, grad=grad)
     torch.cuda.synchronize()
     return scene, q.cpu().numpy().astype(np.uint64), c.cpu().numpy().astype(np.uint32), \
         irr.cpu().numpy(), (gwg.records_view(rec) if rec is not None else None), st
@@ -35,27 +35,48 @@ CASES = [
 ]
 
 
+_ORACLE_CACHE = {}
+
+
+def _oracle_forward(orc, name, w, inp):
+    """Oracle forward, sampled irradiance and every ray's record (cached per case)."""
+    key = (name, repr(w))
+    if key not in _ORACLE_CACHE:
+        osc = orc.OracleScene(w, inp)
+        oq, oc, ows, ost = osc.forward()
+        oirr = osc.forward_sampled(1)
+        orec = osc.trace_rays(np.arange(w.n_rays))
+        _ORACLE_CACHE[key] = (oq, oc, ost, oirr, orec)
+    return _ORACLE_CACHE[key]
+
+
+# forward flavours: plain; with the gradient flag (adjoint entries, tape and
+# the stored sweep checkpoints of the default tuning), which is the forward a
+# training step (and the benchmark) runs; with the gradient flag but no
+# stored checkpoints
+FWD_MODES = {"plain": (False, 0), "grad": (True, 0), "grad_nock": (True, -1)}
+
+
+@pytest.mark.parametrize("fwd", list(FWD_MODES))
 @pytest.mark.parametrize("name,kw,tile", CASES)
-def test_forward_fp64_matches_oracle(gctx, orc, name, kw, tile):
+def test_forward_fp64_matches_oracle(gctx, orc, name, kw, tile, fwd):
     w = inputs.small_variant(name, **kw)
     inp = inputs.make_inputs(w)
-    print(f"forward fp64 {name} {kw} tile={tile}", flush=True)
-    gctx.set_tuning(rays_per_block=tile)
+    grad, ck = FWD_MODES[fwd]
+    print(f"forward fp64 {name} {kw} tile={tile} {fwd}", flush=True)
+    gctx.set_tuning(rays_per_block=tile, ck_entries_per_ray=ck)
     try:
-        scene, q, c, irr, rec, st = _run(gctx, w, inp, 0, stride=1)
+        scene, q, c, irr, rec, st = _run(gctx, w, inp, 0, stride=1, grad=grad)
+        assert gctx.forward_kept_entries() == grad
     finally:
         gctx.set_tuning()
-    osc = orc.OracleScene(w, inp)
-    oq, oc, ows, ost = osc.forward()
+    oq, oc, ost, oirr, orec = _oracle_forward(orc, name, w, inp)
     assert np.array_equal(c, oc), "bin counts differ"
     # at most one fixed-point unit per ray of rounding difference
     dq = np.abs(q.astype(np.int64) - oq.astype(np.int64))
     assert np.all(dq <= oc.astype(np.int64)), dq.max()
-    oirr = osc.forward_sampled(1)
     assert np.array_equal(irr, q.astype(np.float64) * (2.0 ** -24 / w.rays_per_point))
     # per-ray records against the oracle, every ray
-    n = scene.n_rays
-    orec = osc.trace_rays(np.arange(n))
     ob = np.array([r.bin for r in orec])
     oc_ = np.array([r.category for r in orec])
     on = np.array([r.n_events for r in orec])
@@ -175,24 +196,37 @@ def test_forward_memo_table_overflow(gctx, memo_keys):
 
 def test_full_size_sampled_rays(gctx, orc):
     """Differentiation workload at full size (6 mirrors x 200 layers, 3
-    wavelengths, 21 x 21 FoV, 4096 rays per point) in the default launch
-    configuration: every 4099th ray is compared with the oracle."""
+    wavelengths, 21 x 21 FoV, 8192 rays per point) in the default launch
+    configuration, with and without the gradient flag (the forward of a
+    training step, with adjoint entries and stored sweep checkpoints): the
+    bins of both are identical bit for bit, and every 4099th ray of each is
+    compared with the oracle."""
     w = inputs.workload("diff_1200")
     inp = inputs.make_inputs(w)
     stride = 4099
-    scene, q, c, irr, rec, st = _run(gctx, w, inp, 0, stride=stride)
-    ids = np.arange(0, scene.n_rays, stride)
+    ids = np.arange(0, w.n_rays, stride)
     osc = orc.OracleScene(w, inp)
     orec = osc.trace_rays(ids)
-    assert np.array_equal(rec["bin"], [r.bin for r in orec])
-    assert np.array_equal(rec["n_events"], [r.n_events for r in orec])
     ow = np.array([r.w for r in orec])
-    assert np.max(np.abs(rec["w"] - ow)) <= 1e-11 * max(1.0, ow.max())
-    # properties that hold at any size
-    assert c.sum() == st["n_cat"]["eyebox"]
-    assert st["rays"] == scene.n_rays
-    print(f"full size: {scene.n_rays} rays, {st['interactions']} interactions, "
-          f"{st['prma_hits']} mirror hits, {len(ids)} rays compared", flush=True)
+    runs = {}
+    for grad in (False, True):
+        print(f"full size diff_1200 grad={grad}", flush=True)
+        scene, q, c, irr, rec, st = _run(gctx, w, inp, 0, stride=stride, grad=grad)
+        assert gctx.forward_kept_entries() == grad
+        assert np.array_equal(rec["bin"], [r.bin for r in orec])
+        assert np.array_equal(rec["category"], [r.category for r in orec])
+        assert np.array_equal(rec["n_events"], [r.n_events for r in orec])
+        assert np.array_equal(rec["n_prma"], [r.n_prma for r in orec])
+        assert np.max(np.abs(rec["w"] - ow)) <= 1e-11 * max(1.0, ow.max())
+        # properties that hold at any size
+        assert c.sum() == st["n_cat"]["eyebox"]
+        assert st["rays"] == scene.n_rays
+        runs[grad] = (q, c, irr, st)
+        print(f"  {scene.n_rays} rays, {st['interactions']} interactions, "
+              f"{st['prma_hits']} mirror hits, {len(ids)} rays compared", flush=True)
+    for a, b in zip(runs[False][:3], runs[True][:3]):
+        assert np.array_equal(a, b)
+    assert runs[False][3]["interactions"] == runs[True][3]["interactions"]
 
 
 def test_kernel_timing_rings(gctx):
