@@ -307,6 +307,22 @@ int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t 
              int32_t B, int32_t kind, double w_f, double w_e, double* d_loss,
              double* d_dL_dI, void* stream);
 
+/* gwg_loss without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * gwg_loss; its work buffer is a fixed 4 MiB device array inside the library
+ * (one per GPU, held until the process ends, its address looked up when a
+ * context is created on that GPU) instead of context memory.  The shape must
+ * satisfy D * (n_l * F + B + F + 8) <= 524288, else GWG_E_INVAL (nothing is
+ * launched; gwg_loss has no such limit).  Every call on one GPU shares that
+ * array, whichever context or stream it comes from: calls that overlap in
+ * time on one GPU (different streams, or different host threads) race and
+ * give wrong results; serialize them.  The caller still provides d_irr,
+ * d_loss and d_dL_dI. */
+int gwg_loss_noalloc(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
+                     int32_t B, int32_t kind, double w_f, double w_e, double* d_loss,
+                     double* d_dL_dI, void* stream);
+
 /* ---------------------------------------------------------------- tuning */
 /* Launch parameters of the trace kernels (0 = automatic).  rays_per_block
  * is the tile of rays of one (design, wavelength, FoV) point handled by a

@@ -499,6 +499,13 @@ int gwg_create(gwg_ctx** out, int32_t device)
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(nullptr, GWG_E_NODEVICE, "device query failed");
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(nullptr, GWG_E_NODEVICE, "device %d is %s, not gfx950", device, prop.gcnArchName);
+    {
+        // the allocation-free loss's scratch address on this device
+        DeviceGuard g(device);
+        const hipError_t e = loss_scratch_setup(device);
+        if (e != hipSuccess)
+            return fail(nullptr, GWG_E_HIP, "scratch symbol lookup on device %d: %s", device, hipGetErrorString(e));
+    }
     gwg_ctx* c = new gwg_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
@@ -980,10 +987,36 @@ int gwg_loss(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
     hipStream_t s = (hipStream_t)stream;
     const bool cap = stream_capturing(s);
     int rc = GWG_OK;
-    size_t n = (size_t)D * n_l * F + (size_t)D * B + (size_t)D * F + (size_t)D * 8;
+    size_t n = (size_t)loss_work_doubles(D, n_l, F, B);
     rc = ensure_buf(c, c->loss_work, n * sizeof(double), cap, "alloc loss work");
     if (rc) return rc;
     HIP_CHECK(c, launch_loss(d_irr, D, n_l, F, B, kind, w_f, w_e, (double*)c->loss_work.p, d_loss, d_dL_dI, s),
+              "loss kernels");
+    return GWG_OK;
+}
+
+int gwg_loss_noalloc(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, int32_t F, int32_t B, int32_t kind,
+                     double w_f, double w_e, double* d_loss, double* d_dL_dI, void* stream)
+{
+    if (!c) return GWG_E_INVAL;
+    c->err.clear();
+    if (!d_irr || !d_loss) return fail(c, GWG_E_INVAL, "NULL loss pointer");
+    if (D < 1 || n_l < 1 || F < 1 || B < 1) return fail(c, GWG_E_INVAL, "loss shape invalid");
+    if ((int64_t)D * n_l * F > 0x7fffffff) return fail(c, GWG_E_INVAL, "loss shape too large");
+    if (kind != 0 && kind != 1) return fail(c, GWG_E_INVAL, "kind must be 0 or 1");
+    if (!(is_fin(w_f) && is_fin(w_e))) return fail(c, GWG_E_INVAL, "weights must be finite");
+    const int64_t need = loss_work_doubles(D, n_l, F, B);
+    if (need > kLossScratchDoubles)
+        return fail(c, GWG_E_INVAL,
+                    "loss shape needs %lld doubles of scratch, more than the fixed %lld (D*(n_l*F + B + F + 8) "
+                    "must not exceed %lld); use gwg_loss",
+                    (long long)need, (long long)kLossScratchDoubles, (long long)kLossScratchDoubles);
+    DeviceGuard g(c->device);
+    double* work = loss_scratch(c->device);
+    if (!work) return fail(c, GWG_E_STATE, "no scratch address for device %d", c->device);
+    // every scratch word the kernels read is written by an earlier kernel of
+    // the same call, so nothing needs clearing
+    HIP_CHECK(c, launch_loss(d_irr, D, n_l, F, B, kind, w_f, w_e, work, d_loss, d_dL_dI, (hipStream_t)stream),
               "loss kernels");
     return GWG_OK;
 }

@@ -2,6 +2,7 @@
 // with fixed-point eyebox scatter, adjoint trace, gradient reduction,
 // irradiance and loss.  Launch wrappers at the end are the only entry points
 // used by the host API (gwg_api.cpp).
+#include <mutex>
 #include <type_traits>
 
 #include "gwg_internal.h"
@@ -733,6 +734,40 @@ hipError_t launch_loss(const double* I, int D, int nl, int F, int B, int kind, d
     hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, s, (const double*)coef, D, loss);
     if (G) hipLaunchKernelGGL(k_loss_grad, dim3(grid_for((int64_t)D * nl * F * B, 256)), dim3(256), 0, s, E, phi, coef, D, nl, F, B, G);
     return hipGetLastError();
+}
+
+// ------------------------------------------ allocation-free loss scratch
+// Work buffer of gwg_loss_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  On the host
+// the array's name is not a device address: its address on each device is
+// looked up once, with that device current, by hipGetSymbolAddress, and only
+// that pointer is ever passed to kernels.
+static __device__ __align__(256) double scratch[kLossScratchDoubles];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t loss_scratch_setup(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = (double*)p;
+    return hipSuccess;
+}
+
+double* loss_scratch(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace gwg

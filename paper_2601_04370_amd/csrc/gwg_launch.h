@@ -58,5 +58,17 @@ hipError_t launch_tmm_rt(int precision, const double* thk, const uint8_t* slot, 
                          hipStream_t s);
 hipError_t launch_loss(const double* I, int D, int nl, int F, int B, int kind, double w_f, double w_e,
                        double* work, double* loss, double* G, hipStream_t s);
+// Doubles of work a loss of shape (D, nl, F, B) uses (launch_loss's work).
+inline int64_t loss_work_doubles(int64_t D, int64_t nl, int64_t F, int64_t B)
+{
+    return D * nl * F + D * B + D * F + D * 8;
+}
+// Fixed-size device scratch of gwg_loss_noalloc (4 MiB per GPU).
+constexpr int64_t kLossScratchDoubles = 1 << 19;
+// Look up this device's scratch address (with `device` current); once per
+// device, thread-safe.
+hipError_t loss_scratch_setup(int device);
+// The device address of `device`'s scratch, or null before its setup.
+double* loss_scratch(int device);
 
 }  // namespace gwg

@@ -101,7 +101,7 @@ class Tuning(C.Structure):
 EXPORTS = ["gwg_abi_version", "gwg_create", "gwg_destroy", "gwg_last_error", "gwg_tmm_rt",
            "gwg_trace_forward", "gwg_trace_backward", "gwg_loss", "gwg_set_tuning", "gwg_get_tuning",
            "gwg_set_timing", "gwg_kernel_times", "gwg_set_step_source", "gwg_autotune", "gwg_forward_kept_entries",
-           "gwg_omega_gradient", "gwg_source_hash"]
+           "gwg_omega_gradient", "gwg_source_hash", "gwg_loss_noalloc"]
 
 KERNEL_FORWARD, KERNEL_ADJOINT, TIMING_RING = 0, 1, 64
 GWG_FWD_GRAD = 1
@@ -141,6 +141,7 @@ def load_library(path: str = LIB_PATH):
                                      C.c_void_p]
     L.gwg_loss.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                            C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gwg_loss_noalloc.argtypes = L.gwg_loss.argtypes
     L.gwg_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.gwg_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.gwg_set_timing.argtypes = [C.c_void_p, C.c_int32]
