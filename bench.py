@@ -253,7 +253,7 @@ def main():
                 ev[2].record()
                 ev[3].record()
             return irr
-        _, dLdI = ctx.loss(irr, 0)
+        _, dLdI = ctx.loss(irr, w.loss_kind, w.loss_wf, w.loss_we)
         if ev:
             ev[2].record()
         g = ctx.trace_backward(dLdI, sc)
@@ -317,7 +317,7 @@ def main():
         irr_t = irr_t.clone()
         g_t = None
         if not fo:
-            _, dLdI_t = ctx.loss(irr_t, 0)
+            _, dLdI_t = ctx.loss(irr_t, w.loss_kind, w.loss_wf, w.loss_we)
         _, _, irr_e, _, _ = ctx.trace_forward(scene, thk, w.seed, k, prec, grad=not fo)
         e_irr = float((irr_t - irr_e).abs().max() / irr_e.abs().max())
         tab = {"nodes": ctx.get_tuning()["table_nodes"] or 8192, "irradiance_max_rel_err": e_irr,
@@ -339,7 +339,7 @@ def main():
         lay_f += st["layer_steps"]
         fp64h += st["fp64_hits"]
         if not fo:
-            _, dLdI = ctx.loss(irr, 0)
+            _, dLdI = ctx.loss(irr, w.loss_kind, w.loss_wf, w.loss_we)
             _, bst = ctx.trace_backward(dLdI, scene, stats=True)
             lay_b += bst["layer_steps"]
             lay_a += bst["adjoint_layer_steps"]
@@ -392,7 +392,8 @@ def main():
     if not fo:
         extra.update({"bwd_kernel_ms": t_bwd * 1e3, "bwd_tflops": f_bwd / t_bwd / 1e12})
     out = {
-        "metric": (METRIC + (" (memoized thin film)" if a.memo else " (angle-table thin film)" if a.table else ""))
+        "metric": (METRIC + (" (memoized thin film)" if a.memo else " (angle-table thin film)" if a.table else "")
+                   + (" (pupil-image objective)" if w.eye_pupil_grid > 0 else ""))
         if not fo else "fwd ray-surface interactions/s",
         "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -406,6 +407,11 @@ def main():
                    "thin_film": ("memoized per distinct hit key" if a.memo else
                                  "angle table, Catmull-Rom interpolation" if a.table else "per hit"),
                    "launch": "graph" if a.graph else "eager",
+                   "objective": ({"pupils": f"{w.eye_pupil_grid}x{w.eye_pupil_grid}, "
+                                            f"{w.eye_pupil_diam_mm:g} mm diameter",
+                                  "loss": "Eq. 1 on pupil images (kind 2)", "w_f": w.loss_wf, "w_e": w.loss_we}
+                                 if w.eye_pupil_grid > 0 else
+                                 {"loss": f"kind {w.loss_kind}", "w_f": w.loss_wf, "w_e": w.loss_we}),
                    "library_source_hash": gwg.source_hash()},
         "roofline": roof,
         "extra": extra,

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GWG_ABI_VERSION 1
+#define GWG_ABI_VERSION 2
 
 typedef struct gwg_ctx gwg_ctx;   /* opaque; owns scratch memory and scene tables */
 
@@ -119,13 +119,27 @@ int gwg_tmm_rt(gwg_ctx* ctx, const gwg_stack* stack, const gwg_materials* mats,
 /* Slab: glass 0 <= z <= T_mm, 0 <= x <= L_mm, unbounded in y; rays enter
  * through the top-face window [pupil_x0, pupil_x0 + pupil_w] x
  * [-pupil_h/2, pupil_h/2]; they are binned on the plane z = T + eye_relief
- * over the rectangle [eye_x0, eye_x0 + eye_w) x [eye_y0, eye_y0 + eye_h). */
+ * over the rectangle [eye_x0, eye_x0 + eye_w) x [eye_y0, eye_y0 + eye_h).
+ *
+ * Eye pupils (Results, "System Architecture": a grid of pupil positions in
+ * the eyebox, whose images are the objective): with n_eye_pupils > 0 the
+ * eyebox plane holds that many circular pupils of radius
+ * eye_pupil_radius_mm centred at eye_pupil_xy_mm[2 p], [2 p + 1] (host,
+ * mm), and the "bins" are the pupils instead of the grid: a ray crossing the
+ * plane at (x, y) lands in pupil p when (x - cx)^2 + (y - cy)^2 < r^2, and
+ * every eyebox output holds one value per pupil (bins_x must equal
+ * n_eye_pupils and bins_y 1; the eye_x0..eye_h rectangle is then unused).
+ * Pupils must not overlap (centre distances >= 2 r), so a ray lands in at
+ * most one.  With n_eye_pupils = 0 the other two fields are ignored. */
 typedef struct {
     double T_mm, L_mm, eye_relief_mm;
     int32_t mat_glass, mat_air;
     double pupil_x0_mm, pupil_w_mm, pupil_h_mm;
     double eye_x0_mm, eye_y0_mm, eye_w_mm, eye_h_mm;
     int32_t bins_x, bins_y;     /* 1..4096 each */
+    int32_t n_eye_pupils;       /* 0 (eyebox grid) or 1..64 */
+    double eye_pupil_radius_mm; /* > 0 with pupils */
+    const double* eye_pupil_xy_mm;  /* host [n_eye_pupils][2] */
 } gwg_slab;
 
 /* Partially reflective mirror array: n_mirrors (1..16) parallel planes with
@@ -301,7 +315,10 @@ int gwg_trace_backward(gwg_ctx* ctx, const double* d_dL_dI, double* d_grad,
  * + w_f Var_f(phi_f); kind 1: -mean(eta) + w_f CV_f + w_e CV_b, with
  * eta = sum_b I (per wavelength and FoV point), E_b the mean of I over
  * wavelengths and FoV points, phi_f the mean of eta over wavelengths,
- * population moments.  d_loss: device f64 [1]; d_dL_dI: device f64, same
+ * population moments; kind 2 (pupil images, B = pupils): kind 1 with the
+ * brightness term -mean(eta) / B, the mean of I over wavelengths, FoV
+ * points and pupils (with the same number of wavelengths per colour
+ * channel, also the mean over colour channels).  d_loss: device f64 [1]; d_dL_dI: device f64, same
  * shape as d_irr (may be NULL).  Fixed-order reductions: deterministic. */
 int gwg_loss(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
              int32_t B, int32_t kind, double w_f, double w_e, double* d_loss,

@@ -79,6 +79,15 @@ class Workload:
     max_events: int = 64
     bins: Tuple[int, int] = (32, 32)  # (x, y)
     fp_shift: int = 24
+    # eye pupils: a grid x grid array of circular pupils of this diameter
+    # centred on the cells of an equal grid over the eyebox (0: eyebox bins)
+    eye_pupil_grid: int = 0
+    eye_pupil_diam_mm: float = 4.0
+    # the loss of a training step (Eq. 1): kind 0 variances, 1 coefficients
+    # of variation, 2 coefficients of variation on pupil images; weights
+    loss_kind: int = 0
+    loss_wf: float = 1.0
+    loss_we: float = 1.0
 
     # ---- derived workload geometry (input recipe, not the method) ----
     @property
@@ -97,6 +106,22 @@ class Workload:
         """Eyebox rectangle (x0, y0, width, height), mm, centred on the array."""
         side = self.n_mirrors * self.pitch_mm
         return self.center_x_mm - side / 2, -side / 2, side, side
+
+    @property
+    def eye_pupils(self) -> np.ndarray:
+        """Centres (x, y) of the eye pupils, mm, row by row (empty without
+        pupils): the centres of a grid x grid partition of the eyebox."""
+        g = self.eye_pupil_grid
+        if g <= 0:
+            return np.zeros((0, 2))
+        ex0, ey0, ew, eh = self.eyebox
+        return np.array([[ex0 + (i + 0.5) * ew / g, ey0 + (j + 0.5) * eh / g]
+                         for j in range(g) for i in range(g)], dtype=np.float64)
+
+    @property
+    def n_bins(self) -> int:
+        """Cells of one point's eyebox image: pupils, or bins."""
+        return self.eye_pupil_grid ** 2 if self.eye_pupil_grid > 0 else self.bins[0] * self.bins[1]
 
     @property
     def n_fov(self) -> int:
@@ -189,11 +214,15 @@ def make_inputs(w: Workload) -> dict:
         fov = np.array([[-h, h], [-h, h]], dtype=np.float64)
     px0, pxw, pyh = w.pupil
     ex0, ey0, ew, eh = w.eyebox
-    return dict(
+    out = dict(
         lambda_nm=lam, n_re=nre, n_im=nim, thk=thk, mat=mat, n_layers=nlay,
         omega=default_omega(M), fov=fov, lambda_sel=np.arange(len(lam), dtype=np.int32),
         pupil=(px0, pxw, pyh), eyebox=(ex0, ey0, ew, eh),
     )
+    if w.eye_pupil_grid > 0:
+        out["eye_pupils"] = w.eye_pupils
+        out["eye_pupil_r"] = 0.5 * w.eye_pupil_diam_mm
+    return out
 
 
 def _cfg(i: int, **kw) -> Workload:
@@ -217,6 +246,14 @@ WORKLOADS = {
     "precision_ag": _cfg(
         4, name="precision_ag", n_mirrors=6, n_layers=200, thk_range=(0.0, 300.0),
         ag_layer_at=100, rays_per_point=4096, bins=(32, 32)),
+    # the pupil-image objective: diff_1200's stacks, nine wavelengths (three
+    # per colour channel), a 3 x 3 grid of 4 mm eye pupils over the eyebox;
+    # the rays per point keep the interactions per step near diff_1200's
+    "pupil_rgb": _cfg(
+        6, name="pupil_rgb", n_mirrors=6, n_layers=200, thk_range=(0.0, 300.0),
+        lambdas_nm=(450.0, 470.0, 490.0, 500.0, 530.0, 560.0, 620.0, 660.0, 700.0),
+        rays_per_point=2752, bins=(9, 1), eye_pupil_grid=3, eye_pupil_diam_mm=4.0,
+        loss_kind=2, loss_wf=10.0, loss_we=3.0),
     "batched": _cfg(
         5, name="batched", n_mirrors=6, n_designs=64, n_layers=250,
         variable_layers=(10, 250), thk_range=(20.0, 200.0),

@@ -48,6 +48,7 @@ class Scene(C.Structure):
         ("rays_per_point", C.c_int64), ("max_events", C.c_int32), ("fp_shift", C.c_int32),
         ("seed", C.c_uint64), ("step", C.c_uint64),
         ("table_nodes", C.c_int32),
+        ("n_eye_pupils", C.c_int32), ("eye_pupil_r", C.c_double), ("eye_pupil_xy", _dp),
     ]
 
 
@@ -201,6 +202,13 @@ class OracleScene:
         s.seed = w.seed if seed is None else seed
         s.step = step
         s.table_nodes = table_nodes
+        ep = inp.get("eye_pupils")
+        if ep is not None and len(ep):
+            xy = keep("eye_pupils", ep, np.float64)
+            s.n_eye_pupils = xy.shape[0]
+            s.eye_pupil_r = float(inp["eye_pupil_r"])
+            s.eye_pupil_xy = _ptr(xy, _dp)
+            assert (s.bins_x, s.bins_y) == (xy.shape[0], 1)
         self.s = s
 
     @property

@@ -8,7 +8,14 @@
  * E_b is the mean of I_b over wavelengths and FoV points; the FoV profile
  * phi_f is the mean of eta over wavelengths.  kind 1 uses coefficients of
  * variation (std / mean, population std) as in the paper; kind 0 uses the
- * population variances (the differentiation workload's loss).  Summed over
+ * population variances (the differentiation workload's loss).  kind 2 is
+ * Eq. 1 on pupil images (Results: the images of a grid of pupil positions
+ * are the objective; the mean throughput is averaged over pupil positions,
+ * FoV samples and colour channels): I_b is then the power fraction through
+ * pupil b, the brightness term is the mean of I over (wavelength, FoV,
+ * pupil), i.e. mean eta / B, and the CV terms are those of kind 1 with the
+ * pupils as the eyebox samples.  With three wavelengths per colour channel
+ * the mean over channels equals the mean over wavelengths.  Summed over
  * designs.
  */
 #include <math.h>
@@ -46,6 +53,8 @@ double orc_loss(const double* irr, int32_t D, int32_t n_l, int32_t F, int32_t B,
         for (int b = 0; b < B; ++b) var_e += (eyeb[b] - ebar) * (eyeb[b] - ebar) / (double)B;
         for (int f = 0; f < F; ++f) var_f += (phi[f] - ibar) * (phi[f] - ibar) / (double)F;
         double L, ce_b, cf_f, c_mean_e, c_mean_f;
+        /* weight of the throughput's mean in the brightness term */
+        double bright = kind == 2 ? 1.0 / (double)B : 1.0;
         /* dL = -dIbar + a_e dVar_e + a_f dVar_f + m_e dEbar + m_f dIbar */
         double a_e, a_f, m_e, m_f;
         if (kind == 0) {
@@ -54,7 +63,7 @@ double orc_loss(const double* irr, int32_t D, int32_t n_l, int32_t F, int32_t B,
         } else {
             double sd_e = sqrt(var_e), sd_f = sqrt(var_f);
             double cv_e = sd_e / ebar, cv_f = sd_f / ibar;
-            L = -ibar + w_f * cv_f + w_e * cv_e;
+            L = -ibar * bright + w_f * cv_f + w_e * cv_e;
             a_e = sd_e > 0.0 ? w_e / (2.0 * sd_e * ebar) : 0.0;
             a_f = sd_f > 0.0 ? w_f / (2.0 * sd_f * ibar) : 0.0;
             m_e = -w_e * sd_e / (ebar * ebar);
@@ -72,7 +81,7 @@ double orc_loss(const double* irr, int32_t D, int32_t n_l, int32_t F, int32_t B,
                         cf_f = 2.0 * (phi[f] - ibar) / ((double)F * (double)n_l);
                         c_mean_e = 1.0 / ((double)B * npts);
                         c_mean_f = 1.0 / npts;
-                        G[((size_t)l * F + f) * B + b] = -1.0 / npts + a_e * ce_b + a_f * cf_f
+                        G[((size_t)l * F + f) * B + b] = -bright / npts + a_e * ce_b + a_f * cf_f
                                                          + m_e * c_mean_e + m_f * c_mean_f;
                     }
         }

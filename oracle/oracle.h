@@ -94,6 +94,16 @@ typedef struct {
     /* thin film per mirror hit: 0 = the exact response at the hit's angle;
      * n >= 4 = interpolated from an n-angle table (orc_table_weights) */
     int32_t table_nodes;
+    /* eye pupils (Results, "System Architecture": a grid of pupil positions
+     * in the eyebox, one image per pupil).  0: the eyebox is binned on the
+     * bins_x x bins_y grid.  n > 0: the eyebox plane holds n circular pupils
+     * of radius eye_pupil_r (mm) centred at eye_pupil_xy[2 p], [2 p + 1];
+     * a ray whose crossing (x, y) of that plane satisfies
+     * (x - cx)^2 + (y - cy)^2 < r^2 lands in pupil p (the pupils must not
+     * overlap), and "bin" p is pupil p: bins_x = n, bins_y = 1. */
+    int32_t n_eye_pupils;
+    double eye_pupil_r;
+    const double* eye_pupil_xy;
 } orc_scene;
 
 /* Termination categories. */
@@ -166,7 +176,9 @@ int orc_event_probe(const orc_scene* sc, int32_t d, int32_t li, int32_t surface,
 
 /* --------------------------------------------------------------- the loss */
 /* irr: [D][n_l][F][B] irradiance.  kind 0: -mean eta + w_e Var_eyebox + w_f Var_fov;
- * kind 1: -mean eta + w_f CV_fov + w_e CV_eyebox (Eq. 1).  Returns L, writes dL/dI. */
+ * kind 1: -mean eta + w_f CV_fov + w_e CV_eyebox (Eq. 1); kind 2: Eq. 1 on
+ * pupil images (B = pupils): -mean over (wavelength, FoV, pupil) of I +
+ * w_f CV_fov + w_e CV_pupils.  Returns L, writes dL/dI. */
 double orc_loss(const double* irr, int32_t D, int32_t n_l, int32_t F, int32_t B,
                 int32_t kind, double w_f, double w_e, double* dL_dI);
 

@@ -42,7 +42,7 @@ def main():
         t = time.perf_counter()
         _, _, wsum, st = osc.forward()
         if not args.get("forward_only"):
-            _, g = oracle.loss(wsum / osc.s.rays_per_point, 0)
+            _, g = oracle.loss(wsum / osc.s.rays_per_point, w.loss_kind, w.loss_wf, w.loss_we)
             osc.backward(g, 1)
         el += time.perf_counter() - t
         n_int += int(st.counters[1])

@@ -383,11 +383,22 @@ typedef struct {
     int used;
 } decider_t;
 
-/* Eyebox binning of a ray leaving the top face at p with air direction a. */
+/* Eyebox binning of a ray leaving the top face at p with air direction a:
+ * its crossing of the eyebox plane falls in a bin of the grid, or (with eye
+ * pupils) inside one pupil's circle. */
 static int eyebox_bin(const orc_scene* sc, vec3 p, vec3 a)
 {
     double xe = p.x + sc->eye_relief * (a.x / a.z);
     double ye = p.y + sc->eye_relief * (a.y / a.z);
+    if (sc->n_eye_pupils > 0) {
+        double r2 = sc->eye_pupil_r * sc->eye_pupil_r;
+        for (int q = 0; q < sc->n_eye_pupils; ++q) {
+            double dx = xe - sc->eye_pupil_xy[2 * q];
+            double dy = ye - sc->eye_pupil_xy[2 * q + 1];
+            if (dx * dx + dy * dy < r2) return q;
+        }
+        return -1;
+    }
     double fx = ((xe - sc->eye_x0) / sc->eye_w) * (double)sc->bins_x;
     double fy = ((ye - sc->eye_y0) / sc->eye_h) * (double)sc->bins_y;
     if (!(fx >= 0.0 && fx < (double)sc->bins_x && fy >= 0.0 && fy < (double)sc->bins_y)) return -1;

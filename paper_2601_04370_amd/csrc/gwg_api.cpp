@@ -84,7 +84,7 @@ struct gwg_ctx {
     uint64_t scene_hash = 0;
     bool scene_valid = false;
     SceneDev sc{};
-    DevBuf lam_tab, dir_tab, slot, nlay;
+    DevBuf lam_tab, dir_tab, slot, nlay, pupil_xy;
     std::vector<int32_t> h_nlay;
     // per-call buffers
     DevBuf stats, partial, scratch, fwd_scratch, loss_work, grad_tmp;
@@ -222,6 +222,26 @@ int check_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
         return fail(c, GWG_E_INVAL, "eyebox rectangle invalid");
     if (sl->bins_x < 1 || sl->bins_x > 4096 || sl->bins_y < 1 || sl->bins_y > 4096)
         return fail(c, GWG_E_INVAL, "bins %d x %d out of range", sl->bins_x, sl->bins_y);
+    if (sl->n_eye_pupils < 0 || sl->n_eye_pupils > kMaxPupils)
+        return fail(c, GWG_E_INVAL, "n_eye_pupils %d out of range 0..%d", sl->n_eye_pupils, kMaxPupils);
+    if (sl->n_eye_pupils > 0) {
+        const int np = sl->n_eye_pupils;
+        const double r = sl->eye_pupil_radius_mm;
+        if (!(is_fin(r) && r > 0.0)) return fail(c, GWG_E_INVAL, "eye pupil radius must be finite and > 0");
+        if (!sl->eye_pupil_xy_mm) return fail(c, GWG_E_INVAL, "eye_pupil_xy_mm is NULL");
+        if (sl->bins_x != np || sl->bins_y != 1)
+            return fail(c, GWG_E_INVAL, "with %d eye pupils bins must be %d x 1, not %d x %d", np, np, sl->bins_x,
+                        sl->bins_y);
+        const double* xy = sl->eye_pupil_xy_mm;
+        for (int p = 0; p < 2 * np; ++p)
+            if (!is_fin(xy[p])) return fail(c, GWG_E_INVAL, "eye pupil centre %d is not finite", p / 2);
+        for (int p = 0; p < np; ++p)
+            for (int q = p + 1; q < np; ++q) {
+                const double dx = xy[2 * p] - xy[2 * q], dy = xy[2 * p + 1] - xy[2 * q + 1];
+                if (dx * dx + dy * dy < 4.0 * r * r)
+                    return fail(c, GWG_E_INVAL, "eye pupils %d and %d overlap", p, q);
+            }
+    }
     if (pr->n_mirrors < 1 || pr->n_mirrors > kMaxMirrors) return fail(c, GWG_E_INVAL, "n_mirrors %d out of range", pr->n_mirrors);
     if (!pr->omega) return fail(c, GWG_E_INVAL, "omega is NULL");
     for (int m = 0; m < pr->n_mirrors; ++m)
@@ -298,6 +318,7 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     // content hash of everything the tables depend on
     uint64_t h = 1469598103934665603ull;
     h = fnv_v(h, *sl);
+    if (sl->n_eye_pupils > 0) h = fnv(h, sl->eye_pupil_xy_mm, sizeof(double) * 2 * sl->n_eye_pupils);
     h = fnv_v(h, pr->n_mirrors); h = fnv_v(h, pr->tilt_deg); h = fnv_v(h, pr->pitch_mm); h = fnv_v(h, pr->center_x_mm);
     h = fnv(h, pr->omega, sizeof(double) * pr->n_mirrors);
     h = fnv_v(h, mt->n_lambda); h = fnv_v(h, mt->n_mat);
@@ -324,6 +345,8 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     s.px0 = sl->pupil_x0_mm; s.pw = sl->pupil_w_mm; s.ph = sl->pupil_h_mm;
     s.ex0 = sl->eye_x0_mm; s.ey0 = sl->eye_y0_mm; s.ew = sl->eye_w_mm; s.eh = sl->eye_h_mm;
     s.bins_x = sl->bins_x; s.bins_y = sl->bins_y;
+    s.n_pupils = sl->n_eye_pupils;
+    s.pupil_r2 = s.n_pupils > 0 ? sl->eye_pupil_radius_mm * sl->eye_pupil_radius_mm : 0.0;
     s.M = pr->n_mirrors;
     double beta = pr->tilt_deg * (3.14159265358979323846 / 180.0);
     s.nx = -std::sin(beta);
@@ -400,6 +423,10 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     HIP_CHECK(c, c->dir_tab.ensure(dirs.size() * sizeof(double)), "alloc dir_tab");
     HIP_CHECK(c, c->slot.ensure(slots.size()), "alloc slot");
     HIP_CHECK(c, c->nlay.ensure(sizeof(int32_t) * DM), "alloc nlay");
+    HIP_CHECK(c, c->pupil_xy.ensure(sizeof(double) * 2 * (size_t)std::max(s.n_pupils, 1)), "alloc pupil table");
+    if (s.n_pupils > 0)
+        HIP_CHECK(c, hipMemcpyAsync(c->pupil_xy.p, sl->eye_pupil_xy_mm, sizeof(double) * 2 * s.n_pupils,
+                                    hipMemcpyHostToDevice, stream), "upload pupil table");
     HIP_CHECK(c, hipMemcpyAsync(c->lam_tab.p, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload lam_tab");
     HIP_CHECK(c, hipMemcpyAsync(c->dir_tab.p, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload dir_tab");
     HIP_CHECK(c, hipMemcpyAsync(c->slot.p, slots.data(), slots.size(), hipMemcpyHostToDevice, stream), "upload slots");
@@ -409,6 +436,7 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     s.dir_tab = (const double*)c->dir_tab.p;
     s.slot = (const uint8_t*)c->slot.p;
     s.nlay = (const int32_t*)c->nlay.p;
+    s.pupil_xy = (const double*)c->pupil_xy.p;
     c->h_nlay.assign(st->n_layers, st->n_layers + DM);
     c->scene_hash = h;
     c->scene_valid = true;
@@ -519,7 +547,7 @@ int gwg_destroy(gwg_ctx* c)
     {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
+        for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->pupil_xy, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape,
                            &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad,
                            &c->adj_ck, &c->grad_tmp, &c->adj_order, &c->item_work, &c->fwd_order })
@@ -981,7 +1009,7 @@ int gwg_loss(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, int32_t F,
     if (!d_irr || !d_loss) return fail(c, GWG_E_INVAL, "NULL loss pointer");
     if (D < 1 || n_l < 1 || F < 1 || B < 1) return fail(c, GWG_E_INVAL, "loss shape invalid");
     if ((int64_t)D * n_l * F > 0x7fffffff) return fail(c, GWG_E_INVAL, "loss shape too large");
-    if (kind != 0 && kind != 1) return fail(c, GWG_E_INVAL, "kind must be 0 or 1");
+    if (kind < 0 || kind > 2) return fail(c, GWG_E_INVAL, "kind must be 0, 1 or 2");
     if (!(is_fin(w_f) && is_fin(w_e))) return fail(c, GWG_E_INVAL, "weights must be finite");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
@@ -1003,7 +1031,7 @@ int gwg_loss_noalloc(gwg_ctx* c, const double* d_irr, int32_t D, int32_t n_l, in
     if (!d_irr || !d_loss) return fail(c, GWG_E_INVAL, "NULL loss pointer");
     if (D < 1 || n_l < 1 || F < 1 || B < 1) return fail(c, GWG_E_INVAL, "loss shape invalid");
     if ((int64_t)D * n_l * F > 0x7fffffff) return fail(c, GWG_E_INVAL, "loss shape too large");
-    if (kind != 0 && kind != 1) return fail(c, GWG_E_INVAL, "kind must be 0 or 1");
+    if (kind < 0 || kind > 2) return fail(c, GWG_E_INVAL, "kind must be 0, 1 or 2");
     if (!(is_fin(w_f) && is_fin(w_e))) return fail(c, GWG_E_INVAL, "weights must be finite");
     const int64_t need = loss_work_doubles(D, n_l, F, B);
     if (need > kLossScratchDoubles)

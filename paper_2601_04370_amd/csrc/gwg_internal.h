@@ -15,6 +15,7 @@
 namespace gwg {
 
 constexpr int kMaxMirrors = 16;
+constexpr int kMaxPupils = 64;        // eye pupils on the eyebox plane
 constexpr int kMaxSlots = 8;          // distinct layer materials in one scene
 constexpr int kMaxLayers = 1024;
 constexpr int kMaxEvents = 256;
@@ -89,6 +90,10 @@ struct SceneDev {
     double px0, pw, ph;
     double ex0, ey0, ew, eh;
     int32_t bins_x, bins_y;
+    // eye pupils (n_pupils > 0: bin p is pupil p, bins_x = n_pupils, bins_y = 1)
+    int32_t n_pupils;
+    double pupil_r2;                  // radius squared
+    const double* pupil_xy;           // [n_pupils][2] centres
     // mirrors
     int32_t M;
     double nx, nz;                    // mirror normal (nx, 0, nz)

@@ -341,8 +341,10 @@ __device__ inline double block_sum256(double v, double* red)
 }
 
 // Per design (one block of 256 threads each): moments and the coefficients
-// of dL/dI.  coef[d] = { L_d, a_e, a_f, m_e, m_f, ebar, ibar }; phi[d][f]
-// written too.  Sums are strided per thread, then a fixed tree.
+// of dL/dI.  coef[d] = { L_d, a_e, a_f, m_e, m_f, ebar, ibar, bright };
+// phi[d][f] written too.  bright weighs the throughput's mean in the
+// brightness term: 1, or 1 / B for pupil images (kind 2), whose brightness is
+// the mean over pupils rather than the sum over bins.  Sums are strided per thread, then a fixed tree.
 __global__ void __launch_bounds__(256) k_loss_scalar(const double* __restrict__ eta, const double* __restrict__ E,
                                                      int nl, int F, int B, int kind, double w_f, double w_e,
                                                      double* __restrict__ phi, double* __restrict__ coef)
@@ -375,19 +377,20 @@ __global__ void __launch_bounds__(256) k_loss_scalar(const double* __restrict__ 
     const double vf = block_sum256(part, red);
     if (t != 0) return;
     double L, ae, af, me, mf;
+    const double bright = kind == 2 ? 1.0 / (double)B : 1.0;
     if (kind == 0) {
         L = -ibar + w_e * ve + w_f * vf;
         ae = w_e; af = w_f; me = 0.0; mf = 0.0;
     } else {
         double se = sqrt(ve), sf = sqrt(vf);
-        L = -ibar + w_f * (sf / ibar) + w_e * (se / ebar);
+        L = -ibar * bright + w_f * (sf / ibar) + w_e * (se / ebar);
         ae = se > 0.0 ? w_e / (2.0 * se * ebar) : 0.0;
         af = sf > 0.0 ? w_f / (2.0 * sf * ibar) : 0.0;
         me = -w_e * se / (ebar * ebar);
         mf = -w_f * sf / (ibar * ibar);
     }
     double* c = coef + (int64_t)d * 8;
-    c[0] = L; c[1] = ae; c[2] = af; c[3] = me; c[4] = mf; c[5] = ebar; c[6] = ibar;
+    c[0] = L; c[1] = ae; c[2] = af; c[3] = me; c[4] = mf; c[5] = ebar; c[6] = ibar; c[7] = bright;
 }
 
 // Total loss: the designs' L_d in design order.
@@ -415,7 +418,7 @@ __global__ void k_loss_grad(const double* __restrict__ E, const double* __restri
         double npts = (double)nl * (double)F;
         double ce = 2.0 * (E[(int64_t)d * B + b] - c[5]) / ((double)B * npts);
         double cf = 2.0 * (phi[(int64_t)d * F + f] - c[6]) / ((double)F * (double)nl);
-        G[i] = -1.0 / npts + c[1] * ce + c[2] * cf + c[3] / ((double)B * npts) + c[4] / npts;
+        G[i] = -c[7] / npts + c[1] * ce + c[2] * cf + c[3] / ((double)B * npts) + c[4] / npts;
     }
 }
 

@@ -219,11 +219,21 @@ __device__ inline FaceCoef face_coeffs(double ng, double na, double dx, double d
     return f;
 }
 
-// Eyebox bin of a ray leaving the top face at (px, py) along air direction a.
+// Eyebox bin of a ray leaving the top face at (px, py) along air direction
+// a: the grid cell of its crossing of the eyebox plane, or, with eye pupils,
+// the pupil whose circle holds the crossing (pupils do not overlap).
 __device__ inline int eyebox_bin(const SceneDev& sc, const PointLds& pl, double px, double py, const double* a)
 {
     double xe = px + pl.ER * (a[0] / a[2]);
     double ye = py + pl.ER * (a[1] / a[2]);
+    if (sc.n_pupils > 0) {
+        for (int q = 0; q < sc.n_pupils; ++q) {
+            const double dx = xe - sc.pupil_xy[2 * q];
+            const double dy = ye - sc.pupil_xy[2 * q + 1];
+            if (dx * dx + dy * dy < sc.pupil_r2) return q;
+        }
+        return -1;
+    }
     double fx = ((xe - pl.ex0) / pl.ew) * (double)pl.bins_x;
     double fy = ((ye - pl.ey0) / pl.eh) * (double)pl.bins_y;
     if (!(fx >= 0.0 && fx < (double)pl.bins_x && fy >= 0.0 && fy < (double)pl.bins_y)) return -1;

@@ -47,7 +47,8 @@ class Slab(C.Structure):
                 ("mat_glass", C.c_int32), ("mat_air", C.c_int32),
                 ("pupil_x0_mm", C.c_double), ("pupil_w_mm", C.c_double), ("pupil_h_mm", C.c_double),
                 ("eye_x0_mm", C.c_double), ("eye_y0_mm", C.c_double), ("eye_w_mm", C.c_double),
-                ("eye_h_mm", C.c_double), ("bins_x", C.c_int32), ("bins_y", C.c_int32)]
+                ("eye_h_mm", C.c_double), ("bins_x", C.c_int32), ("bins_y", C.c_int32),
+                ("n_eye_pupils", C.c_int32), ("eye_pupil_radius_mm", C.c_double), ("eye_pupil_xy_mm", _dp)]
 
 
 class Prma(C.Structure):
@@ -202,6 +203,9 @@ class SceneSpec:
     rays_per_point: int
     max_events: int
     fp_shift: int = 24
+    # eye pupils: centres [P][2] (mm) and radius; None for the eyebox grid
+    eye_pupils: Optional[np.ndarray] = None
+    eye_pupil_r: float = 0.0
     _keep: dict = field(default_factory=dict, repr=False)
 
     @classmethod
@@ -223,7 +227,10 @@ class SceneSpec:
             lambda_sel=np.ascontiguousarray(inp["lambda_sel"], np.int32),
             fov_mode=w.fov_mode, fov_deg=np.ascontiguousarray(inp["fov"], np.float64),
             rays_per_point=int(w.rays_per_point if rays_per_point is None else rays_per_point),
-            max_events=w.max_events, fp_shift=w.fp_shift)
+            max_events=w.max_events, fp_shift=w.fp_shift,
+            eye_pupils=(np.ascontiguousarray(inp["eye_pupils"], np.float64)
+                        if inp.get("eye_pupils") is not None and len(inp["eye_pupils"]) else None),
+            eye_pupil_r=float(inp.get("eye_pupil_r", 0.0)))
 
     @property
     def n_fov(self) -> int:
@@ -248,6 +255,10 @@ class SceneSpec:
         s = Slab(self.T_mm, self.L_mm, self.eye_relief_mm, self.mat_glass, self.mat_air,
                  self.pupil[0], self.pupil[1], self.pupil[2],
                  self.eyebox[0], self.eyebox[1], self.eyebox[2], self.eyebox[3], self.bins[0], self.bins[1])
+        if self.eye_pupils is not None:
+            s.n_eye_pupils = self.eye_pupils.shape[0]
+            s.eye_pupil_radius_mm = self.eye_pupil_r
+            s.eye_pupil_xy_mm = _np_ptr(self.eye_pupils, _dp)
         p = Prma(self.n_mirrors, self.tilt_deg, self.pitch_mm, self.center_x_mm, _np_ptr(self.omega, _dp))
         st = Stacks(self.n_designs, self.n_mirrors, self.max_layers, None, _np_ptr(self.mat, _u8p),
                     _np_ptr(self.n_layers, _i32p))

@@ -37,7 +37,12 @@ Reading taken here:
 Metrics (Eq. 1's terms, population statistics): mean eyebox throughput Ibar,
 CV_FoV of the per-FoV throughput and CV_eyebox of the per-bin eyebox
 profile, averaged over designs; reported designs are evaluated on several
-seeds and averaged (the paper averages five Monte Carlo runs).
+seeds and averaged (the paper averages five Monte Carlo runs).  With eye
+pupils (Results: the images of a grid of pupil positions are the
+objective) the "bins" are the pupils: Ibar is the mean throughput into one
+pupil (averaged over pupils, FoV samples and wavelengths, hence colour
+channels), CV_eyebox the CV over pupils, and the loss is Eq. 1's pupil form
+(``gwg_loss`` kind 2).
 """
 from __future__ import annotations
 
@@ -63,6 +68,7 @@ class OptimConfig:
     precision: int = FP64
     memo: bool = False              # memoized thin film (exact, faster)
     eval_seeds: int = 5
+    loss_kind: int = 1              # Eq. 1 (1), or its pupil-image form (2)
 
 
 def init_thicknesses(n_layers: np.ndarray, l_max: int, t_min: float = 20.0, t_max: float = 200.0,
@@ -101,17 +107,25 @@ def snap(t, t_min: float):
     return t * (~inside) + t_min * up + 0 * down
 
 
-def metrics(irr) -> dict:
-    """Ibar, CV_FoV, CV_eyebox of irradiance [D][n_l][F][by][bx], averaged over designs."""
+def metrics(irr, pupils: bool = False) -> dict:
+    """Ibar, CV_FoV, CV_eyebox of irradiance [D][n_l][F][by][bx], averaged
+    over designs (pupils: the last axes are pupils, and Ibar is the mean
+    throughput into one pupil)."""
     import torch
     I = irr.reshape(irr.shape[0], irr.shape[1], irr.shape[2], -1).to(torch.float64)
     eta = I.sum(dim=3)                               # [D][n_l][F]
     ibar = eta.mean(dim=(1, 2))                      # [D]
+    if pupils:
+        return {"ibar": float((ibar / I.shape[3]).mean()), **_cvs(I, eta, ibar)}
+    return {"ibar": float(ibar.mean()), **_cvs(I, eta, ibar)}
+
+
+def _cvs(I, eta, ibar) -> dict:
     phi = eta.mean(dim=1)                            # [D][F]
     eyeb = I.mean(dim=(1, 2))                        # [D][B]
     cv_f = phi.std(dim=1, unbiased=False) / ibar
     cv_e = eyeb.std(dim=1, unbiased=False) / eyeb.mean(dim=1)
-    return {"ibar": float(ibar.mean()), "cv_fov": float(cv_f.mean()), "cv_eyebox": float(cv_e.mean())}
+    return {"cv_fov": float(cv_f.mean()), "cv_eyebox": float(cv_e.mean())}
 
 
 class CoatingOptimizer:
@@ -137,7 +151,7 @@ class CoatingOptimizer:
         torch, ctx, cfg = self.torch, self.ctx, self.cfg
         thk = self.param.detach().clone().contiguous()
         _, _, irr, _, _ = ctx.trace_forward(self.scene, thk, self.seed, k, cfg.precision, grad=True, memo=cfg.memo)
-        L, dLdI = ctx.loss(irr, 1, cfg.w_f, cfg.w_e)
+        L, dLdI = ctx.loss(irr, cfg.loss_kind, cfg.w_f, cfg.w_e)
         g = ctx.trace_backward(dLdI, self.scene)
         phi, dphi = gap_penalty(thk, cfg.t_min)
         g = (g + cfg.gap_weight * dphi) * self.mask
@@ -147,7 +161,8 @@ class CoatingOptimizer:
             self.param.copy_(project(self.param, cfg.t_max, self.mask))
             if cfg.snap_every and (k + 1) % cfg.snap_every == 0:
                 self.param.copy_(snap(self.param, cfg.t_min))
-        rec = {"iter": k, "loss": float(L) + cfg.gap_weight * float(phi.sum()), **metrics(irr),
+        rec = {"iter": k, "loss": float(L) + cfg.gap_weight * float(phi.sum()),
+               **metrics(irr, cfg.loss_kind == 2),
                "pruned": int(((self.param == 0) & (self.mask > 0)).sum())}
         self.history.append(rec)
         return rec
@@ -170,8 +185,8 @@ class CoatingOptimizer:
         acc = {"ibar": 0.0, "cv_fov": 0.0, "cv_eyebox": 0.0, "loss": 0.0}
         for s in seeds:
             _, _, irr, _, _ = ctx.trace_forward(self.scene, t.contiguous(), s, step, cfg.precision, memo=cfg.memo)
-            L, _ = ctx.loss(irr, 1, cfg.w_f, cfg.w_e, want_grad=False)
-            m = metrics(irr)
+            L, _ = ctx.loss(irr, cfg.loss_kind, cfg.w_f, cfg.w_e, want_grad=False)
+            m = metrics(irr, cfg.loss_kind == 2)
             for key in ("ibar", "cv_fov", "cv_eyebox"):
                 acc[key] += m[key] / len(seeds)
             acc["loss"] += float(L) / len(seeds)
@@ -245,6 +260,7 @@ def main():
     ap = argparse.ArgumentParser(description="optimise the coating stacks of a synthetic workload")
     ap.add_argument("--workload", default="diff_1200")
     ap.add_argument("--rays-per-point", type=int, default=0)
+    ap.add_argument("--designs", type=int, default=0, help="keep the first n designs of the workload")
     ap.add_argument("--iters", type=int, default=1000)
     ap.add_argument("--lr", type=float, default=2.0)
     ap.add_argument("--memo", action="store_true")
@@ -253,8 +269,10 @@ def main():
     w = inputs.workload(a.workload)
     if a.rays_per_point:
         w = dataclasses.replace(w, rays_per_point=a.rays_per_point)
+    if a.designs:
+        w = dataclasses.replace(w, n_designs=a.designs)
     inp = inputs.make_inputs(w)
-    cfg = OptimConfig(iters=a.iters, lr=a.lr, memo=a.memo)
+    cfg = OptimConfig(iters=a.iters, lr=a.lr, memo=a.memo, loss_kind=2 if w.eye_pupil_grid > 0 else 1)
     thk0 = init_thicknesses(inp["n_layers"], inp["thk"].shape[2], cfg.t_min, cfg.t_max, seed=w.seed)
     ctx = Context(0)
     scene = SceneSpec.from_workload(w, inp)
@@ -271,7 +289,10 @@ def main():
     after = opt.evaluate(thk)
     n_real = int(inp["n_layers"].sum())
     print(json.dumps({"final": after, "pruned_layers": int(((thk == 0) & (opt.mask.cpu().numpy() > 0)).sum()),
-                      "layers": n_real, "s_per_iter": (time.perf_counter() - t0) / cfg.iters}), flush=True)
+                      "layers": n_real, "s_per_iter": (time.perf_counter() - t0) / cfg.iters,
+                      "workload": a.workload, "designs": w.n_designs, "rays_per_point": w.rays_per_point,
+                      "loss_kind": cfg.loss_kind, "memo": cfg.memo, "iters": cfg.iters,
+                      "eval_seeds": cfg.eval_seeds}), flush=True)
 
 
 if __name__ == "__main__":

@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.gwg_abi_version() == 1
+    assert lib.gwg_abi_version() == 2
 
 
 def test_null_context_is_rejected(lib):

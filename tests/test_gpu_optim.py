@@ -45,3 +45,51 @@ def test_memoized_and_per_hit_steps_agree(gctx):
         _, _, _, _, opt = _setup(gctx, rays=256, iters=3, memo=memo)
         runs.append(opt.run())
     assert np.allclose(runs[0], runs[1], rtol=0, atol=1e-9)
+
+
+def test_one_step_on_gpu_gradient_equals_step_on_oracle_gradient(gctx, orc):
+    """One optimiser step driven by the library's gradient equals the step
+    driven by the oracle's gradient of the same loss (same seed and step, so
+    the same paths): Adam's first moment holds the gradient, and the updated
+    thicknesses agree wherever the gradient is not at rounding level."""
+    import torch
+    w, inp, cfg, thk0, opt = _setup(gctx, rays=96, iters=1, memo=False)
+    opt.step(0)
+    gpu_m = opt.opt.state[opt.param]["exp_avg"].cpu().numpy() / (1 - 0.9)
+    gpu_p = opt.param.detach().cpu().numpy()
+    # the same step from the oracle's gradient
+    osc = orc.OracleScene(w, inp, thk=thk0 * opt.mask.cpu().numpy(), seed=w.seed, step=0)
+    irr = osc.forward_sampled(1)
+    L, dLdI = orc.loss(irr, cfg.loss_kind, cfg.w_f, cfg.w_e)
+    og = osc.backward(dLdI, 1)
+    _, _, _, _, opt2 = _setup(gctx, rays=96, iters=1, memo=False)
+    t = opt2.param.detach().clone()
+    phi, dphi = optim.gap_penalty(t, cfg.t_min)
+    opt2.param.grad = (torch.tensor(og, device=t.device) + cfg.gap_weight * dphi) * opt2.mask
+    opt2.opt.step()
+    with torch.no_grad():
+        opt2.param.copy_(optim.project(opt2.param, cfg.t_max, opt2.mask))
+    ora_m = opt2.opt.state[opt2.param]["exp_avg"].cpu().numpy() / (1 - 0.9)
+    ora_p = opt2.param.detach().cpu().numpy()
+    scale = np.max(np.abs(ora_m))
+    assert scale > 0
+    assert np.all(np.abs(gpu_m - ora_m) <= 1e-4 * np.maximum(np.abs(ora_m), 1e-3 * scale))
+    big = np.abs(ora_m) > 1e-3 * scale
+    assert np.max(np.abs(gpu_p - ora_p)[big]) <= 1e-6 * cfg.lr
+    print(f"  one step: {big.sum()} thicknesses moved by the gradient, max |dp| "
+          f"{np.max(np.abs(gpu_p - ora_p)):.2e} nm", flush=True)
+
+
+@pytest.mark.parametrize("name,kind", [("diff_1200", 1), ("pupil_rgb", 2)])
+def test_metrics_match_library_loss(gctx, name, kind):
+    """The optimiser's host metrics combine to the library's Eq. 1 loss."""
+    import torch
+    w = inputs.small_variant(name, rays_per_point=64, fov_n=3)
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    _, _, irr, _, _ = gctx.trace_forward(scene, thk, w.seed, 0, gwg.FP64)
+    L, _ = gctx.loss(irr, kind, 10.0, 3.0, want_grad=False)
+    m = optim.metrics(irr, pupils=(kind == 2))
+    mine = -m["ibar"] + 10.0 * m["cv_fov"] + 3.0 * m["cv_eyebox"]
+    assert abs(mine - L.item()) <= 1e-12 * max(1.0, abs(L.item()))

@@ -56,3 +56,13 @@ def test_metrics_match_oracle_loss(orc):
         avg = optim.metrics(torch.tensor(irr))
         for key in ("ibar", "cv_fov", "cv_eyebox"):
             assert abs(avg[key] - np.mean([x[key] for x in m])) < 1e-14
+
+
+def test_pupil_metrics_match_oracle_loss(orc):
+    """With eye pupils the metrics are Eq. 1's pupil form (loss kind 2)."""
+    rng = np.random.default_rng(8)
+    irr = rng.uniform(0.0, 0.02, size=(2, 9, 5, 1, 9))
+    m = [optim.metrics(torch.tensor(irr[d:d + 1]), pupils=True) for d in range(2)]
+    L, _ = orc.loss(irr, 2, 10.0, 3.0)
+    mine = sum(-x["ibar"] + 10.0 * x["cv_fov"] + 3.0 * x["cv_eyebox"] for x in m)
+    assert abs(mine - L) < 1e-12 * max(1.0, abs(L))
