@@ -159,11 +159,11 @@ def copy_probe(torch, mib: int = 1024, reps: int = 5):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": reps}))
 
 
-def design_slice(inp, d):
-    """Inputs of design d alone (for per-design launches)."""
+def design_slice(inp, d, n=1):
+    """Inputs of designs d .. d + n - 1 alone (per-design or per-chunk launches)."""
     out = dict(inp)
     for k in ("thk", "mat", "n_layers"):
-        out[k] = inp[k][d:d + 1].copy()
+        out[k] = inp[k][d:d + n].copy()
     return out
 
 
@@ -190,6 +190,9 @@ def main():
                     help="rays per work item (tuning rays_per_block; 0: the library's choice)")
     ap.add_argument("--per-design", action="store_true",
                     help="also time one launch per design (the batched workload) for comparison")
+    ap.add_argument("--design-chunks", type=int, default=0,
+                    help="also time the batch as this many launches of consecutive designs (each chunk's "
+                         "forward, loss and adjoint before the next chunk's, so its stored sweeps fit)")
     ap.add_argument("--cpu-interactions", type=float, default=1e6,
                     help="interactions in each CPU-baseline sample (whole points)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -367,6 +370,31 @@ def main():
         pd_wall = time.perf_counter() - tp
         extra["per_design_ms_per_step"] = pd_wall / K * 1e3
         extra["batched_speedup_vs_per_design"] = pd_wall / wall
+
+    if a.design_chunks:
+        # the same batch as a few launches of consecutive designs: the loss is a
+        # sum over designs, so chunking by design changes no result
+        nc = max(1, min(a.design_chunks, w.n_designs))
+        bounds = [round(i * w.n_designs / nc) for i in range(nc + 1)]
+        chunks = []
+        for c0, c1 in zip(bounds[:-1], bounds[1:]):
+            inp_c = design_slice(inp, c0, c1 - c0)
+            chunks.append((gwg.SceneSpec.from_workload(w, inp_c),
+                           torch.tensor(inp_c["thk"], dtype=torch.float64, device=dev)))
+        for sc_c, th_c in chunks:
+            step(0, sc=sc_c, th=th_c)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for i in range(K):
+            for sc_c, th_c in chunks:
+                step(a.warmup + i, sc=sc_c, th=th_c)
+        torch.cuda.synchronize()
+        ch_wall = time.perf_counter() - tp
+        extra["design_chunks"] = nc
+        extra["chunked_ms_per_step"] = ch_wall / K * 1e3
+        extra["chunked_speedup_vs_single_launch"] = wall / ch_wall
+        if a.per_design:
+            extra["chunked_speedup_vs_per_design"] = extra["per_design_ms_per_step"] / extra["chunked_ms_per_step"]
 
     f_fwd = FLOP_FWD_LAYER * lay_f / K
     f_bwd = (FLOP_FWD_LAYER * lay_b + FLOP_ADJ_LAYER * lay_a - FLOP_FWD_LAYER * lay_s) / K

@@ -78,6 +78,7 @@ def lib():
     L.orc_tmm_rt.argtypes = [C.c_int, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                              C.c_double, C.c_double, _dp]
     L.orc_tmm_dthk.argtypes = L.orc_tmm_rt.argtypes
+    L.orc_tmm_rt_batch.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int64, _i32p, _dp, _dp]
     L.orc_trace_forward.argtypes = [C.POINTER(Scene), _u64p, _u32p, _dp, C.POINTER(Stats)]
     L.orc_trace_rays.argtypes = [C.POINTER(Scene), C.c_int64, _i64p, C.POINTER(RayRecord)]
     L.orc_ray_events.argtypes = [C.POINTER(Scene), C.c_int64, C.c_int, _dp]
@@ -125,6 +126,40 @@ def tmm_rt(thk, n_layers_complex, n_in: float, n_out: complex, lambda_nm: float,
     lib().orc_tmm_rt(len(thk), _ptr(thk, _dp), _ptr(nre, _dp), _ptr(nim, _dp), float(n_in),
                      n_out.real, n_out.imag, float(lambda_nm), float(kappa), _ptr(out, _dp))
     return out[0::2] + 1j * out[1::2]
+
+
+def tmm_rt_batch(thk, N_by_lambda, n_in, n_out, lambda_nm, lambda_idx, theta, threads: int = 1) -> np.ndarray:
+    """[n_q, 4] complex coefficients of one stack for queries (lambda_idx[q],
+    theta[q]); N_by_lambda [n_lambda][L] complex layer indices, n_in / n_out /
+    lambda_nm per wavelength.  `threads` host threads split the queries (the
+    C loop releases the interpreter lock)."""
+    import threading
+    thk = np.ascontiguousarray(thk, dtype=np.float64)
+    N = np.asarray(N_by_lambda, dtype=np.complex128)
+    nre, nim = np.ascontiguousarray(N.real), np.ascontiguousarray(N.imag)
+    nin = np.ascontiguousarray(n_in, dtype=np.float64)
+    no = np.asarray(n_out, dtype=np.complex128)
+    nout = np.ascontiguousarray(np.stack([no.real, no.imag], -1).reshape(-1))
+    lam = np.ascontiguousarray(lambda_nm, dtype=np.float64)
+    li = np.ascontiguousarray(lambda_idx, dtype=np.int32)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    n = len(th)
+    out = np.zeros((n, 8))
+    L = lib()
+    bounds = np.linspace(0, n, max(1, threads) + 1).astype(np.int64)
+
+    def run(a, b):
+        if b > a:
+            L.orc_tmm_rt_batch(len(thk), _ptr(thk, _dp), _ptr(nre, _dp), _ptr(nim, _dp), _ptr(nin, _dp),
+                               _ptr(nout, _dp), _ptr(lam, _dp), int(b - a),
+                               li[a:b].ctypes.data_as(_i32p), th[a:b].ctypes.data_as(_dp),
+                               out[a:b].ctypes.data_as(_dp))
+    ts = [threading.Thread(target=run, args=(int(bounds[k]), int(bounds[k + 1]))) for k in range(len(bounds) - 1)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    return out[:, 0::2] + 1j * out[:, 1::2]
 
 
 def tmm_dthk(thk, n_layers_complex, n_in: float, n_out: complex, lambda_nm: float,

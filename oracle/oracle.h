@@ -43,6 +43,13 @@ void orc_tmm_rt(int n_layers, const double* thk_nm, const double* nre, const dou
                 double n_in, double nout_re, double nout_im,
                 double lambda_nm, double kappa, double out[8]);
 
+/* Many queries of one stack, the layer indices per wavelength row li[q]
+ * ([n_lambda][n_layers] tables; n_in, nout, lambda_nm per row, nout as
+ * (re, im)); theta[q] in the incident medium; out[q][8] as orc_tmm_rt. */
+void orc_tmm_rt_batch(int n_layers, const double* thk, const double* nre, const double* nim,
+                      const double* n_in, const double* nout, const double* lambda_nm,
+                      int64_t n_q, const int32_t* li, const double* theta, double* out);
+
 /* Holomorphic derivatives d c / d thk_j (per nm) of the four coefficients,
  * by reverse-mode through the same recursion.  d_out[j*16 + 4*c + 0..3] holds,
  * for c = r_s, r_p, t_s, t_p: (re, im) of dc/dthk_j, then 2 unused slots. */

@@ -190,3 +190,21 @@ void orc__tmm_coeffs(int L, const double* thk, const double* nre, const double* 
     orc_tmm_rt(L, thk, nre, nim, n_glass, n_glass, 0.0, lambda_nm, kappa, out);
     for (int k = 0; k < 4; ++k) c[k] = CMPLX(out[2 * k], out[2 * k + 1]);
 }
+
+/* Many queries of one stack whose layer indices depend on the wavelength:
+ * query q uses wavelength row li[q] of nre/nim ([n_lambda][n_layers]) and of
+ * n_in / nout ([n_lambda]; nout as (re, im) pairs), lambda_nm[li[q]] and the
+ * angle of incidence theta[q] (rad) in the incident medium.  out[q][8] as
+ * orc_tmm_rt.  A plain loop over orc_tmm_rt (callers may split the queries
+ * across threads: nothing is shared). */
+void orc_tmm_rt_batch(int n_layers, const double* thk, const double* nre, const double* nim,
+                      const double* n_in, const double* nout, const double* lambda_nm,
+                      int64_t n_q, const int32_t* li, const double* theta, double* out)
+{
+    for (int64_t q = 0; q < n_q; ++q) {
+        const int l = li[q];
+        const double kappa = n_in[l] * sin(theta[q]);
+        orc_tmm_rt(n_layers, thk, nre + (size_t)l * n_layers, nim + (size_t)l * n_layers, n_in[l],
+                   nout[2 * l], nout[2 * l + 1], lambda_nm[l], kappa, out + 8 * q);
+    }
+}

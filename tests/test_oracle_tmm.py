@@ -311,3 +311,20 @@ def test_fp64_formulation_spread(orc, case):
         b = charmatrix(thk, N, ng, ng, lam[li[q]], ng * np.sin(th[q]))
         worst = max(worst, np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a))))
     assert worst <= tmm_cases.FP64_TOL[case] / 4, worst
+
+
+def test_batch_equals_single_queries(orc):
+    """orc_tmm_rt_batch (threaded) is the single-query solve, query by query."""
+    rng = np.random.default_rng(21)
+    thk, N = rand_stack(rng, 30)
+    N[7] = 0.12 + 3.3j
+    Nl = np.stack([N, N * 1.01, N * 0.99])
+    n_in = np.array([1.52, 1.53, 1.51])
+    n_out = np.array([1.52, 1.0, 2.0 + 0.1j])
+    lam = np.array([460.0, 530.0, 620.0])
+    li = rng.integers(0, 3, size=500).astype(np.int32)
+    th = np.radians(rng.uniform(0, 85, size=500))
+    b = orc.tmm_rt_batch(thk, Nl, n_in, n_out, lam, li, th, threads=4)
+    for q in range(0, 500, 7):
+        a = orc.tmm_rt(thk, Nl[li[q]], n_in[li[q]], n_out[li[q]], lam[li[q]], theta=th[q])
+        assert np.array_equal(a, b[q])
