@@ -393,6 +393,32 @@ def main():
         extra["design_chunks"] = nc
         extra["chunked_ms_per_step"] = ch_wall / K * 1e3
         extra["chunked_speedup_vs_single_launch"] = wall / ch_wall
+        if a.graph:
+            # the whole chunked step in one graph (every chunk's scene was
+            # built above, so the capture rebuilds nothing)
+            d_step = torch.zeros(1, dtype=torch.int32, device=dev)
+            ctx.set_step_source(d_step)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                for sc_c, th_c in chunks:
+                    step(a.warmup + K, sc=sc_c, th=th_c)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            cgraph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cgraph):
+                for sc_c, th_c in chunks:
+                    step(a.warmup + K, sc=sc_c, th=th_c)
+                d_step.add_(1)
+            torch.cuda.synchronize()
+            cgraph.replay()
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            for _ in range(K):
+                cgraph.replay()
+            torch.cuda.synchronize()
+            extra["chunked_graph_ms_per_step"] = (time.perf_counter() - tg) / K * 1e3
+            ctx.set_step_source(None)
         if a.per_design:
             extra["chunked_speedup_vs_per_design"] = extra["per_design_ms_per_step"] / extra["chunked_ms_per_step"]
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -76,16 +77,34 @@ struct KernelTimer {
 constexpr int64_t kAdjEntriesPerRay = 8;
 constexpr double kAdjBudgetBytes = 96.0 * 1024 * 1024 * 1024;
 
+// One built scene: its device tables and the SceneDev that points into them.
+struct SceneEntry {
+    uint64_t hash = 0;
+    uint64_t last_use = 0;
+    SceneDev sc{};
+    DevBuf lam_tab, dir_tab, slot, nlay, pupil_xy;
+    std::vector<int32_t> h_nlay;
+    void release()
+    {
+        for (DevBuf* b : { &lam_tab, &dir_tab, &slot, &nlay, &pupil_xy }) b->release();
+    }
+};
+// Scenes kept per context (least recently used evicted), so that calls
+// that alternate between a few scenes (a batch traced in chunks of designs)
+// rebuild nothing, and can be captured in one graph once each was built.
+constexpr int kSceneCache = 16;
+
 struct gwg_ctx {
     int device = -1;
     int n_cu = 0;
     std::string err;
-    // scene tables
+    // scene tables: the current scene (a copy of its cache entry's) and the cache
     uint64_t scene_hash = 0;
     bool scene_valid = false;
     SceneDev sc{};
-    DevBuf lam_tab, dir_tab, slot, nlay, pupil_xy;
     std::vector<int32_t> h_nlay;
+    std::vector<std::unique_ptr<SceneEntry>> scenes;
+    uint64_t scene_clock = 0;
     // per-call buffers
     DevBuf stats, partial, scratch, fwd_scratch, loss_work, grad_tmp;
     // thin-film queries
@@ -335,11 +354,31 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     h = fnv(h, ry->fov_deg, sizeof(double) * (ry->fov_mode == 0 ? 2 * ry->n_fov : 4));
     h = fnv_v(h, ry->rays_per_point); h = fnv_v(h, ry->max_events);
     if (c->scene_valid && h == c->scene_hash) return GWG_OK;
+    for (auto& e : c->scenes)
+        if (e->hash == h) {
+            e->last_use = ++c->scene_clock;
+            c->sc = e->sc;
+            c->h_nlay = e->h_nlay;
+            c->scene_hash = h;
+            c->scene_valid = true;
+            return GWG_OK;
+        }
     if (stream_capturing(stream))
         return fail(c, GWG_E_STATE, "the scene changed during stream capture; make the same call once before capturing");
     c->scene_valid = false;
+    // a cache entry for the new scene: a fresh one, or the least recently used
+    SceneEntry* ent = nullptr;
+    if ((int)c->scenes.size() < kSceneCache) {
+        c->scenes.emplace_back(new SceneEntry());
+        ent = c->scenes.back().get();
+    } else {
+        ent = c->scenes[0].get();
+        for (auto& e : c->scenes)
+            if (e->last_use < ent->last_use) ent = e.get();
+    }
+    ent->hash = 0;
 
-    SceneDev& s = c->sc;
+    SceneDev& s = ent->sc;
     s = SceneDev{};
     s.T = sl->T_mm; s.Lx = sl->L_mm; s.ER = sl->eye_relief_mm;
     s.px0 = sl->pupil_x0_mm; s.pw = sl->pupil_w_mm; s.ph = sl->pupil_h_mm;
@@ -419,25 +458,31 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     }
     s.N = ry->rays_per_point;
     s.Kmax = ry->max_events;
-    HIP_CHECK(c, c->lam_tab.ensure(lt.size() * sizeof(double)), "alloc lam_tab");
-    HIP_CHECK(c, c->dir_tab.ensure(dirs.size() * sizeof(double)), "alloc dir_tab");
-    HIP_CHECK(c, c->slot.ensure(slots.size()), "alloc slot");
-    HIP_CHECK(c, c->nlay.ensure(sizeof(int32_t) * DM), "alloc nlay");
-    HIP_CHECK(c, c->pupil_xy.ensure(sizeof(double) * 2 * (size_t)std::max(s.n_pupils, 1)), "alloc pupil table");
+    // the entry may have been in use by the stream's earlier kernels
+    HIP_CHECK(c, hipStreamSynchronize(stream), "scene rebuild");
+    HIP_CHECK(c, ent->lam_tab.ensure(lt.size() * sizeof(double)), "alloc lam_tab");
+    HIP_CHECK(c, ent->dir_tab.ensure(dirs.size() * sizeof(double)), "alloc dir_tab");
+    HIP_CHECK(c, ent->slot.ensure(slots.size()), "alloc slot");
+    HIP_CHECK(c, ent->nlay.ensure(sizeof(int32_t) * DM), "alloc nlay");
+    HIP_CHECK(c, ent->pupil_xy.ensure(sizeof(double) * 2 * (size_t)std::max(s.n_pupils, 1)), "alloc pupil table");
     if (s.n_pupils > 0)
-        HIP_CHECK(c, hipMemcpyAsync(c->pupil_xy.p, sl->eye_pupil_xy_mm, sizeof(double) * 2 * s.n_pupils,
+        HIP_CHECK(c, hipMemcpyAsync(ent->pupil_xy.p, sl->eye_pupil_xy_mm, sizeof(double) * 2 * s.n_pupils,
                                     hipMemcpyHostToDevice, stream), "upload pupil table");
-    HIP_CHECK(c, hipMemcpyAsync(c->lam_tab.p, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload lam_tab");
-    HIP_CHECK(c, hipMemcpyAsync(c->dir_tab.p, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload dir_tab");
-    HIP_CHECK(c, hipMemcpyAsync(c->slot.p, slots.data(), slots.size(), hipMemcpyHostToDevice, stream), "upload slots");
-    HIP_CHECK(c, hipMemcpyAsync(c->nlay.p, st->n_layers, sizeof(int32_t) * DM, hipMemcpyHostToDevice, stream), "upload n_layers");
+    HIP_CHECK(c, hipMemcpyAsync(ent->lam_tab.p, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload lam_tab");
+    HIP_CHECK(c, hipMemcpyAsync(ent->dir_tab.p, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, stream), "upload dir_tab");
+    HIP_CHECK(c, hipMemcpyAsync(ent->slot.p, slots.data(), slots.size(), hipMemcpyHostToDevice, stream), "upload slots");
+    HIP_CHECK(c, hipMemcpyAsync(ent->nlay.p, st->n_layers, sizeof(int32_t) * DM, hipMemcpyHostToDevice, stream), "upload n_layers");
     HIP_CHECK(c, hipStreamSynchronize(stream), "scene upload");
-    s.lam_tab = (const double*)c->lam_tab.p;
-    s.dir_tab = (const double*)c->dir_tab.p;
-    s.slot = (const uint8_t*)c->slot.p;
-    s.nlay = (const int32_t*)c->nlay.p;
-    s.pupil_xy = (const double*)c->pupil_xy.p;
-    c->h_nlay.assign(st->n_layers, st->n_layers + DM);
+    s.lam_tab = (const double*)ent->lam_tab.p;
+    s.dir_tab = (const double*)ent->dir_tab.p;
+    s.slot = (const uint8_t*)ent->slot.p;
+    s.nlay = (const int32_t*)ent->nlay.p;
+    s.pupil_xy = (const double*)ent->pupil_xy.p;
+    ent->h_nlay.assign(st->n_layers, st->n_layers + DM);
+    ent->hash = h;
+    ent->last_use = ++c->scene_clock;
+    c->sc = s;
+    c->h_nlay = ent->h_nlay;
     c->scene_hash = h;
     c->scene_valid = true;
     return GWG_OK;
@@ -547,7 +592,8 @@ int gwg_destroy(gwg_ctx* c)
     {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        for (DevBuf* b : { &c->lam_tab, &c->dir_tab, &c->slot, &c->nlay, &c->pupil_xy, &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
+        for (auto& e : c->scenes) e->release();
+        for (DevBuf* b : { &c->stats, &c->partial, &c->scratch, &c->fwd_scratch,
                            &c->loss_work, &c->tmm_tab, &c->tmm_slot, &c->adj_ent, &c->adj_cnt, &c->adj_ovf, &c->fwd_tape,
                            &c->tab, &c->tab_scale, &c->tab_acc, &c->tune_q, &c->tune_c, &c->tune_g, &c->tune_grad,
                            &c->adj_ck, &c->grad_tmp, &c->adj_order, &c->item_work, &c->fwd_order })

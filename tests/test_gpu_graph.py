@@ -89,3 +89,62 @@ def test_autotune_keeps_results(gctx, tmp_path):
         assert len([x for x in open(cache).read().split("\n") if x.strip()]) == 1
     finally:
         gctx.set_tuning()
+
+
+def test_design_chunks_in_one_graph(gctx):
+    """A batch traced as chunks of consecutive designs (each chunk's forward,
+    loss and adjoint before the next chunk's) gives the single launch's
+    irradiance bit for bit and its gradient to rounding (the loss is a sum
+    over designs; only the work items differ).  The context keeps every
+    chunk's scene, so the chunked step captures in one graph, whose replays
+    reproduce the eager chunked steps bit for bit."""
+    import dataclasses
+    w, inp, scene, thk = _scene("batched", n_designs=4, rays_per_point=200, fov_n=3,
+                                lambdas_nm=(450.0, 550.0, 650.0))
+    chunks = []
+    for d0 in (0, 2):
+        inp_c = dict(inp)
+        for k in ("thk", "mat", "n_layers"):
+            inp_c[k] = inp[k][d0:d0 + 2].copy()
+        chunks.append((gwg.SceneSpec.from_workload(w, inp_c),
+                       torch.tensor(inp_c["thk"], dtype=torch.float64, device="cuda:0")))
+
+    def chunked(step):
+        out = [tuple(t.clone() for t in _step(gctx, sc, th, w.seed, step)) for sc, th in chunks]
+        return torch.cat([o[0] for o in out]), torch.cat([o[1] for o in out])
+
+    irr_full, g_full = _step(gctx, scene, thk, w.seed, 3)
+    irr_c, g_c = chunked(3)
+    assert torch.equal(irr_c, irr_full)
+    scale = float(g_full.abs().max())
+    assert scale > 0 and float((g_c - g_full).abs().max()) <= 1e-12 * scale
+    ref = [chunked(5 + k) for k in range(2)]
+    d_step = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    gctx.set_step_source(d_step)
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for sc, th in chunks:
+                _step(gctx, sc, th, w.seed, 5)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            outs = [_step(gctx, sc, th, w.seed, 5) for sc, th in chunks]
+            d_step.add_(1)
+        torch.cuda.synchronize()
+        d_step.zero_()
+        torch.cuda.synchronize()
+        for k in range(2):
+            print(f"chunked replay {k}", flush=True)
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(torch.cat([o[0] for o in outs]), ref[k][0])
+            assert torch.equal(torch.cat([o[1] for o in outs]), ref[k][1])
+            # eager work in between, on a chunk's scene (its buffers were
+            # sized before the capture, so nothing the graph points to moves)
+            sc, th = chunks[k % 2]
+            _step(gctx, sc, th, w.seed, 60 + k)
+    finally:
+        gctx.set_step_source(None)
