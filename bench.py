@@ -357,8 +357,9 @@ def main():
         scenes = []
         for d in range(w.n_designs):
             inp_d = design_slice(inp, d)
-            scenes.append((gwg.SceneSpec.from_workload(w, inp_d),
-                           torch.tensor(inp_d["thk"], dtype=torch.float64, device=dev)))
+            sc_d = gwg.SceneSpec.from_workload(w, inp_d)
+            sc_d.first_design = d
+            scenes.append((sc_d, torch.tensor(inp_d["thk"], dtype=torch.float64, device=dev)))
         for sc_d, th_d in scenes:
             step(0, sc=sc_d, th=th_d)
         torch.cuda.synchronize()
@@ -379,8 +380,9 @@ def main():
         chunks = []
         for c0, c1 in zip(bounds[:-1], bounds[1:]):
             inp_c = design_slice(inp, c0, c1 - c0)
-            chunks.append((gwg.SceneSpec.from_workload(w, inp_c),
-                           torch.tensor(inp_c["thk"], dtype=torch.float64, device=dev)))
+            sc_c = gwg.SceneSpec.from_workload(w, inp_c)
+            sc_c.first_design = c0          # the batch's random streams: the same results
+            chunks.append((sc_c, torch.tensor(inp_c["thk"], dtype=torch.float64, device=dev)))
         for sc_c, th_c in chunks:
             step(0, sc=sc_c, th=th_c)
         torch.cuda.synchronize()

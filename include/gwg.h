@@ -176,6 +176,10 @@ typedef struct {
     const double* fov_deg;      /* host */
     int64_t rays_per_point;     /* 1 .. 2^40 */
     int32_t max_events;         /* 1..256 ray-surface interactions per ray */
+    int32_t first_design;       /* >= 0: the call's designs are designs first_design,
+                                   first_design + 1, ... of a larger batch, and draw that
+                                   batch's random streams (a batch traced in chunks of
+                                   designs gives the same results as in one call) */
 } gwg_rays;
 
 /* Eyebox outputs, device arrays of shape [D][n_lambda_sel][F][bins_y][bins_x]
@@ -221,8 +225,8 @@ typedef struct {
 } gwg_stats;
 
 /* Forward Monte Carlo trace of the whole batch (Methods; Eq. 5, Eq. 6).
- * Ray id = ((d * n_lambda_sel + l) * F + f) * rays_per_point + i draws its
- * random numbers from Philox4x32-10 with key (seed_lo, seed_hi ^ step_lo),
+ * Ray id = (((first_design + d) * n_lambda_sel + l) * F + f) * rays_per_point + i
+ * draws its random numbers from Philox4x32-10 with key (seed_lo, seed_hi ^ step_lo),
  * counter (id_lo, id_hi, block, tag): tag 0 block 0 gives the birth words,
  * tag 1 block h/4 the word of the h-th mirror hit.  step < 2^32.
  * flags: 0 or GWG_FWD_GRAD with at most one of GWG_FWD_MEMO,

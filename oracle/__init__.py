@@ -49,6 +49,7 @@ class Scene(C.Structure):
         ("seed", C.c_uint64), ("step", C.c_uint64),
         ("table_nodes", C.c_int32),
         ("n_eye_pupils", C.c_int32), ("eye_pupil_r", C.c_double), ("eye_pupil_xy", _dp),
+        ("first_design", C.c_int32),
     ]
 
 
@@ -194,7 +195,7 @@ class OracleScene:
 
     def __init__(self, w, inp: dict, seed: Optional[int] = None, step: int = 0,
                  thk: Optional[np.ndarray] = None, rays_per_point: Optional[int] = None,
-                 omega: Optional[np.ndarray] = None, table_nodes: int = 0):
+                 omega: Optional[np.ndarray] = None, table_nodes: int = 0, first_design: int = 0):
         from inputs import MAT_AIR, MAT_GLASS
         self.w = w
         self.arrays = {}
@@ -237,6 +238,7 @@ class OracleScene:
         s.seed = w.seed if seed is None else seed
         s.step = step
         s.table_nodes = table_nodes
+        s.first_design = first_design
         ep = inp.get("eye_pupils")
         if ep is not None and len(ep):
             xy = keep("eye_pupils", ep, np.float64)

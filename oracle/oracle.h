@@ -111,6 +111,11 @@ typedef struct {
     int32_t n_eye_pupils;
     double eye_pupil_r;
     const double* eye_pupil_xy;
+    /* the designs are designs first_design, ... of a larger batch: a ray's
+     * random stream is that of its id in the batch, (((first_design + d)
+     * n_lsel + l) F + f) rays_per_point + i; ray ids passed to and returned
+     * by these functions stay the call's own */
+    int32_t first_design;
 } orc_scene;
 
 /* Termination categories. */

@@ -70,6 +70,7 @@ typedef struct {
     uint32_t* thr;          /* reflect iff word < thr */
     double* p_eff;          /* thr / 2^32 */
     uint32_t key[2];
+    int64_t id_base;        /* added to a ray's id in its random stream */
     /* per point */
     int d, li, f, lam;
     double ng, na, lambda_nm;
@@ -100,6 +101,7 @@ static int ctx_init(ctx_t* c, const orc_scene* sc)
         c->thr[m] = (uint32_t)t;
         c->p_eff[m] = (double)c->thr[m] / 4294967296.0;
     }
+    c->id_base = (int64_t)sc->first_design * sc->n_lsel * (sc->fov_mode == 1 ? 1 : sc->n_fov) * sc->rays_per_point;
     c->key[0] = (uint32_t)sc->seed;
     c->key[1] = (uint32_t)(sc->seed >> 32) ^ (uint32_t)sc->step;
     size_t n = (size_t)M * 2 * (size_t)(sc->max_layers > 0 ? sc->max_layers : 1);
@@ -171,7 +173,8 @@ typedef struct {
 
 static void philox_words(const ctx_t* c, int64_t ray_id, uint32_t block, uint32_t tag, uint32_t out[4])
 {
-    uint32_t ctr[4] = { (uint32_t)(uint64_t)ray_id, (uint32_t)((uint64_t)ray_id >> 32), block, tag };
+    const int64_t gid = ray_id + c->id_base;
+    uint32_t ctr[4] = { (uint32_t)(uint64_t)gid, (uint32_t)((uint64_t)gid >> 32), block, tag };
     orc_philox4x32_10(ctr, c->key, out);
 }
 

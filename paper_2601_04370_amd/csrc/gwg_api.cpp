@@ -296,6 +296,13 @@ int check_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     }
     if (ry->rays_per_point < 1 || ry->rays_per_point > (int64_t(1) << 40)) return fail(c, GWG_E_INVAL, "rays_per_point out of range");
     if (ry->max_events < 1 || ry->max_events > kMaxEvents) return fail(c, GWG_E_INVAL, "max_events out of range");
+    if (ry->first_design < 0) return fail(c, GWG_E_INVAL, "first_design must be >= 0");
+    {
+        const double F = ry->fov_mode == 0 ? (double)ry->n_fov : 1.0;
+        const double ids = ((double)ry->first_design + (double)st->n_designs) * ry->n_lambda_sel * F *
+                           (double)ry->rays_per_point;
+        if (ids > 4.0e18) return fail(c, GWG_E_INVAL, "ray ids of the batch exceed 2^62");
+    }
     return GWG_OK;
 }
 
@@ -352,7 +359,7 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
     h = fnv(h, ry->lambda_sel, sizeof(int32_t) * ry->n_lambda_sel);
     h = fnv_v(h, ry->fov_mode); h = fnv_v(h, ry->n_fov);
     h = fnv(h, ry->fov_deg, sizeof(double) * (ry->fov_mode == 0 ? 2 * ry->n_fov : 4));
-    h = fnv_v(h, ry->rays_per_point); h = fnv_v(h, ry->max_events);
+    h = fnv_v(h, ry->rays_per_point); h = fnv_v(h, ry->max_events); h = fnv_v(h, ry->first_design);
     if (c->scene_valid && h == c->scene_hash) return GWG_OK;
     for (auto& e : c->scenes)
         if (e->hash == h) {
@@ -457,6 +464,7 @@ int build_scene(gwg_ctx* c, const gwg_slab* sl, const gwg_prma* pr, const gwg_ma
         dirs.assign(4, 0.0);
     }
     s.N = ry->rays_per_point;
+    s.id_base = (int64_t)ry->first_design * s.n_lsel * s.F * s.N;
     s.Kmax = ry->max_events;
     // the entry may have been in use by the stream's earlier kernels
     HIP_CHECK(c, hipStreamSynchronize(stream), "scene rebuild");

@@ -114,6 +114,7 @@ struct SceneDev {
     const double* dir_tab;            // [n_lsel][F][4]
     double fov_x0, fov_x1, fov_y0, fov_y1;  // random mode bounds, degrees
     int64_t N;                        // rays per point
+    int64_t id_base;                  // added to a ray's id in its random stream (first_design n_lsel F N)
     int32_t Kmax;
     int32_t fp_shift;
     uint32_t key0, key1;              // Philox key (seed_lo, seed_hi ^ step)

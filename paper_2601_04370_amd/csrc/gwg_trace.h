@@ -116,8 +116,9 @@ __device__ inline uint32_t philox_key1(const SceneDev& sc)
 __device__ inline void ray_birth(const SceneDev& sc, const PointLds& pl, int64_t id, Ray& r)
 {
     r.key1 = philox_key1(sc);
-    u32x4 w = philox10((uint32_t)(uint64_t)id, (uint32_t)((uint64_t)id >> 32), 0u, 0u, sc.key0, r.key1);
-    r.id = id;
+    const int64_t gid = id + sc.id_base;      // the ray's id in the whole batch
+    u32x4 w = philox10((uint32_t)(uint64_t)gid, (uint32_t)((uint64_t)gid >> 32), 0u, 0u, sc.key0, r.key1);
+    r.id = gid;
     r.px = sc.px0 + u24(w.x) * sc.pw;
     r.py = u24(w.y) * sc.ph - 0.5 * sc.ph;
     r.pz = sc.T;

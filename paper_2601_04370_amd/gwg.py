@@ -64,7 +64,7 @@ class Stacks(C.Structure):
 class Rays(C.Structure):
     _fields_ = [("n_lambda_sel", C.c_int32), ("lambda_sel", _i32p), ("fov_mode", C.c_int32),
                 ("n_fov", C.c_int32), ("fov_deg", _dp), ("rays_per_point", C.c_int64),
-                ("max_events", C.c_int32)]
+                ("max_events", C.c_int32), ("first_design", C.c_int32)]
 
 
 class Eyebox(C.Structure):
@@ -206,6 +206,8 @@ class SceneSpec:
     # eye pupils: centres [P][2] (mm) and radius; None for the eyebox grid
     eye_pupils: Optional[np.ndarray] = None
     eye_pupil_r: float = 0.0
+    # the designs are these designs of a larger batch (its random streams)
+    first_design: int = 0
     _keep: dict = field(default_factory=dict, repr=False)
 
     @classmethod
@@ -263,7 +265,7 @@ class SceneSpec:
         st = Stacks(self.n_designs, self.n_mirrors, self.max_layers, None, _np_ptr(self.mat, _u8p),
                     _np_ptr(self.n_layers, _i32p))
         r = Rays(len(self.lambda_sel), _np_ptr(self.lambda_sel, _i32p), self.fov_mode, self.n_fov,
-                 _np_ptr(self.fov_deg, _dp), self.rays_per_point, self.max_events)
+                 _np_ptr(self.fov_deg, _dp), self.rays_per_point, self.max_events, self.first_design)
         k["structs"] = (m, s, p, st, r)
         return m, s, p, st, r
 

@@ -98,7 +98,6 @@ def test_design_chunks_in_one_graph(gctx):
     over designs; only the work items differ).  The context keeps every
     chunk's scene, so the chunked step captures in one graph, whose replays
     reproduce the eager chunked steps bit for bit."""
-    import dataclasses
     w, inp, scene, thk = _scene("batched", n_designs=4, rays_per_point=200, fov_n=3,
                                 lambdas_nm=(450.0, 550.0, 650.0))
     chunks = []
@@ -106,8 +105,9 @@ def test_design_chunks_in_one_graph(gctx):
         inp_c = dict(inp)
         for k in ("thk", "mat", "n_layers"):
             inp_c[k] = inp[k][d0:d0 + 2].copy()
-        chunks.append((gwg.SceneSpec.from_workload(w, inp_c),
-                       torch.tensor(inp_c["thk"], dtype=torch.float64, device="cuda:0")))
+        sc_c = gwg.SceneSpec.from_workload(w, inp_c)
+        sc_c.first_design = d0                 # the batch's random streams
+        chunks.append((sc_c, torch.tensor(inp_c["thk"], dtype=torch.float64, device="cuda:0")))
 
     def chunked(step):
         out = [tuple(t.clone() for t in _step(gctx, sc, th, w.seed, step)) for sc, th in chunks]

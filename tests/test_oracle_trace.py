@@ -260,3 +260,21 @@ def test_fixed_point_bins_round_half_even(orc):
         if r.bin >= 0:
             Q[r.bin] += np.uint64(np.rint(r.w * 2.0 ** 24))
     assert np.array_equal(Q, q.reshape(-1))
+
+
+def test_first_design_selects_the_batch_streams(orc):
+    """Designs traced on their own with first_design set draw the streams
+    they draw inside the whole batch: bins, counts and weights equal that
+    batch's slice (a batch traced in chunks of designs is the same batch)."""
+    w = inputs.small_variant("batched", n_designs=3, rays_per_point=60, fov_n=3, lambdas_nm=(450.0, 600.0))
+    inp = inputs.make_inputs(w)
+    q, c, ws, _ = orc.OracleScene(w, inp).forward()
+    for d0, n in ((1, 2), (2, 1)):
+        sub = dict(inp)
+        for k in ("thk", "mat", "n_layers"):
+            sub[k] = inp[k][d0:d0 + n].copy()
+        qs, cs, wss, _ = orc.OracleScene(w, sub, first_design=d0).forward()
+        assert np.array_equal(qs, q[d0:d0 + n]) and np.array_equal(cs, c[d0:d0 + n])
+        assert np.array_equal(wss, ws[d0:d0 + n])
+        q0, _, _, _ = orc.OracleScene(w, sub).forward()      # without it: other streams
+        assert not np.array_equal(q0, q[d0:d0 + n])
