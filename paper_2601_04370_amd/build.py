@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libgwg.so")
 SOURCES = ["gwg_kernels.hip", "gwg_api.cpp"]
 HEADERS = ["gwg_internal.h", "gwg_device.h", "gwg_adjoint.h", "gwg_trace.h", "gwg_launch.h",
            "gwg_fwd_kernel.h", "gwg_bwd_kernel.h", "gwg_memo_kernel.h",
-           "gwg_table.h", "gwg_table_kernel.h", "gwg_omega_kernel.h"]
+           "gwg_table.h", "gwg_table_kernel.h", "gwg_omega_kernel.h", "gwg_trig_poly.h"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gwg_trig_poly.h"
+
 namespace gwg {
 
 // ---------------------------------------------------------------- complex
@@ -155,21 +157,20 @@ __device__ inline void sincos_cw(float x, float* s, float* c)
 }
 
 // Circular or hyperbolic cosine and sine of a >= 0 with one shared
-// polynomial.  With u = -r^2 (circular) or +r^2 (hyperbolic),
-//     sin r or sinh r = r (1 + u/3! + u^2/5! + ...),
-//     cos r or cosh r = 1 + u/2! + u^2/4! + ...,
-// so the dominant Horner evaluation is common to lanes of either kind and a
-// wave that mixes propagating and evanescent layers executes it once.
+// polynomial evaluation.  With u = -r^2 (circular) or +r^2 (hyperbolic),
+//     sin r or sinh r = r (1 + u P_F(u)),
+//     cos r or cosh r = 1 + u P_G(u),
+// where P_F and P_G are minimax fits (Remez exchange, degrees 5 and 6 in u)
+// of the entire functions the two share, on u in [-(pi/4)^2, (pi/8)^2]
+// (gwg_trig_poly.h, written by gen_trig_poly.py; max errors 8e-17 and 1e-18
+// before rounding, one term fewer each than truncated Taylor series of the
+// same accuracy).  So the dominant Horner evaluation is common to lanes of
+// either kind and a wave that mixes propagating and evanescent layers
+// executes it once.
 // Circular: r = a - n pi/2 (two-term Cody-Waite), then a quadrant rotation.
-// Hyperbolic: r = a / 2^k <= pi/4, then k doublings
+// Hyperbolic: r = a / 2^k <= pi/8, then k doublings
 // (sinh 2r = 2 sinh r cosh r, cosh 2r = cosh^2 r + sinh^2 r).
-// Truncation as for sincos_cw (degree 15/16 in f64, 9/10 in f32).
-// Taylor coefficients 1/n!, n = 0..16, in constant memory: uniform operands
-// that the FMAs of the polynomials below take directly from scalar registers.
-__constant__ double kInvFact[17] = {
-    inv_fact(0), inv_fact(1), inv_fact(2), inv_fact(3), inv_fact(4), inv_fact(5), inv_fact(6), inv_fact(7),
-    inv_fact(8), inv_fact(9), inv_fact(10), inv_fact(11), inv_fact(12), inv_fact(13), inv_fact(14),
-    inv_fact(15), inv_fact(16) };
+// The single-precision variant keeps Taylor coefficients 1/n! (degrees 9/10).
 __constant__ float kInvFactF[11] = {
     (float)inv_fact(0), (float)inv_fact(1), (float)inv_fact(2), (float)inv_fact(3), (float)inv_fact(4),
     (float)inv_fact(5), (float)inv_fact(6), (float)inv_fact(7), (float)inv_fact(8), (float)inv_fact(9),
@@ -188,9 +189,9 @@ __device__ inline void gtrig(double a, bool hyper_in, double* C, double* S)
     double n = rint(a * two_over_pi);
     int k = 0;
     if (hyper) {
-        // smallest k with a / 2^k <= pi/4 (a is finite and moderate)
+        // smallest k with a / 2^k <= pi/8 (a is finite and moderate)
         int e;
-        frexp(a * 1.2732395447351628, &e);      // a / (pi/4) = m 2^e, m in [0.5, 1)
+        frexp(a * 2.5464790894703255, &e);      // a / (pi/8) = m 2^e, m in [0.5, 1)
         k = e > 0 ? e : 0;
         n = 0.0;                                 // the quadrant rotation below is then the identity
     }
@@ -200,22 +201,20 @@ __device__ inline void gtrig(double a, bool hyper_in, double* C, double* S)
     r = fma(-n, pio2_lo, r);
     if (HC) r = ldexp(r, -k);
     double u = hyper ? r * r : -(r * r);
-    double ps = kInvFact[15];
-    ps = fma(ps, u, kInvFact[13]);
-    ps = fma(ps, u, kInvFact[11]);
-    ps = fma(ps, u, kInvFact[9]);
-    ps = fma(ps, u, kInvFact[7]);
-    ps = fma(ps, u, kInvFact[5]);
-    ps = fma(ps, u, kInvFact[3]);
+    double ps = kTrigPolyF[5];
+    ps = fma(ps, u, kTrigPolyF[4]);
+    ps = fma(ps, u, kTrigPolyF[3]);
+    ps = fma(ps, u, kTrigPolyF[2]);
+    ps = fma(ps, u, kTrigPolyF[1]);
+    ps = fma(ps, u, kTrigPolyF[0]);
     double sn = fma(r * u, ps, r);
-    double pc = kInvFact[16];
-    pc = fma(pc, u, kInvFact[14]);
-    pc = fma(pc, u, kInvFact[12]);
-    pc = fma(pc, u, kInvFact[10]);
-    pc = fma(pc, u, kInvFact[8]);
-    pc = fma(pc, u, kInvFact[6]);
-    pc = fma(pc, u, kInvFact[4]);
-    pc = fma(pc, u, kInvFact[2]);
+    double pc = kTrigPolyG[6];
+    pc = fma(pc, u, kTrigPolyG[5]);
+    pc = fma(pc, u, kTrigPolyG[4]);
+    pc = fma(pc, u, kTrigPolyG[3]);
+    pc = fma(pc, u, kTrigPolyG[2]);
+    pc = fma(pc, u, kTrigPolyG[1]);
+    pc = fma(pc, u, 0.5);
     double cs = fma(u, pc, 1.0);
     // Both kinds run the same straight-line code (no divergent branch): the
     // quadrant rotation (the identity for hyperbolic lanes, whose n is 0),
