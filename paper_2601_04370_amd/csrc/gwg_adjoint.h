@@ -257,23 +257,29 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     //    in none: v_0 stays in registers).  stored: the forward solve ran
     //    this sweep and left v_0 in block 0 and the checkpoints in blocks
     //    1.. (64-byte blocks, block g at chk + g cstride), with the same
-    //    arithmetic.
+    //    arithmetic: the half-period sine/cosine, whose sign (-1)^(sum n)
+    //    is put back on each checkpoint and on v_0.
     if (L <= 0) return;
     constexpr int K = kSegL;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
     V2d vp = { 1.0, 0.0, eta0p, 0.0 };
+    double nsum = 0.0;
+    auto sign_bit = [&]() { return (uint32_t)((int)nsum & 1) << 31; };
     auto layer_fwd = [&](int jj) {
         const int idx = front ? jj : (L - 1 - jj);
         double kq, xs, ys, xp, yp, C, S;
         sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-        layer_cs<double, HC>(kq, thk[idx], &C, &S);             // t = 0 gives the identity exactly
+        layer_cs_half<double, HC>(kq, thk[idx], &C, &S, &nsum);   // t = 0 gives the identity exactly
         step_real_d(vs, C, S * xs, S * ys);
         step_real_d(vp, C, S * xp, S * yp);
     };
     auto checkpoint = [&](int g) {
+        const uint32_t sb = sign_bit();
         double* c = chk + (int64_t)g * 8 * cstride;
-        c[0] = vs.br; c[cstride] = vs.bi; c[2 * cstride] = vs.cr; c[3 * cstride] = vs.ci;
-        c[4 * cstride] = vp.br; c[5 * cstride] = vp.bi; c[6 * cstride] = vp.cr; c[7 * cstride] = vp.ci;
+        c[0] = flip_sign(vs.br, sb); c[cstride] = flip_sign(vs.bi, sb);
+        c[2 * cstride] = flip_sign(vs.cr, sb); c[3 * cstride] = flip_sign(vs.ci, sb);
+        c[4 * cstride] = flip_sign(vp.br, sb); c[5 * cstride] = flip_sign(vp.bi, sb);
+        c[6 * cstride] = flip_sign(vp.cr, sb); c[7 * cstride] = flip_sign(vp.ci, sb);
     };
     // a stored block is 64 contiguous bytes, read whole
     auto read_block = [&](const double* c, V2d& a, V2d& b) {
@@ -293,6 +299,9 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             for (int i = K - 1; i >= 0; --i) layer_fwd(g * K + i);
             if (g > 0) checkpoint(g);
         }
+        const uint32_t sb = sign_bit();
+        vs = V2d{ flip_sign(vs.br, sb), flip_sign(vs.bi, sb), flip_sign(vs.cr, sb), flip_sign(vs.ci, sb) };
+        vp = V2d{ flip_sign(vp.br, sb), flip_sign(vp.bi, sb), flip_sign(vp.cr, sb), flip_sign(vp.ci, sb) };
     }
     // 2) cotangent rows of the taken coefficients
     cd u1s, u2s, u1p, u2p;

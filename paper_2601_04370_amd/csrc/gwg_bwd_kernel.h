@@ -191,7 +191,8 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
                 int htotal;
                 const int hoff = wave_excl_scan(nh, &htotal);
                 __threadfence_block();
-                solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, htotal, hoff, &c_fp64, &c_lay);
+                solve_hits<MODE>(sc, *pl, ArrStacks{ s_thk, s_slot, sc.Lmax, LaneSlots3::kPer * kSlotLanes * 8 }, sl,
+                                 hq, htotal, hoff, &c_fp64, &c_lay);
                 __threadfence_block();
             }
             if (active) {

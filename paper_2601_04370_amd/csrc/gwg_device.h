@@ -281,6 +281,63 @@ __device__ inline void gtrig(float a, bool hyper_in, float* C, float* S)
     *C = cs;
 }
 
+// gtrig with a half-period reduction and the sign left to the caller.
+// Circular: a = n pi + r, |r| <= pi/2 (two-term Cody-Waite), and cos a,
+// sin a are (-1)^n cos r, (-1)^n sin r; this returns C = cos r, S = sin r
+// and adds n to *nsum.  A product of layer matrices [[C, .], [., C]] with
+// entries linear in (C, S) then differs from the exact one by (-1)^sum n
+// only, which the caller applies once.  No quadrant rotation is needed, at
+// the price of longer polynomials (degrees 7 and 7 on u in [-(pi/2)^2,
+// (pi/8)^2], max errors 5e-19 and 1e-17 before rounding).  Hyperbolic lanes
+// (n = 0) are as in gtrig.
+template <bool HC = true>
+__device__ inline void gtrig_half(double a, bool hyper_in, double* C, double* S, double* nsum)
+{
+#pragma clang fp contract(fast)
+    const bool hyper = HC && hyper_in;
+    const double one_over_pi = 0.31830988618379067154;
+    const double pi_hi = 3.141592653589793116;
+    const double pi_lo = 1.2246467991473532072e-16;
+    double n = rint(a * one_over_pi);
+    int k = 0;
+    if (hyper) {
+        int e;
+        frexp(a * 2.5464790894703255, &e);      // a / (pi/8) = m 2^e, m in [0.5, 1)
+        k = e > 0 ? e : 0;
+        n = 0.0;
+    }
+    double r = fma(-n, pi_hi, a);
+    r = fma(-n, pi_lo, r);
+    if (HC) r = ldexp(r, -k);
+    const double u = hyper ? r * r : -(r * r);
+    double ps = kTrigHalfPolyF[7];
+    ps = fma(ps, u, kTrigHalfPolyF[6]);
+    ps = fma(ps, u, kTrigHalfPolyF[5]);
+    ps = fma(ps, u, kTrigHalfPolyF[4]);
+    ps = fma(ps, u, kTrigHalfPolyF[3]);
+    ps = fma(ps, u, kTrigHalfPolyF[2]);
+    ps = fma(ps, u, kTrigHalfPolyF[1]);
+    ps = fma(ps, u, kTrigHalfPolyF[0]);
+    double sn = fma(r * u, ps, r);
+    double pc = kTrigHalfPolyG[7];
+    pc = fma(pc, u, kTrigHalfPolyG[6]);
+    pc = fma(pc, u, kTrigHalfPolyG[5]);
+    pc = fma(pc, u, kTrigHalfPolyG[4]);
+    pc = fma(pc, u, kTrigHalfPolyG[3]);
+    pc = fma(pc, u, kTrigHalfPolyG[2]);
+    pc = fma(pc, u, kTrigHalfPolyG[1]);
+    pc = fma(pc, u, 0.5);
+    double cs = fma(u, pc, 1.0);
+    for (int i = 0; i < k; ++i) {
+        double s2 = 2.0 * sn * cs;
+        cs = fma(cs, cs, sn * sn);
+        sn = s2;
+    }
+    *nsum += n;
+    *S = sn;
+    *C = cs;
+}
+
 // cosh and sinh of x >= 0 from expm1 (no cancellation for small x)
 __device__ inline void coshsinh(double x, double* ch, double* sh)
 {
@@ -344,6 +401,104 @@ __device__ inline double* slot_lane_base(double* base, int n_slots, int per, int
     return base + (tid / kSlotLanes) * n_slots * per * kSlotLanes + (tid % kSlotLanes);
 }
 
+// One layer of a stack as the thin-film solves read it from LDS: the
+// thickness, the slot's byte offset in a lane's slot table (slot x values
+// per slot x kSlotLanes x 8) and the slot.  Each stack of Lmax layers sits
+// between kRecPad pad records (zero thickness, slot 0) at either end, so
+// the reads that run ahead of a sweep stay inside the stack's records and
+// a layer is one 16-byte read.
+struct __align__(16) LayerRec {
+    double t;
+    uint32_t soff;
+    uint32_t slot;
+};
+constexpr int kRecPad = 2;
+__host__ __device__ inline int rec_stride(int Lmax) { return Lmax + 2 * kRecPad; }
+
+// Layer sources of the thin-film solves.  A cursor yields one stack's
+// layers in incidence order; reads past the stack's end are harmless:
+// records have pads there, arrays clamp the index to the last layer.
+struct RecCursor {
+    const LayerRec* p;
+    int dir;
+    __device__ LayerRec get() const { return *p; }
+    __device__ void next() { p += dir; }
+};
+struct ArrCursor {
+    const double* thk;
+    const uint8_t* slot;
+    int idx, dir, last;
+    uint32_t unit;                       // bytes per slot in a lane's slot table
+    __device__ LayerRec get() const
+    {
+        const uint32_t s = slot[idx];
+        LayerRec r;
+        r.t = thk[idx]; r.soff = s * unit; r.slot = s;
+        return r;
+    }
+    __device__ void next() { idx = idx == last ? idx : idx + dir; }
+};
+// One stack as records (rec: its layer 0) or as thickness and slot arrays.
+struct RecStack {
+    const LayerRec* rec;
+    __device__ RecCursor cursor(int L, bool front) const
+    {
+        RecCursor c = { rec + (front ? L - 1 : 0), front ? -1 : 1 };
+        return c;
+    }
+};
+struct ArrStack {
+    const double* thk;
+    const uint8_t* slot;
+    uint32_t unit;
+    __device__ ArrCursor cursor(int L, bool front) const
+    {
+        ArrCursor c = { thk, slot, front ? L - 1 : 0, front ? -1 : 1, front ? 0 : L - 1, unit };
+        return c;
+    }
+};
+// A design's stacks (one per mirror) in either form.
+struct RecStacks {
+    const LayerRec* base;                // [M][rec_stride(Lmax)]
+    int Lmax;
+    __device__ RecStack mirror(int m) const
+    {
+        RecStack s = { base + m * rec_stride(Lmax) + kRecPad };
+        return s;
+    }
+};
+struct ArrStacks {
+    const double* thk;                   // [M][Lmax]
+    const uint8_t* slot;
+    int Lmax;
+    uint32_t unit;
+    __device__ ArrStack mirror(int m) const
+    {
+        ArrStack s = { thk + m * Lmax, slot + m * Lmax, unit };
+        return s;
+    }
+};
+
+// Records of n_stacks stacks (thk, slot: [n_stacks][Lmax]) into dst
+// ([n_stacks][rec_stride(Lmax)]), for slot tables of `per` values per slot.
+// Called by the whole block.
+__device__ inline void stage_recs(LayerRec* dst, const double* thk, const uint8_t* slot, int n_stacks, int Lmax,
+                                  int per)
+{
+    const int stride = rec_stride(Lmax), n = n_stacks * stride;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int m = i / stride, j = i - m * stride - kRecPad;
+        LayerRec r = { 0.0, 0u, 0u };
+        if (j >= 0 && j < Lmax) {
+            const uint32_t sl = slot[m * Lmax + j];
+            r.t = thk[m * Lmax + j];
+            r.slot = sl;
+            r.soff = sl * (uint32_t)(per * kSlotLanes * 8);
+        }
+        dst[i] = r;
+    }
+}
+
 // LaneSlots5 keeps all five values per lane (lanes may differ in
 // wavelength).  LaneSlots3 keeps kq, x_s, y_s per lane and takes N^2 of the
 // slot from arrays shared by the workgroup (one wavelength per workgroup):
@@ -367,6 +522,12 @@ struct LaneSlots5 {
         const double* P = sp + s * 5 * ls;
         Pl[0] = P[0]; Pl[1] = P[ls]; Pl[2] = P[2 * ls]; Pl[3] = P[3 * ls];
     }
+    __device__ void lossless_r(const LayerRec& r, double& kq, double& xs, double& ys, double& xp,
+                               double& yp) const
+    {
+        const double* P = (const double*)((const unsigned char*)sp + r.soff);
+        kq = P[0]; xs = P[ls]; ys = P[2 * ls]; xp = P[3 * ls]; yp = P[4 * ls];
+    }
 };
 struct LaneSlots3 {
     static constexpr int kPer = 3;
@@ -383,6 +544,14 @@ struct LaneSlots3 {
         const double* P = sp + s * 3 * ls;
         kq = P[0]; xs = P[ls]; ys = P[2 * ls];
         const double2 c = reinterpret_cast<const double2*>(pxy)[s];   // one paired LDS read
+        xp = ys * c.x; yp = xs * c.y;
+    }
+    __device__ void lossless_r(const LayerRec& r, double& kq, double& xs, double& ys, double& xp,
+                               double& yp) const
+    {
+        const double* P = (const double*)((const unsigned char*)sp + r.soff);
+        kq = P[0]; xs = P[ls]; ys = P[2 * ls];
+        const double2 c = reinterpret_cast<const double2*>(pxy)[r.slot];
         xp = ys * c.x; yp = xs * c.y;
     }
     __device__ void absorbing(int s, double* Pl) const
@@ -417,6 +586,12 @@ struct LaneSlots3x {
     {
         const double* P = sp + s * 5 * ls;
         Pl[0] = P[0]; Pl[1] = P[ls]; Pl[2] = nsq[2 * s]; Pl[3] = nsq[2 * s + 1];
+    }
+    __device__ void lossless_r(const LayerRec& r, double& kq, double& xs, double& ys, double& xp,
+                               double& yp) const
+    {
+        const double* P = (const double*)((const unsigned char*)sp + r.soff);
+        kq = P[0]; xs = P[ls]; ys = P[2 * ls]; xp = P[3 * ls]; yp = P[4 * ls];
     }
 };
 
@@ -470,6 +645,19 @@ __device__ inline void layer_cs(T kq, T t, T* C, T* S)
     gtrig<HC>(hyper ? -kq * t : kq * t, hyper, C, S);
 }
 
+// layer_cs up to a sign: in double precision the half-period form (C, S
+// are (-1)^n times the layer's cosine and sine, n added to *nsum); the
+// single-precision chain keeps the exact sign and leaves *nsum alone.
+template <typename T, bool HC = true>
+__device__ inline void layer_cs_half(T kq, T t, T* C, T* S, double* nsum)
+{
+    const bool hyper = HC && kq < (T)0;
+    if constexpr (sizeof(T) == 8)
+        gtrig_half<HC>(hyper ? -kq * t : kq * t, hyper, C, S, nsum);
+    else
+        gtrig<HC>(hyper ? -kq * t : kq * t, hyper, C, S);
+}
+
 // Entries of an absorbing layer: returns C, X_s, Y_s, X_p, Y_p.
 template <typename T>
 __device__ inline void layer_cplx(const T* P, T k0, T t, CTv<T>* C, CTv<T>* Xs, CTv<T>* Ys,
@@ -521,47 +709,55 @@ __device__ inline Coef4 finish_coeffs(const V2<T>& vs, const V2<T>& vp, int es, 
     return o;
 }
 
-// Lossless stack: one loop body for every layer.  The LDS reads run ahead of
-// the arithmetic: thickness and slot two layers ahead, the slot's parameters
-// one layer ahead.  HC = false: no layer of any lane is evanescent.
-template <typename T, bool HC, class SL>
-__device__ __attribute__((always_inline)) inline void lossless_sweep(const double* __restrict__ thk,
-                                                                     const uint8_t* __restrict__ slot, int L,
-                                                                     bool front, const SL& sl, V2<T>& vs, V2<T>& vp,
-                                                                     int& es, int& ep, double* ck, int64_t ckb)
+// Sign flip of x when sb is 1 << 31 (an exact negation), identity for 0.
+__device__ inline double flip_sign(double x, uint32_t sb)
 {
+    return __hiloint2double(__double2hiint(x) ^ (int)sb, __double2loint(x));
+}
+
+// Lossless stack: one loop body for every layer.  The LDS reads run ahead of
+// the arithmetic: the layer record two layers ahead, the slot's parameters
+// one layer ahead.  HC = false: no layer of any lane is evanescent.
+// In double precision the layers' cosines and sines come from the
+// half-period reduction with the sign (-1)^n of each left out, so the chain
+// vector is (-1)^(sum n) times the exact one; that sign is put back on the
+// stored checkpoints and on the result (exact negations).
+template <typename T, bool HC, class SL, class Cur>
+__device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, int L, const SL& sl, V2<T>& vs,
+                                                                     V2<T>& vp, int& es, int& ep, double* ck,
+                                                                     int64_t ckb)
+{
+    double nsum = 0.0;                                  // sum of the layers' n (exact: small integers)
+    auto sign_bit = [&]() { return (uint32_t)((int)nsum & 1) << 31; };
     // ck (T = double only): the adjoint's sweep checkpoints v_{g kSegL}
     // (incidence-order layer g kSegL and below) go to the 64-byte block g at
     // ck + g ckb, whole; v_0 goes to block 0 after the loop.
     auto store = [&](int g) {
+        const uint32_t sb = sign_bit();
         double2* c = (double2*)(ck + (int64_t)g * ckb);
-        c[0] = make_double2((double)vs.br, (double)vs.bi);
-        c[1] = make_double2((double)vs.cr, (double)vs.ci);
-        c[2] = make_double2((double)vp.br, (double)vp.bi);
-        c[3] = make_double2((double)vp.cr, (double)vp.ci);
+        c[0] = make_double2(flip_sign((double)vs.br, sb), flip_sign((double)vs.bi, sb));
+        c[1] = make_double2(flip_sign((double)vs.cr, sb), flip_sign((double)vs.ci, sb));
+        c[2] = make_double2(flip_sign((double)vp.br, sb), flip_sign((double)vp.bi, sb));
+        c[3] = make_double2(flip_sign((double)vp.cr, sb), flip_sign((double)vp.ci, sb));
     };
-    const int dir = front ? -1 : 1;
-    const int last = front ? 0 : L - 1;
-    const int idx = front ? L - 1 : 0;
-    double t0 = thk[idx];
+    const LayerRec r0 = cur.get();
+    double t0 = r0.t;
     double kq, xs, ys, xp, yp;
-    sl.lossless(slot[idx], kq, xs, ys, xp, yp);
-    int idx1 = idx == last ? idx : idx + dir;
-    double t1 = thk[idx1];
-    int s1 = slot[idx1];
+    sl.lossless_r(r0, kq, xs, ys, xp, yp);
+    cur.next();
+    LayerRec r1 = cur.get();
     // loop index j of the next checkpoint (incidence-order layer L-1-j a
     // positive multiple of kSegL), or L when none is left
     int jck = (L - 1) % kSegL;
     if (jck >= L - 1) jck = L;
 #pragma unroll 4
     for (int j = 0; j < L; ++j) {
-        const int idx2 = idx1 == last ? idx1 : idx1 + dir;
-        const double t2 = thk[idx2];
-        const int s2 = slot[idx2];
+        cur.next();
+        const LayerRec r2 = cur.get();
         double kq1, xs1, ys1, xp1, yp1;
-        sl.lossless(s1, kq1, xs1, ys1, xp1, yp1);
+        sl.lossless_r(r1, kq1, xs1, ys1, xp1, yp1);
         T C, S;
-        layer_cs<T, HC>((T)kq, (T)t0, &C, &S);    // t = 0 gives the identity exactly
+        layer_cs_half<T, HC>((T)kq, (T)t0, &C, &S, &nsum);   // t = 0 gives the identity exactly
         step_real(vs, C, S * (T)xs, S * (T)ys);
         step_real(vp, C, S * (T)xp, S * (T)yp);
         if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
@@ -569,23 +765,31 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(const doubl
             store((L - 1 - j) / kSegL);
             jck = jck + kSegL < L - 1 ? jck + kSegL : L;
         }
-        t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
-        t1 = t2; s1 = s2; idx1 = idx2;
+        t0 = r1.t; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+        r1 = r2;
     }
-    if (sizeof(T) == 8 && ck) store(0);
+    if constexpr (sizeof(T) == 8) {
+        if (ck) store(0);
+        const uint32_t sb = sign_bit();
+        vs.br = flip_sign(vs.br, sb); vs.bi = flip_sign(vs.bi, sb);
+        vs.cr = flip_sign(vs.cr, sb); vs.ci = flip_sign(vs.ci, sb);
+        vp.br = flip_sign(vp.br, sb); vp.bi = flip_sign(vp.bi, sb);
+        vp.cr = flip_sign(vp.cr, sb); vp.ci = flip_sign(vp.ci, sb);
+    }
 }
 
-// Forward solve of one hit.  thk/slot: this mirror's layers in stack order
-// (LDS); `front` selects incidence order 0..L-1 (else reversed).  sl: this
-// lane's slot table.  Exit medium admittances (es, ep) are complex in general.
+// Forward solve of one hit.  stk: this mirror's layers in stack order
+// (LDS, RecStack or ArrStack); `front` selects incidence order 0..L-1
+// (else reversed).  sl: this lane's slot table.  Exit
+// medium admittances (es, ep) are complex in general.
 // The stack thicknesses and slot parameters are read in double precision
 // and rounded to the chain precision T once per layer.  circ: no lane of the
 // calling wave has an evanescent lossless slot (the sweep then skips the
 // hyperbolic case; the results are the same).  ck (lossless FP64 stacks):
 // the entry's checkpoint blocks for the adjoint's sweep (block g at ck + g
 // ckb), or null.
-template <typename T, class SL>
-__device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* __restrict__ thk, const uint8_t* __restrict__ slot, int L,
+template <typename T, class SL, class Stk>
+__device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const Stk& stk, int L,
                                   bool front, const SL& sl, uint32_t cplx_mask, double k0d, double eta0s,
                                   double eta0p, cd etaEs, cd etaEp, cd tp_factor, bool circ = false,
                                   double* ck = nullptr, int64_t ckb = 8)
@@ -595,21 +799,21 @@ __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const double* _
     V2<T> vp = { (T)1, (T)0, (T)etaEp.re, (T)etaEp.im };
     int es = 0, ep = 0;
     if (L <= 0) return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
-    const int dir = front ? -1 : 1;
-    int idx = front ? L - 1 : 0;
     if (cplx_mask == 0u) {
         if (circ)
-            lossless_sweep<T, false>(thk, slot, L, front, sl, vs, vp, es, ep, ck, ckb);
+            lossless_sweep<T, false>(stk.cursor(L, front), L, sl, vs, vp, es, ep, ck, ckb);
         else
-            lossless_sweep<T, true>(thk, slot, L, front, sl, vs, vp, es, ep, ck, ckb);
+            lossless_sweep<T, true>(stk.cursor(L, front), L, sl, vs, vp, es, ep, ck, ckb);
         return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
     }
-    for (int j = 0; j < L; ++j, idx += dir) {
-        T t = (T)thk[idx];                  // t = 0 gives the identity exactly
-        int s = slot[idx];
+    auto cur = stk.cursor(L, front);
+    for (int j = 0; j < L; ++j, cur.next()) {
+        const LayerRec r = cur.get();
+        T t = (T)r.t;                       // t = 0 gives the identity exactly
+        const int s = (int)r.slot;
         if (!((cplx_mask >> s) & 1u)) {
             double kq, xs, ys, xp, yp;
-            sl.lossless(s, kq, xs, ys, xp, yp);
+            sl.lossless_r(r, kq, xs, ys, xp, yp);
             T C, S;
             layer_cs((T)kq, t, &C, &S);
             step_real(vs, C, S * (T)xs, S * (T)ys);

@@ -29,9 +29,9 @@
 // per wave goes on hit by hit.
 
 // Thin-film coefficients of one hit for this lane (fills the lane's slot table).
-template <int MODE, class SL>
-__device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                  const uint8_t* s_slot, const SL& sl, int m, bool front, double kappa,
+template <int MODE, class SL, class Stks>
+__device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const Stks& stks,
+                                  const SL& sl, int m, bool front, double kappa,
                                   bool* used_fp64, double* ck = nullptr, int64_t ckb = 8)
 {
     bool hyp = false;                       // an evanescent lossless slot at this kappa
@@ -46,15 +46,14 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
     const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
     const double eta0s = q0, eta0p = pl.ng * pl.ng / q0;
     const int L = pl.nlay[m];
-    const double* thk = s_thk + m * sc.Lmax;
-    const uint8_t* slot = s_slot + m * sc.Lmax;
+    const auto stk = stks.mirror(m);
     const bool fp64 = (MODE == GWG_FP64) || (MODE == GWG_FP32_MIXED && near_critical(pl, sc.n_slots, kappa));
     *used_fp64 = fp64;
     if (fp64)
-        return tmm_solve<double>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
+        return tmm_solve<double>(stk, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                                  mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ, MODE == GWG_FP64 ? ck : nullptr,
                                  ckb);
-    return tmm_solve<float>(thk, slot, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
+    return tmm_solve<float>(stk, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                             mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
 }
 
@@ -78,9 +77,9 @@ __device__ inline int dense_slot(int p, int off, int)
 // in the order queue field 11 lists (else lane by lane).
 // ck (non-null): checkpoint store of the adjoint entries; a hit whose
 // queue field 10 holds a slot c >= 0 stores its sweep checkpoints there.
-template <int MODE, class SL>
-__device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                  const uint8_t* s_slot, const SL& sl, const HitQueue& hq, int total,
+template <int MODE, class SL, class Stks>
+__device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const Stks& stks,
+                                  const SL& sl, const HitQueue& hq, int total,
                                   int off, unsigned long long* n_fp64, unsigned long long* n_lay,
                                   double* ck = nullptr, int64_t ck_total = 0, bool perm = false)
 {
@@ -99,7 +98,7 @@ __device__ inline void solve_hits(const SceneDev& sc, const PointLds& pl, const 
                 const double c = hq.base[10 * (int64_t)hq.cap + q];
                 if (c >= 0.0) ckp = ck + (int64_t)c * 8;
             }
-            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64, ckp,
+            const Coef4 c = hit_solve<MODE>(sc, pl, stks, sl, m, (meta >> 8) & 1, kappa, &u64, ckp,
                                             8 * ck_total);
             hq.put_coef(q, c);
             *n_fp64 += u64 ? 1ull : 0ull;
@@ -203,9 +202,9 @@ __device__ inline bool fmemo_resolve(const HitQueue& hq, int total, int off, int
 }
 
 // Solve keys [u0, u1) (one per lane) from their first hits into the table.
-template <int MODE, class SL>
-__device__ inline void fmemo_solve(const SceneDev& sc, const PointLds& pl, const double* s_thk,
-                                   const uint8_t* s_slot, const SL& sl, const HitQueue& hq,
+template <int MODE, class SL, class Stks>
+__device__ inline void fmemo_solve(const SceneDev& sc, const PointLds& pl, const Stks& stks,
+                                   const SL& sl, const HitQueue& hq,
                                    const FwdMemo& fm, int u0, int u1, unsigned long long* n_fp64,
                                    unsigned long long* n_lay)
 {
@@ -218,7 +217,7 @@ __device__ inline void fmemo_solve(const SceneDev& sc, const PointLds& pl, const
             const int meta = hq.meta(p);
             const int m = meta & 255;
             bool u64 = false;
-            const Coef4 c = hit_solve<MODE>(sc, pl, s_thk, s_slot, sl, m, (meta >> 8) & 1, kappa, &u64);
+            const Coef4 c = hit_solve<MODE>(sc, pl, stks, sl, m, (meta >> 8) & 1, kappa, &u64);
             double* o = fm.coef + u;
             o[0] = c.rs.re; o[kFwdMemoKeys] = c.rs.im; o[2 * kFwdMemoKeys] = c.rp.re; o[3 * kFwdMemoKeys] = c.rp.im;
             o[4 * kFwdMemoKeys] = c.ts.re; o[5 * kFwdMemoKeys] = c.ts.im;
@@ -287,10 +286,10 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     // slot table: all five values per lane, except with the memoized solves,
     // whose key tables need the LDS (they solve few hits)
     using SlotTable = typename std::conditional<MEMO, LaneSlots3, LaneSlots3x>::type;
-    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, lds_bins != 0, 0, SlotTable::kPer);
+    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, B, lds_bins != 0, 0, SlotTable::kPer, true);
     PointLds* pl = (PointLds*)(smem + lay.off_pl);
-    double* s_thk = (double*)(smem + lay.off_thk);
-    uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
+    LayerRec* s_rec = (LayerRec*)(smem + lay.off_thk);
+    const RecStacks stks = { s_rec, sc.Lmax };
     double* s_sp = (double*)(smem + lay.off_sp);
     unsigned long long* s_q = (unsigned long long*)(smem + lay.off_q);
     uint32_t* s_c = (uint32_t*)(smem + lay.off_c);
@@ -315,7 +314,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
         int64_t point, i0, i1;
         int d, l, f;
         decode_item(sc, item, &point, &d, &l, &f, &i0, &i1);
-        stage_point(sc, d, l, f, pl, s_thk, s_slot);
+        stage_point(sc, d, l, f, pl, nullptr, nullptr, s_rec, SlotTable::kPer);
         int64_t n_work = 0;                               // this wave's mirror hits in this item (uniform)
         if (lds_bins)
             for (int k = tid; k < B; k += WG) { s_q[k] = 0ull; s_c[k] = 0u; }
@@ -398,9 +397,9 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                 const int u0 = n_keys;
                 if (MEMO && memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
                 if (MEMO && memo)
-                    fmemo_solve<MODE>(sc, *pl, s_thk, s_slot, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
+                    fmemo_solve<MODE>(sc, *pl, stks, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
                 else
-                    solve_hits<MODE>(sc, *pl, s_thk, s_slot, sl, hq, total, off, &n_fp64, &n_lay,
+                    solve_hits<MODE>(sc, *pl, stks, sl, hq, total, off, &n_fp64, &n_lay,
                                      cks ? st.ck : nullptr, st.ck_total, !MEMO);
                 __threadfence_block();
             }

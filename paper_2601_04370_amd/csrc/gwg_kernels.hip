@@ -37,14 +37,17 @@ struct SmemLayout {
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
+// recs: the stacks as layer records (LayerRec, off_thk; no slot array)
+// rather than thickness and slot arrays.
 __host__ __device__ inline SmemLayout smem_layout(int M, int Lmax, int n_slots, int wg, int B,
-                                                  bool lds_bins, int n_grad_regions, int slot_per = LaneSlots3::kPer)
+                                                  bool lds_bins, int n_grad_regions, int slot_per = LaneSlots3::kPer,
+                                                  bool recs = false)
 {
     SmemLayout s;
     int o = 0;
     s.off_pl = o; o = align16(o + (int)sizeof(PointLds));
-    s.off_thk = o; o = align16(o + 8 * M * Lmax);
-    s.off_slot = o; o = align16(o + M * Lmax);
+    s.off_thk = o; o = align16(o + (recs ? (int)sizeof(LayerRec) * M * rec_stride(Lmax) : 8 * M * Lmax));
+    s.off_slot = o; o = align16(o + (recs ? 0 : M * Lmax));
     s.off_sp = o; o = align16(o + 8 * n_slots * slot_per * ((wg + 63) / 64 * 64));   // whole waves
     s.off_q = o; o = align16(o + (lds_bins ? 8 * B : 0));
     s.off_c = o; o = align16(o + (lds_bins ? 4 * B : 0));
@@ -54,9 +57,11 @@ __host__ __device__ inline SmemLayout smem_layout(int M, int Lmax, int n_slots, 
     return s;
 }
 
-// Stage one point's uniform data and its design's stacks into LDS.
+// Stage one point's uniform data and its design's stacks into LDS: as
+// thickness and slot arrays (s_thk, s_slot) or as layer records (s_rec, for
+// slot tables of `per` values per slot).
 __device__ inline void stage_point(const SceneDev& sc, int d, int l, int f, PointLds* pl,
-                                   double* s_thk, uint8_t* s_slot)
+                                   double* s_thk, uint8_t* s_slot, LayerRec* s_rec = nullptr, int per = 0)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const double* lt = sc.lam_tab + (int64_t)l * LT_STRIDE;
@@ -95,7 +100,10 @@ __device__ inline void stage_point(const SceneDev& sc, int d, int l, int f, Poin
     const int n = sc.M * sc.Lmax;
     const double* gthk = sc.thk + (int64_t)d * n;
     const uint8_t* gslot = sc.slot + (int64_t)d * n;
-    for (int i = tid; i < n; i += nt) { s_thk[i] = gthk[i]; s_slot[i] = gslot[i]; }
+    if (s_rec)
+        stage_recs(s_rec, gthk, gslot, sc.M, sc.Lmax, per);
+    else
+        for (int i = tid; i < n; i += nt) { s_thk[i] = gthk[i]; s_slot[i] = gslot[i]; }
 }
 
 __device__ inline void decode_item(const SceneDev& sc, int64_t item, int64_t* point, int* d, int* l,
@@ -243,10 +251,9 @@ __global__ void __launch_bounds__(256) k_tmm_rt(const double* __restrict__ thk, 
                                                 double* __restrict__ out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double* s_thk = (double*)smem;
-    uint8_t* s_slot = (uint8_t*)(smem + align16(8 * L));
-    double* s_sp = (double*)(smem + align16(8 * L) + align16(L > 0 ? L : 1));
-    for (int i = threadIdx.x; i < L; i += blockDim.x) { s_thk[i] = thk[i]; s_slot[i] = slot[i]; }
+    LayerRec* s_rec = (LayerRec*)smem;
+    double* s_sp = (double*)(smem + sizeof(LayerRec) * rec_stride(L));
+    stage_recs(s_rec, thk, slot, 1, L, LaneSlots5::kPer);
     __syncthreads();
     const LaneSlots5 sl = { slot_lane_base(s_sp, n_slots, LaneSlots5::kPer, threadIdx.x) };
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
@@ -280,8 +287,9 @@ __global__ void __launch_bounds__(256) k_tmm_rt(const double* __restrict__ thk, 
             for (int s = 0; s < n_slots; ++s)
                 fp64 |= (kappa > lt[LT_CRIT + 2 * s] && kappa < lt[LT_CRIT + 2 * s + 1]);
         }
-        Coef4 c = fp64 ? tmm_solve<double>(s_thk, s_slot, L, true, sl, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf)
-                       : tmm_solve<float>(s_thk, s_slot, L, true, sl, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf);
+        const RecStack stk = { s_rec + kRecPad };
+        Coef4 c = fp64 ? tmm_solve<double>(stk, L, true, sl, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf)
+                       : tmm_solve<float>(stk, L, true, sl, cplx_mask, k0, q0, n0 * n0 / q0, qE, etaEp, tpf);
         o[0] = c.rs.re; o[1] = c.rs.im; o[2] = c.rp.re; o[3] = c.rp.im;
         o[4] = c.ts.re; o[5] = c.ts.im; o[6] = c.tp.re; o[7] = c.tp.im;
     }
@@ -449,7 +457,7 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
 size_t fwd_smem_bytes(const SceneDev& sc, int wg, bool lds_bins)
 {
     return (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, lds_bins, 0,
-                               sc.memo ? LaneSlots3::kPer : LaneSlots3x::kPer).total
+                               sc.memo ? LaneSlots3::kPer : LaneSlots3x::kPer, true).total
            + (sc.memo ? (size_t)(wg / 64) * fwd_memo_wave_bytes() : 0);
 }
 size_t bwd_smem_bytes(const SceneDev& sc, int wg)
@@ -622,7 +630,8 @@ hipError_t launch_table_build(const SceneDev& sc, double* tab, int n_cu, unsigne
     // enough workgroups to fill the device twice, each with at least one wave of entries
     int64_t chunks = std::max<int64_t>(1, (2 * (int64_t)n_cu + dls - 1) / dls);
     chunks = std::min<int64_t>(chunks, (per + wg - 1) / wg);
-    const size_t sm = (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, false, 0).total;
+    const size_t sm = (size_t)smem_layout(sc.M, sc.Lmax, sc.n_slots, wg, sc.bins_x * sc.bins_y, false, 0,
+                                          LaneSlots3::kPer, true).total;
     const dim3 grid((unsigned)(dls * chunks)), block(wg);
     switch (sc.precision) {
     case GWG_FP64:
@@ -699,7 +708,7 @@ hipError_t launch_irradiance(const uint64_t* q, int64_t n, double scale, double*
 
 size_t tmm_smem_bytes(int L, int n_slots, int wg)
 {
-    return (size_t)(align16(8 * L) + align16(L > 0 ? L : 1) + 8 * n_slots * LaneSlots5::kPer * ((wg + 63) / 64 * 64));
+    return (size_t)(sizeof(LayerRec) * rec_stride(L) + 8 * n_slots * LaneSlots5::kPer * ((wg + 63) / 64 * 64));
 }
 
 hipError_t launch_tmm_rt(int precision, const double* thk, const uint8_t* slot, int L,

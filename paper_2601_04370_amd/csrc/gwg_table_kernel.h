@@ -27,17 +27,17 @@ __global__ void __launch_bounds__(256) k_table_build(SceneDev sc, double* __rest
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int WG = blockDim.x;
-    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, sc.bins_x * sc.bins_y, false, 0);
+    const SmemLayout lay = smem_layout(sc.M, sc.Lmax, sc.n_slots, WG, sc.bins_x * sc.bins_y, false, 0,
+                                       LaneSlots3::kPer, true);
     PointLds* pl = (PointLds*)(smem + lay.off_pl);
-    double* s_thk = (double*)(smem + lay.off_thk);
-    uint8_t* s_slot = (uint8_t*)(smem + lay.off_slot);
+    LayerRec* s_rec = (LayerRec*)(smem + lay.off_thk);
     double* s_sp = (double*)(smem + lay.off_sp);
     const int tid = threadIdx.x;
     const LaneSlots3 sl = { slot_lane_base(s_sp, sc.n_slots, LaneSlots3::kPer, tid), pl->nsq, pl->pxy };
     const int64_t dl = blockIdx.x / chunks;
     const int chunk = blockIdx.x % chunks;
     const int d = (int)(dl / sc.n_lsel), l = (int)(dl % sc.n_lsel);
-    stage_point(sc, d, l, 0, pl, s_thk, s_slot);
+    stage_point(sc, d, l, 0, pl, nullptr, nullptr, s_rec, LaneSlots3::kPer);
     __syncthreads();
     const int n = sc.table_n;
     const int64_t per = (int64_t)sc.M * 2 * n;
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(256) k_table_build(SceneDev sc, double* __rest
         const int ms = (int)(q / n);
         const int m = ms >> 1;
         bool u64 = false;
-        const Coef4 c = hit_solve<MODE>(sc, *pl, s_thk, s_slot, sl, m, (ms & 1) == 0, table_kappa(pl->ng, j, n), &u64);
+        const Coef4 c = hit_solve<MODE>(sc, *pl, RecStacks{ s_rec, sc.Lmax }, sl, m, (ms & 1) == 0, table_kappa(pl->ng, j, n), &u64);
         double* o = out + q * 8;
         o[0] = c.rs.re; o[1] = c.rs.im; o[2] = c.rp.re; o[3] = c.rp.im;
         o[4] = c.ts.re; o[5] = c.ts.im; o[6] = c.tp.re; o[7] = c.tp.im;

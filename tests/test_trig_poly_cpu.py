@@ -2,7 +2,10 @@
 
 The thin-film sweeps evaluate cos/sin (circular layers) and cosh/sinh
 (evanescent layers) of the phase thickness with one pair of minimax
-polynomials.  These CPU tests check that
+polynomials: after a quarter-period reduction with an exact quadrant
+rotation (the adjoint's sweeps), or after a half-period reduction that leaves
+the sign (-1)^n to the caller (the forward sweeps).  These CPU tests check
+that
 
 - the committed header is what its generator writes (Remez fit, 60 digits);
 - the device routine's steps, replayed here in exact arithmetic with every
@@ -28,14 +31,15 @@ HEADER = os.path.join(PKG, "csrc", "gwg_trig_poly.h")
 CTX = decimal.Context(prec=80)
 
 
-def _coeffs():
+def _coeffs(name=""):
     src = open(HEADER).read()
     hexf = r"(-?0x[0-9a-f.]+p[-+]?\d+)"
-    f_part = src.split("kTrigPolyF[")[1].split("kTrigPolyG[")[0]
-    g_part = src.split("kTrigPolyG[")[1]
-    F = [float.fromhex(x) for x in re.findall(hexf, f_part)]
-    G = [float.fromhex(x) for x in re.findall(hexf, g_part)]
-    return F, G
+
+    def arr(key):
+        body = src.split(f"double kTrig{name}Poly{key}[")[1].split("};")[0]
+        return [float.fromhex(x) for x in re.findall(hexf, body.split("=", 1)[1])]
+
+    return arr("F"), arr("G")
 
 
 def _fma(a, b, c):
@@ -79,6 +83,33 @@ def _device_trig(a, hyper, F, G):
     return cs, sn
 
 
+def _device_trig_half(a, hyper, F, G):
+    """The half-period routine's operations in order, each rounded once;
+    returns (C, S, n) with cos a = (-1)^n C, sin a = (-1)^n S."""
+    n = float(round(_mul(a, 0.31830988618379067154)))
+    k = 0
+    if hyper:
+        _, e = math.frexp(_mul(a, 2.5464790894703255))
+        k, n = max(e, 0), 0.0
+    r = _fma(-n, 3.141592653589793116, a)
+    r = _fma(-n, 1.2246467991473532072e-16, r)
+    r = math.ldexp(r, -k)
+    u = _mul(r, r) if hyper else -_mul(r, r)
+    ps = F[-1]
+    for c in reversed(F[:-1]):
+        ps = _fma(ps, u, c)
+    sn = _fma(_mul(r, u), ps, r)
+    pc = G[-1]
+    for c in reversed(G[:-1]):
+        pc = _fma(pc, u, c)
+    cs = _fma(u, pc, 1.0)
+    for _ in range(k):
+        s2 = _mul(_mul(2.0, sn), cs)
+        cs = _fma(cs, cs, _mul(sn, sn))
+        sn = s2
+    return cs, sn, int(n)
+
+
 def _series_sin_cos(x):
     x = D(x)
     tiny = D(10) ** -70
@@ -103,15 +134,17 @@ def test_header_matches_generator():
 
 def test_coefficients_near_taylor():
     # minimax coefficients stay close to the Taylor ones they replace; the
-    # top one absorbs the dropped terms (under 1 %), the low ones barely move
-    F, G = _coeffs()
-    assert len(F) == 6 and len(G) == 7
-    for P, first in ((F, 3), (G, 2)):
-        for j, c in enumerate(P):
-            t = 1.0 / math.factorial(2 * j + first)
-            bound = 1e-2 if j == len(P) - 1 else 1e-4
-            assert abs(c - t) <= bound * t, (first, j, c, t)
-    assert G[0] == 0.5
+    # top one absorbs the dropped terms (a few %), the low ones barely move
+    for name, nF, nG in (("", 6, 7), ("Half", 8, 8)):
+        F, G = _coeffs(name)
+        assert len(F) == nF and len(G) == nG
+        for P, first in ((F, 3), (G, 2)):
+            for j, c in enumerate(P):
+                t = 1.0 / math.factorial(2 * j + first)
+                bound = 5e-2 if j == len(P) - 1 else 1e-3
+                assert abs(c - t) <= bound * t, (name, first, j, c, t)
+        # the device code writes the constant term of G as the literal 0.5
+        assert G[0] == 0.5
 
 
 def test_circular_accuracy():
@@ -143,4 +176,33 @@ def test_hyperbolic_accuracy():
         if a > 0:
             worst = max(worst, float(abs(D(s) - sh) / sh))
     # the k doublings each add about an ulp of relative error
+    assert worst <= 4e-15, worst
+
+
+def test_half_period_circular_accuracy():
+    F, G = _coeffs("Half")
+    rng = random.Random(13)
+    worst_c = worst_s = 0.0
+    args = [rng.uniform(0.0, 12.0) for _ in range(1500)] + [rng.uniform(0.0, 1.7) for _ in range(500)]
+    args += [j * math.pi / 4 for j in range(17)] + [0.0, 1e-300, 1e-8]
+    for a in args:
+        c, s_, n = _device_trig_half(a, False, F, G)
+        sg = -1 if n & 1 else 1
+        ce, se = _series_sin_cos(a)
+        worst_c = max(worst_c, abs(float(D(sg * c) - ce)))
+        worst_s = max(worst_s, abs(float(D(sg * s_) - se)))
+        assert abs(a - n * math.pi) <= math.pi / 2 + 1e-12
+    assert worst_c <= 2.5e-16 and worst_s <= 2.5e-16, (worst_c, worst_s)
+
+
+def test_half_period_hyperbolic_accuracy():
+    F, G = _coeffs("Half")
+    rng = random.Random(14)
+    worst = 0.0
+    for a in [rng.uniform(0.0, 6.0) for _ in range(600)] + [math.pi / 8, 1.0, 4.0]:
+        c, s_, n = _device_trig_half(a, True, F, G)
+        assert n == 0
+        ea, eb = D(a).exp(CTX), (-D(a)).exp(CTX)
+        ch, sh = (ea + eb) / 2, (ea - eb) / 2
+        worst = max(worst, float(abs(D(c) - ch) / ch), float(abs(D(s_) - sh) / sh))
     assert worst <= 4e-15, worst
