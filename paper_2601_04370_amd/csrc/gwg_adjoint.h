@@ -315,7 +315,13 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     //    contraction, the covector step and the inverse step, and no
     //    per-segment state is kept.  Checkpoint k + 1 is loaded while segment
     //    k runs; each layer's LDS operands are loaded one layer ahead.
+    //    The sines and cosines are the half-period ones, (-1)^n times the
+    //    layer's own: after layers 0..j-1 the covector and the walked vector
+    //    both carry the factor (-1)^(n_0 + ... + n_{j-1}), so their
+    //    contraction is exact; a checkpoint (exact sign) joins the walk with
+    //    that factor put on it.
     const double k2 = 2.0 * k0;
+    double nsum_c = 0.0;                                // sum of the covector sweep's n so far
     V2d ws = vs, wp = vp, nws = vs, nwp = vp;
     auto load_chk = [&](int k) {
         const double* c = chk + (int64_t)k * (stored ? cstride : 8 * cstride);
@@ -327,26 +333,42 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
         }
     };
     if (K < L) load_chk(1);
+    // Software pipeline over the layers, as in the forward sweep: layer
+    // j+1's argument is reduced from slot parameters read one iteration
+    // earlier, layer j+2's parameters and thickness are read, and layer
+    // j+3's slot index.  Indices past the last layer stay at the last.
+    using LT = LayerTrig<double, HC>;
     int idx = front ? 0 : L - 1;
     const int step = front ? 1 : -1;
-    double t0 = thk[idx];
+    const int last = front ? L - 1 : 0;
+    auto nxt = [&](int i) { return i == last ? i : i + step; };
     double kq, xs, ys, xp, yp;
     sl.lossless(slot[idx], kq, xs, ys, xp, yp);
+    TrigArg ta = LT::reduce(kq, thk[idx]);              // t = 0 gives the identity exactly
+    int idn = nxt(idx);
+    double kq1, xs1, ys1, xp1, yp1;
+    sl.lossless(slot[idn], kq1, xs1, ys1, xp1, yp1);
+    double t1 = thk[idn];
+    int idn2 = nxt(idn);
+    int s2 = slot[idn2];
     for (int lo = 0; lo < L; lo += K) {
         if (lo > 0) {
-            ws = nws;
-            wp = nwp;
+            const uint32_t sb = (uint32_t)((int)nsum_c & 1) << 31;
+            ws = V2d{ flip_sign(nws.br, sb), flip_sign(nws.bi, sb), flip_sign(nws.cr, sb), flip_sign(nws.ci, sb) };
+            wp = V2d{ flip_sign(nwp.br, sb), flip_sign(nwp.bi, sb), flip_sign(nwp.cr, sb), flip_sign(nwp.ci, sb) };
             if (lo + K < L) load_chk(lo / K + 1);
         }
         const int hi = lo + K < L ? lo + K : L;
 #pragma unroll 2
         for (int j = lo; j < hi; ++j) {
-            const int idn = j + 1 < L ? idx + step : idx;
-            const double t1 = thk[idn];
-            double kq1, xs1, ys1, xp1, yp1;
-            sl.lossless(slot[idn], kq1, xs1, ys1, xp1, yp1);
+            const int idn3 = nxt(idn2);
+            double kq2, xs2, ys2, xp2, yp2;
+            sl.lossless(s2, kq2, xs2, ys2, xp2, yp2);
+            const double t2 = thk[idn2];
+            s2 = slot[idn3];
+            const TrigArg ta1 = LT::reduce(kq1, t1);        // the next layer's (the last layer's again at the end)
             double C, S;
-            layer_cs<double, HC>(kq, t0, &C, &S);
+            LT::eval(ta, &C, &S, &nsum_c);
             const double sXs = S * xs, sYs = S * ys, sXp = S * xp, sYp = S * yp;
             const double gys = kq < 0.0 ? -ys : ys;
             // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
@@ -360,7 +382,9 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             cov_step_real(u1p, u2p, C, sXp, sYp);
             step_real_d(ws, C, -sXs, -sYs);
             step_real_d(wp, C, -sXp, -sYp);
-            idx = idn; t0 = t1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+            idx = idn; ta = ta1; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+            idn = idn2; kq1 = kq2; xs1 = xs2; ys1 = ys2; xp1 = xp2; yp1 = yp2; t1 = t2;
+            idn2 = idn3;
         }
     }
 }

@@ -258,6 +258,36 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
         if (s_st[k]) atomicAdd(&stats[k], s_st[k]);
 }
 
+// One kind's queue of entry indices in a wave: n (wave-uniform) entries at
+// positions 0..n-1, position p in lane p of lo (p < 64) or of hi (p >= 64).
+struct KindQueue {
+    int lo = -1, hi = -1, n = 0;
+    // file lane's entry c if `mine` (all lanes call; entries keep lane order)
+    __device__ void add(bool mine, int c, int lane)
+    {
+        const unsigned long long m = __ballot(mine);
+        const int below = __popcll(m & ((1ull << lane) - 1ull));
+        const int cnt = __popcll(m);
+        // a permutation of the lanes: the entries go to lanes (n + rank) mod
+        // 64, the other lanes' pushes fill the remaining lanes (unread)
+        const int dst = mine ? ((n + below) & 63) : ((n + cnt + (lane - below)) & 63);
+        const int got = __builtin_amdgcn_ds_permute(dst << 2, c);
+        if (lane >= n && lane < n + cnt) lo = got;               // positions n .. 63
+        if (lane + 64 < n + cnt) hi = got;                       // positions 64 .. n + cnt - 1
+        n += cnt;
+    }
+    // the first min(n, 64) entries, one per lane (-1 past n)
+    __device__ int take()
+    {
+        const int lane = (int)(threadIdx.x & 63);
+        const int v = lane < n ? lo : -1;
+        lo = hi;
+        hi = -1;
+        n = n > 64 ? n - 64 : 0;
+        return v;
+    }
+};
+
 // Thin-film part of the adjoint over the entries stored by the forward trace.
 // Items whose regions overflowed are left to k_trace_bwd.  LOSSLESS: the
 // scene has no absorbing slot.
@@ -302,9 +332,41 @@ __global__ void __launch_bounds__(128, 2) k_adj_entries(SceneDev sc, const doubl
         const int32_t* cnt = st.cnt + item * st.waves;
         int total = 0;
         for (int w = 0; w < st.waves; ++w) total += cnt[w];
-        for (int b = wave; b * 64 < total; b += n_waves) {
-            const int v = b * 64 + lane;
-            if (v < total) {
+        // Batches of one kind: the wave scans its chunks of 64 entries (item
+        // order) and files each entry under its kind, an entry whose kappa
+        // may meet an evanescent layer or one that cannot; a batch of 64 is
+        // taken from a kind's queue as soon as it holds that many, the rest
+        // at the end.  Most batches then take the sweeps without the
+        // hyperbolic case, and a batch's entries stay close together in item
+        // order (their stored sweeps share lines).  Each kind's queue is two
+        // registers per lane, positions 0-63 and 64-127; entries reach their
+        // positions by a lane permutation.
+        KindQueue qc, qh;
+        int chunk = wave;
+        for (;;) {
+            int v = -1;
+            for (;;) {                                    // wave-uniform: the next batch
+                if (qc.n >= 64) { v = qc.take(); break; }
+                if (qh.n >= 64) { v = qh.take(); break; }
+                if (chunk * 64 >= total) {
+                    if (qc.n > 0) { v = qc.take(); break; }
+                    if (qh.n > 0) { v = qh.take(); break; }
+                    break;
+                }
+                const int c = chunk * 64 + lane;
+                bool ev = false;
+                if (c < total) {
+                    int rr = 0, k = c;
+                    while (k >= cnt[rr]) { k -= cnt[rr]; ++rr; }
+                    const double kap = st.ent[(item * st.waves + rr) * st.cap_w + k];
+                    ev = kap * kap > pl->kap2_evan;
+                }
+                qc.add(c < total && !ev, c, lane);
+                qh.add(c < total && ev, c, lane);
+                chunk += n_waves;
+            }
+            if (__ballot(v >= 0) == 0ull) break;
+            if (v >= 0) {
                 int rr = 0, k = v;
                 while (k >= cnt[rr]) { k -= cnt[rr]; ++rr; }
                 const int64_t e = (item * st.waves + rr) * st.cap_w + k;

@@ -290,8 +290,15 @@ __device__ inline void gtrig(float a, bool hyper_in, float* C, float* S)
 // the price of longer polynomials (degrees 7 and 7 on u in [-(pi/2)^2,
 // (pi/8)^2], max errors 5e-19 and 1e-17 before rounding).  Hyperbolic lanes
 // (n = 0) are as in gtrig.
+// The work is split in two: trig_reduce takes the argument to (r, u, n, k)
+// and trig_eval evaluates the polynomials and the doublings, so a sweep can
+// reduce the next layer's argument while it evaluates the current one's
+// (the two are independent; the FP64 pipeline then has two chains to
+// interleave).  gtrig_half is the two in a row.
+struct TrigArg { double r, u, n; int k; };
+
 template <bool HC = true>
-__device__ inline void gtrig_half(double a, bool hyper_in, double* C, double* S, double* nsum)
+__device__ inline TrigArg trig_reduce(double a, bool hyper_in)
 {
 #pragma clang fp contract(fast)
     const bool hyper = HC && hyper_in;
@@ -309,33 +316,46 @@ __device__ inline void gtrig_half(double a, bool hyper_in, double* C, double* S,
     double r = fma(-n, pi_hi, a);
     r = fma(-n, pi_lo, r);
     if (HC) r = ldexp(r, -k);
-    const double u = hyper ? r * r : -(r * r);
-    double ps = kTrigHalfPolyF[7];
-    ps = fma(ps, u, kTrigHalfPolyF[6]);
-    ps = fma(ps, u, kTrigHalfPolyF[5]);
-    ps = fma(ps, u, kTrigHalfPolyF[4]);
-    ps = fma(ps, u, kTrigHalfPolyF[3]);
-    ps = fma(ps, u, kTrigHalfPolyF[2]);
-    ps = fma(ps, u, kTrigHalfPolyF[1]);
-    ps = fma(ps, u, kTrigHalfPolyF[0]);
+    TrigArg t;
+    t.r = r;
+    t.u = hyper ? r * r : -(r * r);
+    t.n = n;
+    t.k = k;
+    return t;
+}
+
+template <bool HC = true>
+__device__ inline void trig_eval(const TrigArg& t, double* C, double* S, double* nsum)
+{
+#pragma clang fp contract(fast)
+    const double r = t.r, u = t.u;
+    // the two Horner chains step in turn: each FP64 step waits on the one
+    // before it, so the other chain's step fills the gap
+    double ps = kTrigHalfPolyF[7], pc = kTrigHalfPolyG[7];
+    ps = fma(ps, u, kTrigHalfPolyF[6]); pc = fma(pc, u, kTrigHalfPolyG[6]);
+    ps = fma(ps, u, kTrigHalfPolyF[5]); pc = fma(pc, u, kTrigHalfPolyG[5]);
+    ps = fma(ps, u, kTrigHalfPolyF[4]); pc = fma(pc, u, kTrigHalfPolyG[4]);
+    ps = fma(ps, u, kTrigHalfPolyF[3]); pc = fma(pc, u, kTrigHalfPolyG[3]);
+    ps = fma(ps, u, kTrigHalfPolyF[2]); pc = fma(pc, u, kTrigHalfPolyG[2]);
+    ps = fma(ps, u, kTrigHalfPolyF[1]); pc = fma(pc, u, kTrigHalfPolyG[1]);
+    ps = fma(ps, u, kTrigHalfPolyF[0]); pc = fma(pc, u, 0.5);
     double sn = fma(r * u, ps, r);
-    double pc = kTrigHalfPolyG[7];
-    pc = fma(pc, u, kTrigHalfPolyG[6]);
-    pc = fma(pc, u, kTrigHalfPolyG[5]);
-    pc = fma(pc, u, kTrigHalfPolyG[4]);
-    pc = fma(pc, u, kTrigHalfPolyG[3]);
-    pc = fma(pc, u, kTrigHalfPolyG[2]);
-    pc = fma(pc, u, kTrigHalfPolyG[1]);
-    pc = fma(pc, u, 0.5);
     double cs = fma(u, pc, 1.0);
-    for (int i = 0; i < k; ++i) {
-        double s2 = 2.0 * sn * cs;
-        cs = fma(cs, cs, sn * sn);
-        sn = s2;
-    }
-    *nsum += n;
+    if (HC)
+        for (int i = 0; i < t.k; ++i) {
+            double s2 = 2.0 * sn * cs;
+            cs = fma(cs, cs, sn * sn);
+            sn = s2;
+        }
+    *nsum += t.n;
     *S = sn;
     *C = cs;
+}
+
+template <bool HC = true>
+__device__ inline void gtrig_half(double a, bool hyper_in, double* C, double* S, double* nsum)
+{
+    trig_eval<HC>(trig_reduce<HC>(a, hyper_in), C, S, nsum);
 }
 
 // cosh and sinh of x >= 0 from expm1 (no cancellation for small x)
@@ -412,7 +432,7 @@ struct __align__(16) LayerRec {
     uint32_t soff;
     uint32_t slot;
 };
-constexpr int kRecPad = 2;
+constexpr int kRecPad = 3;
 __host__ __device__ inline int rec_stride(int Lmax) { return Lmax + 2 * kRecPad; }
 
 // Layer sources of the thin-film solves.  A cursor yields one stack's
@@ -658,6 +678,28 @@ __device__ inline void layer_cs_half(T kq, T t, T* C, T* S, double* nsum)
         gtrig<HC>(hyper ? -kq * t : kq * t, hyper, C, S);
 }
 
+// layer_cs_half in two parts (see trig_reduce): LayerTrig<T, HC>::reduce
+// for a layer's (kq, t), then eval.  The single-precision chain keeps the
+// whole routine in eval.
+template <typename T, bool HC> struct LayerTrig;
+template <bool HC> struct LayerTrig<double, HC> {
+    using Arg = TrigArg;
+    __device__ static Arg reduce(double kq, double t)
+    {
+        const bool hyper = HC && kq < 0.0;
+        return trig_reduce<HC>(hyper ? -kq * t : kq * t, hyper);
+    }
+    __device__ static void eval(const Arg& a, double* C, double* S, double* nsum) { trig_eval<HC>(a, C, S, nsum); }
+};
+template <bool HC> struct LayerTrig<float, HC> {
+    struct Arg { float kq, t; };
+    __device__ static Arg reduce(float kq, float t) { return Arg{ kq, t }; }
+    __device__ static void eval(const Arg& a, float* C, float* S, double* nsum)
+    {
+        layer_cs_half<float, HC>(a.kq, a.t, C, S, nsum);
+    }
+};
+
 // Entries of an absorbing layer: returns C, X_s, Y_s, X_p, Y_p.
 template <typename T>
 __device__ inline void layer_cplx(const T* P, T k0, T t, CTv<T>* C, CTv<T>* Xs, CTv<T>* Ys,
@@ -740,12 +782,22 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
         c[2] = make_double2(flip_sign((double)vp.br, sb), flip_sign((double)vp.bi, sb));
         c[3] = make_double2(flip_sign((double)vp.cr, sb), flip_sign((double)vp.ci, sb));
     };
+    // Software pipeline over the layers: while layer j is evaluated and
+    // applied, layer j+1's argument is reduced (from slot parameters read
+    // one iteration earlier), layer j+2's slot parameters are read, and
+    // layer j+3's record; no value is used in the iteration that loads it.
+    using LT = LayerTrig<T, HC>;
     const LayerRec r0 = cur.get();
-    double t0 = r0.t;
     double kq, xs, ys, xp, yp;
     sl.lossless_r(r0, kq, xs, ys, xp, yp);
+    typename LT::Arg ta = LT::reduce((T)kq, (T)r0.t);      // t = 0 gives the identity exactly
     cur.next();
-    LayerRec r1 = cur.get();
+    const LayerRec r1 = cur.get();
+    double kq1, xs1, ys1, xp1, yp1;
+    sl.lossless_r(r1, kq1, xs1, ys1, xp1, yp1);
+    double t1 = r1.t;
+    cur.next();
+    LayerRec r2 = cur.get();
     // loop index j of the next checkpoint (incidence-order layer L-1-j a
     // positive multiple of kSegL), or L when none is left
     int jck = (L - 1) % kSegL;
@@ -753,11 +805,12 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
 #pragma unroll 4
     for (int j = 0; j < L; ++j) {
         cur.next();
-        const LayerRec r2 = cur.get();
-        double kq1, xs1, ys1, xp1, yp1;
-        sl.lossless_r(r1, kq1, xs1, ys1, xp1, yp1);
+        const LayerRec r3 = cur.get();                               // past the stack: pad records
+        double kq2, xs2, ys2, xp2, yp2;
+        sl.lossless_r(r2, kq2, xs2, ys2, xp2, yp2);
+        const typename LT::Arg ta1 = LT::reduce((T)kq1, (T)t1);     // the next layer's (past the stack: unused)
         T C, S;
-        layer_cs_half<T, HC>((T)kq, (T)t0, &C, &S, &nsum);   // t = 0 gives the identity exactly
+        LT::eval(ta, &C, &S, &nsum);
         step_real(vs, C, S * (T)xs, S * (T)ys);
         step_real(vp, C, S * (T)xp, S * (T)yp);
         if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
@@ -765,8 +818,9 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
             store((L - 1 - j) / kSegL);
             jck = jck + kSegL < L - 1 ? jck + kSegL : L;
         }
-        t0 = r1.t; kq = kq1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
-        r1 = r2;
+        ta = ta1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+        kq1 = kq2; xs1 = xs2; ys1 = ys2; xp1 = xp2; yp1 = yp2; t1 = r2.t;
+        r2 = r3;
     }
     if constexpr (sizeof(T) == 8) {
         if (ck) store(0);

@@ -12,8 +12,8 @@ from paper_2601_04370_amd import optim
 pytestmark = pytest.mark.gpu
 
 
-def _setup(gctx, rays=512, iters=40, memo=True):
-    w = inputs.small_variant("diff_1200", rays_per_point=rays, fov_n=3)
+def _setup(gctx, rays=512, iters=40, memo=True, bins=(32, 32)):
+    w = inputs.small_variant("diff_1200", rays_per_point=rays, fov_n=3, bins=bins)
     inp = inputs.make_inputs(w)
     cfg = optim.OptimConfig(iters=iters, lr=5.0, memo=memo, snap_every=20, eval_seeds=3)
     thk0 = optim.init_thicknesses(inp["n_layers"], inp["thk"].shape[2], cfg.t_min, cfg.t_max, seed=w.seed)
@@ -22,7 +22,11 @@ def _setup(gctx, rays=512, iters=40, memo=True):
 
 
 def test_optimizer_lowers_loss_and_stays_feasible(gctx):
-    w, inp, cfg, thk0, opt = _setup(gctx)
+    # 4 x 4 eyebox bins and 2048 rays per point: with R rays over B bins the
+    # eyebox coefficient of variation carries shot noise of about
+    # sqrt(B / R), which at 32 x 32 bins and 512 rays (about 1.4 of the 1.8
+    # measured) swamps what 40 steps can change; here it is about 0.1
+    w, inp, cfg, thk0, opt = _setup(gctx, rays=2048, bins=(4, 4))
     before = opt.evaluate(thk0)
     thk = opt.run()
     after = opt.evaluate(thk)

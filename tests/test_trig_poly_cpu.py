@@ -3,8 +3,9 @@
 The thin-film sweeps evaluate cos/sin (circular layers) and cosh/sinh
 (evanescent layers) of the phase thickness with one pair of minimax
 polynomials: after a quarter-period reduction with an exact quadrant
-rotation (the adjoint's sweeps), or after a half-period reduction that leaves
-the sign (-1)^n to the caller (the forward sweeps).  These CPU tests check
+rotation (the sweeps through absorbing stacks), or after a half-period
+reduction that leaves the sign (-1)^n to the caller (the lossless sweeps of
+the forward and the adjoint).  These CPU tests check
 that
 
 - the committed header is what its generator writes (Remez fit, 60 digits);
