@@ -791,6 +791,9 @@ int gwg_trace_forward(gwg_ctx* c, const gwg_slab* slab, const gwg_prma* prma, co
     if (sc.n_items > 0x7fffffff) return fail(c, GWG_E_INVAL, "too many work items; raise rays_per_block");
     const int64_t nbins = (int64_t)sc.D * sc.n_lsel * sc.F * B;
     const bool table = (flags & GWG_FWD_TABLE) != 0;
+    // per-hit solves take a wave's rays in pools of rounds (all of an item's
+    // rounds, up to kPoolMax); the memoized and table forwards round by round
+    sc.pool = (sc.memo || table) ? 1 : (int32_t)std::min<int64_t>(kPoolMax, (sc.rays_per_tile + wg - 1) / wg);
     if (table) {
         const int n = c->tune.table_nodes ? c->tune.table_nodes : kTableNodesDefault;
         const size_t tab_b = sizeof(double) * 8 * (size_t)sc.D * sc.n_lsel * sc.M * 2 * (size_t)n;

@@ -267,6 +267,74 @@ struct GetCoef {
     }
 };
 
+// ----------------------------------------------------- pooled rounds
+// The per-hit forward handles a wave's rays in pools of up to sc.pool rounds
+// (kPoolMax at most): the queue holds the pool's hits, ncol = 64 sc.pool
+// columns of Kmax slots, hit h of column col in slot h * ncol + col.
+constexpr int kSortBins = 128;                      // walk-length classes of the field-pass order
+
+// LDS of one wave for ordering a pool's columns: class counts, then the
+// order; it fits the wave's slot tables (64 lanes x 5 values x 8 bytes a
+// slot, at least one slot)
+constexpr int kPoolSortBytes = kSortBins * 4 + 64 * kPoolMax * 2;
+static_assert(kPoolSortBytes <= 64 * 5 * 8, "pool ordering exceeds one slot's tables");
+
+// doubles of global scratch per wave: the hit queue (kHitFields fields of
+// 64 sc.pool sc.Kmax slots) and one 64-bit word per pool column
+__host__ __device__ inline int64_t fwd_wave_doubles(const SceneDev& sc)
+{
+    return (int64_t)kHitFields * 64 * sc.pool * sc.Kmax + 64 * sc.pool;
+}
+
+struct PutHitP {
+    HitQueue q;
+    int col, ncol;
+    __device__ void operator()(int h, double kappa, int meta) const { q.put(h * ncol + col, kappa, meta); }
+    __device__ void branch(int, bool) const {}
+};
+struct GetCoefP {
+    HitQueue q;
+    int col, ncol;
+    static constexpr bool kStoredBranch = true;   // the geometry walk stored the branch in the meta word
+    __device__ bool refl(int h) const { return (((int)q.base[q.cap + h * ncol + col]) >> 9) & 1; }
+    __device__ Coef4 operator()(int h, double, double, double, int, bool) const { return q.coef(h * ncol + col); }
+};
+
+// Solve a pool's ne + nc queued hits in batches of 64 (one per lane): field
+// 11 lists the possibly evanescent hits' slots from its front (positions
+// 0 .. ne-1) and the others' from its back (cap-1 down to cap-nc), so the
+// batches of the second kind take the circular-only sweep.  ck (non-null):
+// the checkpoint store; a hit whose field 10 holds a slot c >= 0 stores its
+// sweep checkpoints there.
+template <int MODE, class SL, class Stks>
+__device__ inline void solve_pool(const SceneDev& sc, const PointLds& pl, const Stks& stks, const SL& sl,
+                                  const HitQueue& hq, int ne, int nc, unsigned long long* n_fp64,
+                                  unsigned long long* n_lay, double* ck, int64_t ck_total)
+{
+    const int lane = wave_lane();
+    const int total = ne + nc;
+    const double* ord = hq.base + 11 * (int64_t)hq.cap;
+    for (int b = 0; b < total; b += 64) {
+        const int p = b + lane;
+        if (p < total) {
+            const int q = (int)ord[p < ne ? p : hq.cap - 1 - (p - ne)];
+            const double kappa = hq.kappa(q);
+            const int meta = hq.meta(q);
+            const int m = meta & 255;
+            bool u64 = false;
+            double* ckp = nullptr;
+            if (ck) {
+                const double c = hq.base[10 * (int64_t)hq.cap + q];
+                if (c >= 0.0) ckp = ck + (int64_t)c * 8;
+            }
+            const Coef4 c = hit_solve<MODE>(sc, pl, stks, sl, m, (meta >> 8) & 1, kappa, &u64, ckp, 8 * ck_total);
+            hq.put_coef(q, c);
+            *n_fp64 += u64 ? 1ull : 0ull;
+            *n_lay += (unsigned long long)pl.nlay[m];
+        }
+    }
+}
+
 // Persistent workgroups walk the work items with a fixed stride; each wave
 // handles a strided share of the item's rays.  Eyebox bins of the current
 // point accumulate in LDS (integer atomics) and are flushed per item with
@@ -296,15 +364,16 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     unsigned long long* s_st = (unsigned long long*)(smem + lay.off_st);
     const int tid = threadIdx.x, wave = tid / 64, lane = wave_lane();
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
-    const int cap = 64 * sc.Kmax;
-    const HitQueue hq = { scratch + gwave * (int64_t)kHitFields * cap, cap };
+    const int cap = 64 * sc.pool * sc.Kmax;                // queue slots of a wave (a pool of rounds)
+    constexpr bool POOL = !MEMO && !TAB;
+    const HitQueue hq = { scratch + gwave * fwd_wave_doubles(sc), cap };
     const SlotTable sl = { slot_lane_base(s_sp, sc.n_slots, SlotTable::kPer, tid), pl->nsq, pl->pxy };
     const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;
     const TapeRef tape = { tape_scratch + (int64_t)blockIdx.x * WG + tid, (int64_t)gridDim.x * WG };
     const FwdMemo fm = fwd_memo(smem + lay.total, wave,
-                                scratch + (int64_t)gridDim.x * n_waves * kHitFields * cap + gwave * 8 * kFwdMemoKeys);
+                                scratch + (int64_t)gridDim.x * n_waves * fwd_wave_doubles(sc) + gwave * 8 * kFwdMemoKeys);
     constexpr bool tabm = TAB;                           // angle-table thin film: no hit queue
     double t_gmax = 0.0;                                 // largest cotangent component (angle table)
     unsigned long long t_ne = 0;                         // cotangent pairs emitted (angle table)
@@ -331,86 +400,19 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
         }
         const int64_t ent0 = (item * st.waves + wave) * st.cap_w;
         const double* tab_dl = tabm ? sc.table + (int64_t)(d * sc.n_lsel + l) * sc.M * 2 * sc.table_n * 8 : nullptr;
-        for (int64_t round = 0;; ++round) {
-            const int64_t wave_first = i0 + (int64_t)wave * 64 + round * WG;
-            if (wave_first >= i1) break;                  // uniform across the wave
-            const int64_t i = wave_first + lane;
-            const bool active = i < i1;
-            const int64_t id = base + i;
+        // The field pass of one ray: the walk with the polarization field
+        // (coefficients from gcoef), the tape of the rays bound for the
+        // eyebox, the statistics and the eyebox scatter, then the reverse
+        // field sweep, whose adjoint entries take positions kent, kent + 1,
+        // ... of the wave's region (the ray's hits, last to first).
+        auto field_pass = [&](bool active, int64_t id, bool to_eyebox, int64_t kent, const auto& gcoef) {
             Ray r;
             Outcome o;
-            TapeRef none = { nullptr, 0 };
-            int nh = 0;
-            bool to_eyebox = false;                        // fixed by geometry alone
-            // geometry walk: the hits go to this lane's slots of the queue
-            // (the angle table needs no queue: the walk only finds the rays
-            // bound for the eyebox, whose fields the adjoint tapes)
-            const int own = lane;                          // this lane's column of the hit queue
-            if (active && (!tabm || ADJ)) {
-                ray_birth(sc, *pl, id, r);
-                if (tabm)
-                    walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
-                else
-                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, own }, NoCoef{}, none, nullptr);
-                nh = r.nprma;
-                to_eyebox = o.cat == CAT_EYEBOX;
-            }
-            if (!tabm) {
-                int total;
-                const int off = wave_excl_scan(nh, &total);
-                n_work += total;
-                // FP64 with a checkpoint store: the hits of rays bound for the
-                // eyebox learn the slots of their future adjoint entries (the
-                // sweep emits a ray's hits last to first)
-                const bool cks = ADJ && MODE == GWG_FP64 && st.ck != nullptr && !memo;
-                if (cks) {
-                    int etot;
-                    const int eoff = wave_excl_scan(to_eyebox ? nh : 0, &etot);
-                    for (int h = 0; h < nh; ++h) {
-                        const int64_t k = n_ent + eoff + (nh - 1 - h);
-                        double c = -1.0;
-                        if (to_eyebox && k < st.ck_cap) c = (double)((item * st.waves + wave) * st.ck_cap + k);
-                        hq.base[10 * (int64_t)cap + hq_slot(own, h)] = c;
-                    }
-                }
-                // solve order: first the hits that may meet an evanescent
-                // layer (kappa^2 above the smallest lossless Re N^2), then the
-                // rest, so that most batches of 64 take the circular-only sweep
-                // (a batch's kind is still decided from its hits' own layers)
-                if (!MEMO) {
-                    int ne = 0;
-                    for (int h = 0; h < nh; ++h) {
-                        const double k = hq.kappa(hq_slot(own, h));
-                        ne += k * k > pl->kap2_evan ? 1 : 0;
-                    }
-                    int net;
-                    const int eo = wave_excl_scan(ne, &net);
-                    int pe = eo, pc = net + (off - eo);    // positions < total
-                    for (int h = 0; h < nh; ++h) {
-                        const int q = hq_slot(own, h);
-                        const double k = hq.kappa(q);
-                        const int pos = k * k > pl->kap2_evan ? pe++ : pc++;
-                        hq.base[11 * (int64_t)cap + pos] = (double)q;
-                    }
-                }
-                __threadfence_block();
-                const int u0 = n_keys;
-                if (MEMO && memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
-                if (MEMO && memo)
-                    fmemo_solve<MODE>(sc, *pl, stks, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
-                else
-                    solve_hits<MODE>(sc, *pl, stks, sl, hq, total, off, &n_fp64, &n_lay,
-                                     cks ? st.ck : nullptr, st.ck_total, !MEMO);
-                __threadfence_block();
-            }
             int nt = 0;
             if (active) {
                 ray_birth(sc, *pl, id, r);
                 const TapeRef rt = { to_eyebox ? tape.base : nullptr, tape.ts };
-                if constexpr (TAB)
-                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, TabCoef{ tab_dl, sc.table_n, pl->ng, sc.nx, sc.nz }, rt, &nt);
-                else
-                    walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, GetCoef{ hq, own, MEMO && memo ? fm.coef : nullptr }, rt, &nt);
+                walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, gcoef, rt, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
                 atomicAdd(&s_st[ST_PRMA], (unsigned long long)r.nprma);
@@ -437,34 +439,212 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     q->w = o.w;
                 }
             }
-            if (ADJ) {
-                const bool eb = active && o.cat == CAT_EYEBOX;
-                int etotal;
-                const int eoff = wave_excl_scan(eb ? r.nprma : 0, &etotal);
-                if (eb) {
-                    int64_t k = n_ent + eoff;
-                    const int64_t cap = st.cap_w;
-                    const int64_t meta_bin = (int64_t)o.bin << 10;
-                    reverse_sweep(sc, *pl, r.e, tape, nt, [&](double kappa, cd Gs, cd Gp, int meta) {
-                        if constexpr (TAB) {
-                            const double a = fmax(fmax(fabs(Gs.re), fabs(Gs.im)), fmax(fabs(Gp.re), fabs(Gp.im)));
-                            t_gmax = a > t_gmax ? a : t_gmax;
-                            ++t_ne;
-                        }
-                        if (k < cap) {
-                            const int64_t e = ent0 + k;
-                            st.ent[e] = kappa;
-                            st.ent[1 * st.total + e] = Gs.re;
-                            st.ent[2 * st.total + e] = Gs.im;
-                            st.ent[3 * st.total + e] = Gp.re;
-                            st.ent[4 * st.total + e] = Gp.im;
-                            st.ent[5 * st.total + e] = (double)(meta_bin | (int64_t)meta);
-                        }
-                        ++k;
-                    });
-                }
-                n_ent += etotal;
+            if (ADJ && active && o.cat == CAT_EYEBOX) {
+                int64_t k = kent;
+                const int64_t cap_w = st.cap_w;
+                const int64_t meta_bin = (int64_t)o.bin << 10;
+                reverse_sweep(sc, *pl, r.e, tape, nt, [&](double kappa, cd Gs, cd Gp, int meta) {
+                    if constexpr (TAB) {
+                        const double a = fmax(fmax(fabs(Gs.re), fabs(Gs.im)), fmax(fabs(Gp.re), fabs(Gp.im)));
+                        t_gmax = a > t_gmax ? a : t_gmax;
+                        ++t_ne;
+                    }
+                    if (k < cap_w) {
+                        const int64_t e = ent0 + k;
+                        st.ent[e] = kappa;
+                        st.ent[1 * st.total + e] = Gs.re;
+                        st.ent[2 * st.total + e] = Gs.im;
+                        st.ent[3 * st.total + e] = Gp.re;
+                        st.ent[4 * st.total + e] = Gp.im;
+                        st.ent[5 * st.total + e] = (double)(meta_bin | (int64_t)meta);
+                    }
+                    ++k;
+                });
             }
+        };
+        if constexpr (POOL) {
+            // Pools of up to sc.pool rounds of this wave's rays (64 per
+            // round, a stride of WG rays apart): one geometry walk per ray,
+            // the pool's hits solved in batches of 64, then the field passes
+            // with the rays ordered by walk length, longest first, so that
+            // the lanes of a round walk about equally long.  A ray's column
+            // in the pool's queue is rr * 64 + lane (round rr of the pool);
+            // its hit h sits in slot h * ncol + col.
+            const int ncol = 64 * sc.pool;
+            const int64_t first = i0 + (int64_t)wave * 64;
+            const int n_rounds = first < i1 ? (int)((i1 - first + WG - 1) / WG) : 0;     // uniform
+            // the ordering's LDS is this wave's slot tables, which only the
+            // solves use (each hit's solve fills its lane's table first)
+            uint32_t* s_hist = (uint32_t*)(s_sp + (int64_t)wave * sc.n_slots * SlotTable::kPer * kSlotLanes);
+            uint16_t* s_ord = (uint16_t*)(s_hist + kSortBins);
+            int64_t* colinfo = (int64_t*)(hq.base + (int64_t)kHitFields * cap);         // [ncol]
+            const bool cks = ADJ && MODE == GWG_FP64 && st.ck != nullptr;
+            for (int r0 = 0; r0 < n_rounds; r0 += sc.pool) {
+                const int nr = n_rounds - r0 < sc.pool ? n_rounds - r0 : sc.pool;
+                int n_e = 0, n_c = 0;                     // the pool's possibly evanescent / other hits (uniform)
+                for (int rr = 0; rr < nr; ++rr) {
+                    const int col = rr * 64 + lane;
+                    const int64_t i = first + (int64_t)(r0 + rr) * WG + lane;
+                    const bool active = i < i1;
+                    Ray r;
+                    Outcome o;
+                    TapeRef none = { nullptr, 0 };
+                    int nh = 0, nev = 0;
+                    bool to_eyebox = false;                // fixed by geometry alone
+                    if (active) {
+                        ray_birth(sc, *pl, base + i, r);
+                        walk_ray<false, false>(sc, *pl, r, o, PutHitP{ hq, col, ncol }, NoCoef{}, none, nullptr);
+                        nh = r.nprma;
+                        nev = r.nev;
+                        to_eyebox = o.cat == CAT_EYEBOX;
+                    }
+                    int total;
+                    (void)wave_excl_scan(nh, &total);
+                    n_work += total;
+                    // the ray's adjoint entries (rays bound for the eyebox)
+                    // start at kent of the wave's region; with a checkpoint
+                    // store its hits learn their entries' checkpoint slots
+                    int64_t kent = 0;
+                    if (ADJ) {
+                        int etot;
+                        const int eoff = wave_excl_scan(to_eyebox ? nh : 0, &etot);
+                        kent = n_ent + eoff;
+                        if (cks)
+                            for (int h = 0; h < nh; ++h) {
+                                const int64_t k = kent + (nh - 1 - h);
+                                double c = -1.0;
+                                if (to_eyebox && k < st.ck_cap) c = (double)((item * st.waves + wave) * st.ck_cap + k);
+                                hq.base[10 * (int64_t)cap + h * ncol + col] = c;
+                            }
+                        n_ent += etot;
+                    }
+                    // solve order: the hits that may meet an evanescent layer
+                    // from the front of field 11, the others from its back
+                    int ne = 0;
+                    for (int h = 0; h < nh; ++h) {
+                        const double k = hq.kappa(h * ncol + col);
+                        ne += k * k > pl->kap2_evan ? 1 : 0;
+                    }
+                    int te, tc;
+                    const int eo = wave_excl_scan(ne, &te);
+                    const int co = wave_excl_scan(nh - ne, &tc);
+                    int pe = n_e + eo, pc = n_c + co;
+                    for (int h = 0; h < nh; ++h) {
+                        const int q = h * ncol + col;
+                        const double k = hq.kappa(q);
+                        const int pos = k * k > pl->kap2_evan ? pe++ : cap - 1 - pc++;
+                        hq.base[11 * (int64_t)cap + pos] = (double)q;
+                    }
+                    n_e += te;
+                    n_c += tc;
+                    // walk-length class (0: no ray), carried data
+                    const int cost = nev + (to_eyebox ? nev : 0);
+                    const int key = active ? 1 + (cost < kSortBins - 2 ? cost : kSortBins - 2) : 0;
+                    colinfo[col] = (kent << 16) | (int64_t)(key << 1) | (to_eyebox ? 1 : 0);
+                }
+                __threadfence_block();
+                solve_pool<MODE>(sc, *pl, stks, sl, hq, n_e, n_c, &n_fp64, &n_lay, cks ? st.ck : nullptr,
+                                 st.ck_total);
+                __threadfence_block();
+                // counting sort of the pool's columns, longest class first
+                for (int k = lane; k < kSortBins; k += 64) s_hist[k] = 0u;
+                wave_lds_sync();
+                for (int rr = 0; rr < nr; ++rr) {
+                    const int key = (int)((colinfo[rr * 64 + lane] >> 1) & 255);
+                    atomicAdd(&s_hist[key], 1u);
+                }
+                wave_lds_sync();
+                {
+                    // bin offsets in decreasing class order (two bins a lane)
+                    const int b0 = kSortBins - 1 - 2 * lane, b1 = b0 - 1;
+                    const int h0 = (int)s_hist[b0], h1 = (int)s_hist[b1];
+                    int tot;
+                    const int ex = wave_excl_scan(h0 + h1, &tot);
+                    s_hist[b0] = (uint32_t)ex;
+                    s_hist[b1] = (uint32_t)(ex + h0);
+                }
+                wave_lds_sync();
+                for (int rr = 0; rr < nr; ++rr) {
+                    const int col = rr * 64 + lane;
+                    const int key = (int)((colinfo[col] >> 1) & 255);
+                    const uint32_t pos = atomicAdd(&s_hist[key], 1u);
+                    s_ord[pos] = (uint16_t)col;
+                }
+                wave_lds_sync();
+                for (int s2 = 0; s2 < nr; ++s2) {
+                    const int col = (int)s_ord[s2 * 64 + lane];
+                    const int64_t info = colinfo[col];
+                    const int64_t i = first + (int64_t)(r0 + col / 64) * WG + (col & 63);
+                    field_pass(((info >> 1) & 255) != 0, base + i, (info & 1) != 0, info >> 16,
+                               GetCoefP{ hq, col, ncol });
+                }
+                wave_lds_sync();                          // s_hist / s_ord are reused by the next pool
+            }
+        } else {
+        for (int64_t round = 0;; ++round) {
+            const int64_t wave_first = i0 + (int64_t)wave * 64 + round * WG;
+            if (wave_first >= i1) break;                  // uniform across the wave
+            const int64_t i = wave_first + lane;
+            const bool active = i < i1;
+            const int64_t id = base + i;
+            Ray r;
+            Outcome o;
+            TapeRef none = { nullptr, 0 };
+            int nh = 0;
+            bool to_eyebox = false;                        // fixed by geometry alone
+            // geometry walk: the hits go to this lane's slots of the queue
+            // (the angle table needs no queue: the walk only finds the rays
+            // bound for the eyebox, whose fields the adjoint tapes)
+            const int own = lane;                          // this lane's column of the hit queue
+            if (active && (!tabm || ADJ)) {
+                ray_birth(sc, *pl, id, r);
+                if (tabm)
+                    walk_ray<false, false>(sc, *pl, r, o, NoHit{}, NoCoef{}, none, nullptr);
+                else
+                    walk_ray<false, false>(sc, *pl, r, o, PutHit{ hq, own }, NoCoef{}, none, nullptr);
+                nh = r.nprma;
+                to_eyebox = o.cat == CAT_EYEBOX;
+            }
+            // this round's adjoint entries: ray by ray from kent (eyebox rays)
+            int64_t kent = 0, etot_r = 0;
+            if (ADJ) {
+                int etot;
+                const int eoff = wave_excl_scan(to_eyebox ? nh : 0, &etot);
+                kent = n_ent + eoff;
+                etot_r = etot;
+            }
+            if (!tabm) {
+                int total;
+                const int off = wave_excl_scan(nh, &total);
+                n_work += total;
+                // FP64 with a checkpoint store: the hits of rays bound for the
+                // eyebox learn the slots of their future adjoint entries (the
+                // sweep emits a ray's hits last to first)
+                const bool cks = ADJ && MODE == GWG_FP64 && st.ck != nullptr && !memo;
+                if (cks) {
+                    for (int h = 0; h < nh; ++h) {
+                        const int64_t k = kent + (nh - 1 - h);
+                        double c = -1.0;
+                        if (to_eyebox && k < st.ck_cap) c = (double)((item * st.waves + wave) * st.ck_cap + k);
+                        hq.base[10 * (int64_t)cap + hq_slot(own, h)] = c;
+                    }
+                }
+                __threadfence_block();
+                const int u0 = n_keys;
+                if (MEMO && memo && !fmemo_resolve(hq, total, off, sc.Kmax, fm, sc.memo, &n_keys)) memo = false;
+                if (MEMO && memo)
+                    fmemo_solve<MODE>(sc, *pl, stks, sl, hq, fm, u0, n_keys, &n_fp64, &n_lay);
+                else
+                    solve_hits<MODE>(sc, *pl, stks, sl, hq, total, off, &n_fp64, &n_lay,
+                                     cks ? st.ck : nullptr, st.ck_total, false);
+                __threadfence_block();
+            }
+            if constexpr (TAB)
+                field_pass(active, id, to_eyebox, kent, TabCoef{ tab_dl, sc.table_n, pl->ng, sc.nx, sc.nz });
+            else
+                field_pass(active, id, to_eyebox, kent, GetCoef{ hq, own, MEMO && memo ? fm.coef : nullptr });
+            if (ADJ) n_ent += etot_r;
+        }
         }
         if (ADJ && lane == 0) {
             st.cnt[item * st.waves + wave] = (int32_t)(n_ent < st.cap_w ? n_ent : st.cap_w);
@@ -496,5 +676,5 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
 
 int64_t fwd_scratch_doubles(const SceneDev& sc, int64_t grid_blocks, int wg)
 {
-    return grid_blocks * (wg / 64) * ((int64_t)kHitFields * 64 * sc.Kmax + (sc.memo ? 8 * kFwdMemoKeys : 0));
+    return grid_blocks * (wg / 64) * (fwd_wave_doubles(sc) + (sc.memo ? 8 * kFwdMemoKeys : 0));
 }

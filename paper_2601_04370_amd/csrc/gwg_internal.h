@@ -60,6 +60,7 @@ constexpr int kEntFields = 6;
 constexpr int kFwdMemoKeys = 128;      // largest key table per wave of the memoized forward
 constexpr int kTableNodesDefault = 8192;
 constexpr int kCkEntriesPerRay = 4;        // sweep checkpoints kept per ray (entry regions)
+constexpr int kPoolMax = 8;                // per-hit forward: rounds of 64 rays per wave pool, at most
 constexpr double kCkBudgetBytes = 128.0 * (1ull << 30);
 constexpr int kTableNodesMax = 1 << 20;
 struct AdjStore {
@@ -122,6 +123,7 @@ struct SceneDev {
     const uint32_t* step_dev;         // optional device step counter (graph replays)
     int32_t precision;
     int32_t memo;                     // forward: key table capacity per wave (0: solve every hit)
+    int32_t pool;                     // forward: rounds of 64 rays per pool of a wave (per-hit solves; else 1)
     // angle table (table_n = 0: exact per-hit thin film)
     const double* table;              // [D][n_lsel][M][2 sides][table_n][8]
     int32_t table_n;
