@@ -269,21 +269,21 @@ struct GetCoef {
 
 // ----------------------------------------------------- pooled rounds
 // The per-hit forward handles a wave's rays in pools of up to sc.pool rounds
-// (kPoolMax at most): the queue holds the pool's hits, ncol = 64 sc.pool
-// columns of Kmax slots, hit h of column col in slot h * ncol + col.
+// (kPoolMax at most).  The queue holds the pool's hits: ncol = 64 sc.pool
+// columns (one per ray) of Kmax slots, hit h of column col in slot
+// h * ncol + col.  Inputs of the solves: fields 0 (kappa), 1 (meta), 10
+// (checkpoint slot), 11 (solve order).  The solves write each hit's taken
+// coefficients (c_s, c_p: fields 2-5) and its branch (field 6) in the slot
+// of the ray's place in the field-pass order (column pos), so the lanes of a
+// field pass read adjacent slots.
 constexpr int kSortBins = 128;                      // walk-length classes of the field-pass order
 
-// LDS of one wave for ordering a pool's columns: class counts, then the
-// order; it fits the wave's slot tables (64 lanes x 5 values x 8 bytes a
-// slot, at least one slot)
-constexpr int kPoolSortBytes = kSortBins * 4 + 64 * kPoolMax * 2;
-static_assert(kPoolSortBytes <= 64 * 5 * 8, "pool ordering exceeds one slot's tables");
-
 // doubles of global scratch per wave: the hit queue (kHitFields fields of
-// 64 sc.pool sc.Kmax slots) and one 64-bit word per pool column
+// 64 sc.pool sc.Kmax slots), one 64-bit word per column (carried data), and
+// two 32-bit words per column (place in the order, column at each place)
 __host__ __device__ inline int64_t fwd_wave_doubles(const SceneDev& sc)
 {
-    return (int64_t)kHitFields * 64 * sc.pool * sc.Kmax + 64 * sc.pool;
+    return (int64_t)kHitFields * 64 * sc.pool * sc.Kmax + 2 * 64 * sc.pool;
 }
 
 struct PutHitP {
@@ -292,24 +292,36 @@ struct PutHitP {
     __device__ void operator()(int h, double kappa, int meta) const { q.put(h * ncol + col, kappa, meta); }
     __device__ void branch(int, bool) const {}
 };
+// The field pass's coefficients of the ray at place pos of the order: the
+// taken pair (c_s, c_p) returned as both the reflected and the transmitted
+// one, and the branch.
 struct GetCoefP {
     HitQueue q;
-    int col, ncol;
-    static constexpr bool kStoredBranch = true;   // the geometry walk stored the branch in the meta word
-    __device__ bool refl(int h) const { return (((int)q.base[q.cap + h * ncol + col]) >> 9) & 1; }
-    __device__ Coef4 operator()(int h, double, double, double, int, bool) const { return q.coef(h * ncol + col); }
+    int pos, ncol;
+    static constexpr bool kStoredBranch = true;
+    __device__ bool refl(int h) const { return q.base[6 * (int64_t)q.cap + h * ncol + pos] != 0.0; }
+    __device__ Coef4 operator()(int h, double, double, double, int, bool) const
+    {
+        const double* b = q.base + 2 * (int64_t)q.cap + h * ncol + pos;
+        const int64_t c = q.cap;
+        Coef4 o;
+        o.rs = o.ts = mk(b[0], b[c]);
+        o.rp = o.tp = mk(b[2 * c], b[3 * c]);
+        return o;
+    }
 };
 
 // Solve a pool's ne + nc queued hits in batches of 64 (one per lane): field
 // 11 lists the possibly evanescent hits' slots from its front (positions
 // 0 .. ne-1) and the others' from its back (cap-1 down to cap-nc), so the
-// batches of the second kind take the circular-only sweep.  ck (non-null):
-// the checkpoint store; a hit whose field 10 holds a slot c >= 0 stores its
-// sweep checkpoints there.
+// batches of the second kind take the circular-only sweep.  colpos[col]:
+// the place of column col in the field-pass order, where the hit's taken
+// coefficients go.  ck (non-null): the checkpoint store; a hit whose field
+// 10 holds a slot c >= 0 stores its sweep checkpoints there.
 template <int MODE, class SL, class Stks>
 __device__ inline void solve_pool(const SceneDev& sc, const PointLds& pl, const Stks& stks, const SL& sl,
-                                  const HitQueue& hq, int ne, int nc, unsigned long long* n_fp64,
-                                  unsigned long long* n_lay, double* ck, int64_t ck_total)
+                                  const HitQueue& hq, int ncol, const int32_t* colpos, int ne, int nc,
+                                  unsigned long long* n_fp64, unsigned long long* n_lay, double* ck, int64_t ck_total)
 {
     const int lane = wave_lane();
     const int total = ne + nc;
@@ -328,7 +340,13 @@ __device__ inline void solve_pool(const SceneDev& sc, const PointLds& pl, const 
                 if (c >= 0.0) ckp = ck + (int64_t)c * 8;
             }
             const Coef4 c = hit_solve<MODE>(sc, pl, stks, sl, m, (meta >> 8) & 1, kappa, &u64, ckp, 8 * ck_total);
-            hq.put_coef(q, c);
+            const int h = q / ncol, col = q - h * ncol;
+            const bool rf = (meta >> 9) & 1;
+            double* o = hq.base + 2 * (int64_t)hq.cap + h * ncol + colpos[col];
+            const int64_t cc = hq.cap;
+            const cd cs = rf ? c.rs : c.ts, cp = rf ? c.rp : c.tp;
+            o[0] = cs.re; o[cc] = cs.im; o[2 * cc] = cp.re; o[3 * cc] = cp.im;
+            o[4 * cc] = rf ? 1.0 : 0.0;
             *n_fp64 += u64 ? 1ull : 0ull;
             *n_lay += (unsigned long long)pl.nlay[m];
         }
@@ -473,11 +491,13 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             const int ncol = 64 * sc.pool;
             const int64_t first = i0 + (int64_t)wave * 64;
             const int n_rounds = first < i1 ? (int)((i1 - first + WG - 1) / WG) : 0;     // uniform
-            // the ordering's LDS is this wave's slot tables, which only the
-            // solves use (each hit's solve fills its lane's table first)
+            // the ordering's class counts sit in this wave's slot tables,
+            // which only the solves use (each hit's solve fills its lane's
+            // table first)
             uint32_t* s_hist = (uint32_t*)(s_sp + (int64_t)wave * sc.n_slots * SlotTable::kPer * kSlotLanes);
-            uint16_t* s_ord = (uint16_t*)(s_hist + kSortBins);
-            int64_t* colinfo = (int64_t*)(hq.base + (int64_t)kHitFields * cap);         // [ncol]
+            int64_t* colinfo = (int64_t*)(hq.base + (int64_t)kHitFields * cap);         // [ncol] carried data
+            int32_t* colpos = (int32_t*)(colinfo + ncol);                               // [ncol] place of a column
+            int32_t* colord = colpos + ncol;                                            // [ncol] column at a place
             const bool cks = ADJ && MODE == GWG_FP64 && st.ck != nullptr;
             for (int r0 = 0; r0 < n_rounds; r0 += sc.pool) {
                 const int nr = n_rounds - r0 < sc.pool ? n_rounds - r0 : sc.pool;
@@ -543,10 +563,8 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     colinfo[col] = (kent << 16) | (int64_t)(key << 1) | (to_eyebox ? 1 : 0);
                 }
                 __threadfence_block();
-                solve_pool<MODE>(sc, *pl, stks, sl, hq, n_e, n_c, &n_fp64, &n_lay, cks ? st.ck : nullptr,
-                                 st.ck_total);
-                __threadfence_block();
-                // counting sort of the pool's columns, longest class first
+                // the field-pass order: the pool's columns by walk-length
+                // class, longest first (a counting sort)
                 for (int k = lane; k < kSortBins; k += 64) s_hist[k] = 0u;
                 wave_lds_sync();
                 for (int rr = 0; rr < nr; ++rr) {
@@ -567,18 +585,24 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                 for (int rr = 0; rr < nr; ++rr) {
                     const int col = rr * 64 + lane;
                     const int key = (int)((colinfo[col] >> 1) & 255);
-                    const uint32_t pos = atomicAdd(&s_hist[key], 1u);
-                    s_ord[pos] = (uint16_t)col;
+                    const int pos = (int)atomicAdd(&s_hist[key], 1u);
+                    colpos[col] = pos;
+                    colord[pos] = col;
                 }
-                wave_lds_sync();
+                wave_lds_sync();                          // the slot tables are the solves' again
+                __threadfence_block();
+                solve_pool<MODE>(sc, *pl, stks, sl, hq, ncol, colpos, n_e, n_c, &n_fp64, &n_lay,
+                                 cks ? st.ck : nullptr, st.ck_total);
+                __threadfence_block();
                 for (int s2 = 0; s2 < nr; ++s2) {
-                    const int col = (int)s_ord[s2 * 64 + lane];
+                    const int pos = s2 * 64 + lane;
+                    const int col = colord[pos];
                     const int64_t info = colinfo[col];
                     const int64_t i = first + (int64_t)(r0 + col / 64) * WG + (col & 63);
                     field_pass(((info >> 1) & 255) != 0, base + i, (info & 1) != 0, info >> 16,
-                               GetCoefP{ hq, col, ncol });
+                               GetCoefP{ hq, pos, ncol });
                 }
-                wave_lds_sync();                          // s_hist / s_ord are reused by the next pool
+                __threadfence_block();                    // the next pool's solves rewrite the queue
             }
         } else {
         for (int64_t round = 0;; ++round) {
