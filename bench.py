@@ -159,6 +159,12 @@ def copy_probe(torch, mib: int = 1024, reps: int = 5):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": reps}))
 
 
+def progress(msg: str) -> None:
+    """One line on stderr as each phase of the run ends (stdout carries only
+    the result line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def design_slice(inp, d, n=1):
     """Inputs of designs d .. d + n - 1 alone (per-design or per-chunk launches)."""
     out = dict(inp)
@@ -267,6 +273,7 @@ def main():
     for k in range(a.warmup):
         step(k)
     torch.cuda.synchronize()
+    progress(f"{a.warmup} warm-up steps done")
     ctx.set_timing(True)
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
     torch.cuda.synchronize()
@@ -276,6 +283,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    progress(f"{a.steps} timed steps done: {wall / a.steps * 1e3:.2f} ms per step")
     fwd_ms = [e[0].elapsed_time(e[1]) for e in events]
     loss_ms = [e[1].elapsed_time(e[2]) for e in events]
     bwd_ms = [e[2].elapsed_time(e[3]) for e in events]
@@ -311,6 +319,7 @@ def main():
         ctx.set_step_source(None)
         extra["graph_ms_per_step"] = g_wall / a.steps * 1e3
         extra["eager_ms_per_step"] = wall / a.steps * 1e3
+        progress(f"graph replays done: {extra['graph_ms_per_step']:.2f} ms per step")
 
     if a.table:
         # the interpolated model against the per-hit solve on the same paths
@@ -347,6 +356,7 @@ def main():
             lay_b += bst["layer_steps"]
             lay_a += bst["adjoint_layer_steps"]
             lay_s += bst["adjoint_stored_layer_steps"]
+    progress("step counters recomputed")
     K = a.steps
     if a.graph:
         wall = extra["graph_ms_per_step"] * 1e-3 * K
@@ -363,11 +373,13 @@ def main():
         for sc_d, th_d in scenes:
             step(0, sc=sc_d, th=th_d)
         torch.cuda.synchronize()
+        progress("per-design warm-up done")
         tp = time.perf_counter()
         for i in range(K):
             for sc_d, th_d in scenes:
                 step(a.warmup + i, sc=sc_d, th=th_d)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            progress(f"per-design step {i + 1} of {K} done")
         pd_wall = time.perf_counter() - tp
         extra["per_design_ms_per_step"] = pd_wall / K * 1e3
         extra["batched_speedup_vs_per_design"] = pd_wall / wall
@@ -386,11 +398,13 @@ def main():
         for sc_c, th_c in chunks:
             step(0, sc=sc_c, th=th_c)
         torch.cuda.synchronize()
+        progress("design-chunk warm-up done")
         tp = time.perf_counter()
         for i in range(K):
             for sc_c, th_c in chunks:
                 step(a.warmup + i, sc=sc_c, th=th_c)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            progress(f"design-chunk step {i + 1} of {K} done")
         ch_wall = time.perf_counter() - tp
         extra["design_chunks"] = nc
         extra["chunked_ms_per_step"] = ch_wall / K * 1e3
@@ -420,6 +434,7 @@ def main():
                 cgraph.replay()
             torch.cuda.synchronize()
             extra["chunked_graph_ms_per_step"] = (time.perf_counter() - tg) / K * 1e3
+            progress(f"design-chunk graph replays done: {extra['chunked_graph_ms_per_step']:.1f} ms per step")
             ctx.set_step_source(None)
         if a.per_design:
             extra["chunked_speedup_vs_per_design"] = extra["per_design_ms_per_step"] / extra["chunked_ms_per_step"]
