@@ -165,6 +165,24 @@ def progress(msg: str) -> None:
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+# Per-ray storage the forward keeps for the adjoint (gwg_api.cpp): entry
+# regions of 8 entries of 6 doubles, checkpoints of 4 entries of
+# (Lmax / 16 + 1) blocks of 64 bytes; and their budgets.
+ENTRY_BYTES_PER_RAY = 8 * 6 * 8
+ENTRY_BUDGET = 96 * 2**30
+CHECKPOINT_BUDGET = 128 * 2**30
+
+
+def auto_design_chunks(w) -> int:
+    """Fewest consecutive-design chunks whose entries and sweep checkpoints
+    both fit the library's budgets at full per-ray counts."""
+    rays_per_design = len(w.lambdas_nm) * w.fov_n * w.fov_n * w.rays_per_point
+    ck_per_ray = 4 * (w.n_layers // 16 + 1) * 64
+    per_design = rays_per_design * max(ENTRY_BYTES_PER_RAY / ENTRY_BUDGET, ck_per_ray / CHECKPOINT_BUDGET)
+    fit = max(1, int(1.0 / per_design))                # designs per chunk
+    return -(-w.n_designs // fit)
+
+
 def design_slice(inp, d, n=1):
     """Inputs of designs d .. d + n - 1 alone (per-design or per-chunk launches)."""
     out = dict(inp)
@@ -198,7 +216,9 @@ def main():
                     help="also time one launch per design (the batched workload) for comparison")
     ap.add_argument("--design-chunks", type=int, default=0,
                     help="also time the batch as this many launches of consecutive designs (each chunk's "
-                         "forward, loss and adjoint before the next chunk's, so its stored sweeps fit)")
+                         "forward, loss and adjoint before the next chunk's, so its stored sweeps fit); "
+                         "-1: the fewest chunks whose adjoint entries and sweep checkpoints fit the library's "
+                         "budgets")
     ap.add_argument("--cpu-interactions", type=float, default=1e6,
                     help="interactions in each CPU-baseline sample (whole points)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -387,7 +407,8 @@ def main():
     if a.design_chunks:
         # the same batch as a few launches of consecutive designs: the loss is a
         # sum over designs, so chunking by design changes no result
-        nc = max(1, min(a.design_chunks, w.n_designs))
+        nc = a.design_chunks if a.design_chunks > 0 else auto_design_chunks(w)
+        nc = max(1, min(nc, w.n_designs))
         bounds = [round(i * w.n_designs / nc) for i in range(nc + 1)]
         chunks = []
         for c0, c1 in zip(bounds[:-1], bounds[1:]):

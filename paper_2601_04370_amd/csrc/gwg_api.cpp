@@ -92,7 +92,7 @@ struct SceneEntry {
 // Scenes kept per context (least recently used evicted), so that calls
 // that alternate between a few scenes (a batch traced in chunks of designs)
 // rebuild nothing, and can be captured in one graph once each was built.
-constexpr int kSceneCache = 16;
+constexpr int kSceneCache = 128;
 
 struct gwg_ctx {
     int device = -1;

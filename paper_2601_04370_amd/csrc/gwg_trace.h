@@ -467,6 +467,26 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
     }
 }
 
+// One tape event as the reverse sweep reads it.
+struct TapeEv {
+    double dx, dy, dz;
+    double e[6];                  // incoming field (mirror events only)
+    double cs_re, cs_im, cp_re, cp_im, scale;
+    int meta;
+};
+__device__ inline TapeEv tape_get(const TapeRef& tape, int k)
+{
+    const int64_t ts = tape.ts;
+    const double* b = tape.base + (int64_t)k * kTapeStride * ts;
+    TapeEv v;
+    v.dx = b[0]; v.dy = b[ts]; v.dz = b[2 * ts];
+    for (int c = 0; c < 6; ++c) v.e[c] = b[(3 + c) * ts];
+    v.cs_re = b[9 * ts]; v.cs_im = b[10 * ts]; v.cp_re = b[11 * ts]; v.cp_im = b[12 * ts];
+    v.scale = b[13 * ts];
+    v.meta = (int)b[14 * ts];
+    return v;
+}
+
 // Reverse field sweep along one ray's fixed path (the adjoint of Eq. 5 and
 // Eq. 6 for w = |E_K|^2): lambda_K = E_K, lambda_{k-1} = A_k^H lambda_k with
 // A = scale (c_s s s^T + c_p p_out p_in^T).  For every mirror hit, last to
@@ -480,13 +500,17 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
                                      int nt, Emit emit)
 {
     cd lam[3] = { e_final[0], e_final[1], e_final[2] };
-    const int64_t ts = tape.ts;
+    // each event's tape words are requested one event ahead of their use,
+    // so the memory latency overlaps the previous event's arithmetic
+    TapeEv nx;
+    if (nt > 0) nx = tape_get(tape, nt - 1);
     for (int k = nt - 1; k >= 0; --k) {
-        const double* b = tape.base + (int64_t)k * kTapeStride * ts;
-        const double dx = b[0], dy = b[ts], dz = b[2 * ts];
-        const cd cs = mk(b[9 * ts], b[10 * ts]), cp = mk(b[11 * ts], b[12 * ts]);
-        const double scale = b[13 * ts];
-        const int meta = (int)b[14 * ts];
+        const TapeEv ev = nx;
+        if (k > 0) nx = tape_get(tape, k - 1);
+        const double dx = ev.dx, dy = ev.dy, dz = ev.dz;
+        const cd cs = mk(ev.cs_re, ev.cs_im), cp = mk(ev.cp_re, ev.cp_im);
+        const double scale = ev.scale;
+        const int meta = ev.meta;
         const int type = meta & 15, m = (meta >> 4) & 255;
         const int front = (meta >> 12) & 1, refl = (meta >> 13) & 1;
         double sv[3], pin[3], pout[3];
@@ -497,7 +521,7 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
             if (refl) mirror_reflect(pl.nx, pl.nz, dx, dz, &ndx, &ndz);
             cross3(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
             cd E[3];
-            for (int c = 0; c < 3; ++c) E[c] = mk(b[(3 + 2 * c) * ts], b[(4 + 2 * c) * ts]);
+            for (int c = 0; c < 3; ++c) E[c] = mk(ev.e[2 * c], ev.e[2 * c + 1]);
             const cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
             const cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
             const cd es = cadd(cadd(cscale(E[0], sv[0]), cscale(E[1], sv[1])), cscale(E[2], sv[2]));

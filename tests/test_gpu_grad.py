@@ -67,6 +67,39 @@ def test_backward_fp64_matches_oracle(gctx, orc, name, kw, stride, tile, mode):
             assert np.all(g[d, m, inp["n_layers"][d, m]:] == 0.0)
 
 
+@pytest.mark.parametrize("wg,tile", [(64, 1280), (128, 2150)])
+def test_backward_pooled_rounds_match_oracle(gctx, orc, wg, tile):
+    """The per-hit forward takes a wave's rays in pools of at most 8 rounds of
+    64: with 64-thread workgroups and 1280-ray tiles a wave walks 20 rounds of
+    a point's first item (pools of 8, 8 and 4) and 14 of its second (8 and 6,
+    the last round partial); with 128 threads and one 2150-ray tile per point
+    17 rounds (8, 8 and 1, partial in the second wave), so entries, checkpoint
+    slots and the field-pass order cross pools.  Forward counts and gradient
+    against the oracle."""
+    w = inputs.small_variant("diff_1200", rays_per_point=2150, fov_n=2, lambdas_nm=(530.0,))
+    inp = inputs.make_inputs(w)
+    scene = gwg.SceneSpec.from_workload(w, inp)
+    thk = torch.tensor(inp["thk"], dtype=torch.float64, device="cuda:0")
+    osc = orc.OracleScene(w, inp)
+    oq, oc, ows, ost = osc.forward()
+    oirr = osc.forward_sampled(1)
+    L, dLdI = orc.loss(oirr, 0)
+    print(f"pooled rounds wg={wg} tile={tile}", flush=True)
+    gctx.set_tuning(block_threads=wg, rays_per_block=tile)
+    try:
+        q, c, irr, _, _ = gctx.trace_forward(scene, thk, w.seed, 0, 0, grad=True)
+        assert gctx.forward_kept_entries()
+        g = gctx.trace_backward(torch.tensor(dLdI), scene).cpu().numpy()
+    finally:
+        gctx.set_tuning()
+    assert np.array_equal(c.cpu().numpy().astype(np.uint32), oc)
+    og = osc.backward(dLdI, 1)
+    scale = np.max(np.abs(og))
+    err = np.abs(g - og)
+    print(f"  max |g| {scale:.3e}  rel err {err.max() / scale:.2e}", flush=True)
+    assert np.all(err <= 1e-4 * np.maximum(np.abs(og), 1e-3 * scale))
+
+
 @pytest.mark.parametrize("grad,memo", [(True, False), (False, False), (True, True)])
 def test_backward_is_deterministic(gctx, orc, grad, memo):
     w = inputs.small_variant("diff_1200", rays_per_point=128, fov_n=3)
