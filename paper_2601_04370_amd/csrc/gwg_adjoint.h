@@ -359,7 +359,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             if (lo + K < L) load_chk(lo / K + 1);
         }
         const int hi = lo + K < L ? lo + K : L;
-#pragma unroll 2
+#pragma unroll 4
         for (int j = lo; j < hi; ++j) {
             const int idn3 = nxt(idn2);
             double kq2, xs2, ys2, xp2, yp2;
