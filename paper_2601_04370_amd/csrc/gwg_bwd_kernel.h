@@ -126,8 +126,9 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     const int64_t nthreads = (int64_t)gridDim.x * WG;
     const int64_t gtid = (int64_t)blockIdx.x * WG + tid;
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
-    // scratch: [tape Kmax x 15][checkpoints n_chk x 8] per lane, then queues per wave
-    TapeRef tape = { scratch + gtid, nthreads };
+    // scratch: the tape (Kmax event slots of every lane), then n_chk x 8
+    // checkpoint doubles per lane, then queues per wave
+    const TapeRef tape = tape_lane(scratch, sc.Kmax, nthreads, gtid);
     const int64_t n_chk = sc.Lmax / kSeg + 1;
     double* chk = scratch + (int64_t)sc.Kmax * kTapeStride * nthreads + gtid;
     const int qcap = 64 * (sc.Kmax + 1);
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             o.cat = CAT_LOST;
             o.bin = -1;
             int nt = 0;
-            TapeRef none = { nullptr, 0 };
+            TapeRef none = { nullptr, nullptr, 0 };
             int nh = 0;
             double gscale = 0.0;
             const int own = lane;                // this lane's column of the hit queue
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             if constexpr (TAB) {
                 if (contrib) {
                     c_arays += 1;
-                    reverse_sweep(sc, *pl, r.e, tape, nt, TableEmit{ acc_dl, sc.table_n, pl->ng, gscale, fx });
+                    reverse_sweep(sc, *pl, r.e, tape, nt, r.nprma, TableEmit{ acc_dl, sc.table_n, pl->ng, gscale, fx });
                 }
                 continue;
             }
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             if (contrib) {
                 c_arays += 1;
                 int slotpos = qhead + qcount + off;
-                reverse_sweep(sc, *pl, r.e, tape, nt, QueueEmit{ q, &slotpos, gscale });
+                reverse_sweep(sc, *pl, r.e, tape, nt, r.nprma, QueueEmit{ q, &slotpos, gscale });
             }
             qcount += total;
             __threadfence_block();

@@ -28,7 +28,9 @@ constexpr int LT_SLOT = 4;            // slot s: (re, im) at LT_SLOT + 2 s
 constexpr int LT_CRIT = 24;           // slot s: near-critical kappa interval (lo, hi) at LT_CRIT + 2 s
 constexpr int LT_NSLOT = 40;          // number of slots (as double)
 
-constexpr int kTapeStride = 15;       // doubles per tape entry (backward)
+constexpr int kTapeLine = 8;          // doubles of a tape event line
+constexpr int kTapeMir = 4;           // doubles of a tape mirror record
+constexpr int kTapeStride = kTapeLine + kTapeMir;  // tape doubles per lane and event slot
 constexpr int kSeg = 4;               // layers per recomputation segment (backward)
 constexpr int kSegL = 16;             // checkpoint interval of the lossless adjoint (multiple of kSeg)
 // checkpoint blocks per stored adjoint entry: v_0 and v_{g kSegL}, g >= 1

@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) k_omega_grad(SceneDev sc, const double* _
             if (i < i1) {
                 Ray r;
                 Outcome o;
-                TapeRef none = { nullptr, 0 };
+                TapeRef none = { nullptr, nullptr, 0 };
                 ray_birth(sc, *pl, base + i, r);
                 walk_ray<false, false>(sc, *pl, r, o, score, NoCoef{}, none, nullptr);
                 fw = (o.cat == CAT_EYEBOX ? Wp[o.bin] : 0.0) - beta;

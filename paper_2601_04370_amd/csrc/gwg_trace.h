@@ -73,14 +73,25 @@ __device__ inline void s_basis(double dx, double dy, double dz, double nx, doubl
     s[0] = c[0] * il; s[1] = c[1] * il; s[2] = c[2] * il;
 }
 
+// Components of a complex field along a real unit vector: sum_c e_c v_c.
+__device__ inline cd dot_re(const cd* e, const double* v)
+{
+    return cadd(cadd(cscale(e[0], v[0]), cscale(e[1], v[1])), cscale(e[2], v[2]));
+}
+
+// Eq. 5 given the incoming field's components es = s.E and ep = p_in.E.
+__device__ inline void apply_sp_proj(cd* e, const double* s, const double* pout, cd cs, cd cp, double scale,
+                                     cd es, cd ep)
+{
+    cd as = cscale(cmul(cs, es), scale), ap = cscale(cmul(cp, ep), scale);
+    for (int k = 0; k < 3; ++k) e[k] = cadd(cscale(as, s[k]), cscale(ap, pout[k]));
+}
+
 // Eq. 5 on the local basis: E <- scale (cs (E.s) s + cp (E.p_in) p_out)
 __device__ inline void apply_sp(cd* e, const double* s, const double* pin, const double* pout,
                                 cd cs, cd cp, double scale)
 {
-    cd es = cadd(cadd(cscale(e[0], s[0]), cscale(e[1], s[1])), cscale(e[2], s[2]));
-    cd ep = cadd(cadd(cscale(e[0], pin[0]), cscale(e[1], pin[1])), cscale(e[2], pin[2]));
-    cd as = cscale(cmul(cs, es), scale), ap = cscale(cmul(cp, ep), scale);
-    for (int k = 0; k < 3; ++k) e[k] = cadd(cscale(as, s[k]), cscale(ap, pout[k]));
+    apply_sp_proj(e, s, pout, cs, cp, scale, dot_re(e, s), dot_re(e, pin));
 }
 
 __device__ inline double norm2(const cd* e)
@@ -323,19 +334,40 @@ struct HitQueue {
 constexpr int kHitFields = 12;
 
 // ------------------------------------------------------------ tape
-// Field-changing events of one ray for the adjoint (this lane's doubles, stride ts).
-struct TapeRef { double* base; int64_t ts; };
+// Field-changing events of one ray, for the reverse field sweep.  Each event
+// takes one 64-byte line of the lane's own: the direction before the event,
+// meta (type | mirror << 4 | front << 12 | reflected << 13) and four
+// coefficient words (mirror hit and total internal reflection: c_s, c_p;
+// exit: t_s, t_p and the flux factor, the transmission coefficients being
+// real below the critical angle).  A mirror hit also takes a 32-byte record
+// with the incoming field's components s.E and p_in.E.  Line k of a lane is
+// at ev + 8 k ts, its mirror record h at mr + 4 h ts (ts = lanes of the
+// grid): a lane writes and reads whole lines of its own, so lanes that
+// record nothing move no memory.
+struct TapeRef { double* ev; double* mr; int64_t ts; };
 
-__device__ inline void tape_put(TapeRef t, int k, const Ray& r_before, cd cs, cd cp, double scale,
-                                int type, int m, int front, int refl)
+// The tape of lane gtid of nthreads in a region of kmax * kTapeStride *
+// nthreads doubles (event lines first, then mirror records).
+__device__ inline TapeRef tape_lane(double* region, int64_t kmax, int64_t nthreads, int64_t gtid)
 {
-    double* b = t.base + (int64_t)k * kTapeStride * t.ts;
-    b[0] = r_before.dx; b[t.ts] = r_before.dy; b[2 * t.ts] = r_before.dz;
-    if (type == EV_MIRROR)      // the incoming field is only read back at mirror hits
-        for (int c = 0; c < 3; ++c) { b[(3 + 2 * c) * t.ts] = r_before.e[c].re; b[(4 + 2 * c) * t.ts] = r_before.e[c].im; }
-    b[9 * t.ts] = cs.re; b[10 * t.ts] = cs.im; b[11 * t.ts] = cp.re; b[12 * t.ts] = cp.im;
-    b[13 * t.ts] = scale;
-    b[14 * t.ts] = (double)(type | (m << 4) | (front << 12) | (refl << 13));
+    return { region + gtid * kTapeLine, region + kmax * kTapeLine * nthreads + gtid * kTapeMir, nthreads };
+}
+
+__device__ inline void tape_put(const TapeRef& t, int k, double dx, double dy, double dz, int meta,
+                                double c0, double c1, double c2, double c3)
+{
+    double2* b = (double2*)(t.ev + (int64_t)k * kTapeLine * t.ts);
+    b[0] = make_double2(dx, dy);
+    b[1] = make_double2(dz, (double)meta);
+    b[2] = make_double2(c0, c1);
+    b[3] = make_double2(c2, c3);
+}
+
+__device__ inline void tape_put_mirror(const TapeRef& t, int h, cd es, cd ep)
+{
+    double2* b = (double2*)(t.mr + (int64_t)h * kTapeMir * t.ts);
+    b[0] = make_double2(es.re, es.im);
+    b[1] = make_double2(ep.re, ep.im);
 }
 
 // Outcome of a terminated ray.
@@ -392,7 +424,7 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
                         cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
                         cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
                         o.w_in = norm2(r.e);
-                        if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, fc.ts, fc.tp, fc.flux, EV_EXIT, 0, 0, 0);
+                        if (TAPE && tape.ev) tape_put(tape, (*ntape)++, r.dx, r.dy, r.dz, EV_EXIT, fc.ts.re, fc.tp.re, fc.flux, 0.0);
                         apply_sp(r.e, sv, pin, pout, fc.ts, fc.tp, fc.flux);
                         o.w = norm2(r.e);
                     }
@@ -452,8 +484,13 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
             s_basis(r.dx, r.dy, r.dz, bnx, 0.0, bnz, sv);
             cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
             cross3(ndx, r.dy, ndz, sv[0], sv[1], sv[2], pout);
-            if (TAPE && tape.base) tape_put(tape, (*ntape)++, r, cs, cp, scale, ev, m, front, refl);
-            apply_sp(r.e, sv, pin, pout, cs, cp, scale);
+            const cd es = dot_re(r.e, sv), ep = dot_re(r.e, pin);
+            if (TAPE && tape.ev) {
+                tape_put(tape, (*ntape)++, r.dx, r.dy, r.dz, ev | (m << 4) | (front << 12) | (refl << 13),
+                         cs.re, cs.im, cp.re, cp.im);
+                if (ev == EV_MIRROR) tape_put_mirror(tape, r.nprma, es, ep);
+            }
+            apply_sp_proj(r.e, sv, pout, cs, cp, scale, es, ep);
         }
         r.dx = ndx;
         r.dz = ndz;
@@ -467,24 +504,13 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
     }
 }
 
-// One tape event as the reverse sweep reads it.
-struct TapeEv {
-    double dx, dy, dz;
-    double e[6];                  // incoming field (mirror events only)
-    double cs_re, cs_im, cp_re, cp_im, scale;
-    int meta;
-};
-__device__ inline TapeEv tape_get(const TapeRef& tape, int k)
+// One tape line as the reverse sweep reads it.
+struct TapeLine { double dx, dy, dz, meta, c0, c1, c2, c3; };
+__device__ inline TapeLine tape_line(const TapeRef& t, int k)
 {
-    const int64_t ts = tape.ts;
-    const double* b = tape.base + (int64_t)k * kTapeStride * ts;
-    TapeEv v;
-    v.dx = b[0]; v.dy = b[ts]; v.dz = b[2 * ts];
-    for (int c = 0; c < 6; ++c) v.e[c] = b[(3 + c) * ts];
-    v.cs_re = b[9 * ts]; v.cs_im = b[10 * ts]; v.cp_re = b[11 * ts]; v.cp_im = b[12 * ts];
-    v.scale = b[13 * ts];
-    v.meta = (int)b[14 * ts];
-    return v;
+    const double2* b = (const double2*)(t.ev + (int64_t)k * kTapeLine * t.ts);
+    const double2 a0 = b[0], a1 = b[1], a2 = b[2], a3 = b[3];
+    return { a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, a3.x, a3.y };
 }
 
 // Reverse field sweep along one ray's fixed path (the adjoint of Eq. 5 and
@@ -494,38 +520,51 @@ __device__ inline TapeEv tape_get(const TapeRef& tape, int k)
 // the taken coefficients,
 //     G_s = scale conj(lambda_k . s) (s . E_{k-1}),
 //     G_p = scale conj(lambda_k . p_out) (p_in . E_{k-1}),
-// and meta = mirror | front << 8 | reflected << 9.
+// and meta = mirror | front << 8 | reflected << 9.  nt events and nm mirror
+// records are on the tape; a mirror hit's scale is the point's branch
+// weight, that of a total internal reflection 1.
 template <class Emit>
 __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, const cd* e_final, TapeRef tape,
-                                     int nt, Emit emit)
+                                     int nt, int nm, Emit emit)
 {
     cd lam[3] = { e_final[0], e_final[1], e_final[2] };
-    // each event's tape words are requested one event ahead of their use,
-    // so the memory latency overlaps the previous event's arithmetic
-    TapeEv nx;
-    if (nt > 0) nx = tape_get(tape, nt - 1);
+    // event lines are requested two events ahead of their use and the next
+    // mirror record as soon as the previous one is taken, so the memory
+    // latency overlaps the arithmetic of the events in between
+    const TapeLine zl = { 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0 };
+    TapeLine n1 = zl, n2 = zl;
+    if (nt > 0) n1 = tape_line(tape, nt - 1);
+    if (nt > 1) n2 = tape_line(tape, nt - 2);
+    int hm = nm - 1;
+    double2 m0 = make_double2(0.0, 0.0), m1 = m0;
+    if (hm >= 0) {
+        const double2* b = (const double2*)(tape.mr + (int64_t)hm * kTapeMir * tape.ts);
+        m0 = b[0]; m1 = b[1];
+    }
     for (int k = nt - 1; k >= 0; --k) {
-        const TapeEv ev = nx;
-        if (k > 0) nx = tape_get(tape, k - 1);
+        const TapeLine ev = n1;
+        n1 = n2;
+        if (k > 1) n2 = tape_line(tape, k - 2);
         const double dx = ev.dx, dy = ev.dy, dz = ev.dz;
-        const cd cs = mk(ev.cs_re, ev.cs_im), cp = mk(ev.cp_re, ev.cp_im);
-        const double scale = ev.scale;
-        const int meta = ev.meta;
+        const int meta = (int)ev.meta;
         const int type = meta & 15, m = (meta >> 4) & 255;
         const int front = (meta >> 12) & 1, refl = (meta >> 13) & 1;
+        cd cs = mk(ev.c0, ev.c1), cp = mk(ev.c2, ev.c3);
+        double scale = 1.0;
         double sv[3], pin[3], pout[3];
         if (type == EV_MIRROR) {
+            const cd es = mk(m0.x, m0.y), ep = mk(m1.x, m1.y);
+            if (--hm >= 0) {
+                const double2* b = (const double2*)(tape.mr + (int64_t)hm * kTapeMir * tape.ts);
+                m0 = b[0]; m1 = b[1];
+            }
+            scale = refl ? pl.sc_r[m] : pl.sc_t[m];
             s_basis(dx, dy, dz, pl.nx, 0.0, pl.nz, sv);
             cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
             double ndx = dx, ndz = dz;
             if (refl) mirror_reflect(pl.nx, pl.nz, dx, dz, &ndx, &ndz);
             cross3(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
-            cd E[3];
-            for (int c = 0; c < 3; ++c) E[c] = mk(ev.e[2 * c], ev.e[2 * c + 1]);
-            const cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
-            const cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
-            const cd es = cadd(cadd(cscale(E[0], sv[0]), cscale(E[1], sv[1])), cscale(E[2], sv[2]));
-            const cd ep = cadd(cadd(cscale(E[0], pin[0]), cscale(E[1], pin[1])), cscale(E[2], pin[2]));
+            const cd ls = dot_re(lam, sv), lp = dot_re(lam, pout);
             const cd Gs = cscale(cmul(cconj(ls), es), scale);
             const cd Gp = cscale(cmul(cconj(lp), ep), scale);
             double c3[3];
@@ -538,6 +577,10 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
             if (type == EV_TIR) {
                 cross3(dx, dy, -dz, sv[0], sv[1], sv[2], pout);
             } else {
+                // exit: real t_s, t_p and the flux factor
+                cs = mk(ev.c0, -0.0);
+                cp = mk(ev.c1, -0.0);
+                scale = ev.c2;
                 Ray tmp;
                 tmp.dx = dx; tmp.dy = dy; tmp.dz = dz;
                 const double st2 = (pl.ng * pl.ng) * (dx * dx + dy * dy);
@@ -546,8 +589,7 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
                 cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
             }
         }
-        const cd ls = cadd(cadd(cscale(lam[0], sv[0]), cscale(lam[1], sv[1])), cscale(lam[2], sv[2]));
-        const cd lp = cadd(cadd(cscale(lam[0], pout[0]), cscale(lam[1], pout[1])), cscale(lam[2], pout[2]));
+        const cd ls = dot_re(lam, sv), lp = dot_re(lam, pout);
         const cd as = cscale(cmul(cconj(cs), ls), scale), ap = cscale(cmul(cconj(cp), lp), scale);
         for (int c = 0; c < 3; ++c) lam[c] = cadd(cscale(as, sv[c]), cscale(ap, pin[c]));
     }
