@@ -249,10 +249,11 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
                                             int L, bool front, const LaneSlots3& sl, double k0,
                                             double eta0s, double eta0p, bool reflect, cd Gs, cd Gp,
                                             double* grad_row, double* __restrict__ chk, int64_t cstride,
-                                            bool stored = false)
+                                            bool stored = false, int kseg = kSegL)
 {
     // 1) exit -> incident sweep v_j = M_j v_{j+1}, checkpoints v_K, v_2K, ...
-    //    (K = kSegL): first the L % K layers above the last multiple of K,
+    //    (K = kseg, the hit's interval, the same as the forward solve's
+    //    for a stored sweep): first the L % K layers above the last multiple of K,
     //    then whole groups of K layers, each ending in a checkpoint (group 0
     //    in none: v_0 stays in registers).  stored: the forward solve ran
     //    this sweep and left v_0 in block 0 and the checkpoints in blocks
@@ -260,7 +261,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
     //    arithmetic: the half-period sine/cosine, whose sign (-1)^(sum n)
     //    is put back on each checkpoint and on v_0.
     if (L <= 0) return;
-    constexpr int K = kSegL;
+    const int K = kseg;
     V2d vs = { 1.0, 0.0, eta0s, 0.0 };
     V2d vp = { 1.0, 0.0, eta0p, 0.0 };
     double nsum = 0.0;
@@ -333,6 +334,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
         }
     };
     if (K < L) load_chk(1);
+    int gnext = 2;                                      // block of the checkpoint after the loaded one
     // Software pipeline over the layers, as in the forward sweep: layer
     // j+1's argument is reduced from slot parameters read one iteration
     // earlier, layer j+2's parameters and thickness are read, and layer
@@ -356,7 +358,8 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             const uint32_t sb = (uint32_t)((int)nsum_c & 1) << 31;
             ws = V2d{ flip_sign(nws.br, sb), flip_sign(nws.bi, sb), flip_sign(nws.cr, sb), flip_sign(nws.ci, sb) };
             wp = V2d{ flip_sign(nwp.br, sb), flip_sign(nwp.bi, sb), flip_sign(nwp.cr, sb), flip_sign(nwp.ci, sb) };
-            if (lo + K < L) load_chk(lo / K + 1);
+            if (lo + K < L) load_chk(gnext);
+            ++gnext;
         }
         const int hi = lo + K < L ? lo + K : L;
 #pragma unroll 4

@@ -67,10 +67,12 @@ __device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const
         // the hyperbolic case (same results)
         if (__ballot(hyp) == 0ull)
             tmm_adjoint_lossless<false>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
-                                        pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored);
+                                        pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored,
+                                        ck_interval(hyp));
         else
             tmm_adjoint_lossless<true>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
-                                       pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored);
+                                       pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored,
+                                       ck_interval(hyp));
     }
     else if (!LOSSLESS)
         tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, sc.slot_complex,

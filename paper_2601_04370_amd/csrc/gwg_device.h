@@ -767,12 +767,12 @@ __device__ inline double flip_sign(double x, uint32_t sb)
 template <typename T, bool HC, class SL, class Cur>
 __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, int L, const SL& sl, V2<T>& vs,
                                                                      V2<T>& vp, int& es, int& ep, double* ck,
-                                                                     int64_t ckb)
+                                                                     int64_t ckb, int kseg = kSegL)
 {
     double nsum = 0.0;                                  // sum of the layers' n (exact: small integers)
     auto sign_bit = [&]() { return (uint32_t)((int)nsum & 1) << 31; };
-    // ck (T = double only): the adjoint's sweep checkpoints v_{g kSegL}
-    // (incidence-order layer g kSegL and below) go to the 64-byte block g at
+    // ck (T = double only): the adjoint's sweep checkpoints v_{g kseg}
+    // (incidence-order layer g kseg and below) go to the 64-byte block g at
     // ck + g ckb, whole; v_0 goes to block 0 after the loop.
     auto store = [&](int g) {
         const uint32_t sb = sign_bit();
@@ -799,8 +799,9 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
     cur.next();
     LayerRec r2 = cur.get();
     // loop index j of the next checkpoint (incidence-order layer L-1-j a
-    // positive multiple of kSegL), or L when none is left
-    int jck = (L - 1) % kSegL;
+    // positive multiple of kseg, a power of two), or L when none is left
+    const int ksh = 31 - __builtin_clz((unsigned)kseg);
+    int jck = (L - 1) & (kseg - 1);
     if (jck >= L - 1) jck = L;
 #pragma unroll 4
     for (int j = 0; j < L; ++j) {
@@ -815,8 +816,8 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
         step_real(vp, C, S * (T)xp, S * (T)yp);
         if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
         if (sizeof(T) == 8 && ck && j == jck) {
-            store((L - 1 - j) / kSegL);
-            jck = jck + kSegL < L - 1 ? jck + kSegL : L;
+            store((L - 1 - j) >> ksh);
+            jck = jck + (1 << ksh) < L - 1 ? jck + (1 << ksh) : L;
         }
         ta = ta1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
         kq1 = kq2; xs1 = xs2; ys1 = ys2; xp1 = xp2; yp1 = yp2; t1 = r2.t;
@@ -841,12 +842,12 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
 // calling wave has an evanescent lossless slot (the sweep then skips the
 // hyperbolic case; the results are the same).  ck (lossless FP64 stacks):
 // the entry's checkpoint blocks for the adjoint's sweep (block g at ck + g
-// ckb), or null.
+// ckb, one every kseg layers), or null.
 template <typename T, class SL, class Stk>
 __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const Stk& stk, int L,
                                   bool front, const SL& sl, uint32_t cplx_mask, double k0d, double eta0s,
                                   double eta0p, cd etaEs, cd etaEp, cd tp_factor, bool circ = false,
-                                  double* ck = nullptr, int64_t ckb = 8)
+                                  double* ck = nullptr, int64_t ckb = 8, int kseg = kSegL)
 {
     const T k0 = (T)k0d;
     V2<T> vs = { (T)1, (T)0, (T)etaEs.re, (T)etaEs.im };
@@ -855,9 +856,9 @@ __device__ __attribute__((always_inline)) inline Coef4 tmm_solve(const Stk& stk,
     if (L <= 0) return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
     if (cplx_mask == 0u) {
         if (circ)
-            lossless_sweep<T, false>(stk.cursor(L, front), L, sl, vs, vp, es, ep, ck, ckb);
+            lossless_sweep<T, false>(stk.cursor(L, front), L, sl, vs, vp, es, ep, ck, ckb, kseg);
         else
-            lossless_sweep<T, true>(stk.cursor(L, front), L, sl, vs, vp, es, ep, ck, ckb);
+            lossless_sweep<T, true>(stk.cursor(L, front), L, sl, vs, vp, es, ep, ck, ckb, kseg);
         return finish_coeffs(vs, vp, es, ep, eta0s, eta0p, tp_factor);
     }
     auto cur = stk.cursor(L, front);

@@ -52,7 +52,7 @@ __device__ inline Coef4 hit_solve(const SceneDev& sc, const PointLds& pl, const 
     if (fp64)
         return tmm_solve<double>(stk, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                                  mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ, MODE == GWG_FP64 ? ck : nullptr,
-                                 ckb);
+                                 ckb, ck_interval(hyp));
     return tmm_solve<float>(stk, L, front, sl, sc.slot_complex, pl.k0, eta0s, eta0p,
                             mk(eta0s, 0.0), mk(eta0p, 0.0), mk(1.0, 0.0), circ);
 }

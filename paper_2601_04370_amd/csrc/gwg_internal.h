@@ -32,8 +32,20 @@ constexpr int kTapeLine = 8;          // doubles of a tape event line
 constexpr int kTapeMir = 4;           // doubles of a tape mirror record
 constexpr int kTapeStride = kTapeLine + kTapeMir;  // tape doubles per lane and event slot
 constexpr int kSeg = 4;               // layers per recomputation segment (backward)
-constexpr int kSegL = 16;             // checkpoint interval of the lossless adjoint (multiple of kSeg)
-// checkpoint blocks per stored adjoint entry: v_0 and v_{g kSegL}, g >= 1
+// Checkpoint interval of the lossless adjoint's sweep (the adjoint walks each
+// interval down from its top checkpoint with inverse layer matrices): kSegL
+// for a hit that meets an evanescent lossless layer, kSegLC for one whose
+// layers all propagate.  A walk's rounding error grows at most like the
+// square of the interval's transfer growth: with circular layers that is
+// polynomial in the interval except inside a reflection band, where a
+// quarter-wave pair of index ratio 1.64 grows it 1.64-fold; 32 layers keep it
+// below 1e7 there.  Hyperbolic layers grow it exponentially in their
+// thickness, so their hits keep the shorter interval.
+constexpr int kSegL = 16;
+constexpr int kSegLC = 32;                 // both powers of two
+__host__ __device__ inline int ck_interval(bool evanescent) { return evanescent ? kSegL : kSegLC; }
+// checkpoint blocks per stored adjoint entry: v_0 and v_{g K}, g >= 1, for
+// either interval K
 __host__ __device__ inline int64_t ck_blocks(int lmax) { return lmax / kSegL + 1; }
 
 enum EventType { EV_NONE = 0, EV_TIR = 1, EV_EXIT = 2, EV_LEAK = 3, EV_END = 4, EV_MIRROR = 5 };

@@ -252,12 +252,13 @@ def test_stored_sweep_checkpoints_give_the_same_gradient(gctx, name, kw):
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
-@pytest.mark.parametrize("n_layers", [1, 15, 16, 17, 33])
+@pytest.mark.parametrize("n_layers", [1, 15, 16, 17, 31, 32, 33, 65])
 def test_checkpoint_schedule_layer_counts(gctx, orc, n_layers):
-    """Stacks with no checkpoint (L <= 16) and with L - 1 just below, at and
-    above a multiple of the 16-layer checkpoint interval: the gradient with
-    the forward's stored sweep checkpoints matches the oracle and equals the
-    recomputing adjoint's bit for bit."""
+    """Stacks with no checkpoint (L at most the interval) and with L - 1 just
+    below, at and above a multiple of either checkpoint interval (16 layers
+    for hits that meet an evanescent layer, 32 for the others): the gradient
+    with the forward's stored sweep checkpoints matches the oracle and equals
+    the recomputing adjoint's bit for bit."""
     w = inputs.small_variant("diff_1200", rays_per_point=96, fov_n=3, n_layers=n_layers)
     inp = inputs.make_inputs(w)
     print(f"checkpoint schedule diff_1200 n_layers={n_layers}", flush=True)
@@ -278,6 +279,33 @@ def test_checkpoint_schedule_layer_counts(gctx, orc, n_layers):
         finally:
             gctx.set_tuning()
     assert np.array_equal(out[0], out[1])
+
+
+def test_gradient_on_a_quarter_wave_stack(gctx, orc):
+    """Every layer of an SiO2/TiO2 stack a quarter wave thick at the first
+    mirror incidence of the centre field (kappa = n_glass sin 25 deg): the
+    hits there lie deep in the stack's reflection band, where the transfer
+    matrix grows fastest over a checkpoint interval and the adjoint's walk
+    down each interval with inverse layer matrices loses the most digits.
+    Gradient against the oracle elementwise to 1e-7 (relative, with a floor
+    at 1e-3 of the largest component)."""
+    lam = 530.0
+    w = inputs.small_variant("diff_1200", rays_per_point=512, fov_n=3, lambdas_nm=(lam,),
+                             cycle=(inputs.MAT_SIO2, inputs.MAT_TIO2))
+    inp = inputs.make_inputs(w)
+    kap = w.n_glass * np.sin(np.radians(w.tilt_deg))
+    for m in range(w.n_mirrors):
+        for j in range(w.n_layers):
+            n = inp["n_re"][0, inp["mat"][0, m, j]]
+            inp["thk"][0, m, j] = lam / (4.0 * np.sqrt(n * n - kap * kap))
+    print(f"quarter-wave stack: thicknesses {inp['thk'][0, 0, :2]} nm", flush=True)
+    g, og = _grad_case(gctx, orc, w, inp, 0, 1, 0, mode="entries")
+    scale = np.max(np.abs(og))
+    assert scale > 0
+    err = np.abs(g - og)
+    rel = err / np.maximum(np.abs(og), 1e-3 * scale)
+    print(f"  max |g| {scale:.3e}  max abs err {err.max():.3e}  max rel {rel.max():.2e}", flush=True)
+    assert np.all(err <= 1e-7 * np.maximum(np.abs(og), 1e-3 * scale))
 
 
 def test_work_order_does_not_change_results(gctx):
