@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
     const int64_t gwave = (int64_t)blockIdx.x * n_waves + wave;
     // scratch: the tape (Kmax event slots of every lane), then n_chk x 8
     // checkpoint doubles per lane, then queues per wave
-    const TapeRef tape = tape_lane(scratch, sc.Kmax, nthreads, gtid);
+    const TapeRef tape = tape_lane(scratch, sc.Kmax, (int64_t)gridDim.x * n_waves, gwave, lane);
     const int64_t n_chk = sc.Lmax / kSeg + 1;
     double* chk = scratch + (int64_t)sc.Kmax * kTapeStride * nthreads + gtid;
     const int qcap = 64 * (sc.Kmax + 1);
@@ -209,10 +209,11 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
                 c_hits += (unsigned long long)r.nprma;
             }
             const bool contrib = active;
+            const int ntw = wave_max_int(contrib ? nt : 0);
             if constexpr (TAB) {
                 if (contrib) {
                     c_arays += 1;
-                    reverse_sweep(sc, *pl, r.e, tape, nt, r.nprma, TableEmit{ acc_dl, sc.table_n, pl->ng, gscale, fx });
+                    reverse_sweep(sc, *pl, r.e, tape, nt, ntw, TableEmit{ acc_dl, sc.table_n, pl->ng, gscale, fx });
                 }
                 continue;
             }
@@ -221,7 +222,7 @@ __global__ void __launch_bounds__(128, 2) k_trace_bwd(SceneDev sc, const double*
             if (contrib) {
                 c_arays += 1;
                 int slotpos = qhead + qcount + off;
-                reverse_sweep(sc, *pl, r.e, tape, nt, r.nprma, QueueEmit{ q, &slotpos, gscale });
+                reverse_sweep(sc, *pl, r.e, tape, nt, ntw, QueueEmit{ q, &slotpos, gscale });
             }
             qcount += total;
             __threadfence_block();

@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
     const double wscale = ldexp(1.0, sc.fp_shift), wcap = ldexp(1.0, 40), pscale = 16777216.0;
     for (int k = tid; k < ST_WORDS; k += WG) s_st[k] = 0ull;
     unsigned long long n_fp64 = 0, n_lay = 0;
-    const TapeRef tape = tape_lane(tape_scratch, sc.Kmax, (int64_t)gridDim.x * WG, (int64_t)blockIdx.x * WG + tid);
+    const TapeRef tape = tape_lane(tape_scratch, sc.Kmax, (int64_t)gridDim.x * n_waves, gwave, lane);
     const FwdMemo fm = fwd_memo(smem + lay.total, wave,
                                 scratch + (int64_t)gridDim.x * n_waves * fwd_wave_doubles(sc) + gwave * 8 * kFwdMemoKeys);
     constexpr bool tabm = TAB;                           // angle-table thin film: no hit queue
@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
             int nt = 0;
             if (active) {
                 ray_birth(sc, *pl, id, r);
-                const TapeRef rt = { to_eyebox ? tape.ev : nullptr, tape.mr, tape.ts };
+                const TapeRef rt = { to_eyebox ? tape.ev : nullptr, tape.mr, tape.ks };
                 walk_ray<true, ADJ>(sc, *pl, r, o, NoHit{}, gcoef, rt, &nt);
                 atomicAdd(&s_st[ST_RAYS], 1ull);
                 atomicAdd(&s_st[ST_EVENTS], (unsigned long long)r.nev);
@@ -457,11 +457,12 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     q->w = o.w;
                 }
             }
+            const int ntw = ADJ ? wave_max_int(active && o.cat == CAT_EYEBOX ? nt : 0) : 0;
             if (ADJ && active && o.cat == CAT_EYEBOX) {
                 int64_t k = kent;
                 const int64_t cap_w = st.cap_w;
                 const int64_t meta_bin = (int64_t)o.bin << 10;
-                reverse_sweep(sc, *pl, r.e, tape, nt, r.nprma, [&](double kappa, cd Gs, cd Gp, int meta) {
+                reverse_sweep(sc, *pl, r.e, tape, nt, ntw, [&](double kappa, cd Gs, cd Gp, int meta) {
                     if constexpr (TAB) {
                         const double a = fmax(fmax(fabs(Gs.re), fabs(Gs.im)), fmax(fabs(Gp.re), fabs(Gp.im)));
                         t_gmax = a > t_gmax ? a : t_gmax;

@@ -294,6 +294,17 @@ __device__ inline int wave_excl_scan(int x, int* total)
     return v - x;
 }
 
+// Largest x over the 64 lanes (every lane must call).
+__device__ inline int wave_max_int(int x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int y = __shfl_xor(x, o, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
 // ------------------------------------------------------------ hit queue
 // Mirror hits of one wave's current round of rays: entry p holds the hit's
 // kappa and meta (mirror | front << 8), after the solve its four
@@ -334,40 +345,45 @@ struct HitQueue {
 constexpr int kHitFields = 12;
 
 // ------------------------------------------------------------ tape
-// Field-changing events of one ray, for the reverse field sweep.  Each event
-// takes one 64-byte line of the lane's own: the direction before the event,
-// meta (type | mirror << 4 | front << 12 | reflected << 13) and four
-// coefficient words (mirror hit and total internal reflection: c_s, c_p;
-// exit: t_s, t_p and the flux factor, the transmission coefficients being
-// real below the critical angle).  A mirror hit also takes a 32-byte record
-// with the incoming field's components s.E and p_in.E.  Line k of a lane is
-// at ev + 8 k ts, its mirror record h at mr + 4 h ts (ts = lanes of the
-// grid): a lane writes and reads whole lines of its own, so lanes that
-// record nothing move no memory.
-struct TapeRef { double* ev; double* mr; int64_t ts; };
+// Field-changing events of one ray, for the reverse field sweep.  Event k
+// takes four 16-byte words: the direction before the event (dx, dy), (dz,
+// meta) with meta = type | mirror << 4 | front << 12 | reflected << 13, and
+// two coefficient words (mirror hit and total internal reflection: c_s,
+// c_p; exit: t_s, t_p and the flux factor, the transmission coefficients
+// being real below the critical angle).  A mirror hit adds a record of two
+// words, the incoming field's components s.E and p_in.E.  The 64 lanes of a
+// wave keep word q of their event k side by side: 1 KB at ev + (k W + w) 512
+// + 128 q doubles (W waves in the grid, w this wave), the mirror record at
+// mr + (k W + w) 256 + 128 q.  In the field walk every walking lane records
+// one event per iteration, so a wave's lanes store the same k together and
+// each store instruction fills 16 whole cache lines; the reverse sweep reads
+// the same way (reverse_sweep).
+struct TapeRef { double* ev; double* mr; int64_t ks; };   // ks: doubles from event k to k + 1 (event words)
 
-// The tape of lane gtid of nthreads in a region of kmax * kTapeStride *
-// nthreads doubles (event lines first, then mirror records).
-__device__ inline TapeRef tape_lane(double* region, int64_t kmax, int64_t nthreads, int64_t gtid)
+// The tape of lane `lane` of wave gwave of n_waves in a region of kmax *
+// kTapeStride * 64 * n_waves doubles (event words first, then mirror records).
+__device__ inline TapeRef tape_lane(double* region, int64_t kmax, int64_t n_waves, int64_t gwave, int lane)
 {
-    return { region + gtid * kTapeLine, region + kmax * kTapeLine * nthreads + gtid * kTapeMir, nthreads };
+    return { region + gwave * (64 * kTapeLine) + 2 * lane,
+             region + kmax * n_waves * (64 * kTapeLine) + gwave * (64 * kTapeMir) + 2 * lane,
+             n_waves * (64 * kTapeLine) };
 }
 
 __device__ inline void tape_put(const TapeRef& t, int k, double dx, double dy, double dz, int meta,
                                 double c0, double c1, double c2, double c3)
 {
-    double2* b = (double2*)(t.ev + (int64_t)k * kTapeLine * t.ts);
+    double2* b = (double2*)(t.ev + (int64_t)k * t.ks);
     b[0] = make_double2(dx, dy);
-    b[1] = make_double2(dz, (double)meta);
-    b[2] = make_double2(c0, c1);
-    b[3] = make_double2(c2, c3);
+    b[64] = make_double2(dz, (double)meta);
+    b[128] = make_double2(c0, c1);
+    b[192] = make_double2(c2, c3);
 }
 
-__device__ inline void tape_put_mirror(const TapeRef& t, int h, cd es, cd ep)
+__device__ inline void tape_put_mirror(const TapeRef& t, int k, cd es, cd ep)
 {
-    double2* b = (double2*)(t.mr + (int64_t)h * kTapeMir * t.ts);
+    double2* b = (double2*)(t.mr + (int64_t)k * (t.ks / 2));
     b[0] = make_double2(es.re, es.im);
-    b[1] = make_double2(ep.re, ep.im);
+    b[64] = make_double2(ep.re, ep.im);
 }
 
 // Outcome of a terminated ray.
@@ -486,9 +502,10 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
             cross3(ndx, r.dy, ndz, sv[0], sv[1], sv[2], pout);
             const cd es = dot_re(r.e, sv), ep = dot_re(r.e, pin);
             if (TAPE && tape.ev) {
-                tape_put(tape, (*ntape)++, r.dx, r.dy, r.dz, ev | (m << 4) | (front << 12) | (refl << 13),
+                const int k = (*ntape)++;
+                tape_put(tape, k, r.dx, r.dy, r.dz, ev | (m << 4) | (front << 12) | (refl << 13),
                          cs.re, cs.im, cp.re, cp.im);
-                if (ev == EV_MIRROR) tape_put_mirror(tape, r.nprma, es, ep);
+                if (ev == EV_MIRROR) tape_put_mirror(tape, k, es, ep);
             }
             apply_sp_proj(r.e, sv, pout, cs, cp, scale, es, ep);
         }
@@ -504,12 +521,12 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
     }
 }
 
-// One tape line as the reverse sweep reads it.
+// One tape event as the reverse sweep reads it.
 struct TapeLine { double dx, dy, dz, meta, c0, c1, c2, c3; };
 __device__ inline TapeLine tape_line(const TapeRef& t, int k)
 {
-    const double2* b = (const double2*)(t.ev + (int64_t)k * kTapeLine * t.ts);
-    const double2 a0 = b[0], a1 = b[1], a2 = b[2], a3 = b[3];
+    const double2* b = (const double2*)(t.ev + (int64_t)k * t.ks);
+    const double2 a0 = b[0], a1 = b[64], a2 = b[128], a3 = b[192];
     return { a0.x, a0.y, a1.x, a1.y, a2.x, a2.y, a3.x, a3.y };
 }
 
@@ -520,31 +537,38 @@ __device__ inline TapeLine tape_line(const TapeRef& t, int k)
 // the taken coefficients,
 //     G_s = scale conj(lambda_k . s) (s . E_{k-1}),
 //     G_p = scale conj(lambda_k . p_out) (p_in . E_{k-1}),
-// and meta = mirror | front << 8 | reflected << 9.  nt events and nm mirror
-// records are on the tape; a mirror hit's scale is the point's branch
-// weight, that of a total internal reflection 1.
+// and meta = mirror | front << 8 | reflected << 9.  nt events are on this
+// lane's tape; ntw, the same on every calling lane, is the longest tape of
+// the calling lanes.  The sweep steps a common event index i down from
+// ntw - 1 and a lane takes event i once i < nt, so the lanes read the same
+// event together.  A mirror hit's scale is the point's branch weight, that
+// of a total internal reflection 1.
 template <class Emit>
 __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, const cd* e_final, TapeRef tape,
-                                     int nt, int nm, Emit emit)
+                                     int nt, int ntw, Emit emit)
 {
     cd lam[3] = { e_final[0], e_final[1], e_final[2] };
-    // event lines are requested two events ahead of their use and the next
-    // mirror record as soon as the previous one is taken, so the memory
+    // event words are requested two events ahead of their use, a mirror
+    // record one event ahead (once that event's meta is in), so the memory
     // latency overlaps the arithmetic of the events in between
     const TapeLine zl = { 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0 };
+    auto mirror_rec = [&](int k, double2& a, double2& b) {
+        const double2* p = (const double2*)(tape.mr + (int64_t)k * (tape.ks / 2));
+        a = p[0];
+        b = p[64];
+    };
     TapeLine n1 = zl, n2 = zl;
-    if (nt > 0) n1 = tape_line(tape, nt - 1);
-    if (nt > 1) n2 = tape_line(tape, nt - 2);
-    int hm = nm - 1;
+    if (ntw >= 1 && ntw - 1 < nt) n1 = tape_line(tape, ntw - 1);
+    if (ntw >= 2 && ntw - 2 < nt) n2 = tape_line(tape, ntw - 2);
     double2 m0 = make_double2(0.0, 0.0), m1 = m0;
-    if (hm >= 0) {
-        const double2* b = (const double2*)(tape.mr + (int64_t)hm * kTapeMir * tape.ts);
-        m0 = b[0]; m1 = b[1];
-    }
-    for (int k = nt - 1; k >= 0; --k) {
+    if (ntw >= 1 && ntw - 1 < nt && ((int)n1.meta & 15) == EV_MIRROR) mirror_rec(ntw - 1, m0, m1);
+    for (int i = ntw - 1; i >= 0; --i) {
         const TapeLine ev = n1;
+        const double2 e0 = m0, e1 = m1;
         n1 = n2;
-        if (k > 1) n2 = tape_line(tape, k - 2);
+        if (i >= 2 && i - 2 < nt) n2 = tape_line(tape, i - 2);
+        if (i >= 1 && i - 1 < nt && ((int)n1.meta & 15) == EV_MIRROR) mirror_rec(i - 1, m0, m1);
+        if (i >= nt) continue;                          // this lane's tape is shorter
         const double dx = ev.dx, dy = ev.dy, dz = ev.dz;
         const int meta = (int)ev.meta;
         const int type = meta & 15, m = (meta >> 4) & 255;
@@ -553,11 +577,7 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
         double scale = 1.0;
         double sv[3], pin[3], pout[3];
         if (type == EV_MIRROR) {
-            const cd es = mk(m0.x, m0.y), ep = mk(m1.x, m1.y);
-            if (--hm >= 0) {
-                const double2* b = (const double2*)(tape.mr + (int64_t)hm * kTapeMir * tape.ts);
-                m0 = b[0]; m1 = b[1];
-            }
+            const cd es = mk(e0.x, e0.y), ep = mk(e1.x, e1.y);
             scale = refl ? pl.sc_r[m] : pl.sc_t[m];
             s_basis(dx, dy, dz, pl.nx, 0.0, pl.nz, sv);
             cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
