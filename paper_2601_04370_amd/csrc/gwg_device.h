@@ -799,12 +799,14 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
     cur.next();
     LayerRec r2 = cur.get();
     // loop index j of the next checkpoint (incidence-order layer L-1-j a
-    // positive multiple of kseg, a power of two), or L when none is left
+    // positive multiple of kseg, a power of two), or L when none is left.
+    // Checkpoint layers have j = L-1 (mod 4): after the first L mod 4
+    // layers the loop takes four layers at a time and looks for a
+    // checkpoint after the fourth only.
     const int ksh = 31 - __builtin_clz((unsigned)kseg);
     int jck = (L - 1) & (kseg - 1);
     if (jck >= L - 1) jck = L;
-#pragma unroll 4
-    for (int j = 0; j < L; ++j) {
+    auto layer = [&](int j) {
         cur.next();
         const LayerRec r3 = cur.get();                               // past the stack: pad records
         double kq2, xs2, ys2, xp2, yp2;
@@ -815,13 +817,27 @@ __device__ __attribute__((always_inline)) inline void lossless_sweep(Cur cur, in
         step_real(vs, C, S * (T)xs, S * (T)ys);
         step_real(vp, C, S * (T)xp, S * (T)yp);
         if (sizeof(T) == 4 && (j & 7) == 7) { renorm(vs, es); renorm(vp, ep); }
+        ta = ta1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
+        kq1 = kq2; xs1 = xs2; ys1 = ys2; xp1 = xp2; yp1 = yp2; t1 = r2.t;
+        r2 = r3;
+    };
+    auto checkpoint = [&](int j) {
         if (sizeof(T) == 8 && ck && j == jck) {
             store((L - 1 - j) >> ksh);
             jck = jck + (1 << ksh) < L - 1 ? jck + (1 << ksh) : L;
         }
-        ta = ta1; xs = xs1; ys = ys1; xp = xp1; yp = yp1;
-        kq1 = kq2; xs1 = xs2; ys1 = ys2; xp1 = xp2; yp1 = yp2; t1 = r2.t;
-        r2 = r3;
+    };
+    const int pre = L & 3;
+    int j = 0;
+    for (; j < pre; ++j) layer(j);
+    if (pre > 0) checkpoint(pre - 1);
+#pragma unroll 1
+    for (; j < L; j += 4) {
+        layer(j);
+        layer(j + 1);
+        layer(j + 2);
+        layer(j + 3);
+        checkpoint(j + 3);
     }
     if constexpr (sizeof(T) == 8) {
         if (ck) store(0);
