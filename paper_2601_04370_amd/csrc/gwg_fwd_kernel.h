@@ -286,10 +286,22 @@ __host__ __device__ inline int64_t fwd_wave_doubles(const SceneDev& sc)
     return (int64_t)kHitFields * 64 * sc.pool * sc.Kmax + 2 * 64 * sc.pool;
 }
 
+// Also counts the ray's hits whose kappa^2 exceeds kap2 (they may meet an
+// evanescent layer) in *ne and marks hits h < 64 of them in bit h of *evm.
 struct PutHitP {
     HitQueue q;
     int col, ncol;
-    __device__ void operator()(int h, double kappa, int meta) const { q.put(h * ncol + col, kappa, meta); }
+    double kap2;
+    int* ne;
+    unsigned long long* evm;
+    __device__ void operator()(int h, double kappa, int meta) const
+    {
+        q.put(h * ncol + col, kappa, meta);
+        if (kappa * kappa > kap2) {
+            ++*ne;
+            if (h < 64) *evm |= 1ull << h;
+        }
+    }
     __device__ void branch(int, bool) const {}
 };
 // The field pass's coefficients of the ray at place pos of the order: the
@@ -510,11 +522,13 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     Ray r;
                     Outcome o;
                     TapeRef none = { nullptr, nullptr, 0 };
-                    int nh = 0, nev = 0;
+                    int nh = 0, nev = 0, ne = 0;
+                    unsigned long long evm = 0ull;         // bit h: hit h may meet an evanescent layer
                     bool to_eyebox = false;                // fixed by geometry alone
                     if (active) {
                         ray_birth(sc, *pl, base + i, r);
-                        walk_ray<false, false>(sc, *pl, r, o, PutHitP{ hq, col, ncol }, NoCoef{}, none, nullptr);
+                        walk_ray<false, false>(sc, *pl, r, o, PutHitP{ hq, col, ncol, pl->kap2_evan, &ne, &evm },
+                                               NoCoef{}, none, nullptr);
                         nh = r.nprma;
                         nev = r.nev;
                         to_eyebox = o.cat == CAT_EYEBOX;
@@ -541,19 +555,20 @@ __global__ void __launch_bounds__(256, 2) k_trace_fwd(SceneDev sc, uint64_t* __r
                     }
                     // solve order: the hits that may meet an evanescent layer
                     // from the front of field 11, the others from its back
-                    int ne = 0;
-                    for (int h = 0; h < nh; ++h) {
-                        const double k = hq.kappa(h * ncol + col);
-                        ne += k * k > pl->kap2_evan ? 1 : 0;
-                    }
                     int te, tc;
                     const int eo = wave_excl_scan(ne, &te);
                     const int co = wave_excl_scan(nh - ne, &tc);
                     int pe = n_e + eo, pc = n_c + co;
                     for (int h = 0; h < nh; ++h) {
                         const int q = h * ncol + col;
-                        const double k = hq.kappa(q);
-                        const int pos = k * k > pl->kap2_evan ? pe++ : cap - 1 - pc++;
+                        bool ev;
+                        if (h < 64) {
+                            ev = (evm >> h) & 1ull;
+                        } else {
+                            const double k = hq.kappa(q);
+                            ev = k * k > pl->kap2_evan;
+                        }
+                        const int pos = ev ? pe++ : cap - 1 - pc++;
                         hq.base[11 * (int64_t)cap + pos] = (double)q;
                     }
                     n_e += te;
