@@ -156,41 +156,40 @@ __device__ inline void ray_birth(const SceneDev& sc, const PointLds& pl, int64_t
 // Nearest bounding plane of the current cell; moves the ray onto it.
 __device__ inline int next_surface(const SceneDev& sc, const PointLds& pl, Ray& r)
 {
+    // One division per kind of surface, whatever the lanes of a wave face:
+    // the face ahead (top or bottom, by the sign of dz), the mirror ahead
+    // (the cell's left or right one, by the sign of dn) and, in an end cell,
+    // the end face.  Each lane's quotient is the same as its own surface's;
+    // the candidates are compared face first, then the left side (end 0 or
+    // mirror cell-1), then the right side (end 1 or mirror cell), an earlier
+    // candidate keeping a tie.
     double best = 0.0;
     int hit = -1;
-    if (r.dz > 0.0 && r.last != SURF_TOP) {
-        double t = (pl.T - r.pz) / r.dz;
-        if (hit < 0 || t < best) { best = t; hit = SURF_TOP; }
+    const bool up = r.dz > 0.0;
+    if ((up && r.last != SURF_TOP) || (r.dz < 0.0 && r.last != SURF_BOTTOM)) {
+        best = ((up ? pl.T : 0.0) - r.pz) / r.dz;
+        hit = up ? SURF_TOP : SURF_BOTTOM;
     }
-    if (r.dz < 0.0 && r.last != SURF_BOTTOM) {
-        double t = (0.0 - r.pz) / r.dz;
-        if (hit < 0 || t < best) { best = t; hit = SURF_BOTTOM; }
+    const double dn = pl.nx * r.dx + pl.nz * r.dz;
+    const double pn = pl.nx * r.px + pl.nz * r.pz;
+    const bool ml = r.cell != 0 && dn > 0.0 && r.last != r.cell - 1;
+    const bool mr = r.cell != pl.M && dn < 0.0 && r.last != r.cell;
+    double tm = 0.0;
+    const int mm = ml ? r.cell - 1 : r.cell;
+    if (ml || mr) tm = (pl.h[mm] - pn) / dn;
+    const bool e0 = r.cell == 0 && r.dx < 0.0 && r.last != SURF_END0;
+    const bool e1 = r.cell == pl.M && r.dx > 0.0 && r.last != SURF_END1;
+    double te = 0.0;
+    if (e0 || e1) te = ((e0 ? 0.0 : pl.Lx) - r.px) / r.dx;
+    if (e0) {
+        if (hit < 0 || te < best) { best = te; hit = SURF_END0; }
+    } else if (ml) {
+        if (hit < 0 || tm < best) { best = tm; hit = mm; }
     }
-    double dn = pl.nx * r.dx + pl.nz * r.dz;
-    double pn = pl.nx * r.px + pl.nz * r.pz;
-    if (r.cell == 0) {
-        if (r.dx < 0.0 && r.last != SURF_END0) {
-            double t = (0.0 - r.px) / r.dx;
-            if (hit < 0 || t < best) { best = t; hit = SURF_END0; }
-        }
-    } else {
-        int m = r.cell - 1;
-        if (dn > 0.0 && r.last != m) {
-            double t = (pl.h[m] - pn) / dn;
-            if (hit < 0 || t < best) { best = t; hit = m; }
-        }
-    }
-    if (r.cell == pl.M) {
-        if (r.dx > 0.0 && r.last != SURF_END1) {
-            double t = (pl.Lx - r.px) / r.dx;
-            if (hit < 0 || t < best) { best = t; hit = SURF_END1; }
-        }
-    } else {
-        int m = r.cell;
-        if (dn < 0.0 && r.last != m) {
-            double t = (pl.h[m] - pn) / dn;
-            if (hit < 0 || t < best) { best = t; hit = m; }
-        }
+    if (e1) {
+        if (hit < 0 || te < best) { best = te; hit = SURF_END1; }
+    } else if (mr) {
+        if (hit < 0 || tm < best) { best = tm; hit = mm; }
     }
     if (hit < 0) return -1;
     r.px = r.px + best * r.dx;
