@@ -375,11 +375,13 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             const double sXs = S * xs, sYs = S * ys, sXp = S * xp, sYp = S * yp;
             const double gys = kq < 0.0 ? -ys : ys;
             // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
-            const double i_s1 = u1s.re * ws.ci + u1s.im * ws.cr;   // Im(u1s C_s)
-            const double i_s2 = u2s.re * ws.bi + u2s.im * ws.br;   // Im(u2s B_s)
-            const double i_p1 = u1p.re * wp.ci + u1p.im * wp.cr;   // Im(u1p C_p)
-            const double i_p2 = u2p.re * wp.bi + u2p.im * wp.br;   // Im(u2p B_p)
-            const double g = k2 * (i_s1 + gys * (ys * i_s2 + xp * i_p1 + yp * i_p2));
+            // (fused multiply-adds written out: the library builds without
+            // contraction)
+            const double i_s1 = fma(u1s.re, ws.ci, u1s.im * ws.cr);   // Im(u1s C_s)
+            const double i_s2 = fma(u2s.re, ws.bi, u2s.im * ws.br);   // Im(u2s B_s)
+            const double i_p1 = fma(u1p.re, wp.ci, u1p.im * wp.cr);   // Im(u1p C_p)
+            const double i_p2 = fma(u2p.re, wp.bi, u2p.im * wp.br);   // Im(u2p B_p)
+            const double g = k2 * fma(gys, fma(yp, i_p2, fma(xp, i_p1, ys * i_s2)), i_s1);
             atomicAdd(&grad_row[idx], g);
             cov_step_real(u1s, u2s, C, sXs, sYs);
             cov_step_real(u1p, u2p, C, sXp, sYp);
