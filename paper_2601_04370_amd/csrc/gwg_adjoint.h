@@ -373,7 +373,7 @@ __device__ inline void tmm_adjoint_lossless(const double* __restrict__ thk, cons
             double C, S;
             LT::eval(ta, &C, &S, &nsum_c);
             const double sXs = S * xs, sYs = S * ys, sXp = S * xp, sYp = S * yp;
-            const double gys = kq < 0.0 ? -ys : ys;
+            const double gys = (HC && kq < 0.0) ? -ys : ys;       // sg y_s (an evanescent layer: sg = -1)
             // Im(u^T D w) summed over s and p, D = -i k0 [[0, a], [b, 0]]
             // (fused multiply-adds written out: the library builds without
             // contraction)
