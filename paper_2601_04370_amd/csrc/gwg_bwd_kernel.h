@@ -64,15 +64,21 @@ __device__ inline void adjoint_hit(const SceneDev& sc, const PointLds& pl, const
     const double q0 = sqrt(z0 > kTinyZ ? z0 : kTinyZ);
     if (LOSSLESS || sc.slot_complex == 0u) {
         // waves whose lanes all see circular layers take the sweep without
-        // the hyperbolic case (same results)
-        if (__ballot(hyp) == 0ull)
+        // the hyperbolic case (same results).  A sweep the forward stored
+        // has its hit's checkpoint interval; a sweep run here takes one
+        // interval for the whole wave (lanes of one interval walk their
+        // segments together), the longer one only if no lane meets an
+        // evanescent layer.
+        const bool circ = __ballot(hyp) == 0ull;
+        const int kseg = stored ? ck_interval(hyp) : ck_interval(!circ);
+        if (circ)
             tmm_adjoint_lossless<false>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
                                         pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored,
-                                        ck_interval(hyp));
+                                        kseg);
         else
             tmm_adjoint_lossless<true>(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, pl.k0, q0,
                                        pl.ng * pl.ng / q0, refl, Gs, Gp, gw + m * sc.Lmax, chk, cstride, stored,
-                                       ck_interval(hyp));
+                                       kseg);
     }
     else if (!LOSSLESS)
         tmm_adjoint(s_thk + m * sc.Lmax, s_slot + m * sc.Lmax, pl.nlay[m], front, sl, sc.slot_complex,
