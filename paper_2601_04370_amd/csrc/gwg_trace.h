@@ -57,17 +57,31 @@ __device__ inline void cross3(double ax, double ay, double az, double bx, double
     o[2] = ax * by - ay * bx;
 }
 
+// The field's arithmetic (polarization bases, projections, Eq. 5, the face
+// coefficients and weights) uses fused multiply-adds, written out because
+// the library builds without contraction; the geometry (positions, surfaces,
+// directions, kappa, bins) keeps the oracle's plain products so that paths
+// and bins agree bit for bit.
+__device__ inline void cross3_f(double ax, double ay, double az, double bx, double by, double bz, double* o)
+{
+    o[0] = fma(ay, bz, -(az * by));
+    o[1] = fma(az, bx, -(ax * bz));
+    o[2] = fma(ax, by, -(ay * bx));
+}
+__device__ inline cd cmul_f(cd a, cd b) { return mk(fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)); }
+__device__ inline double dot3_f(const double* a) { return fma(a[2], a[2], fma(a[1], a[1], a[0] * a[0])); }
+
 // s unit vector for direction d on a surface of normal n; when d is nearly
 // parallel to n (s and p equivalent) the y axis projected orthogonal to d.
 __device__ inline void s_basis(double dx, double dy, double dz, double nx, double ny, double nz, double* s)
 {
     double c[3];
-    cross3(dx, dy, dz, nx, ny, nz, c);
-    double l = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    cross3_f(dx, dy, dz, nx, ny, nz, c);
+    double l = sqrt(dot3_f(c));
     if (l < 1e-6) {
         double yd = dy;
-        c[0] = -yd * dx; c[1] = 1.0 - yd * dy; c[2] = -yd * dz;
-        l = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        c[0] = -yd * dx; c[1] = fma(-yd, dy, 1.0); c[2] = -yd * dz;
+        l = sqrt(dot3_f(c));
     }
     double il = 1.0 / l;
     s[0] = c[0] * il; s[1] = c[1] * il; s[2] = c[2] * il;
@@ -76,15 +90,17 @@ __device__ inline void s_basis(double dx, double dy, double dz, double nx, doubl
 // Components of a complex field along a real unit vector: sum_c e_c v_c.
 __device__ inline cd dot_re(const cd* e, const double* v)
 {
-    return cadd(cadd(cscale(e[0], v[0]), cscale(e[1], v[1])), cscale(e[2], v[2]));
+    return mk(fma(e[2].re, v[2], fma(e[1].re, v[1], e[0].re * v[0])),
+              fma(e[2].im, v[2], fma(e[1].im, v[1], e[0].im * v[0])));
 }
 
 // Eq. 5 given the incoming field's components es = s.E and ep = p_in.E.
 __device__ inline void apply_sp_proj(cd* e, const double* s, const double* pout, cd cs, cd cp, double scale,
                                      cd es, cd ep)
 {
-    cd as = cscale(cmul(cs, es), scale), ap = cscale(cmul(cp, ep), scale);
-    for (int k = 0; k < 3; ++k) e[k] = cadd(cscale(as, s[k]), cscale(ap, pout[k]));
+    cd as = cscale(cmul_f(cs, es), scale), ap = cscale(cmul_f(cp, ep), scale);
+    for (int k = 0; k < 3; ++k)
+        e[k] = mk(fma(as.re, s[k], ap.re * pout[k]), fma(as.im, s[k], ap.im * pout[k]));
 }
 
 // Eq. 5 on the local basis: E <- scale (cs (E.s) s + cp (E.p_in) p_out)
@@ -96,9 +112,9 @@ __device__ inline void apply_sp(cd* e, const double* s, const double* pin, const
 
 __device__ inline double norm2(const cd* e)
 {
-    double ax = e[0].re * e[0].re + e[0].im * e[0].im;
-    double ay = e[1].re * e[1].re + e[1].im * e[1].im;
-    double az = e[2].re * e[2].re + e[2].im * e[2].im;
+    double ax = fma(e[0].re, e[0].re, e[0].im * e[0].im);
+    double ay = fma(e[1].re, e[1].re, e[1].im * e[1].im);
+    double az = fma(e[2].re, e[2].re, e[2].im * e[2].im);
     return (ax + ay) + az;
 }
 
@@ -144,7 +160,7 @@ __device__ inline void ray_birth(const SceneDev& sc, const PointLds& pl, int64_t
     }
     double s0[3], p0[3];
     s_basis(r.dx, r.dy, r.dz, 0.0, 0.0, 1.0, s0);
-    cross3(r.dx, r.dy, r.dz, s0[0], s0[1], s0[2], p0);
+    cross3_f(r.dx, r.dy, r.dz, s0[0], s0[1], s0[2], p0);
     const double* e = (w.x & 1u) ? p0 : s0;
     for (int k = 0; k < 3; ++k) r.e[k] = mk(e[k], 0.0);
     r.cell = 0;
@@ -218,13 +234,13 @@ __device__ inline FaceCoef face_coeffs(double ng, double na, double dx, double d
     const cd den_s = cadd(mk(qi, 0.0), qt);
     const double is = 1.0 / (den_s.re * den_s.re + den_s.im * den_s.im);
     const cd inv_s = mk(den_s.re * is, -den_s.im * is);
-    f.rs = cmul(csub(mk(qi, 0.0), qt), inv_s);
+    f.rs = cmul_f(csub(mk(qi, 0.0), qt), inv_s);
     f.ts = cscale(inv_s, 2.0 * qi);
     const cd a = mk(na2 * qi, 0.0), b = cscale(qt, ng2);
     const cd den_p = cadd(a, b);
     const double ip = 1.0 / (den_p.re * den_p.re + den_p.im * den_p.im);
     const cd inv_p = mk(den_p.re * ip, -den_p.im * ip);
-    f.rp = cmul(csub(a, b), inv_p);
+    f.rp = cmul_f(csub(a, b), inv_p);
     f.tp = cscale(inv_p, 2.0 * ng * na * qi);
     f.flux = f.tir ? 0.0 : sqrt(qt.re / qi);
     return f;
@@ -436,8 +452,8 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
                     o.w = 0.0;
                     if (FIELD) {
                         s_basis(r.dx, r.dy, r.dz, 0.0, 0.0, 1.0, sv);
-                        cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
-                        cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
+                        cross3_f(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
+                        cross3_f(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
                         o.w_in = norm2(r.e);
                         if (TAPE && tape.ev) tape_put(tape, (*ntape)++, r.dx, r.dy, r.dz, EV_EXIT, fc.ts.re, fc.tp.re, fc.flux, 0.0);
                         apply_sp(r.e, sv, pin, pout, fc.ts, fc.tp, fc.flux);
@@ -497,8 +513,8 @@ __device__ inline void walk_ray(const SceneDev& sc, const PointLds& pl, Ray& r, 
         if (FIELD) {
             double sv[3], pin[3], pout[3];
             s_basis(r.dx, r.dy, r.dz, bnx, 0.0, bnz, sv);
-            cross3(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
-            cross3(ndx, r.dy, ndz, sv[0], sv[1], sv[2], pout);
+            cross3_f(r.dx, r.dy, r.dz, sv[0], sv[1], sv[2], pin);
+            cross3_f(ndx, r.dy, ndz, sv[0], sv[1], sv[2], pout);
             const cd es = dot_re(r.e, sv), ep = dot_re(r.e, pin);
             if (TAPE && tape.ev) {
                 const int k = (*ntape)++;
@@ -579,22 +595,22 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
             const cd es = mk(e0.x, e0.y), ep = mk(e1.x, e1.y);
             scale = refl ? pl.sc_r[m] : pl.sc_t[m];
             s_basis(dx, dy, dz, pl.nx, 0.0, pl.nz, sv);
-            cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
+            cross3_f(dx, dy, dz, sv[0], sv[1], sv[2], pin);
             double ndx = dx, ndz = dz;
             if (refl) mirror_reflect(pl.nx, pl.nz, dx, dz, &ndx, &ndz);
-            cross3(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
+            cross3_f(ndx, dy, ndz, sv[0], sv[1], sv[2], pout);
             const cd ls = dot_re(lam, sv), lp = dot_re(lam, pout);
-            const cd Gs = cscale(cmul(cconj(ls), es), scale);
-            const cd Gp = cscale(cmul(cconj(lp), ep), scale);
+            const cd Gs = cscale(cmul_f(cconj(ls), es), scale);
+            const cd Gp = cscale(cmul_f(cconj(lp), ep), scale);
             double c3[3];
             cross3(dx, dy, dz, pl.nx, 0.0, pl.nz, c3);
             const double kappa = pl.ng * sqrt(c3[0] * c3[0] + c3[1] * c3[1] + c3[2] * c3[2]);
             emit(kappa, Gs, Gp, m | (front << 8) | (refl << 9));
         } else {
             s_basis(dx, dy, dz, 0.0, 0.0, 1.0, sv);
-            cross3(dx, dy, dz, sv[0], sv[1], sv[2], pin);
+            cross3_f(dx, dy, dz, sv[0], sv[1], sv[2], pin);
             if (type == EV_TIR) {
-                cross3(dx, dy, -dz, sv[0], sv[1], sv[2], pout);
+                cross3_f(dx, dy, -dz, sv[0], sv[1], sv[2], pout);
             } else {
                 // exit: real t_s, t_p and the flux factor
                 cs = mk(ev.c0, -0.0);
@@ -605,12 +621,12 @@ __device__ inline void reverse_sweep(const SceneDev& sc, const PointLds& pl, con
                 const double st2 = (pl.ng * pl.ng) * (dx * dx + dy * dy);
                 double a[3];
                 exit_direction(pl.ng, pl.na, tmp, st2, a);
-                cross3(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
+                cross3_f(a[0], a[1], a[2], sv[0], sv[1], sv[2], pout);
             }
         }
         const cd ls = dot_re(lam, sv), lp = dot_re(lam, pout);
-        const cd as = cscale(cmul(cconj(cs), ls), scale), ap = cscale(cmul(cconj(cp), lp), scale);
-        for (int c = 0; c < 3; ++c) lam[c] = cadd(cscale(as, sv[c]), cscale(ap, pin[c]));
+        const cd as = cscale(cmul_f(cconj(cs), ls), scale), ap = cscale(cmul_f(cconj(cp), lp), scale);
+        for (int c = 0; c < 3; ++c) lam[c] = mk(fma(as.re, sv[c], ap.re * pin[c]), fma(as.im, sv[c], ap.im * pin[c]));
     }
 }
 
