@@ -356,8 +356,10 @@ int gwg_loss_noalloc(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, 
  * table_nodes (0 = 8192, else 4..2^20) is the number of incidence angles of
  * the angle table (GWG_FWD_TABLE).  ck_entries_per_ray (0 = 4, -1 = none,
  * else 1..64): with GWG_FWD_GRAD at FP64 on lossless stacks, the forward
- * solve keeps the adjoint's sweep checkpoints (8 doubles every 16 layers)
- * for up to this many entries per ray of each entry region, within a memory
+ * solve keeps the adjoint's sweep checkpoints (8 doubles every 32 layers
+ * of a hit whose layers all propagate, every 16 of one that meets an
+ * evanescent layer) for up to this many entries per ray of each entry
+ * region, within a memory
  * budget (the smaller of 128 GiB and half the free memory), so the backward
  * skips that sweep for them; the gradient is the same bit for bit. */
 typedef struct {
