@@ -359,9 +359,9 @@ int gwg_loss_noalloc(gwg_ctx* ctx, const double* d_irr, int32_t D, int32_t n_l, 
  * solve keeps the adjoint's sweep checkpoints (8 doubles every 32 layers
  * of a hit whose layers all propagate, every 16 of one that meets an
  * evanescent layer) for up to this many entries per ray of each entry
- * region, within a memory
- * budget (the smaller of 128 GiB and half the free memory), so the backward
- * skips that sweep for them; the gradient is the same bit for bit. */
+ * region, within a memory budget (the smaller of 128 GiB and half the free
+ * memory), so the backward skips that sweep for them; the gradient is the
+ * same bit for bit. */
 typedef struct {
     int32_t block_threads;
     int64_t rays_per_block;
